@@ -1,0 +1,185 @@
+#!/usr/bin/env python
+"""Benchmark of the HBPC hot path on one MI355X.
+
+Workload (default): 2-D compressible Euler isentropic vortex on the periodic
+[0,10]^2, gamma 1.4, background Mach 0.5, strength 5, seeded centre
+(seed 2109), DGSEM N = 5 on Gauss nodes, 128 x 128 elements (2,359,296 DOF),
+Rusanov flux, HBPC(6,4) (3 nodes c = 0, 1/2, 1; 4 corrector sweeps), dt = 0.1,
+Newton tolerance 1e-8, FGMRES(30) with eps_G = 1e-3, BJ_ext preconditioner.
+Two forms are timed: all-FP64, and FP64 Newton with FP32 Krylov vectors, JVP
+and BJ_ext ("mixed").  A step is one full HBPC step (all stage solves) on the
+state resident in HBM; inputs are synthetic.
+
+Prints ONE JSON line: value = DOF-steps/s of the headline (mixed) form, the
+FP64 form beside it, the roofline of the dominant kernel (HIP events around
+every launch on the library's stream, algorithmic bytes per launch), and the
+FP64 NumPy oracle timed on the host on a bounded sample of the workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "HBPC DOF-steps/s at 1e-8 Newton tol, learned+FP32 vs plain FP64; HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+WORKLOADS = {
+    "euler_vortex_128x128_N5": dict(dim=2, nelem=[128, 128], length=[10.0, 10.0], N=5, dt=0.1),
+    # small variant for quick checks
+    "euler_vortex_32x32_N5": dict(dim=2, nelem=[32, 32], length=[10.0, 10.0], N=5, dt=0.1),
+}
+
+
+def vortex_state(ctx, wl):
+    import numpy as np
+    from paper_2109_04804_amd import inputs
+    xi, _ = ctx.nodes()
+    X = inputs.node_coords(2, wl["nelem"], wl["length"], [0.0, 0.0], xi)
+    xc, yc, beta = inputs.vortex_params(inputs.DEFAULT_SEED, beta=5.0)
+    return inputs.isentropic_vortex(X[0], X[1], xc, yc, beta, mach=0.5, gamma=1.4, box=wl["length"][0])
+
+
+def run_form(wl, precision, steps, warmup):
+    import numpy as np
+    import torch
+    from paper_2109_04804_amd.hbpc import Context
+    ctx = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], "euler", flux="rusanov", gamma=1.4, eps_ref=1.0,
+                  q=6, kmax=4, newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=30, gmres_maxit=7000,
+                  precond="bjext", precision=precision)
+    w0 = vortex_state(ctx, wl)
+    w = torch.tensor(np.ascontiguousarray(w0).reshape(-1), dtype=torch.float64, device="cuda")
+    for i in range(warmup):
+        st = ctx.step(w, wl["dt"])
+        print("[bench] %s warmup %d: newton %d gmres %d  %.1f ms" % (precision, i, st["newton_its"],
+              st["gmres_its"], st["t_step_ms"]), file=sys.stderr, flush=True)
+    ctx.profile_read(reset=True)
+    ctx.profile_enable(True)
+    stats = []
+    torch.cuda.synchronize()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    t_start.record()
+    for i in range(steps):
+        st = ctx.step(w, wl["dt"])
+        stats.append(st)
+        print("[bench] %s step %d: newton %d gmres %d  %.1f ms" % (precision, i, st["newton_its"],
+              st["gmres_its"], st["t_step_ms"]), file=sys.stderr, flush=True)
+    t_end.record()
+    torch.cuda.synchronize()
+    ms = t_start.elapsed_time(t_end)
+    prof = ctx.profile_read(reset=True)
+    ctx.profile_enable(False)
+    finite = bool(torch.isfinite(w).all().item())
+    ctx.close()
+    return {"ms_total": ms, "ms_per_step": ms / steps, "dof": ctx.ndof,
+            "newton_its": [s["newton_its"] for s in stats], "gmres_its": [s["gmres_its"] for s in stats],
+            "pc_builds": [s["pc_builds"] for s in stats], "kernels": prof, "finite": finite}
+
+
+def roofline_of(prof):
+    """Dominant kernel class by total time; HBM-bound kernels against 8 TB/s,
+    the BJ_ext inversion (dense FP64 arithmetic) against the FP64 peak."""
+    name, k = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
+    per_launch_ms = k["total_ms"] / k["launches"]
+    if name == "bj_invert":
+        ach = k["flops"] / k["launches"] / (per_launch_ms * 1e-3) / 1e12
+        return {"kernel": name, "bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
+                "avg_launch_ms": per_launch_ms, "launches": k["launches"]}
+    ach = k["bytes"] / k["launches"] / (per_launch_ms * 1e-3) / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": k["bytes"] / k["launches"],
+            "avg_launch_ms": per_launch_ms, "launches": k["launches"]}
+
+
+def cpu_baseline(seconds_hint=30.0):
+    """FP64 NumPy oracle, one thread, one HBPC(6,4) step of the vortex workload
+    on a reduced 8 x 8-element mesh of the same domain (N = 5, dt = 0.1,
+    eps_N 1e-8, GMRES(30) + BJ_ext)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle.dgsem import DGSEM, Mesh
+    from oracle.equations import Euler
+    from oracle.solvers import StageSolver, dg_hbpc_step
+    from paper_2109_04804_amd import inputs
+    n = 8
+    dg = DGSEM(Mesh(2, [n, n], [10.0, 10.0]), 5, Euler(2), flux="rusanov")
+    X = dg.node_coords()
+    xc, yc, beta = inputs.vortex_params(inputs.DEFAULT_SEED, beta=5.0)
+    w = inputs.isentropic_vortex(X[0], X[1], xc, yc, beta)
+    sol = StageSolver(dg, newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=30)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        dg_hbpc_step(dg, w, 0.1, 6, 4, sol)
+        dt = time.perf_counter() - t0
+    return {"value": dg.ndof / dt, "unit": "DOF-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "one HBPC(6,4) step, vortex on 8x8 elements of [0,10]^2 (%d DOF), N=5, dt=0.1, "
+                      "eps_N 1e-8, GMRES(30)+BJ_ext, NumPy FP64, 1 thread, %.1f s" % (dg.ndof, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="euler_vortex_128x128_N5", choices=sorted(WORKLOADS))
+    ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(the multi-GPU design is described in DESIGN.md)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
+    wl = WORKLOADS[a.workload]
+    forms = [f for f in a.forms.split(",") if f]
+    res = {}
+    for f in forms:
+        res[f] = run_form(wl, f, a.steps, a.warmup)
+    head = "mixed" if "mixed" in res else forms[0]
+    h = res[head]
+    dof = h["dof"]
+    value = dof * a.steps / (h["ms_total"] * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": h["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "dof": dof, "scheme": "HBPC(6,4)", "dt": wl["dt"],
+                   "newton_rtol": 1e-8, "krylov": "FGMRES(30), eps_G 1e-3", "precond": "BJ_ext",
+                   "form": head, "learned_preconditioner": "not built"},
+        "forms": {f: {"dof_steps_per_s": dof * a.steps / (r["ms_total"] * 1e-3), "ms_per_step": r["ms_per_step"],
+                      "newton_its": r["newton_its"], "gmres_its": r["gmres_its"], "finite": r["finite"]}
+                  for f, r in res.items()},
+        "roofline": roofline_of(h["kernels"]),
+        "kernels": {f: {k: {"launches": v["launches"], "total_ms": round(v["total_ms"], 3),
+                            "GBps": (v["bytes"] / (v["total_ms"] * 1e-3) / 1e9) if v["total_ms"] > 0 else None}
+                        for k, v in r["kernels"].items()} for f, r in res.items()},
+    }
+    if "fp64" in res and head != "fp64":
+        out["speedup_vs_fp64"] = res["fp64"]["ms_per_step"] / h["ms_per_step"]
+    if not a.no_cpu_baseline:
+        cb = cpu_baseline()
+        out["cpu_baseline"] = cb
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * libhbpc -- HBPC(q, k_max) two-derivative deferred-correction time stepping
+ * of the DGSEM on uniform periodic Cartesian meshes, for one AMD MI355X GPU.
+ *
+ * Method: Zeifang & Schuetz, "Two-derivative deferred correction time
+ * discretization for the discontinuous Galerkin method" (arXiv 2109.04804).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ *  - State layout: w[e][v][node], contiguous, FP64 unless the name ends in
+ *    _f32.  node = i + (N+1)(j + (N+1)k); elements are lexicographic with x
+ *    fastest; v runs over the nvar conserved variables (advection and Burgers
+ *    1, Euler d+2: rho, rho v_1..rho v_d, E).
+ *  - ndof = n_elem (N+1)^d nvar (hbpc_ndof).  Extended vectors X = (w, sigma)
+ *    hold the w block followed by the sigma block (2 ndof values).
+ *  - All data pointers are DEVICE pointers owned by the caller, unless stated
+ *    otherwise.  Input and output buffers must not overlap.
+ *  - residual/JVP/preconditioner calls are asynchronous on the context's
+ *    stream (hbpc_params.stream, or hbpc_set_stream); hbpc_step synchronises.
+ *  - Return value 0 on success, a negative HBPC_ERR_* code otherwise; no
+ *    exception crosses the ABI.  hbpc_last_error gives a message.
+ *  - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef HBPC_H
+#define HBPC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hbpc_ctx hbpc_ctx;
+
+/* error codes */
+#define HBPC_OK 0
+#define HBPC_ERR_ARG (-1)          /* invalid argument or unsupported combination */
+#define HBPC_ERR_OOM (-2)          /* device allocation failed */
+#define HBPC_ERR_HIP (-3)          /* HIP runtime error */
+#define HBPC_ERR_NONFINITE (-4)    /* NaN/Inf in a residual norm */
+#define HBPC_ERR_NEWTON (-5)       /* Newton did not converge within newton_maxit */
+#define HBPC_ERR_GMRES (-6)        /* GMRES did not reach gmres_rtol within gmres_maxit */
+#define HBPC_ERR_UNSUPPORTED (-7)  /* (dim, N, equation) not compiled in */
+
+/* equations (Sec. 4.1.1 advection, Eq. Euler; viscous Burgers with BR1) */
+#define HBPC_EQ_ADVECTION 1
+#define HBPC_EQ_BURGERS_BR1 2
+#define HBPC_EQ_EULER 3
+
+/* interpolation/quadrature nodes (Sec. 3.1.1 uses Gauss-Legendre) */
+#define HBPC_NODES_GAUSS 0
+#define HBPC_NODES_LOBATTO 1
+
+/* numerical flux (Eq. Riemann): f* = (F(wL)+F(wR)).n/2 + lambda (wL - wR)/2 */
+#define HBPC_FLUX_CENTRAL 0        /* lambda = 0 */
+#define HBPC_FLUX_UPWIND 1         /* lambda = |a.n| (advection) */
+#define HBPC_FLUX_LF 2             /* lambda = params.lambda, a global constant */
+#define HBPC_FLUX_RUSANOV 3        /* lambda = max(|vL.n| + cL/eps, |vR.n| + cR/eps) (Euler) */
+
+/* precision of the Krylov solve */
+#define HBPC_FP64 0                /* everything FP64 */
+#define HBPC_MIXED 1               /* FP64 Newton residual/updates, FP32 Krylov, JVP and BJ_ext */
+
+/* preconditioner */
+#define HBPC_PC_NONE 0
+#define HBPC_PC_BJEXT 1            /* extended block-Jacobi, Sec. 3.2.3 */
+
+/* preconditioner rebuild frequency */
+#define HBPC_PC_PER_SOLVE 0        /* once per stage solve, at the Newton initial guess */
+#define HBPC_PC_PER_NEWTON_IT 1    /* at every Newton iterate */
+
+/* Jacobian-vector product */
+#define HBPC_JVP_LINEARISED 0      /* exact directional derivatives (hyper-dual flux) */
+#define HBPC_JVP_FD 1              /* finite differences, Eq. MatrixFree_nonlinear (FP64 only) */
+
+typedef struct {
+    int dim;              /* 1, 2 or 3 */
+    int nelem[3];         /* elements per direction (entries beyond dim ignored) */
+    double length[3];     /* domain length per direction */
+    double origin[3];     /* lower corner */
+} hbpc_mesh;
+
+typedef struct {
+    int nodes;            /* HBPC_NODES_* */
+    int flux;             /* HBPC_FLUX_* */
+    double lambda;        /* constant lambda for HBPC_FLUX_LF */
+    double adv[3];        /* advection velocity (HBPC_EQ_ADVECTION) */
+    double nu;            /* viscosity (HBPC_EQ_BURGERS_BR1) */
+    double gamma;         /* ratio of specific heats (Euler) */
+    double eps_ref;       /* reference Mach number eps (Euler, Eq. Euler) */
+    int q;                /* quadrature order of the tableau: 4, 6 or 8 (appendix) */
+    int kmax;             /* corrector sweeps k_max */
+    double newton_rtol;   /* eps_N: stop when ||G(X^r)|| <= eps_N ||G(X^0)|| */
+    double newton_atol_dw;/* ... or when ||dw^r||_2 / sqrt(ndof) <= this (default 1.95e-15):
+                             the paper's absolute Newton tolerance ||dw||_2 <= 1e-12 (Sec. 5.1,
+                             for 262,144 coefficients) taken per coefficient, so that it stays
+                             above the round-off floor at every problem size */
+    int newton_maxit;     /* default 30 */
+    double gmres_rtol;    /* eps_G: stop when ||r_j|| <= eps_G ||r_0|| */
+    int gmres_restart;    /* m of GMRES(m), <= 64 */
+    int gmres_maxit;      /* per Newton step (default 7000) */
+    int precision;        /* HBPC_FP64 | HBPC_MIXED */
+    int precond;          /* HBPC_PC_* */
+    int pc_rebuild;       /* HBPC_PC_PER_SOLVE | HBPC_PC_PER_NEWTON_IT */
+    int jvp_mode;         /* HBPC_JVP_* */
+    int hessian;          /* 1: include dR2/dw in the JVP (exact Newton), 0: drop it */
+    void* stream;         /* hipStream_t; NULL = the null stream */
+} hbpc_params;
+
+#define HBPC_MAX_SOLVES 64
+typedef struct {
+    int n_solves;                               /* stage solves in the last step */
+    int newton_its;                             /* total Newton iterations */
+    int gmres_its;                              /* total Krylov iterations */
+    int pc_builds;                              /* BJ_ext builds */
+    int newton_per_solve[HBPC_MAX_SOLVES];
+    int gmres_per_solve[HBPC_MAX_SOLVES];
+    double t_step_ms;                           /* wall time of the step (host clock) */
+    double t_pc_build_ms, t_gmres_ms, t_residual_ms;  /* phase times (host clock, synchronised) */
+} hbpc_stats;
+
+/* Fill *p with the defaults: Gauss nodes, Rusanov flux, gamma 1.4, eps 1,
+ * HBPC(6,4), eps_N 1e-8, atol_dw 1.95e-15 (RMS), 30 Newton its, eps_G 1e-3,
+ * GMRES(30), 7000 its, FP64, BJ_ext per solve, linearised JVP with Hessian. */
+void hbpc_default_params(hbpc_params* p);
+
+/* Create a context: mesh (host struct), degree N (1..7), equation HBPC_EQ_*.
+ * Computes the 1-D operators (Sec. 3.1.1) on the host and allocates all
+ * device work space (stage vectors, Krylov bases, BJ_ext blocks).  *out is
+ * owned by the caller and released by hbpc_destroy.
+ * Errors: HBPC_ERR_ARG, HBPC_ERR_UNSUPPORTED, HBPC_ERR_OOM, HBPC_ERR_HIP. */
+int hbpc_create(const hbpc_mesh* mesh, int N, int equation, const hbpc_params* params, hbpc_ctx** out);
+int hbpc_destroy(hbpc_ctx* ctx);
+int hbpc_set_stream(hbpc_ctx* ctx, void* stream);
+size_t hbpc_ndof(const hbpc_ctx* ctx);
+/* Element block size ne = nvar (N+1)^d. */
+int hbpc_block_size(const hbpc_ctx* ctx);
+/* 1-D nodes and weights into HOST arrays of N+1 doubles. */
+int hbpc_nodes(const hbpc_ctx* ctx, double* xi_host, double* w_host);
+
+/* R1_h(w) -> r1 (Eq. DGSEM_wt). */
+int hbpc_residual1(hbpc_ctx* ctx, const double* w, double* r1);
+/* R2_h(w, sigma) = R1_h'(w) sigma -> r2 (Eq. DGSEM_wtt, exact directional
+ * derivative).  sigma == NULL: sigma = R1_h(w) is computed first. */
+int hbpc_residual2(hbpc_ctx* ctx, const double* w, const double* sigma, double* r2);
+/* Extended residual of Sec. 3.2.1 with X = (w, sigma):
+ *   G[0:ndof]      = w - a1dt R1(w) + bcoef R2(w, sigma) - b
+ *   G[ndof:2ndof]  = sigma - R1(w)
+ * a1dt = alpha_1 dt, bcoef = alpha_2 dt^2 / 2 (Eq. Newton_Residual). */
+int hbpc_newton_residual(hbpc_ctx* ctx, const double* w, const double* sigma, const double* b,
+                         double a1dt, double bcoef, double* G);
+/* Extended Jacobian-vector product (Eq. nonlinear_eqsys):
+ *   JdX = ( dw - a1dt T1 + bcoef (T2 + T3),  dsigma - T1 )
+ *   T1 = R1'(w) dw, T2 = R1'(w) dsigma, T3 = R1''(w)[sigma, dw] (0 if params.hessian == 0)
+ * dX and JdX hold 2 ndof values.  mode: HBPC_JVP_LINEARISED or HBPC_JVP_FD
+ * (Eq. MatrixFree_nonlinear with eps_FD = sqrt(eps_mach)/(eps ||d||_2)). */
+int hbpc_jvp(hbpc_ctx* ctx, const double* w, const double* sigma, double a1dt, double bcoef,
+             const double* dX, double* JdX, int mode);
+/* Same, linearised, in FP32 on FP32 copies of w and sigma. */
+int hbpc_jvp_f32(hbpc_ctx* ctx, const float* w, const float* sigma, double a1dt, double bcoef,
+                 const float* dX, float* JdX);
+
+/* Build BJ_ext at state w (Sec. 3.2.3): K_i = element-local dR1/dw (every
+ * quantity read from a neighbour held constant), S_i = I - a1dt K_i +
+ * bcoef K_i^2, S_i^-1 by Gauss-Jordan elimination with partial pivoting.
+ * precision HBPC_FP64 or HBPC_MIXED selects the storage of S^-1.  The blocks
+ * are kept in the context until the next build. */
+int hbpc_pc_build(hbpc_ctx* ctx, const double* w, double a1dt, double bcoef, int precision);
+/* Y = P^-1 X with the blocks of the last build: (D vw + E vs, F vw + G vs). */
+int hbpc_pc_apply(hbpc_ctx* ctx, const double* X, double* Y);
+int hbpc_pc_apply_f32(hbpc_ctx* ctx, const float* X, float* Y);
+
+/* One HBPC(q, k_max) step (Algorithm 1) of size dt, in place.  Transactional:
+ * on any error w_inout is unchanged.  stats may be NULL.  Synchronises. */
+int hbpc_step(hbpc_ctx* ctx, double* w_inout, double dt, hbpc_stats* stats);
+
+/* Kernel timing (HIP events recorded around every launch on the context's
+ * stream, resolved after synchronisation).  Classes: trace, r1, r2, res, jvp,
+ * kcol, pcpre, bj_apply, bj_invert, mdot, gemv, vec.  `bytes` and `flops` are
+ * the algorithmic figures of all recorded launches: inputs read once and
+ * outputs written once (bytes), the method's floating-point operations
+ * (flops, only for bj_invert).  Timing adds a few microseconds per launch. */
+typedef struct {
+    char name[16];
+    int launches;
+    double total_ms;
+    double bytes;
+    double flops;
+} hbpc_kernel_prof;
+int hbpc_profile_enable(hbpc_ctx* ctx, int enable);
+/* Copy up to max classes (those with launches) into out; reset != 0 clears
+ * the counters.  Synchronises the stream.  Returns the number of classes
+ * written, or a negative error code. */
+int hbpc_profile_read(hbpc_ctx* ctx, hbpc_kernel_prof* out, int max, int reset);
+
+const char* hbpc_strerror(int code);
+const char* hbpc_last_error(const hbpc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,217 @@
+// Vector kernels of the Newton-Krylov solver: block-partial dot products with
+// several basis vectors at once (classical Gram-Schmidt), the update
+// w -= V h, norms, axpby, casts.  Reductions are deterministic: each block sums
+// a fixed set of indices in a fixed order, partial results are combined by
+// one block in a fixed tree, so two runs give bitwise equal results.
+#include <hip/hip_runtime.h>
+#include <cstddef>
+
+constexpr int BLAS_THREADS = 256;
+constexpr int MDOT_CHUNK = 8;
+
+template <typename T> __device__ __forceinline__ double block_sum(double v, double* sh) {
+    // wave64 shuffle tree, then LDS across the 4 waves
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+    }
+    return r;
+}
+
+// part[blockIdx.x * ldp + j] = sum_{i in block} V_j[i] * w[i], j < kc (<= MDOT_CHUNK)
+template <typename T>
+__global__ void __launch_bounds__(BLAS_THREADS) mdot_kernel(const T* __restrict__ V, size_t ld, int kc,
+                                                            const T* __restrict__ w, size_t n,
+                                                            double* __restrict__ part, int ldp) {
+    __shared__ double sh[BLAS_THREADS / 64];
+    double acc[MDOT_CHUNK];
+#pragma unroll
+    for (int j = 0; j < MDOT_CHUNK; ++j) acc[j] = 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double wi = (double)w[i];
+#pragma unroll
+        for (int j = 0; j < MDOT_CHUNK; ++j)
+            if (j < kc) acc[j] += (double)V[j * ld + i] * wi;
+    }
+    for (int j = 0; j < kc; ++j) {
+        double s = block_sum<T>(acc[j], sh);
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * ldp + j] = s;
+    }
+}
+
+// out[j] = scale * sum_b part[b * ldp + j]; one block per j
+__global__ void __launch_bounds__(BLAS_THREADS) reduce_parts_kernel(const double* __restrict__ part, int nb, int ldp,
+                                                                    double* __restrict__ out, double scale) {
+    __shared__ double sh[BLAS_THREADS / 64];
+    const int j = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(size_t)b * ldp + j];
+    s = block_sum<double>(s, sh);
+    if (threadIdx.x == 0) out[j] = scale * s;
+}
+
+// w[i] -= sum_j h[j] V_j[i]   (h on the device)
+template <typename T>
+__global__ void __launch_bounds__(BLAS_THREADS) gemv_sub_kernel(const T* __restrict__ V, size_t ld, int k,
+                                                                const double* __restrict__ h, T* __restrict__ w,
+                                                                size_t n) {
+    __shared__ double sh[64];
+    for (int j = threadIdx.x; j < k; j += blockDim.x) sh[j] = h[j];
+    __syncthreads();
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double acc = 0.0;
+        for (int j = 0; j < k; ++j) acc += sh[j] * (double)V[j * ld + i];
+        w[i] = (T)((double)w[i] - acc);
+    }
+}
+
+// y[i] = a * x[i] + b * y[i] (b == 0: y is not read)
+template <typename TX, typename TY>
+__global__ void __launch_bounds__(BLAS_THREADS) axpby_kernel(double a, const TX* x, double b,
+                                                             TY* y, size_t n) {   // x may alias y
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double v = a * (double)x[i];
+        if (b != 0.0) v += b * (double)y[i];
+        y[i] = (TY)v;
+    }
+}
+
+// y[i] = a * x[i] + b * z[i]
+template <typename T>
+__global__ void __launch_bounds__(BLAS_THREADS) lincomb2_kernel(double a, const T* __restrict__ x, double b,
+                                                                const T* __restrict__ z, T* __restrict__ y, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        y[i] = (T)(a * (double)x[i] + b * (double)z[i]);
+}
+
+// y[i] += sum_j c[j] Z_j[i]  (c on the host, passed by value in chunks of 8)
+struct Coef8 { double c[8]; };
+template <typename TZ, typename TY>
+__global__ void __launch_bounds__(BLAS_THREADS) gemv_add_kernel(const TZ* __restrict__ Z, size_t ld, int k, Coef8 c,
+                                                                TY* __restrict__ y, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (j < k) acc += c.c[j] * (double)Z[j * ld + i];
+        y[i] = (TY)((double)y[i] + acc);
+    }
+}
+
+// status |= 1 if any non-finite value
+template <typename T>
+__global__ void __launch_bounds__(BLAS_THREADS) nonfinite_kernel(const T* __restrict__ x, size_t n, int* status) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    int bad = 0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        T v = x[i];
+        if (!(v == v) || v - v != v - v) bad = 1;
+    }
+    if (bad) atomicOr(status, 1);
+}
+
+// ------------------------------------------------------------------ launchers
+static int blas_grid(size_t n) {
+    size_t g = (n + BLAS_THREADS - 1) / BLAS_THREADS;
+    if (g > 2048) g = 2048;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+int blas_mdot_grid(size_t n) { return blas_grid(n); }
+
+// h[j] = V_j . w for j < k; part must hold grid * k doubles.
+hipError_t blas_mdot(const void* V, size_t ld, int k, const void* w, size_t n, int f32, double* part, double* h,
+                     hipStream_t st) {
+    int g = blas_grid(n);
+    for (int j0 = 0; j0 < k; j0 += MDOT_CHUNK) {
+        int kc = k - j0 < MDOT_CHUNK ? k - j0 : MDOT_CHUNK;
+        if (f32)
+            hipLaunchKernelGGL(mdot_kernel<float>, dim3(g), dim3(BLAS_THREADS), 0, st,
+                               (const float*)V + j0 * ld, ld, kc, (const float*)w, n, part + j0, k);
+        else
+            hipLaunchKernelGGL(mdot_kernel<double>, dim3(g), dim3(BLAS_THREADS), 0, st,
+                               (const double*)V + j0 * ld, ld, kc, (const double*)w, n, part + j0, k);
+    }
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(k), dim3(BLAS_THREADS), 0, st, part, g, k, h, 1.0);
+    return hipGetLastError();
+}
+
+hipError_t blas_gemv_sub(const void* V, size_t ld, int k, const double* h, void* w, size_t n, int f32,
+                         hipStream_t st) {
+    int g = blas_grid(n);
+    if (f32)
+        hipLaunchKernelGGL(gemv_sub_kernel<float>, dim3(g), dim3(BLAS_THREADS), 0, st, (const float*)V, ld, k, h,
+                           (float*)w, n);
+    else
+        hipLaunchKernelGGL(gemv_sub_kernel<double>, dim3(g), dim3(BLAS_THREADS), 0, st, (const double*)V, ld, k, h,
+                           (double*)w, n);
+    return hipGetLastError();
+}
+
+// type codes: 0 = double, 1 = float
+hipError_t blas_axpby(double a, const void* x, int tx, double b, void* y, int ty, size_t n, hipStream_t st) {
+    int g = blas_grid(n);
+    if (tx == 0 && ty == 0)
+        hipLaunchKernelGGL((axpby_kernel<double, double>), dim3(g), dim3(BLAS_THREADS), 0, st, a, (const double*)x, b,
+                           (double*)y, n);
+    else if (tx == 0 && ty == 1)
+        hipLaunchKernelGGL((axpby_kernel<double, float>), dim3(g), dim3(BLAS_THREADS), 0, st, a, (const double*)x, b,
+                           (float*)y, n);
+    else if (tx == 1 && ty == 0)
+        hipLaunchKernelGGL((axpby_kernel<float, double>), dim3(g), dim3(BLAS_THREADS), 0, st, a, (const float*)x, b,
+                           (double*)y, n);
+    else
+        hipLaunchKernelGGL((axpby_kernel<float, float>), dim3(g), dim3(BLAS_THREADS), 0, st, a, (const float*)x, b,
+                           (float*)y, n);
+    return hipGetLastError();
+}
+
+hipError_t blas_lincomb2(double a, const double* x, double b, const double* z, double* y, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(lincomb2_kernel<double>, dim3(blas_grid(n)), dim3(BLAS_THREADS), 0, st, a, x, b, z, y, n);
+    return hipGetLastError();
+}
+
+// y += sum_j c[j] Z_j (Z of type tz, y of type ty)
+hipError_t blas_gemv_add(const void* Z, int tz, size_t ld, int k, const double* c, void* y, int ty, size_t n,
+                         hipStream_t st) {
+    int g = blas_grid(n);
+    for (int j0 = 0; j0 < k; j0 += 8) {
+        Coef8 cc;
+        int kc = k - j0 < 8 ? k - j0 : 8;
+        for (int j = 0; j < 8; ++j) cc.c[j] = j < kc ? c[j0 + j] : 0.0;
+        if (tz == 0 && ty == 0)
+            hipLaunchKernelGGL((gemv_add_kernel<double, double>), dim3(g), dim3(BLAS_THREADS), 0, st,
+                               (const double*)Z + j0 * ld, ld, kc, cc, (double*)y, n);
+        else if (tz == 1 && ty == 1)
+            hipLaunchKernelGGL((gemv_add_kernel<float, float>), dim3(g), dim3(BLAS_THREADS), 0, st,
+                               (const float*)Z + j0 * ld, ld, kc, cc, (float*)y, n);
+        else if (tz == 1 && ty == 0)
+            hipLaunchKernelGGL((gemv_add_kernel<float, double>), dim3(g), dim3(BLAS_THREADS), 0, st,
+                               (const float*)Z + j0 * ld, ld, kc, cc, (double*)y, n);
+        else
+            hipLaunchKernelGGL((gemv_add_kernel<double, float>), dim3(g), dim3(BLAS_THREADS), 0, st,
+                               (const double*)Z + j0 * ld, ld, kc, cc, (float*)y, n);
+    }
+    return hipGetLastError();
+}
+
+hipError_t blas_nonfinite(const void* x, int f32, size_t n, int* status, hipStream_t st) {
+    int g = blas_grid(n);
+    if (f32)
+        hipLaunchKernelGGL(nonfinite_kernel<float>, dim3(g), dim3(BLAS_THREADS), 0, st, (const float*)x, n, status);
+    else
+        hipLaunchKernelGGL(nonfinite_kernel<double>, dim3(g), dim3(BLAS_THREADS), 0, st, (const double*)x, n, status);
+    return hipGetLastError();
+}

@@ -1,0 +1,130 @@
+// Host-side launch of the DGSEM operator kernels for one (equation, d) family.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "dg_ops.hpp"
+
+enum {
+    OPK_TRACE = 0, OPK_R1, OPK_R2, OPK_RES, OPK_JVP, OPK_JVP_NOHESS, OPK_KCOL, OPK_PCPRE,
+    OPK_LIFT      // BR1 lifting (viscous Burgers only)
+};
+
+struct GeomHost {
+    int D, NP, NV, nE;
+    int nel[3];
+    double two_h[3];
+    double Dhat[8][8], lp[8], lm[8], lhp[8], lhm[8];
+    double adv[3], lam, nu, gamma, eps;
+    int flux;
+};
+
+struct LaunchReq {
+    int op;
+    const void* fld[4];
+    const void* trc[4];
+    const void* q[4][3];
+    const void* qtr[4];
+    void* out[4];
+    double c0, c1;
+    int col;
+    int e_begin, e_end;   // element range (e_end <= 0: whole mesh)
+    hipStream_t stream;
+};
+
+template <typename T, int NP> Basis<T, NP> make_basis(const GeomHost& g) {
+    Basis<T, NP> b;
+    for (int i = 0; i < NP; ++i) {
+        for (int j = 0; j < NP; ++j) b.Dhat[i][j] = (T)g.Dhat[i][j];
+        b.lp[i] = (T)g.lp[i];
+        b.lm[i] = (T)g.lm[i];
+        b.lhp[i] = (T)g.lhp[i];
+        b.lhm[i] = (T)g.lhm[i];
+    }
+    return b;
+}
+
+template <typename T> EqParams<T> make_eq(const GeomHost& g) {
+    EqParams<T> p;
+    for (int m = 0; m < 3; ++m) p.adv[m] = (T)g.adv[m];
+    p.lam = (T)g.lam;
+    p.nu = (T)g.nu;
+    p.gm1 = (T)(g.gamma - 1.0);
+    p.gamma = (T)g.gamma;
+    p.half_eps2 = (T)(0.5 * g.eps * g.eps);
+    p.inv_eps = (T)(1.0 / g.eps);
+    p.inv_eps2 = (T)(1.0 / (g.eps * g.eps));
+    p.flux = g.flux;
+    return p;
+}
+
+template <typename T> OpArgs<T> make_args(const GeomHost& g, const LaunchReq& r) {
+    OpArgs<T> a;
+    for (int j = 0; j < 4; ++j) {
+        a.fld[j] = (const T*)r.fld[j];
+        a.trc[j] = (const T*)r.trc[j];
+        a.qtr[j] = (const T*)r.qtr[j];
+        for (int m = 0; m < 3; ++m) a.q[j][m] = (const T*)r.q[j][m];
+    }
+    a.out[0] = (T*)r.out[0];
+    a.out[1] = (T*)r.out[1];
+    a.c0 = (T)r.c0;
+    a.c1 = (T)r.c1;
+    a.col = r.col;
+    a.nE = g.nE;
+    a.e_begin = r.e_end > 0 ? r.e_begin : 0;
+    a.e_end = r.e_end > 0 ? r.e_end : g.nE;
+    for (int m = 0; m < 3; ++m) {
+        a.nel[m] = g.nel[m];
+        a.two_h[m] = (T)g.two_h[m];
+    }
+    return a;
+}
+
+template <int D, int NP, class EQ, class OP, typename T>
+hipError_t launch_op(const GeomHost& g, const LaunchReq& r) {
+    constexpr int NN = ipow(NP, D);
+    constexpr int EPB = op_epb<D, NP, EQ::NV, OP::NJ, OP::NC, T>();
+    OpArgs<T> a = make_args<T>(g, r);
+    int grid = (a.e_end - a.e_begin + EPB - 1) / EPB;
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((dg_op_kernel<D, NP, EQ, OP, T>), dim3(grid), dim3(EPB * NN), 0, r.stream,
+                       a, make_basis<T, NP>(g), make_eq<T>(g));
+    return hipGetLastError();
+}
+
+template <int D, int NP, class EQ, typename T> hipError_t launch_family_np(const GeomHost& g, const LaunchReq& r) {
+    constexpr int NV = EQ::NV;
+    constexpr int NN = ipow(NP, D);
+    switch (r.op) {
+    case OPK_TRACE: {
+        constexpr int EPB = 256 / NN > 0 ? 256 / NN : 1;
+        int grid = (g.nE + EPB - 1) / EPB;
+        if (grid == 0) return hipSuccess;
+        hipLaunchKernelGGL((trace_kernel<D, NP, NV, T>), dim3(grid), dim3(EPB * NN), 0, r.stream,
+                           (const T*)r.fld[0], (T*)r.out[0], g.nE, make_basis<T, NP>(g));
+        return hipGetLastError();
+    }
+    case OPK_R1: return launch_op<D, NP, EQ, OpR1<T>, T>(g, r);
+    case OPK_R2: return launch_op<D, NP, EQ, OpR2<T>, T>(g, r);
+    case OPK_RES: return launch_op<D, NP, EQ, OpRes<T>, T>(g, r);
+    case OPK_JVP: return launch_op<D, NP, EQ, OpJvp<T, true>, T>(g, r);
+    case OPK_JVP_NOHESS: return launch_op<D, NP, EQ, OpJvp<T, false>, T>(g, r);
+    case OPK_KCOL: return launch_op<D, NP, EQ, OpKcol<T, NV * NN>, T>(g, r);
+    case OPK_PCPRE: return launch_op<D, NP, EQ, OpPcPre<T>, T>(g, r);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int D, class EQ> hipError_t launch_family(const GeomHost& g, const LaunchReq& r, int f32) {
+#define HBPC_NP_CASE(NPV)                                                          \
+    case NPV:                                                                      \
+        return f32 ? launch_family_np<D, NPV, EQ, float>(g, r)                     \
+                   : launch_family_np<D, NPV, EQ, double>(g, r);
+    switch (g.NP) {
+        HBPC_NP_CASE(3)
+        HBPC_NP_CASE(4)
+        HBPC_NP_CASE(5)
+        HBPC_NP_CASE(6)
+    default: return hipErrorInvalidValue;
+    }
+#undef HBPC_NP_CASE
+}

@@ -1,0 +1,115 @@
+// Physical and numerical fluxes on device, templated on the scalar/jet type S.
+//
+// Numerical flux (Eq. Riemann, textbook 1/2 on the dissipation):
+//   f*(wL, wR; +e_m) = (F_m(wL) + F_m(wR))/2 + lambda (wL - wR)/2
+// lambda: central 0, upwind |a_m|, lf a global constant, rusanov
+// max(|v_m,L| + c_L/eps, |v_m,R| + c_R/eps) with c = sqrt(gamma p / rho).
+// Euler is the eps-scaled system of Eq. Euler: momentum flux carries p/eps^2,
+// p = (gamma - 1)(E - eps^2/2 |rho v|^2 / rho).
+#pragma once
+#include "jets.hpp"
+
+enum { FLUX_CENTRAL = 0, FLUX_UPWIND = 1, FLUX_LF = 2, FLUX_RUSANOV = 3 };
+
+template <typename T> struct EqParams {
+    T adv[3];
+    T lam;      // constant lambda (lf)
+    T nu;       // viscosity (Burgers)
+    T gm1;      // gamma - 1
+    T gamma;
+    T half_eps2;
+    T inv_eps;
+    T inv_eps2;
+    int flux;
+};
+
+template <int D> struct AdvectionEq {
+    static constexpr int NV = 1;
+    static constexpr bool VISC = false;
+    template <class S, class T> HD static void flux_dir(const S* w, int m, S* F, const EqParams<T>& p) {
+        F[0] = w[0] * p.adv[m];
+    }
+    template <class S, class T> HD static void flux_all(const S* w, S (*F)[NV], const EqParams<T>& p) {
+#pragma unroll
+        for (int m = 0; m < D; ++m) F[m][0] = w[0] * p.adv[m];
+    }
+    template <class S, class T> HD static S wave_speed(const S* w, int m, const EqParams<T>& p) {
+        return jconst<S, T>(jabs(p.adv[m]));
+    }
+};
+
+template <int D> struct BurgersEq {   // inviscid part u^2/2 per direction; viscous terms added by the operator
+    static constexpr int NV = 1;
+    static constexpr bool VISC = true;
+    template <class S, class T> HD static void flux_dir(const S* w, int m, S* F, const EqParams<T>& p) {
+        F[0] = w[0] * w[0] * T(0.5);
+    }
+    template <class S, class T> HD static void flux_all(const S* w, S (*F)[NV], const EqParams<T>& p) {
+        S f = w[0] * w[0] * T(0.5);
+#pragma unroll
+        for (int m = 0; m < D; ++m) F[m][0] = f;
+    }
+    template <class S, class T> HD static S wave_speed(const S* w, int m, const EqParams<T>& p) {
+        return jabs(w[0]);
+    }
+};
+
+template <int D> struct EulerEq {
+    static constexpr int NV = D + 2;
+    static constexpr bool VISC = false;
+    template <class S, class T> HD static S pressure(const S* w, S irho, const EqParams<T>& p) {
+        S m2 = w[1] * w[1];
+#pragma unroll
+        for (int k = 1; k < D; ++k) m2 = m2 + w[1 + k] * w[1 + k];
+        return (w[D + 1] - m2 * irho * p.half_eps2) * p.gm1;
+    }
+    template <class S, class T> HD static void flux_dir(const S* w, int m, S* F, const EqParams<T>& p) {
+        S irho = jrecip(w[0]);
+        S pr = pressure(w, irho, p);
+        S vm = w[1 + m] * irho;
+        F[0] = w[1 + m];
+#pragma unroll
+        for (int k = 0; k < D; ++k) F[1 + k] = w[1 + k] * vm;
+        F[1 + m] = F[1 + m] + pr * p.inv_eps2;
+        F[D + 1] = (w[D + 1] + pr) * vm;
+    }
+    template <class S, class T> HD static void flux_all(const S* w, S (*F)[NV], const EqParams<T>& p) {
+        S irho = jrecip(w[0]);
+        S pr = pressure(w, irho, p);
+        S pe = pr * p.inv_eps2;
+        S Ep = w[D + 1] + pr;
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+            S vm = w[1 + m] * irho;
+            F[m][0] = w[1 + m];
+#pragma unroll
+            for (int k = 0; k < D; ++k) F[m][1 + k] = w[1 + k] * vm;
+            F[m][1 + m] = F[m][1 + m] + pe;
+            F[m][D + 1] = Ep * vm;
+        }
+    }
+    template <class S, class T> HD static S wave_speed(const S* w, int m, const EqParams<T>& p) {
+        S irho = jrecip(w[0]);
+        S pr = pressure(w, irho, p);
+        S c = jsqrt(pr * irho * p.gamma);
+        return jabs(w[1 + m] * irho) + c * p.inv_eps;
+    }
+};
+
+template <class EQ, class S, class T>
+HD void numerical_flux(const S* wL, const S* wR, int m, S* f, const EqParams<T>& p) {
+    constexpr int NV = EQ::NV;
+    S FL[NV], FR[NV];
+    EQ::flux_dir(wL, m, FL, p);
+    EQ::flux_dir(wR, m, FR, p);
+    if (p.flux == FLUX_RUSANOV) {
+        S lam = jmax(EQ::wave_speed(wL, m, p), EQ::wave_speed(wR, m, p)) * T(0.5);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) f[v] = (FL[v] + FR[v]) * T(0.5) + lam * (wL[v] - wR[v]);
+    } else {
+        T lam = p.flux == FLUX_UPWIND ? jabs(p.adv[m]) : (p.flux == FLUX_LF ? p.lam : T(0));
+        lam *= T(0.5);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) f[v] = (FL[v] + FR[v]) * T(0.5) + (wL[v] - wR[v]) * lam;
+    }
+}

@@ -1,0 +1,996 @@
+// libhbpc host side: context, operator wrappers, Newton-Krylov stage solver and
+// the HBPC(q, k_max) driver (Algorithm 1), behind the C ABI of include/hbpc.h.
+//
+// Stage solve (Sec. 3.2): Newton on the extended residual
+//   G(X) = (w - a1dt R1(w) + bcoef R2(w, sigma) - b,  sigma - R1(w)),
+// each correction from right-preconditioned restarted FGMRES on the extended
+// Jacobian (Eq. nonlinear_eqsys).  Stopping rules: Newton stops when
+// ||G(X^r)|| <= eps_N ||G(X^0)|| or ||dw^r||_2 / sqrt(ndof) <= atol_dw; no iteration when
+// ||G(X^0)|| <= 1e-14 sqrt(2 ndof); FGMRES starts from 0 and stops when
+// ||r_j|| <= eps_G ||r_0||.  Norms are Euclidean over all coefficients.
+// Initial guess X^0 = (guess, R1(guess)).
+//
+// Mixed precision: G, the stage vectors and X += dX stay FP64; the Krylov
+// vectors, the JVP (on FP32 copies of w, sigma taken once per Newton
+// iteration) and S^-1 of BJ_ext are FP32.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include "hbpc_internal.hpp"
+
+// ------------------------------------------------------------------ tableaux (appendix)
+struct Tab {
+    int s;
+    double c[4];
+    double B1[4][4];
+    double B2[4][4];
+};
+
+static bool tableau(int q, Tab& t) {
+    std::memset(&t, 0, sizeof(t));
+    if (q == 4) {
+        t.s = 2;
+        t.c[0] = 0; t.c[1] = 1;
+        t.B1[1][0] = 0.5; t.B1[1][1] = 0.5;
+        t.B2[1][0] = 1.0 / 12; t.B2[1][1] = -1.0 / 12;
+        return true;
+    }
+    if (q == 6) {
+        t.s = 3;
+        t.c[0] = 0; t.c[1] = 0.5; t.c[2] = 1;
+        t.B1[1][0] = 101.0 / 480; t.B1[1][1] = 8.0 / 30; t.B1[1][2] = 55.0 / 2400;
+        t.B1[2][0] = 7.0 / 30; t.B1[2][1] = 16.0 / 30; t.B1[2][2] = 7.0 / 30;
+        t.B2[1][0] = 65.0 / 4800; t.B2[1][1] = -25.0 / 600; t.B2[1][2] = -25.0 / 8000;
+        t.B2[2][0] = 5.0 / 300; t.B2[2][1] = 0.0; t.B2[2][2] = -5.0 / 300;
+        return true;
+    }
+    if (q == 8) {
+        t.s = 4;
+        t.c[0] = 0; t.c[1] = 1.0 / 3; t.c[2] = 2.0 / 3; t.c[3] = 1;
+        const double b1[3][4] = {{6893.0 / 54432, 313.0 / 2016, 89.0 / 2016, 397.0 / 54432},
+                                 {223.0 / 1701, 20.0 / 63, 13.0 / 63, 20.0 / 1701},
+                                 {31.0 / 224, 81.0 / 224, 81.0 / 224, 31.0 / 224}};
+        const double b2[3][4] = {{1283.0 / 272160, -851.0 / 30240, -269.0 / 30240, -163.0 / 272160},
+                                 {43.0 / 8505, -16.0 / 945, -19.0 / 945, -8.0 / 8505},
+                                 {19.0 / 3360, -9.0 / 1120, 9.0 / 1120, -19.0 / 3360}};
+        for (int l = 1; l < 4; ++l)
+            for (int j = 0; j < 4; ++j) {
+                t.B1[l][j] = b1[l - 1][j];
+                t.B2[l][j] = b2[l - 1][j];
+            }
+        return true;
+    }
+    return false;
+}
+
+// ------------------------------------------------------------------ error handling
+namespace {
+struct Fail {
+    int code;
+};
+
+void set_err(hbpc_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    throw Fail{code};
+}
+
+void hipchk(hbpc_ctx* c, hipError_t e, const char* what) {
+    if (e != hipSuccess) set_err(c, HBPC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename T> T* dalloc(hbpc_ctx* c, size_t count) {
+    if (count == 0) count = 1;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_err(c, HBPC_ERR_OOM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    return (T*)p;
+}
+
+void dfree(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace
+
+// ------------------------------------------------------------------ kernel timing
+static const char* KC_NAMES[KC_COUNT] = {"trace", "r1", "r2", "res", "jvp", "kcol", "pcpre", "bj_apply",
+                                         "bj_invert", "mdot", "gemv", "vec"};
+
+static long prof_begin(hbpc_ctx* c) {
+    if (!c->prof) return -1;
+    size_t i = c->ev_used;
+    if (c->ev.size() < 2 * (i + 1)) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -1;
+        c->ev.push_back(a);
+        c->ev.push_back(b);
+        c->ev_class.push_back(0);
+        c->ev_bytes.push_back(0);
+        c->ev_flops.push_back(0);
+    }
+    (void)hipEventRecord(c->ev[2 * i], c->stream);
+    c->ev_used = i + 1;
+    return (long)i;
+}
+
+static void prof_end(hbpc_ctx* c, long i, int cls, double bytes, double flops = 0.0) {
+    if (i < 0) return;
+    (void)hipEventRecord(c->ev[2 * i + 1], c->stream);
+    c->ev_class[i] = cls;
+    c->ev_bytes[i] = bytes;
+    c->ev_flops[i] = flops;
+}
+
+static void prof_resolve(hbpc_ctx* c) {
+    if (c->ev_used == 0) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (size_t i = 0; i < c->ev_used; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]) != hipSuccess) continue;
+        int k = c->ev_class[i];
+        c->kp_launch[k] += 1;
+        c->kp_ms[k] += ms;
+        c->kp_bytes[k] += c->ev_bytes[i];
+        c->kp_flops[k] += c->ev_flops[i];
+    }
+    c->ev_used = 0;
+}
+
+// ------------------------------------------------------------------ operator wrappers
+LaunchReq op_req(hbpc_ctx* c, int op) {
+    LaunchReq r;
+    std::memset(&r, 0, sizeof(r));
+    r.op = op;
+    r.stream = c->stream;
+    return r;
+}
+
+int op_launch(hbpc_ctx* c, const LaunchReq& r, int f32) {
+    const double esz = f32 ? 4.0 : 8.0, n = (double)c->ndof;
+    int cls = KC_VEC;
+    double bytes = 0.0;
+    switch (r.op) {
+    case OPK_TRACE: cls = KC_TRACE; bytes = (n + (double)c->tsz) * esz; break;
+    case OPK_R1: cls = KC_R1; bytes = 2 * n * esz; break;
+    case OPK_R2: cls = KC_R2; bytes = 3 * n * esz; break;
+    case OPK_RES: cls = KC_RES; bytes = 5 * n * esz; break;
+    case OPK_JVP:
+    case OPK_JVP_NOHESS: cls = KC_JVP; bytes = 6 * n * esz; break;
+    case OPK_KCOL: cls = KC_KCOL; bytes = 2.0 * (r.e_end - r.e_begin) * c->NE * 8.0; break;
+    case OPK_PCPRE: cls = KC_PCPRE; bytes = 5 * n * esz; break;
+    }
+    long pi = prof_begin(c);
+    hipError_t e = c->launch(c->geom, r, f32);
+    prof_end(c, pi, cls, bytes);
+    if (e != hipSuccess) set_err(c, HBPC_ERR_HIP, std::string("operator kernel launch: ") + hipGetErrorString(e));
+    return 0;
+}
+
+static void op_trace(hbpc_ctx* c, const void* x, void* tr, int f32) {
+    LaunchReq r = op_req(c, OPK_TRACE);
+    r.fld[0] = x;
+    r.out[0] = tr;
+    op_launch(c, r, f32);
+}
+
+// R1(w) -> out; traces of w written to trw (FP64)
+static void op_r1(hbpc_ctx* c, const double* w, double* out, double* trw) {
+    op_trace(c, w, trw, 0);
+    LaunchReq r = op_req(c, OPK_R1);
+    r.fld[0] = w;
+    r.trc[0] = trw;
+    r.out[0] = out;
+    op_launch(c, r, 0);
+}
+
+// R2(w, sigma) -> out with given traces of w and sigma
+static void op_r2_tr(hbpc_ctx* c, const double* w, const double* s, const double* trw, const double* trs,
+                     double* out) {
+    LaunchReq r = op_req(c, OPK_R2);
+    r.fld[0] = w;
+    r.fld[1] = s;
+    r.trc[0] = trw;
+    r.trc[1] = trs;
+    r.out[0] = out;
+    op_launch(c, r, 0);
+}
+
+// R1 and R2(w, R1(w)) of a stage value
+static void op_r1r2(hbpc_ctx* c, const double* w, double* r1, double* r2) {
+    op_r1(c, w, r1, c->trw);
+    op_trace(c, r1, c->trs, 0);
+    op_r2_tr(c, w, r1, c->trw, c->trs, r2);
+}
+
+// G(X) with the traces of X in trw/trs (FP64)
+static void op_res(hbpc_ctx* c, const double* X, const double* b, double a1dt, double bc, double* G) {
+    LaunchReq r = op_req(c, OPK_RES);
+    r.fld[0] = X;
+    r.fld[1] = X + c->ndof;
+    r.fld[2] = b;
+    r.trc[0] = c->trw;
+    r.trc[1] = c->trs;
+    r.out[0] = G;
+    r.out[1] = G + c->ndof;
+    r.c0 = a1dt;
+    r.c1 = bc;
+    op_launch(c, r, 0);
+}
+
+// linearised JVP in precision f32: state (w, s) with traces (trw, trs), input dX, output Y (2 ndof)
+static void op_jvp(hbpc_ctx* c, const void* w, const void* s, const void* trw, const void* trs, const void* dX,
+                   void* Y, double a1dt, double bc, int f32, int hess) {
+    size_t esz = f32 ? 4 : 8;
+    const char* dx = (const char*)dX;
+    char* y = (char*)Y;
+    void* t1 = f32 ? (void*)c->trd1_32 : (void*)c->trd1;
+    void* t2 = f32 ? (void*)c->trd2_32 : (void*)c->trd2;
+    op_trace(c, dx, t1, f32);
+    op_trace(c, dx + c->ndof * esz, t2, f32);
+    LaunchReq r = op_req(c, hess ? OPK_JVP : OPK_JVP_NOHESS);
+    r.fld[0] = w;
+    r.fld[1] = s;
+    r.fld[2] = dx;
+    r.fld[3] = dx + c->ndof * esz;
+    r.trc[0] = trw;
+    r.trc[1] = trs;
+    r.trc[2] = t1;
+    r.trc[3] = t2;
+    r.out[0] = y;
+    r.out[1] = y + c->ndof * esz;
+    r.c0 = a1dt;
+    r.c1 = bc;
+    op_launch(c, r, f32);
+}
+
+static void status_reset(hbpc_ctx* c) { hipchk(c, hipMemsetAsync(c->dstatus, 0, sizeof(int), c->stream), "memset"); }
+
+static int status_read(hbpc_ctx* c) {
+    int h = 0;
+    hipchk(c, hipMemcpyAsync(&h, c->dstatus, sizeof(int), hipMemcpyDeviceToHost, c->stream), "copy status");
+    hipchk(c, hipStreamSynchronize(c->stream), "sync");
+    return h;
+}
+
+// ||x||_2 (FP64 or FP32 vector of length n), synchronising
+static double dnorm(hbpc_ctx* c, const void* x, size_t n, int f32) {
+    hipchk(c, blas_mdot(x, 0, 1, x, n, f32, c->part, c->dres, c->stream), "norm");
+    hipchk(c, hipMemcpyAsync(c->hres, c->dres, sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy");
+    hipchk(c, hipStreamSynchronize(c->stream), "sync");
+    return std::sqrt(c->hres[0]);
+}
+
+// ------------------------------------------------------------------ BJ_ext
+static void pc_build(hbpc_ctx* c, const double* w, double a1dt, double bc, int f32) {
+    double t0 = now_ms();
+    if (c->NE > 144) set_err(c, HBPC_ERR_UNSUPPORTED, "BJ_ext supports element blocks up to 144 unknowns");
+    if (!c->Sinv || c->sinv_f32 != f32) {
+        dfree(c->Sinv);
+        c->Sinv = nullptr;
+        size_t cnt = (size_t)c->nE * c->NE * c->NE;
+        c->Sinv = f32 ? (void*)dalloc<float>(c, cnt) : (void*)dalloc<double>(c, cnt);
+        c->sinv_f32 = f32;
+    }
+    if (!c->KT) c->KT = dalloc<double>(c, c->kt_chunk * c->NE * c->NE);
+    op_trace(c, w, c->trw, 0);
+    status_reset(c);
+    const size_t esz = f32 ? 4 : 8;
+    for (size_t eb = 0; eb < (size_t)c->nE; eb += c->kt_chunk) {
+        size_t ee = std::min((size_t)c->nE, eb + c->kt_chunk);
+        for (int col = 0; col < c->NE; ++col) {
+            LaunchReq r = op_req(c, OPK_KCOL);
+            r.fld[0] = w;
+            r.trc[0] = c->trw;
+            r.out[0] = c->KT;
+            r.col = col;
+            r.e_begin = (int)eb;
+            r.e_end = (int)ee;
+            op_launch(c, r, 0);
+        }
+        long pi = prof_begin(c);
+        hipchk(c, bj_invert(c->KT, (char*)c->Sinv + eb * c->NE * c->NE * esz, f32, c->NE, (int)(ee - eb), a1dt, bc,
+                            c->dstatus, c->stream),
+               "bj_invert");
+        const double ne = c->NE, cnt = (double)(ee - eb);
+        prof_end(c, pi, KC_BJINV, cnt * ne * ne * (8.0 + esz), cnt * 4.0 * ne * ne * ne);
+    }
+    if (status_read(c)) set_err(c, HBPC_ERR_NONFINITE, "BJ_ext: singular or non-finite element block");
+    c->pc_a1dt = a1dt;
+    c->pc_bc = bc;
+    c->pc_valid = 1;
+    c->st.pc_builds++;
+    c->st.t_pc_build_ms += now_ms() - t0;
+}
+
+// Y = P^-1 X in precision f32; the linearisation state (w, traces) in the same precision
+static void pc_apply(hbpc_ctx* c, const void* w, const void* trw, const void* X, void* Y, int f32) {
+    size_t esz = f32 ? 4 : 8;
+    char* kv = (char*)c->kv;   // a | c
+    LaunchReq r = op_req(c, OPK_PCPRE);
+    r.fld[0] = w;
+    r.fld[1] = X;
+    r.fld[2] = (const char*)X + c->ndof * esz;
+    r.trc[0] = trw;
+    r.out[0] = kv;
+    r.out[1] = kv + c->ndof * esz;
+    r.c0 = c->pc_a1dt;
+    r.c1 = c->pc_bc;
+    op_launch(c, r, f32);
+    long pi = prof_begin(c);
+    hipchk(c, bj_apply(c->Sinv, c->sinv_f32, kv, kv + c->ndof * esz, Y, (char*)Y + c->ndof * esz, f32, c->NE, c->nE,
+                       c->stream),
+           "bj_apply");
+    prof_end(c, pi, KC_BJAPPLY,
+             (double)c->nE * c->NE * c->NE * (c->sinv_f32 ? 4.0 : 8.0) + 4.0 * c->ndof * esz);
+}
+
+// ------------------------------------------------------------------ FD JVP (Eq. MatrixFree_nonlinear), FP64
+static void fd_alloc(hbpc_ctx* c) {
+    for (int i = 0; i < 6; ++i)
+        if (!c->fd[i]) c->fd[i] = dalloc<double>(c, c->ndof);
+}
+
+// requires fd[0] = R1(w), fd[1] = R2(w, sigma) precomputed; trw/trs traces of (w, sigma)
+static void op_jvp_fd(hbpc_ctx* c, const double* w, const double* s, const double* dX, double* Y, double a1dt,
+                      double bc) {
+    const size_t n = c->ndof;
+    const double* dw = dX;
+    const double* ds = dX + n;
+    const double emach = 2.220446049250313e-16;
+    double nw = dnorm(c, dw, n, 0), ns = dnorm(c, ds, n, 0);
+    double* T1 = c->fd[2];
+    double* T3 = c->fd[3];
+    double* T2 = c->fd[4];
+    double* wp = c->fd[5];
+    double* trp = c->trd1;   // traces of the perturbed state
+    double* trq = c->trd2;
+    double* r1p = (double*)c->kv;   // 3 n scratch in FP64 mode only
+    double* r2p = r1p + n;
+    double* sp = r2p + n;
+    if (nw > 0) {
+        double ew = std::sqrt(emach) / (c->geom.eps * nw);
+        hipchk(c, blas_lincomb2(1.0, w, ew, dw, wp, n, c->stream), "fd");
+        op_r1(c, wp, r1p, trp);                     // R1(w + ew dw); traces of wp in trp
+        hipchk(c, blas_lincomb2(1.0 / ew, r1p, -1.0 / ew, c->fd[0], T1, n, c->stream), "fd");
+        op_r2_tr(c, wp, s, trp, c->trs, r2p);       // R2(w + ew dw, sigma)
+        hipchk(c, blas_lincomb2(1.0 / ew, r2p, -1.0 / ew, c->fd[1], T3, n, c->stream), "fd");
+    } else {
+        hipchk(c, hipMemsetAsync(T1, 0, n * 8, c->stream), "memset");
+        hipchk(c, hipMemsetAsync(T3, 0, n * 8, c->stream), "memset");
+    }
+    if (ns > 0) {
+        double es = std::sqrt(emach) / (c->geom.eps * ns);
+        hipchk(c, blas_lincomb2(1.0, s, es, ds, sp, n, c->stream), "fd");
+        op_trace(c, sp, trq, 0);
+        op_r2_tr(c, w, sp, c->trw, trq, r2p);       // R2(w, sigma + es dsigma)
+        hipchk(c, blas_lincomb2(1.0 / es, r2p, -1.0 / es, c->fd[1], T2, n, c->stream), "fd");
+    } else {
+        hipchk(c, hipMemsetAsync(T2, 0, n * 8, c->stream), "memset");
+    }
+    // Yw = dw - a1dt T1 + bc (T3 + T2);  Ys = ds - T1
+    hipchk(c, blas_axpby(1.0, dw, 0, 0.0, Y, 0, n, c->stream), "fd");
+    hipchk(c, blas_axpby(-a1dt, T1, 0, 1.0, Y, 0, n, c->stream), "fd");
+    if (c->prm.hessian) hipchk(c, blas_axpby(bc, T3, 0, 1.0, Y, 0, n, c->stream), "fd");
+    hipchk(c, blas_axpby(bc, T2, 0, 1.0, Y, 0, n, c->stream), "fd");
+    hipchk(c, blas_lincomb2(1.0, ds, -1.0, T1, Y + n, n, c->stream), "fd");
+}
+
+// ------------------------------------------------------------------ FGMRES
+// Solve J dX = rhs (FP64 rhs, FP64 dX accumulation) with Krylov vectors in precision f32.
+// The linearisation state is c->X (FP64) / c->X32 (FP32) with traces trw/trs (and *_32).
+static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, double bc, int f32) {
+    const size_t n2 = c->n2;
+    const size_t esz = f32 ? 4 : 8;
+    const int m = c->prm.gmres_restart;
+    const int maxit = c->prm.gmres_maxit;
+    const double rtol = c->prm.gmres_rtol;
+    const int use_pc = c->prm.precond == HBPC_PC_BJEXT;
+    const int fd = c->prm.jvp_mode == HBPC_JVP_FD && !f32;
+    char* V = (char*)c->V;
+    char* Z = (char*)c->Z;
+    const void* w = f32 ? (const void*)c->X32 : (const void*)c->X;
+    const void* s = f32 ? (const void*)(c->X32 + c->ndof) : (const void*)(c->X + c->ndof);
+    const void* trw = f32 ? (const void*)c->trw32 : (const void*)c->trw;
+    const void* trs = f32 ? (const void*)c->trs32 : (const void*)c->trs;
+    auto Vj = [&](int j) { return (void*)(V + (size_t)j * n2 * esz); };
+    auto Zj = [&](int j) { return (void*)(Z + (size_t)j * n2 * esz); };
+    auto jvp = [&](const void* x, void* y) {
+        if (fd) op_jvp_fd(c, (const double*)w, (const double*)s, (const double*)x, (double*)y, a1dt, bc);
+        else op_jvp(c, w, s, trw, trs, x, y, a1dt, bc, f32, c->prm.hessian);
+    };
+    if (fd) {   // R1(w), R2(w, sigma) of the linearisation state
+        fd_alloc(c);
+        op_r1(c, c->X, c->fd[0], c->trd1);
+        op_r2_tr(c, c->X, c->X + c->ndof, c->trw, c->trs, c->fd[1]);
+    }
+    hipchk(c, hipMemsetAsync(dX, 0, n2 * 8, c->stream), "memset");
+    const double beta0 = dnorm(c, rhs, n2, 0);
+    if (!std::isfinite(beta0)) set_err(c, HBPC_ERR_NONFINITE, "non-finite Newton residual");
+    if (beta0 == 0.0) return 0;
+    // residual vector r (precision f32) in V_0 slot; first cycle r = rhs
+    hipchk(c, blas_axpby(1.0, rhs, 0, 0.0, Vj(0), f32, n2, c->stream), "copy");
+    int total = 0;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    auto Hc = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+    for (;;) {
+        double beta = dnorm(c, Vj(0), n2, f32);
+        if (!std::isfinite(beta)) set_err(c, HBPC_ERR_NONFINITE, "non-finite Krylov residual");
+        hipchk(c, blas_axpby(1.0 / beta, Vj(0), f32, 0.0, Vj(0), f32, n2, c->stream), "scale");
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        bool converged = false;
+        int k = 0;
+        for (int j = 0; j < m; ++j) {
+            void* zj = use_pc ? Zj(j) : Vj(j);
+            if (use_pc) pc_apply(c, w, trw, Vj(j), zj, f32);
+            void* u = Vj(j + 1);
+            jvp(zj, u);
+            // CGS2 against V_0..V_j
+            double* h1 = c->dres;
+            double* h2 = c->dres + 64;
+            double* hn = c->dres + 128;
+            const double vb = (double)n2 * esz;
+            long pi = prof_begin(c);
+            hipchk(c, blas_mdot(V, n2, j + 1, u, n2, f32, c->part, h1, c->stream), "mdot");
+            prof_end(c, pi, KC_MDOT, (j + 2) * vb);
+            pi = prof_begin(c);
+            hipchk(c, blas_gemv_sub(V, n2, j + 1, h1, u, n2, f32, c->stream), "gemv");
+            prof_end(c, pi, KC_GEMV, (j + 3) * vb);
+            pi = prof_begin(c);
+            hipchk(c, blas_mdot(V, n2, j + 1, u, n2, f32, c->part, h2, c->stream), "mdot");
+            prof_end(c, pi, KC_MDOT, (j + 2) * vb);
+            pi = prof_begin(c);
+            hipchk(c, blas_gemv_sub(V, n2, j + 1, h2, u, n2, f32, c->stream), "gemv");
+            prof_end(c, pi, KC_GEMV, (j + 3) * vb);
+            pi = prof_begin(c);
+            hipchk(c, blas_mdot(u, 0, 1, u, n2, f32, c->part, hn, c->stream), "norm");
+            prof_end(c, pi, KC_MDOT, vb);
+            hipchk(c, hipMemcpyAsync(c->hres, c->dres, 129 * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+                   "copy");
+            hipchk(c, hipStreamSynchronize(c->stream), "sync");
+            for (int i = 0; i <= j; ++i) Hc(i, j) = c->hres[i] + c->hres[64 + i];
+            double hnrm = std::sqrt(c->hres[128]);
+            Hc(j + 1, j) = hnrm;
+            if (!std::isfinite(hnrm)) set_err(c, HBPC_ERR_NONFINITE, "non-finite Arnoldi vector");
+            for (int i = 0; i < j; ++i) {
+                double t = cs[i] * Hc(i, j) + sn[i] * Hc(i + 1, j);
+                Hc(i + 1, j) = -sn[i] * Hc(i, j) + cs[i] * Hc(i + 1, j);
+                Hc(i, j) = t;
+            }
+            double den = std::hypot(Hc(j, j), Hc(j + 1, j));
+            cs[j] = Hc(j, j) / den;
+            sn[j] = Hc(j + 1, j) / den;
+            Hc(j, j) = den;
+            Hc(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++total;
+            k = j + 1;
+            if (std::fabs(g[j + 1]) <= rtol * beta0) { converged = true; break; }
+            if (total >= maxit) break;
+            if (hnrm == 0.0) { converged = true; break; }
+            hipchk(c, blas_axpby(1.0 / hnrm, u, f32, 0.0, u, f32, n2, c->stream), "scale");
+        }
+        // y = H^-1 g (upper triangular), dX += Z y
+        for (int i = k - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int l = i + 1; l < k; ++l) t -= Hc(i, l) * y[l];
+            y[i] = t / Hc(i, i);
+        }
+        hipchk(c, blas_gemv_add(use_pc ? Z : V, f32, n2, k, y.data(), dX, 0, n2, c->stream), "update");
+        if (converged) return total;
+        if (total >= maxit) {
+            set_err(c, HBPC_ERR_GMRES, "GMRES did not reach eps_G within " + std::to_string(maxit) + " iterations");
+        }
+        // restart: r = rhs - J dX, computed in precision f32 in V_0
+        void* xw = Vj(1);   // dX in precision f32
+        hipchk(c, blas_axpby(1.0, dX, 0, 0.0, xw, f32, n2, c->stream), "cast");
+        jvp(xw, Vj(0));
+        hipchk(c, blas_axpby(1.0, rhs, 0, -1.0, Vj(0), f32, n2, c->stream), "residual");
+    }
+}
+
+// ------------------------------------------------------------------ Newton
+static void state_traces(hbpc_ctx* c, int mixed) {
+    op_trace(c, c->X, c->trw, 0);
+    op_trace(c, c->X + c->ndof, c->trs, 0);
+    if (mixed) {
+        hipchk(c, blas_axpby(1.0, c->X, 0, 0.0, c->X32, 1, c->n2, c->stream), "cast");
+        op_trace(c, c->X32, c->trw32, 1);
+        op_trace(c, c->X32 + c->ndof, c->trs32, 1);
+    }
+}
+
+// solve g(W) = b for W (a1dt = alpha1 dt, bc = alpha2 dt^2/2), initial guess `guess`; W -> out
+static void newton_solve(hbpc_ctx* c, const double* b, double a1dt, double bc, const double* guess, double* out) {
+    const size_t n = c->ndof;
+    const int mixed = c->prm.precision == HBPC_MIXED;
+    double* X = c->X;
+    hipchk(c, hipMemcpyAsync(X, guess, n * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
+    op_r1(c, X, X + n, c->trw);              // sigma^0 = R1(guess)
+    state_traces(c, 0);
+    op_res(c, X, b, a1dt, bc, c->G);
+    const double n0 = dnorm(c, c->G, c->n2, 0);
+    if (!std::isfinite(n0)) set_err(c, HBPC_ERR_NONFINITE, "non-finite residual at the Newton initial guess");
+    int its = 0, gits = 0;
+    const int sidx = c->cur_solve;
+    if (n0 > 1e-14 * std::sqrt((double)c->n2)) {
+        if (mixed) state_traces(c, 1);
+        const int use_pc = c->prm.precond == HBPC_PC_BJEXT;
+        if (use_pc) pc_build(c, X, a1dt, bc, mixed);
+        for (;;) {
+            ++its;
+            if (use_pc && c->prm.pc_rebuild == HBPC_PC_PER_NEWTON_IT && its > 1) pc_build(c, X, a1dt, bc, mixed);
+            hipchk(c, blas_axpby(-1.0, c->G, 0, 0.0, c->rhs, 0, c->n2, c->stream), "rhs");
+            double tg = now_ms();
+            gits += fgmres(c, c->rhs, c->dX, a1dt, bc, mixed);
+            c->st.t_gmres_ms += now_ms() - tg;
+            hipchk(c, blas_axpby(1.0, c->dX, 0, 1.0, X, 0, c->n2, c->stream), "update");
+            state_traces(c, mixed);
+            op_res(c, X, b, a1dt, bc, c->G);
+            double nr = dnorm(c, c->G, c->n2, 0);
+            double ndw = dnorm(c, c->dX, n, 0);
+            if (c->verbose)
+                std::fprintf(stderr, "[hbpc] solve %d newton %d |G| %.6e (|G0| %.6e) |dw| %.3e gmres %d\n", sidx, its,
+                             nr, n0, ndw, gits);
+            if (!std::isfinite(nr)) set_err(c, HBPC_ERR_NONFINITE, "non-finite Newton residual");
+            // absolute criterion per coefficient (RMS of dw), see hbpc_params.newton_atol_dw
+            if (nr <= c->prm.newton_rtol * n0 || ndw <= c->prm.newton_atol_dw * std::sqrt((double)n)) break;
+            if (its >= c->prm.newton_maxit)
+                set_err(c, HBPC_ERR_NEWTON,
+                        "Newton did not converge within " + std::to_string(c->prm.newton_maxit) + " iterations");
+        }
+    }
+    hipchk(c, hipMemcpyAsync(out, X, n * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
+    if (sidx < HBPC_MAX_SOLVES) {
+        c->st.newton_per_solve[sidx] = its;
+        c->st.gmres_per_solve[sidx] = gits;
+    }
+    c->st.newton_its += its;
+    c->st.gmres_its += gits;
+    c->cur_solve++;
+    c->st.n_solves = c->cur_solve;
+}
+
+// ------------------------------------------------------------------ HBPC step (Algorithm 1)
+static void hbpc_step_impl(hbpc_ctx* c, double* w_inout, double dt) {
+    Tab t;
+    if (!tableau(c->prm.q, t)) set_err(c, HBPC_ERR_ARG, "q must be 4, 6 or 8");
+    const int s = t.s;
+    const size_t n = c->ndof;
+    double** W = c->W;
+    auto R1 = [&](int j) { return c->R1all + (size_t)j * n; };
+    auto R2 = [&](int j) { return c->R2all + (size_t)j * n; };
+    hipchk(c, hipMemcpyAsync(W[0], w_inout, n * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
+    op_r1r2(c, W[0], R1(0), R2(0));
+    // predictor: successive two-point Hermite-Birkhoff substeps
+    for (int l = 1; l < s; ++l) {
+        double dc = t.c[l] - t.c[l - 1];
+        double a1dt = dc / 2 * dt;
+        double bc = dc * dc / 6 * dt * dt / 2;
+        double coef1[4] = {0, 0, 0, 0}, coef2[4] = {0, 0, 0, 0};
+        coef1[l - 1] = a1dt;
+        coef2[l - 1] = bc;
+        hipchk(c, hipMemcpyAsync(c->b, W[l - 1], n * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
+        hipchk(c, blas_gemv_add(c->R1all, 0, n, s, coef1, c->b, 0, n, c->stream), "b");
+        hipchk(c, blas_gemv_add(c->R2all, 0, n, s, coef2, c->b, 0, n, c->stream), "b");
+        newton_solve(c, c->b, a1dt, bc, W[l - 1], W[l]);
+        op_r1r2(c, W[l], R1(l), R2(l));
+    }
+    // corrector sweeps: every stage of sweep k uses iterate [k] of all stages
+    for (int k = 0; k < c->prm.kmax; ++k) {
+        for (int l = 1; l < s; ++l) {
+            double coef1[4], coef2[4];
+            for (int j = 0; j < s; ++j) {
+                coef1[j] = dt * t.B1[l][j] - (j == l ? dt : 0.0);
+                coef2[j] = dt * dt * t.B2[l][j] + (j == l ? dt * dt / 2 : 0.0);
+            }
+            hipchk(c, hipMemcpyAsync(c->b, W[0], n * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
+            hipchk(c, blas_gemv_add(c->R1all, 0, n, s, coef1, c->b, 0, n, c->stream), "b");
+            hipchk(c, blas_gemv_add(c->R2all, 0, n, s, coef2, c->b, 0, n, c->stream), "b");
+            newton_solve(c, c->b, dt, dt * dt / 2, W[l], c->Wn[l]);
+        }
+        for (int l = 1; l < s; ++l) std::swap(W[l], c->Wn[l]);
+        if (k < c->prm.kmax - 1)
+            for (int l = 1; l < s; ++l) op_r1r2(c, W[l], R1(l), R2(l));
+    }
+    status_reset(c);
+    hipchk(c, blas_nonfinite(W[s - 1], 0, n, c->dstatus, c->stream), "check");
+    if (status_read(c)) set_err(c, HBPC_ERR_NONFINITE, "non-finite value in the new state");
+    hipchk(c, hipMemcpyAsync(w_inout, W[s - 1], n * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
+    hipchk(c, hipStreamSynchronize(c->stream), "sync");
+}
+
+// ------------------------------------------------------------------ context
+static void ctx_free(hbpc_ctx* c) {
+    for (int i = 0; i < 4; ++i) {
+        dfree(c->W[i]);
+        dfree(c->Wn[i]);
+        dfree(c->tmp[i]);
+    }
+    void* bufs[] = {c->R1all, c->R2all, c->X, c->b, c->G, c->dX, c->rhs, c->trw, c->trs, c->trd1, c->trd2,
+                    c->X32, c->trw32, c->trs32, c->trd1_32, c->trd2_32, c->V, c->Z, c->kv, c->KT, c->Sinv,
+                    c->part, c->dres, c->dstatus};
+    for (void* p : bufs) dfree(p);
+    for (int i = 0; i < 6; ++i) dfree(c->fd[i]);
+    if (c->hres) (void)hipHostFree(c->hres);
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    c->ev.clear();
+}
+
+static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, const hbpc_params* prm) {
+    const char* vb = std::getenv("HBPC_VERBOSE");
+    c->verbose = vb && vb[0] && vb[0] != '0';
+    c->mesh = *mesh;
+    c->prm = *prm;
+    c->N = N;
+    c->NP = N + 1;
+    c->D = mesh->dim;
+    c->equation = equation;
+    if (c->D < 1 || c->D > 3) set_err(c, HBPC_ERR_ARG, "dim must be 1, 2 or 3");
+    if (N < 2 || N > 5) set_err(c, HBPC_ERR_UNSUPPORTED, "N must be in 2..5");
+    for (int m = 0; m < c->D; ++m)
+        if (mesh->nelem[m] < 1 || !(mesh->length[m] > 0)) set_err(c, HBPC_ERR_ARG, "bad mesh extent");
+    if (equation == HBPC_EQ_ADVECTION) {
+        c->NV = 1;
+        c->launch = dg_launch_advection;
+    } else if (equation == HBPC_EQ_EULER) {
+        if (c->D < 2) set_err(c, HBPC_ERR_UNSUPPORTED, "Euler needs dim 2 or 3");
+        c->NV = c->D + 2;
+        c->launch = dg_launch_euler;
+    } else if (equation == HBPC_EQ_BURGERS_BR1) {
+        set_err(c, HBPC_ERR_UNSUPPORTED, "viscous Burgers is not compiled in this build");
+    } else {
+        set_err(c, HBPC_ERR_ARG, "unknown equation");
+    }
+    if (prm->flux < 0 || prm->flux > 3) set_err(c, HBPC_ERR_ARG, "unknown flux");
+    if (prm->flux == HBPC_FLUX_RUSANOV && equation != HBPC_EQ_EULER)
+        set_err(c, HBPC_ERR_ARG, "Rusanov flux needs the Euler equations");
+    if (prm->flux == HBPC_FLUX_UPWIND && equation != HBPC_EQ_ADVECTION)
+        set_err(c, HBPC_ERR_ARG, "upwind flux needs advection");
+    if (prm->gmres_restart < 1 || prm->gmres_restart > 64) set_err(c, HBPC_ERR_ARG, "gmres_restart must be 1..64");
+    if (prm->q != 4 && prm->q != 6 && prm->q != 8) set_err(c, HBPC_ERR_ARG, "q must be 4, 6 or 8");
+    if (prm->kmax < 0) set_err(c, HBPC_ERR_ARG, "kmax must be >= 0");
+    if (equation == HBPC_EQ_EULER && !(prm->eps_ref > 0 && prm->gamma > 1))
+        set_err(c, HBPC_ERR_ARG, "Euler needs gamma > 1 and eps_ref > 0");
+    if (!basis1d_build(N, prm->nodes, c->basis)) set_err(c, HBPC_ERR_ARG, "bad node set");
+    c->stream = (hipStream_t)prm->stream;
+    c->NN = 1;
+    c->NFP = 1;
+    for (int m = 0; m < c->D; ++m) c->NN *= c->NP;
+    for (int m = 0; m + 1 < c->D; ++m) c->NFP *= c->NP;
+    c->NE = c->NV * c->NN;
+    c->nE = 1;
+    for (int m = 0; m < c->D; ++m) c->nE *= mesh->nelem[m];
+    c->ndof = (size_t)c->nE * c->NE;
+    c->n2 = 2 * c->ndof;
+    c->tsz = (size_t)c->nE * 2 * c->D * c->NV * c->NFP;
+    GeomHost& g = c->geom;
+    std::memset(&g, 0, sizeof(g));
+    g.D = c->D;
+    g.NP = c->NP;
+    g.NV = c->NV;
+    g.nE = c->nE;
+    for (int m = 0; m < 3; ++m) {
+        g.nel[m] = m < c->D ? mesh->nelem[m] : 1;
+        g.two_h[m] = m < c->D ? 2.0 * mesh->nelem[m] / mesh->length[m] : 0.0;
+        g.adv[m] = prm->adv[m];
+    }
+    for (int i = 0; i < c->NP; ++i) {
+        for (int j = 0; j < c->NP; ++j) g.Dhat[i][j] = c->basis.Dhat[i * c->NP + j];
+        g.lp[i] = c->basis.lp[i];
+        g.lm[i] = c->basis.lm[i];
+        g.lhp[i] = c->basis.lhp[i];
+        g.lhm[i] = c->basis.lhm[i];
+    }
+    g.lam = prm->lambda;
+    g.nu = prm->nu;
+    g.gamma = equation == HBPC_EQ_EULER ? prm->gamma : 1.4;
+    g.eps = equation == HBPC_EQ_EULER ? prm->eps_ref : 1.0;
+    g.flux = prm->flux;
+
+    const size_t n = c->ndof;
+    for (int i = 0; i < 4; ++i) {
+        c->W[i] = dalloc<double>(c, n);
+        c->Wn[i] = dalloc<double>(c, n);
+        c->tmp[i] = dalloc<double>(c, n);
+    }
+    c->R1all = dalloc<double>(c, 4 * n);
+    c->R2all = dalloc<double>(c, 4 * n);
+    c->X = dalloc<double>(c, 2 * n);
+    c->b = dalloc<double>(c, n);
+    c->G = dalloc<double>(c, 2 * n);
+    c->dX = dalloc<double>(c, 2 * n);
+    c->rhs = dalloc<double>(c, 2 * n);
+    c->trw = dalloc<double>(c, c->tsz);
+    c->trs = dalloc<double>(c, c->tsz);
+    c->trd1 = dalloc<double>(c, c->tsz);
+    c->trd2 = dalloc<double>(c, c->tsz);
+    c->X32 = dalloc<float>(c, 2 * n);
+    c->trw32 = dalloc<float>(c, c->tsz);
+    c->trs32 = dalloc<float>(c, c->tsz);
+    c->trd1_32 = dalloc<float>(c, c->tsz);
+    c->trd2_32 = dalloc<float>(c, c->tsz);
+    c->m_alloc = prm->gmres_restart;
+    c->kr_f32 = prm->precision == HBPC_MIXED;
+    size_t ksz = c->kr_f32 ? 4 : 8;
+    c->V = dalloc<char>(c, (size_t)(c->m_alloc + 1) * c->n2 * ksz);
+    c->Z = prm->precond == HBPC_PC_BJEXT ? (void*)dalloc<char>(c, (size_t)c->m_alloc * c->n2 * ksz) : nullptr;
+    c->kv = dalloc<double>(c, 3 * n);
+    // K build in chunks of <= 256 MB of FP64 blocks
+    size_t per = (size_t)c->NE * c->NE * 8;
+    c->kt_chunk = std::max<size_t>(1, std::min<size_t>(c->nE, (size_t)(256u << 20) / per));
+    c->part = dalloc<double>(c, (size_t)blas_mdot_grid(c->n2) * 65 + 64);
+    c->dres = dalloc<double>(c, 256);
+    c->dstatus = dalloc<int>(c, 1);
+    void* h = nullptr;
+    hipchk(c, hipHostMalloc(&h, 256 * sizeof(double)), "hipHostMalloc");
+    c->hres = (double*)h;
+}
+
+// ------------------------------------------------------------------ C ABI
+#define HBPC_TRY(ctx, body)                              \
+    try {                                                \
+        body;                                            \
+        return HBPC_OK;                                  \
+    } catch (const Fail& f) {                            \
+        return f.code;                                   \
+    } catch (...) {                                      \
+        if (ctx) (ctx)->err = "unexpected C++ exception"; \
+        return HBPC_ERR_ARG;                             \
+    }
+
+extern "C" {
+
+void hbpc_default_params(hbpc_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->nodes = HBPC_NODES_GAUSS;
+    p->flux = HBPC_FLUX_RUSANOV;
+    p->lambda = 1.0;
+    p->adv[0] = 1.0;
+    p->nu = 0.0;
+    p->gamma = 1.4;
+    p->eps_ref = 1.0;
+    p->q = 6;
+    p->kmax = 4;
+    p->newton_rtol = 1e-8;
+    p->newton_atol_dw = 1.95e-15;   // 1e-12 in the 2-norm over 262,144 coefficients
+    p->newton_maxit = 30;
+    p->gmres_rtol = 1e-3;
+    p->gmres_restart = 30;
+    p->gmres_maxit = 7000;
+    p->precision = HBPC_FP64;
+    p->precond = HBPC_PC_BJEXT;
+    p->pc_rebuild = HBPC_PC_PER_SOLVE;
+    p->jvp_mode = HBPC_JVP_LINEARISED;
+    p->hessian = 1;
+    p->stream = nullptr;
+}
+
+int hbpc_create(const hbpc_mesh* mesh, int N, int equation, const hbpc_params* params, hbpc_ctx** out) {
+    if (!mesh || !params || !out) return HBPC_ERR_ARG;
+    *out = nullptr;
+    hbpc_ctx* c = new (std::nothrow) hbpc_ctx();
+    if (!c) return HBPC_ERR_OOM;
+    try {
+        ctx_init(c, mesh, N, equation, params);
+    } catch (const Fail& f) {
+        ctx_free(c);
+        delete c;
+        return f.code;
+    }
+    *out = c;
+    return HBPC_OK;
+}
+
+int hbpc_destroy(hbpc_ctx* c) {
+    if (!c) return HBPC_ERR_ARG;
+    (void)hipStreamSynchronize(c->stream);
+    ctx_free(c);
+    delete c;
+    return HBPC_OK;
+}
+
+int hbpc_set_stream(hbpc_ctx* c, void* stream) {
+    if (!c) return HBPC_ERR_ARG;
+    c->stream = (hipStream_t)stream;
+    c->prm.stream = stream;
+    return HBPC_OK;
+}
+
+size_t hbpc_ndof(const hbpc_ctx* c) { return c ? c->ndof : 0; }
+
+int hbpc_block_size(const hbpc_ctx* c) { return c ? c->NE : 0; }
+
+int hbpc_nodes(const hbpc_ctx* c, double* xi, double* w) {
+    if (!c || !xi || !w) return HBPC_ERR_ARG;
+    for (int i = 0; i < c->NP; ++i) {
+        xi[i] = c->basis.xi[i];
+        w[i] = c->basis.w[i];
+    }
+    return HBPC_OK;
+}
+
+int hbpc_residual1(hbpc_ctx* c, const double* w, double* r1) {
+    if (!c || !w || !r1) return HBPC_ERR_ARG;
+    HBPC_TRY(c, op_r1(c, w, r1, c->trw));
+}
+
+int hbpc_residual2(hbpc_ctx* c, const double* w, const double* sigma, double* r2) {
+    if (!c || !w || !r2) return HBPC_ERR_ARG;
+    HBPC_TRY(c, {
+        if (!sigma) {
+            op_r1(c, w, c->tmp[0], c->trw);
+            sigma = c->tmp[0];
+        } else {
+            op_trace(c, w, c->trw, 0);
+        }
+        op_trace(c, sigma, c->trs, 0);
+        op_r2_tr(c, w, sigma, c->trw, c->trs, r2);
+    });
+}
+
+int hbpc_newton_residual(hbpc_ctx* c, const double* w, const double* sigma, const double* b, double a1dt,
+                         double bcoef, double* G) {
+    if (!c || !w || !sigma || !b || !G) return HBPC_ERR_ARG;
+    HBPC_TRY(c, {
+        op_trace(c, w, c->trw, 0);
+        op_trace(c, sigma, c->trs, 0);
+        LaunchReq r = op_req(c, OPK_RES);
+        r.fld[0] = w;
+        r.fld[1] = sigma;
+        r.fld[2] = b;
+        r.trc[0] = c->trw;
+        r.trc[1] = c->trs;
+        r.out[0] = G;
+        r.out[1] = G + c->ndof;
+        r.c0 = a1dt;
+        r.c1 = bcoef;
+        op_launch(c, r, 0);
+    });
+}
+
+int hbpc_jvp(hbpc_ctx* c, const double* w, const double* sigma, double a1dt, double bcoef, const double* dX,
+             double* JdX, int mode) {
+    if (!c || !w || !sigma || !dX || !JdX) return HBPC_ERR_ARG;
+    if (mode != HBPC_JVP_LINEARISED && mode != HBPC_JVP_FD) return HBPC_ERR_ARG;
+    HBPC_TRY(c, {
+        op_trace(c, w, c->trw, 0);
+        op_trace(c, sigma, c->trs, 0);
+        if (mode == HBPC_JVP_FD) {
+            fd_alloc(c);
+            op_r1(c, w, c->fd[0], c->trd1);
+            op_r2_tr(c, w, sigma, c->trw, c->trs, c->fd[1]);
+            op_jvp_fd(c, w, sigma, dX, JdX, a1dt, bcoef);
+        } else {
+            op_jvp(c, w, sigma, c->trw, c->trs, dX, JdX, a1dt, bcoef, 0, c->prm.hessian);
+        }
+    });
+}
+
+int hbpc_jvp_f32(hbpc_ctx* c, const float* w, const float* sigma, double a1dt, double bcoef, const float* dX,
+                 float* JdX) {
+    if (!c || !w || !sigma || !dX || !JdX) return HBPC_ERR_ARG;
+    HBPC_TRY(c, {
+        op_trace(c, w, c->trw32, 1);
+        op_trace(c, sigma, c->trs32, 1);
+        op_jvp(c, w, sigma, c->trw32, c->trs32, dX, JdX, a1dt, bcoef, 1, c->prm.hessian);
+    });
+}
+
+int hbpc_pc_build(hbpc_ctx* c, const double* w, double a1dt, double bcoef, int precision) {
+    if (!c || !w) return HBPC_ERR_ARG;
+    HBPC_TRY(c, {
+        pc_build(c, w, a1dt, bcoef, precision == HBPC_MIXED);
+        if (precision == HBPC_MIXED) {
+            hipchk(c, blas_axpby(1.0, w, 0, 0.0, c->X32, 1, c->ndof, c->stream), "cast");
+            op_trace(c, c->X32, c->trw32, 1);
+        } else {
+            hipchk(c, hipMemcpyAsync(c->tmp[1], w, c->ndof * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
+        }
+    });
+}
+
+int hbpc_pc_apply(hbpc_ctx* c, const double* X, double* Y) {
+    if (!c || !X || !Y) return HBPC_ERR_ARG;
+    if (!c->pc_valid || c->sinv_f32) {
+        c->err = "hbpc_pc_apply needs an FP64 hbpc_pc_build first";
+        return HBPC_ERR_ARG;
+    }
+    HBPC_TRY(c, {
+        op_trace(c, c->tmp[1], c->trw, 0);
+        pc_apply(c, c->tmp[1], c->trw, X, Y, 0);
+    });
+}
+
+int hbpc_pc_apply_f32(hbpc_ctx* c, const float* X, float* Y) {
+    if (!c || !X || !Y) return HBPC_ERR_ARG;
+    if (!c->pc_valid || !c->sinv_f32) {
+        c->err = "hbpc_pc_apply_f32 needs an HBPC_MIXED hbpc_pc_build first";
+        return HBPC_ERR_ARG;
+    }
+    HBPC_TRY(c, pc_apply(c, c->X32, c->trw32, X, Y, 1));
+}
+
+int hbpc_step(hbpc_ctx* c, double* w_inout, double dt, hbpc_stats* stats) {
+    if (!c || !w_inout || !(dt > 0)) return HBPC_ERR_ARG;
+    if ((c->prm.precision == HBPC_MIXED) != (c->kr_f32 == 1)) {
+        c->err = "precision differs from the one the context was created with";
+        return HBPC_ERR_ARG;
+    }
+    std::memset(&c->st, 0, sizeof(c->st));
+    c->cur_solve = 0;
+    double t0 = now_ms();
+    int rc = HBPC_OK;
+    try {
+        hbpc_step_impl(c, w_inout, dt);
+    } catch (const Fail& f) {
+        rc = f.code;
+        (void)hipStreamSynchronize(c->stream);
+    } catch (...) {
+        c->err = "unexpected C++ exception";
+        rc = HBPC_ERR_ARG;
+    }
+    c->st.t_step_ms = now_ms() - t0;
+    if (stats) *stats = c->st;
+    prof_resolve(c);
+    return rc;
+}
+
+int hbpc_profile_enable(hbpc_ctx* c, int enable) {
+    if (!c) return HBPC_ERR_ARG;
+    c->prof = enable ? 1 : 0;
+    return HBPC_OK;
+}
+
+int hbpc_profile_read(hbpc_ctx* c, hbpc_kernel_prof* out, int max, int reset) {
+    if (!c || (max > 0 && !out)) return HBPC_ERR_ARG;
+    prof_resolve(c);
+    int k = 0;
+    for (int i = 0; i < KC_COUNT && k < max; ++i) {
+        if (c->kp_launch[i] == 0) continue;
+        std::memset(&out[k], 0, sizeof(out[k]));
+        std::strncpy(out[k].name, KC_NAMES[i], sizeof(out[k].name) - 1);
+        out[k].launches = c->kp_launch[i];
+        out[k].total_ms = c->kp_ms[i];
+        out[k].bytes = c->kp_bytes[i];
+        out[k].flops = c->kp_flops[i];
+        ++k;
+    }
+    if (reset) {
+        for (int i = 0; i < 16; ++i) {
+            c->kp_launch[i] = 0;
+            c->kp_ms[i] = c->kp_bytes[i] = c->kp_flops[i] = 0.0;
+        }
+    }
+    return k;
+}
+
+const char* hbpc_strerror(int code) {
+    switch (code) {
+    case HBPC_OK: return "ok";
+    case HBPC_ERR_ARG: return "invalid argument";
+    case HBPC_ERR_OOM: return "out of device memory";
+    case HBPC_ERR_HIP: return "HIP runtime error";
+    case HBPC_ERR_NONFINITE: return "non-finite value";
+    case HBPC_ERR_NEWTON: return "Newton did not converge";
+    case HBPC_ERR_GMRES: return "GMRES did not converge";
+    case HBPC_ERR_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown error";
+    }
+}
+
+const char* hbpc_last_error(const hbpc_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

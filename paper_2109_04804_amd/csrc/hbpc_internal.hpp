@@ -1,0 +1,112 @@
+// Internal declarations of libhbpc (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <string>
+#include <vector>
+#include "../../include/hbpc.h"
+#include "dg_launch.hpp"
+
+// ---- kernel launchers (one translation unit per family)
+hipError_t dg_launch_euler(const GeomHost& g, const LaunchReq& r, int f32);
+hipError_t dg_launch_advection(const GeomHost& g, const LaunchReq& r, int f32);
+hipError_t dg_launch_burgers(const GeomHost& g, const LaunchReq& r, int f32);
+hipError_t bj_invert(const double* KT, void* SinvT, int f32, int NE, int nE, double a1dt, double bc, int* status,
+                     hipStream_t st);
+hipError_t bj_apply(const void* SinvT, int m_f32, const void* xa, const void* xc, void* yw, void* ys, int v_f32,
+                    int NE, int nE, hipStream_t st);
+int blas_mdot_grid(size_t n);
+hipError_t blas_mdot(const void* V, size_t ld, int k, const void* w, size_t n, int f32, double* part, double* h,
+                     hipStream_t st);
+hipError_t blas_gemv_sub(const void* V, size_t ld, int k, const double* h, void* w, size_t n, int f32,
+                         hipStream_t st);
+hipError_t blas_axpby(double a, const void* x, int tx, double b, void* y, int ty, size_t n, hipStream_t st);
+hipError_t blas_lincomb2(double a, const double* x, double b, const double* z, double* y, size_t n, hipStream_t st);
+hipError_t blas_gemv_add(const void* Z, int tz, size_t ld, int k, const double* c, void* y, int ty, size_t n,
+                         hipStream_t st);
+hipError_t blas_nonfinite(const void* x, int f32, size_t n, int* status, hipStream_t st);
+
+// ---- 1-D operators (host, FP64)
+struct Basis1DHost {
+    int N, NP;
+    std::vector<double> xi, w, Dhat /*NP*NP, Dhat[i*NP+lam]*/, lp, lm, lhp, lhm;
+};
+bool basis1d_build(int N, int kind, Basis1DHost& out);
+
+// ---- error carrier
+struct HbpcError {
+    int code;
+    std::string msg;
+};
+
+typedef hipError_t (*FamilyLauncher)(const GeomHost&, const LaunchReq&, int);
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct hbpc_ctx {
+    hbpc_mesh mesh;
+    hbpc_params prm;
+    int N, NP, D, NV, NN, NFP, NE, nE, equation;
+    size_t ndof, n2, tsz;     // tsz: trace values per field
+    GeomHost geom;
+    Basis1DHost basis;
+    FamilyLauncher launch;
+    hipStream_t stream;
+    std::string err;
+
+    // FP64 state
+    double* W[4];             // stage values
+    double* R1all;            // s x ndof
+    double* R2all;            // s x ndof
+    double* Wn[4];            // corrector targets
+    double* X;                // Newton iterate (w | sigma), 2 ndof
+    double* b;
+    double* G;                // 2 ndof
+    double* dX;               // 2 ndof, FP64 accumulation of the Krylov solution
+    double* rhs;              // 2 ndof
+    double* tmp[4];           // ndof scratch
+    double* trw; double* trs; double* trd1; double* trd2;   // FP64 traces
+    // FP32 snapshots
+    float* X32;               // 2 ndof
+    float* trw32; float* trs32; float* trd1_32; float* trd2_32;
+    // Krylov (type chosen by precision): V (m+1) x n2, Z m x n2, u n2
+    void* V; void* Z; void* kv;        // kv: 3 x n2 work (pc pre-products a|c, residual)
+    int kr_f32;                        // type of V/Z
+    int m_alloc;
+    // BJ_ext
+    double* KT;               // chunk_e x NE x NE (column-major blocks)
+    void* Sinv;               // nE x NE x NE
+    int sinv_f32;
+    size_t kt_chunk;          // elements per K build chunk
+    double pc_a1dt, pc_bc;
+    int pc_valid;
+    // reductions
+    double* part;             // blas partials
+    double* dres;             // device results (256)
+    double* hres;             // pinned host copy (256)
+    int* dstatus;
+    // FD scratch (allocated on demand)
+    double* fd[6];
+    // statistics of the last step
+    hbpc_stats st;
+    int cur_solve;
+    int verbose;              // HBPC_VERBOSE=1: Newton progress on stderr
+    // kernel timing
+    int prof;
+    std::vector<hipEvent_t> ev;          // pairs (start, stop)
+    std::vector<int> ev_class;
+    std::vector<double> ev_bytes, ev_flops;
+    size_t ev_used;
+    int kp_launch[16];
+    double kp_ms[16], kp_bytes[16], kp_flops[16];
+};
+
+enum { KC_TRACE = 0, KC_R1, KC_R2, KC_RES, KC_JVP, KC_KCOL, KC_PCPRE, KC_BJAPPLY, KC_BJINV, KC_MDOT, KC_GEMV,
+       KC_VEC, KC_COUNT };
+
+// helpers implemented in ops.cpp
+int op_launch(hbpc_ctx* c, const LaunchReq& r, int f32);
+LaunchReq op_req(hbpc_ctx* c, int op);

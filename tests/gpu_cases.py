@@ -1,0 +1,166 @@
+"""Shared set-up for the GPU parity tests: configurations, seeded inputs, the
+oracle counterpart of each configuration, and 3^d element patches for
+sampled checks at full size."""
+import numpy as np
+
+from oracle.dgsem import DGSEM, Mesh
+from oracle.equations import Advection, Burgers, Euler
+from paper_2109_04804_amd import inputs
+
+TWO_PI = 2 * np.pi
+
+CASES = {
+    # 1-D advection workload (16 elements, N = 3, Lobatto, upwind / central)
+    "adv1_upwind": dict(dim=1, nelem=[16], length=[1.0], N=3, equation="advection", nodes="lobatto",
+                        flux="upwind", adv=[1.0]),
+    "adv1_central": dict(dim=1, nelem=[16], length=[1.0], N=3, equation="advection", nodes="lobatto",
+                         flux="central", adv=[1.0]),
+    "adv2_ragged": dict(dim=2, nelem=[5, 3], length=[2.0, 1.0], N=4, equation="advection", nodes="gauss",
+                        flux="upwind", adv=[0.3, -0.7]),
+    "adv3": dict(dim=3, nelem=[3, 2, 4], length=[1.0, 1.0, 1.0], N=2, equation="advection", nodes="gauss",
+                 flux="upwind", adv=[0.3, 0.5, -0.2]),
+    # 2-D Euler, N = 5 as in the vortex workload, ragged element count (46)
+    "euler2_n5": dict(dim=2, nelem=[23, 2], length=[10.0, 10.0], N=5, equation="euler", nodes="gauss",
+                      flux="rusanov"),
+    "euler2_n3_lobatto": dict(dim=2, nelem=[4, 5], length=[10.0, 10.0], N=3, equation="euler",
+                              nodes="lobatto", flux="rusanov"),
+    "euler2_lf": dict(dim=2, nelem=[3, 3], length=[10.0, 10.0], N=4, equation="euler", nodes="gauss",
+                      flux="lf", **{"lambda": 3.0}),
+    # 3-D eps-scaled Euler (eps = 0.1), N = 3 as in the Taylor-Green workload
+    "euler3_n3": dict(dim=3, nelem=[3, 4, 5], length=[TWO_PI] * 3, N=3, equation="euler", nodes="gauss",
+                      flux="rusanov", eps_ref=0.1),
+    # degenerate: one element per direction (every neighbour is the element itself)
+    "euler2_single": dict(dim=2, nelem=[1, 1], length=[10.0, 10.0], N=5, equation="euler", nodes="gauss",
+                          flux="rusanov"),
+}
+
+
+def oracle_for(case):
+    c = dict(case)
+    dim = c["dim"]
+    mesh = Mesh(dim, c["nelem"], c["length"], c.get("origin"))
+    if c["equation"] == "advection":
+        eq = Advection(dim, c["adv"])
+    elif c["equation"] == "burgers":
+        eq = Burgers(dim, c.get("nu", 0.0))
+    else:
+        eq = Euler(dim, c.get("gamma", 1.4), c.get("eps_ref", 1.0))
+    return DGSEM(mesh, c["N"], eq, nodes=c.get("nodes", "gauss"), flux=c["flux"], lam=c.get("lambda", 0.0))
+
+
+def lib_kwargs(case):
+    kw = {k: v for k, v in case.items() if k not in ("dim", "nelem", "length", "N", "equation", "origin")}
+    return kw
+
+
+def state(dg, seed=0):
+    """Smooth admissible state for the oracle's configuration."""
+    X = dg.node_coords()
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0, TWO_PI, size=4)
+    if dg.nvar == 1:
+        s = sum(np.sin(TWO_PI * x / dg.mesh.length[m] + ph[m]) for m, x in enumerate(X))
+        return (0.5 + 0.2 * s)[:, None, :]
+    if dg.d == 2:
+        L = dg.mesh.length[0]
+        return inputs.isentropic_vortex(X[0], X[1], 0.3 * L + ph[0] / 5, 0.6 * L - ph[1] / 5, 5.0, box=L)
+    w = inputs.taylor_green(X[0] + ph[0], X[1] + ph[2], X[2] + ph[3], eps=dg.eq.eps)
+    w[:, 3, :] += 0.05 * np.sin(X[0] + X[2] + ph[1])
+    return w
+
+
+def perturbation(dg, seed, scale=None):
+    w = state(dg)
+    rng = np.random.default_rng(1000 + seed)
+    s = np.abs(w).mean() if scale is None else scale
+    return s * rng.standard_normal(w.shape)
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def patch_indices(nelem, e):
+    """Element indices of the 3^d patch centred on element e (periodic), in
+    the lexicographic order of a 3^d mesh (x fastest)."""
+    d = len(nelem)
+    coords = []
+    r = e
+    for m in range(d):
+        coords.append(r % nelem[m])
+        r //= nelem[m]
+    idx = []
+    for k in range(3 if d > 2 else 1):
+        for j in range(3 if d > 1 else 1):
+            for i in range(3):
+                off = [i - 1, j - 1, k - 1][:d]
+                c = [(coords[m] + off[m]) % nelem[m] for m in range(d)]
+                g = 0
+                mul = 1
+                for m in range(d):
+                    g += c[m] * mul
+                    mul *= nelem[m]
+                idx.append(g)
+    return np.array(idx)
+
+
+def patch_oracle(case, dg_full):
+    """Oracle on a 3^d periodic patch with the full mesh's element size; the
+    centre element (index (3^d - 1)/2) sees exactly its true neighbours."""
+    d = case["dim"]
+    h = [case["length"][m] / case["nelem"][m] for m in range(d)]
+    sub = dict(case)
+    sub["nelem"] = [3] * d
+    sub["length"] = [3 * h[m] for m in range(d)]
+    return oracle_for(sub), (3 ** d - 1) // 2
+
+
+def _rowsum(dg):
+    return float(np.abs(dg.basis.Dhat).sum(axis=1).max() + np.abs(dg.basis.lhat_plus).max()
+                 + np.abs(dg.basis.lhat_minus).max())
+
+
+def flux_scale(dg, w, sigma=None):
+    """Sum-of-magnitudes scale of DG[F] (sigma None) or DG[F'(w) sigma]:
+    sum_m (2/h_m) (max row sum of |Dhat| + |lhat|) ||F_m||_2.  Floating-point
+    summation of the operator's terms errs by a small multiple of
+    eps_mach times this scale, whatever cancellation the result has."""
+    from oracle import jets
+    u = dg.to_vars(w)
+    if sigma is not None:
+        sv = dg.to_vars(sigma)
+        u = [jets.HD(a, b) for a, b in zip(u, sv)]
+    tot = 0.0
+    for m in range(dg.d):
+        F = dg.eq.flux(u, m)
+        F = [jets.part(f, "b" if sigma is not None else "a") for f in F]
+        tot += 2.0 / dg.mesh.h[m] * _rowsum(dg) * float(np.sqrt(sum((f ** 2).sum() for f in F)))
+    return tot
+
+
+def lipschitz(dg, w):
+    """Upper estimate of ||R1'(w)||: sum_m (2/h_m) rowsum * max wave speed."""
+    u = dg.to_vars(w)
+    sp = 0.0
+    for m in range(dg.d):
+        if hasattr(dg.eq, "wave_speed"):
+            c = float(np.max(np.abs(dg.eq.wave_speed(u, m))))
+        elif hasattr(dg.eq, "a"):
+            c = abs(dg.eq.a[m])
+        else:
+            c = float(np.max(np.abs(u[0]))) + 1.0
+        sp += 2.0 / dg.mesh.h[m] * _rowsum(dg) * c
+    return sp
+
+
+def check(got, ref, scale, c=1e-13, label=""):
+    """||got - ref|| <= c * (||ref|| + scale); prints the figures."""
+    got = np.asarray(got, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    err = float(np.linalg.norm(got - ref))
+    bound = c * (float(np.linalg.norm(ref)) + scale)
+    print("%s err %.3e  ||ref|| %.3e  scale %.3e  bound %.3e  rel %.3e"
+          % (label, err, np.linalg.norm(ref), scale, bound, err / max(np.linalg.norm(ref), 1e-300)), flush=True)
+    assert err <= bound, (err, bound)

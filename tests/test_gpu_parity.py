@@ -1,0 +1,171 @@
+"""GPU parity: every libhbpc entry point against the FP64 oracle on the same
+seeded inputs.  Tolerances:
+  FP64 operators (R1, R2, G)               ||err|| <= 1e-13 (||ref|| + S), S the
+                                           sum-of-magnitudes scale of the operator's
+                                           terms (gpu_cases.flux_scale): round-off
+                                           of the summation, whatever cancellation
+                                           the result has; R2(w) with sigma = R1(w)
+                                           adds ||R1'|| times the R1 bound
+  FP64 JVP                                 relative L2 1e-12
+  FP32 JVP on FP32-rounded inputs          5e-5  (FP32 unit round-off 6e-8 times the
+                                                  O(10^2) amplification of the 2/h-scaled
+                                                  derivative sums, with margin)
+  BJ_ext apply FP64 (explicit inverse vs LU) 1e-10 (cond(S_i) times round-off)
+  finite-difference JVP vs exact JVP       1e-6  (O(sqrt(eps_mach)) truncation + cancellation)
+"""
+import numpy as np
+import pytest
+
+from gpu_cases import (CASES, check, flux_scale, lib_kwargs, lipschitz, oracle_for, patch_indices, patch_oracle,
+                       perturbation, rel, state)
+from oracle.solvers import BJExt
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(x, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda").reshape(-1)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def make_ctx(case, **over):
+    from paper_2109_04804_amd.hbpc import Context
+    kw = lib_kwargs(case)
+    kw.update(over)
+    return Context(case["dim"], case["nelem"], case["length"], case["N"], case["equation"], **kw)
+
+
+def setup(name, **over):
+    case = CASES[name]
+    dg = oracle_for(case)
+    ctx = make_ctx(case, **over)
+    assert ctx.ndof == dg.ndof
+    print("case", name, "ndof", dg.ndof, flush=True)
+    return case, dg, ctx
+
+
+ALL = list(CASES)
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_nodes_match_oracle(name):
+    case, dg, ctx = setup(name)
+    xi, w = ctx.nodes()
+    assert np.abs(xi - dg.basis.xi).max() < 1e-14 and np.abs(w - dg.basis.w).max() < 1e-14
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_residual1(name):
+    case, dg, ctx = setup(name)
+    w = state(dg)
+    out = torch.empty(ctx.ndof, dtype=torch.float64, device="cuda")
+    ctx.residual1(dev(w), out)
+    check(host(out), dg.r1(w), flux_scale(dg, w), label="R1")
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_residual2(name):
+    case, dg, ctx = setup(name)
+    w = state(dg)
+    s = perturbation(dg, 1)
+    out = torch.empty(ctx.ndof, dtype=torch.float64, device="cuda")
+    ctx.residual2(dev(w), dev(s), out)
+    check(host(out), dg.r2(w, s), flux_scale(dg, w, s), label="R2(w,s)")
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_residual2_of_r1(name):
+    """R2(w) := R2(w, R1(w)); the R1 round-off enters through R1'(w)."""
+    case, dg, ctx = setup(name)
+    w = state(dg)
+    out = torch.empty(ctx.ndof, dtype=torch.float64, device="cuda")
+    ctx.residual2(dev(w), None, out)
+    s1 = dg.r1(w)
+    scale = flux_scale(dg, w, s1) + lipschitz(dg, w) * (np.linalg.norm(s1) + flux_scale(dg, w))
+    check(host(out), dg.r2(w), scale, label="R2(w)")
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_newton_residual(name):
+    case, dg, ctx = setup(name)
+    w = state(dg)
+    s = dg.r1(w) + perturbation(dg, 2, 0.01)
+    b = w + perturbation(dg, 3, 0.01)
+    a1dt, bc = 0.025, 0.1 ** 2 / 48
+    G = torch.empty(2 * ctx.ndof, dtype=torch.float64, device="cuda")
+    ctx.newton_residual(dev(w), dev(s), dev(b), a1dt, bc, G)
+    g1, g2 = dg.residual_G(w, s, b, a1dt, bc)
+    ref = np.concatenate([g1.ravel(), g2.ravel()])
+    scale = (np.linalg.norm(w) + np.linalg.norm(b) + np.linalg.norm(s)
+             + (1 + a1dt) * flux_scale(dg, w) + bc * flux_scale(dg, w, s))
+    check(host(G), ref, scale, label="G")
+
+
+@pytest.mark.parametrize("name", ALL)
+@pytest.mark.parametrize("hessian", [1, 0])
+def test_jvp_fp64(name, hessian):
+    case, dg, ctx = setup(name, hessian=hessian)
+    w = state(dg)
+    s = dg.r1(w)
+    dw, ds = perturbation(dg, 4), perturbation(dg, 5)
+    a1dt, bc = 0.1, 0.1 ** 2 / 2
+    out = torch.empty(2 * ctx.ndof, dtype=torch.float64, device="cuda")
+    ctx.jvp(dev(w), dev(s), a1dt, bc, dev(np.concatenate([dw.ravel(), ds.ravel()])), out)
+    Jw, Js = dg.jvp(w, s, dw, ds, a1dt, bc, hessian=bool(hessian))
+    assert rel(host(out), np.concatenate([Jw.ravel(), Js.ravel()])) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["euler2_n5", "euler3_n3", "adv2_ragged", "euler2_single"])
+def test_jvp_fp32(name):
+    case, dg, ctx = setup(name)
+    f32 = lambda x: np.asarray(x, dtype=np.float32).astype(np.float64)
+    w = f32(state(dg))
+    s = f32(dg.r1(w))
+    dw, ds = f32(perturbation(dg, 4)), f32(perturbation(dg, 5))
+    a1dt, bc = 0.1, 0.1 ** 2 / 2
+    out = torch.empty(2 * ctx.ndof, dtype=torch.float32, device="cuda")
+    ctx.jvp_f32(dev(w, torch.float32), dev(s, torch.float32), a1dt, bc,
+                dev(np.concatenate([dw.ravel(), ds.ravel()]), torch.float32), out)
+    Jw, Js = dg.jvp(w, s, dw, ds, a1dt, bc)
+    assert rel(host(out), np.concatenate([Jw.ravel(), Js.ravel()])) < 5e-5
+
+
+@pytest.mark.parametrize("name", ["euler2_n5", "euler3_n3", "adv1_upwind"])
+def test_jvp_finite_difference(name):
+    """Eq. MatrixFree_nonlinear on the GPU against the exact (oracle) JVP."""
+    case, dg, ctx = setup(name)
+    w = state(dg)
+    s = dg.r1(w)
+    dw, ds = perturbation(dg, 4), perturbation(dg, 5)
+    a1dt, bc = 0.1, 0.1 ** 2 / 2
+    out = torch.empty(2 * ctx.ndof, dtype=torch.float64, device="cuda")
+    ctx.jvp(dev(w), dev(s), a1dt, bc, dev(np.concatenate([dw.ravel(), ds.ravel()])), out, mode="fd")
+    Jw, Js = dg.jvp(w, s, dw, ds, a1dt, bc)
+    assert rel(host(out), np.concatenate([Jw.ravel(), Js.ravel()])) < 1e-6
+
+
+@pytest.mark.parametrize("name", ["euler2_n3_lobatto", "euler2_n5", "adv2_ragged", "adv1_upwind", "euler3_n3"])
+def test_pc_apply(name):
+    """BJ_ext: GPU (explicit S^-1, commuted form) vs oracle (LU, D/E/F/G blocks)."""
+    case, dg, ctx = setup(name)
+    if ctx.block > 144:
+        pytest.skip("element block above 144 unknowns")
+    w = state(dg)
+    a1dt, bc = 0.1, 0.1 ** 2 / 2
+    pc = BJExt(dg, w, a1dt, bc)
+    X = np.concatenate([perturbation(dg, 6).ravel(), perturbation(dg, 7).ravel()])
+    ref = pc.apply(X)
+    ctx.pc_build(dev(w), a1dt, bc, "fp64")
+    out = torch.empty(2 * ctx.ndof, dtype=torch.float64, device="cuda")
+    ctx.pc_apply(dev(X), out)
+    assert rel(host(out), ref) < 1e-10
+    ctx.pc_build(dev(w), a1dt, bc, "mixed")
+    out32 = torch.empty(2 * ctx.ndof, dtype=torch.float32, device="cuda")
+    ctx.pc_apply_f32(dev(X, torch.float32), out32)
+    assert rel(host(out32), ref) < 1e-4
