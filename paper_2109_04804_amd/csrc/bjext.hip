@@ -14,164 +14,179 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
-template <int TG, int R, typename T, typename TO>
-__global__ void __launch_bounds__(TG* TG) bj_invert_kernel(const T* __restrict__ KT, TO* __restrict__ SinvT, int NE,
-                                                          T a1dt, T bc, int* __restrict__ status) {
-    constexpr int NT = TG * TG;
+template <int TGR, int TGC, int RR, int RC, typename T, typename TO>
+__global__ void __launch_bounds__(TGR* TGC) bj_invert_kernel(const T* __restrict__ KT, TO* __restrict__ SinvT,
+                                                            int NE, T a1dt, T bc, int* __restrict__ status) {
+    // thread (tr, tc), tid = tr + TGR tc, owns rows tr + TGR a (a < RR) and
+    // columns tc + TGC b (b < RC); a column group (fixed tc) is TGR
+    // consecutive lanes of one wave.  Register indices are compile-time
+    // constants throughout (runtime indices would move acc[][] to scratch).
+    constexpr int NT = TGR * TGC;
     constexpr int KC = 8;
-    constexpr int NMAX = TG * R;
+    constexpr int NRMAX = TGR * RR;
+    constexpr int NCMAX = TGC * RC;
+    constexpr int NMAX = NRMAX > NCMAX ? NRMAX : NCMAX;
     __shared__ T sA[KC][NMAX];   // K[r][kk+t]
     __shared__ T sB[KC][NMAX];   // K[kk+t][c]
-    __shared__ T s_row[NMAX];
-    __shared__ T s_rowk[NMAX];
-    __shared__ T s_col[NMAX];
-    __shared__ int s_piv[NMAX];
-    __shared__ int s_perm[NMAX];
+    __shared__ T s_row[NMAX];    // pivot row p
+    __shared__ T s_col[NMAX];    // column k
+    __shared__ int s_prow[NMAX]; // pivot row of step k
+    __shared__ int s_pinv[NMAX]; // step at which row r was pivot
     __shared__ int s_p;
 
     const int tid = threadIdx.x;
-    const int tr = tid % TG, tc = tid / TG;
+    const int tr = tid % TGR, tc = tid / TGR;
     const size_t e = blockIdx.x;
     const T* K = KT + e * (size_t)NE * NE;
 
-    T acc[R][R];
+    T acc[RR][RC];
 #pragma unroll
-    for (int a = 0; a < R; ++a)
+    for (int a = 0; a < RR; ++a)
 #pragma unroll
-        for (int b = 0; b < R; ++b) acc[a][b] = T(0);
+        for (int b = 0; b < RC; ++b) acc[a][b] = T(0);
 
-    // ---- K^2 (rows owned x cols owned), staged through LDS in slabs of KC
+    // ---- K^2 for the owned entries, K staged through LDS in slabs of KC
     for (int kk = 0; kk < NE; kk += KC) {
         for (int i = tid; i < KC * NE; i += NT) {
             int t = i / NE, x = i % NE;
             int k = kk + t;
             sA[t][x] = k < NE ? K[(size_t)k * NE + x] : T(0);   // K[x][k] = KT[k][x]
+        }
+        for (int i = tid; i < KC * NE; i += NT) {
+            int x = i / KC, t = i % KC;                      // consecutive threads: consecutive k
+            int k = kk + t;
             sB[t][x] = k < NE ? K[(size_t)x * NE + k] : T(0);   // K[k][x] = KT[x][k]
         }
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < KC; ++t) {
-            T ra[R], cb[R];
+            T ra[RR], cb[RC];
 #pragma unroll
-            for (int a = 0; a < R; ++a) ra[a] = (tr + TG * a) < NE ? sA[t][tr + TG * a] : T(0);
+            for (int a = 0; a < RR; ++a) ra[a] = sA[t][(tr + TGR * a) < NE ? tr + TGR * a : 0];
 #pragma unroll
-            for (int b = 0; b < R; ++b) cb[b] = (tc + TG * b) < NE ? sB[t][tc + TG * b] : T(0);
+            for (int b = 0; b < RC; ++b) cb[b] = sB[t][(tc + TGC * b) < NE ? tc + TGC * b : 0];
 #pragma unroll
-            for (int a = 0; a < R; ++a)
+            for (int a = 0; a < RR; ++a)
 #pragma unroll
-                for (int b = 0; b < R; ++b) acc[a][b] += ra[a] * cb[b];
+                for (int b = 0; b < RC; ++b) acc[a][b] += ra[a] * cb[b];
         }
         __syncthreads();
     }
-    // ---- S = I - a1dt K + bc K^2 (padding rows/cols: identity)
+    // ---- S = I - a1dt K + bc K^2 (padding rows/columns: identity, never used)
+    unsigned used = 0u;   // bit a: owned row a has been a pivot row
 #pragma unroll
-    for (int a = 0; a < R; ++a)
+    for (int a = 0; a < RR; ++a)
 #pragma unroll
-        for (int b = 0; b < R; ++b) {
-            int r = tr + TG * a, c = tc + TG * b;
+        for (int b = 0; b < RC; ++b) {
+            int r = tr + TGR * a, c = tc + TGC * b;
             T v = (r == c) ? T(1) : T(0);
             if (r < NE && c < NE) v += -a1dt * K[(size_t)c * NE + r] + bc * acc[a][b];
             acc[a][b] = v;
         }
 
-    // ---- Gauss-Jordan with partial pivoting, in place.  Every register index is
-    // a compile-time constant (runtime indices would move acc[][] to scratch).
+    // ---- Gauss-Jordan exchange steps without row swaps: step k pivots on
+    // (p_k, k) with p_k the largest unused entry of column k; afterwards
+    // S^-1[k][p_j] = T[p_k][j].
     for (int k = 0; k < NE; ++k) {
-        const int ck = k % TG, bk = k / TG;
+        const int ck = k % TGC, bk = k / TGC;
         if (tc == ck) {
             T best = T(-1);
             int bi = NE;
 #pragma unroll
-            for (int a = 0; a < R; ++a) {
-                const int r = tr + TG * a;
+            for (int a = 0; a < RR; ++a) {
+                const int r = tr + TGR * a;
                 T v = T(0);
 #pragma unroll
-                for (int b = 0; b < R; ++b) v = (b == bk) ? acc[a][b] : v;
+                for (int b = 0; b < RC; ++b) v = (b == bk) ? acc[a][b] : v;
                 v = v >= T(0) ? v : -v;
-                if (r >= k && r < NE && v > best) { best = v; bi = r; }
+                const bool take = r < NE && !((used >> a) & 1u) && v > best;
+                best = take ? v : best;
+                bi = take ? r : bi;
             }
-            // reduce over the TG threads of this column group (consecutive lanes)
 #pragma unroll
-            for (int off = 1; off < TG; off <<= 1) {
-                T ob = __shfl_xor(best, off, TG);
-                int oi = __shfl_xor(bi, off, TG);
+            for (int off = 1; off < TGR; off <<= 1) {
+                T ob = __shfl_xor(best, off, TGR);
+                int oi = __shfl_xor(bi, off, TGR);
                 if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
             }
-            if (tr == 0) s_p = bi < NE ? bi : k;   // all-NaN column: keep k, flagged below
+            if (tr == 0) s_p = bi;
         }
         __syncthreads();
         const int p = s_p;
-        if (tid == 0) s_piv[k] = p;
-        // publish row p, row k and column k
+        if (p >= NE) {                     // no finite pivot left: flag, stop
+            if (tid == 0) atomicOr(status, 1);
+            return;
+        }
+        if (tid == 0) {
+            s_prow[k] = p;
+            s_pinv[p] = k;
+        }
+        const int ap = p / TGR;
+        if (tr == p % TGR) {               // owners of row p publish it
+            used |= 1u << ap;
 #pragma unroll
-        for (int a = 0; a < R; ++a) {
-            const int r = tr + TG * a;
+            for (int b = 0; b < RC; ++b) {
+                const int c = tc + TGC * b;
+                T v = T(0);
 #pragma unroll
-            for (int b = 0; b < R; ++b) {
-                const int c = tc + TG * b;
-                if (c < NE) {
-                    if (r == p) s_row[c] = acc[a][b];
-                    if (r == k) s_rowk[c] = acc[a][b];
-                }
-                if (c == k && r < NE) s_col[r] = acc[a][b];
+                for (int a = 0; a < RR; ++a) v = (a == ap) ? acc[a][b] : v;
+                if (c < NE) s_row[c] = v;
+            }
+        }
+        if (tc == ck) {                    // owners of column k publish it
+#pragma unroll
+            for (int a = 0; a < RR; ++a) {
+                const int r = tr + TGR * a;
+                T v = T(0);
+#pragma unroll
+                for (int b = 0; b < RC; ++b) v = (b == bk) ? acc[a][b] : v;
+                if (r < NE) s_col[r] = v;
             }
         }
         __syncthreads();
         const T piv = s_col[p];
         const T ipiv = T(1) / piv;
-        T pr[R], rk[R], f[R];
-#pragma unroll
-        for (int b = 0; b < R; ++b) {
-            const int c = tc + TG * b;
-            const bool in = c < NE;
-            pr[b] = (c == k) ? ipiv : (in ? s_row[c] * ipiv : T(0));   // new pivot row / pivot
-            rk[b] = in ? s_rowk[c] : T(0);                              // old row k (moves to row p)
-        }
-#pragma unroll
-        for (int a = 0; a < R; ++a) {
-            const int r = tr + TG * a;
-            f[a] = (r < NE) ? (r == p ? s_col[k] : s_col[r]) : T(0);  // multiplier A'[r][k]
-        }
-#pragma unroll
-        for (int a = 0; a < R; ++a) {
-            const int r = tr + TG * a;
-#pragma unroll
-            for (int b = 0; b < R; ++b) {
-                const int c = tc + TG * b;
-                T cur = (r == p) ? rk[b] : acc[a][b];
-                cur = (c == k) ? T(0) : cur;
-                T upd = cur - f[a] * pr[b];
-                acc[a][b] = (r == k) ? pr[b] : upd;
-            }
-        }
         if (!(piv == piv) || piv == T(0)) {
             if (tid == 0) atomicOr(status, 1);
         }
+        T pr[RC], f[RR];
+#pragma unroll
+        for (int b = 0; b < RC; ++b) {
+            const int c = tc + TGC * b;
+            pr[b] = c < NE ? s_row[c] * ipiv : T(0);
+        }
+#pragma unroll
+        for (int a = 0; a < RR; ++a) {
+            const int r = tr + TGR * a;
+            f[a] = r < NE ? s_col[r] : T(0);
+        }
+        // branch-free update (selects only): pivot row / pivot column / the rest
+#pragma unroll
+        for (int a = 0; a < RR; ++a) {
+            const bool isp = (tr + TGR * a == p);
+            const T fcol = -f[a] * ipiv;
+            const T pk = isp ? ipiv : fcol;
+#pragma unroll
+            for (int b = 0; b < RC; ++b) {
+                const bool isk = (tc + TGC * b == k);
+                const T upd = acc[a][b] - f[a] * pr[b];
+                const T v = isp ? pr[b] : upd;
+                acc[a][b] = isk ? pk : v;
+            }
+        }
         __syncthreads();
     }
-    // ---- undo the column permutation: S^-1 = A P, swaps applied in reverse order
-    if (tid == 0) {
-        for (int j = 0; j < NE; ++j) s_perm[j] = j;
-        for (int k = NE - 1; k >= 0; --k) {
-            int p = s_piv[k];
-            int t = s_perm[k];
-            s_perm[k] = s_perm[p];
-            s_perm[p] = t;
-        }
-        // invert the permutation in place into s_piv
-        for (int j = 0; j < NE; ++j) s_piv[s_perm[j]] = j;
-    }
-    __syncthreads();
+    // ---- S^-1[pinv[r]][prow[c]] = T[r][c], stored column-major (SinvT[col][row])
     TO* out = SinvT + e * (size_t)NE * NE;
 #pragma unroll
-    for (int b = 0; b < R; ++b) {
-        int c = tc + TG * b;
+    for (int b = 0; b < RC; ++b) {
+        const int c = tc + TGC * b;
         if (c >= NE) continue;
-        int j = s_piv[c];
+        const int col = s_prow[c];
 #pragma unroll
-        for (int a = 0; a < R; ++a) {
-            int r = tr + TG * a;
-            if (r < NE) out[(size_t)j * NE + r] = (TO)acc[a][b];
+        for (int a = 0; a < RR; ++a) {
+            const int r = tr + TGR * a;
+            if (r < NE) out[(size_t)col * NE + s_pinv[r]] = (TO)acc[a][b];
         }
     }
 }
@@ -215,33 +230,25 @@ __global__ void __launch_bounds__(256) bj_apply_kernel(const TM* __restrict__ Si
     ys[(size_t)e * NE + r] = s1;
 }
 
-template <int TG, int R, typename TO>
+template <int TGR, int TGC, int RR, int RC, typename TO>
 static hipError_t launch_inv(const double* KT, TO* SinvT, int NE, int nE, double a1dt, double bc, int* status,
                              hipStream_t st) {
-    hipLaunchKernelGGL((bj_invert_kernel<TG, R, double, TO>), dim3(nE), dim3(TG * TG), 0, st, KT, SinvT, NE,
-                       a1dt, bc, status);
+    hipLaunchKernelGGL((bj_invert_kernel<TGR, TGC, RR, RC, double, TO>), dim3(nE), dim3(TGR * TGC), 0, st, KT,
+                       SinvT, NE, a1dt, bc, status);
     return hipGetLastError();
 }
 
 hipError_t bj_invert(const double* KT, void* SinvT, int f32, int NE, int nE, double a1dt, double bc, int* status,
                      hipStream_t st) {
     if (nE == 0) return hipSuccess;
-    if (NE <= 16) {
-        return f32 ? launch_inv<4, 4, float>(KT, (float*)SinvT, NE, nE, a1dt, bc, status, st)
-                   : launch_inv<4, 4, double>(KT, (double*)SinvT, NE, nE, a1dt, bc, status, st);
-    }
-    if (NE <= 32) {
-        return f32 ? launch_inv<8, 4, float>(KT, (float*)SinvT, NE, nE, a1dt, bc, status, st)
-                   : launch_inv<8, 4, double>(KT, (double*)SinvT, NE, nE, a1dt, bc, status, st);
-    }
-    if (NE <= 64) {
-        return f32 ? launch_inv<16, 4, float>(KT, (float*)SinvT, NE, nE, a1dt, bc, status, st)
-                   : launch_inv<16, 4, double>(KT, (double*)SinvT, NE, nE, a1dt, bc, status, st);
-    }
-    if (NE <= 144) {
-        return f32 ? launch_inv<16, 9, float>(KT, (float*)SinvT, NE, nE, a1dt, bc, status, st)
-                   : launch_inv<16, 9, double>(KT, (double*)SinvT, NE, nE, a1dt, bc, status, st);
-    }
+#define HBPC_INV(TGR, TGC, RR, RC)                                                                         \
+    return f32 ? launch_inv<TGR, TGC, RR, RC, float>(KT, (float*)SinvT, NE, nE, a1dt, bc, status, st)    \
+               : launch_inv<TGR, TGC, RR, RC, double>(KT, (double*)SinvT, NE, nE, a1dt, bc, status, st);
+    if (NE <= 16) { HBPC_INV(4, 4, 4, 4) }
+    if (NE <= 32) { HBPC_INV(8, 8, 4, 4) }
+    if (NE <= 64) { HBPC_INV(16, 16, 4, 4) }
+    if (NE <= 144) { HBPC_INV(16, 32, 9, 5) }
+#undef HBPC_INV
     return hipErrorInvalidValue;
 }
 

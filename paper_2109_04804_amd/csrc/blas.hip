@@ -121,6 +121,30 @@ __global__ void __launch_bounds__(BLAS_THREADS) nonfinite_kernel(const T* __rest
     if (bad) atomicOr(status, 1);
 }
 
+// ------------------------------------------------------------------ Gram-Schmidt passes
+// w[i] -= sum_j h[j] V_j[i] and a per-block partial of ||w||^2 (part[blockIdx.x])
+template <typename T>
+__global__ void __launch_bounds__(BLAS_THREADS) gemv_sub_norm_kernel(const T* __restrict__ V, size_t ld, int k,
+                                                                     const double* __restrict__ h,
+                                                                     T* __restrict__ w, size_t n,
+                                                                     double* __restrict__ part) {
+    __shared__ double sh[64];
+    __shared__ double red[BLAS_THREADS / 64];
+    for (int j = threadIdx.x; j < k; j += blockDim.x) sh[j] = h[j];
+    __syncthreads();
+    double nrm = 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double acc = 0.0;
+        for (int j = 0; j < k; ++j) acc += sh[j] * (double)V[j * ld + i];
+        const T wn = (T)((double)w[i] - acc);
+        w[i] = wn;
+        nrm += (double)wn * (double)wn;
+    }
+    double t = block_sum<double>(nrm, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
 // ------------------------------------------------------------------ launchers
 static int blas_grid(size_t n) {
     size_t g = (n + BLAS_THREADS - 1) / BLAS_THREADS;
@@ -145,6 +169,21 @@ hipError_t blas_mdot(const void* V, size_t ld, int k, const void* w, size_t n, i
                                (const double*)V + j0 * ld, ld, kc, (const double*)w, n, part + j0, k);
     }
     hipLaunchKernelGGL(reduce_parts_kernel, dim3(k), dim3(BLAS_THREADS), 0, st, part, g, k, h, 1.0);
+    return hipGetLastError();
+}
+
+// u -= V h (k columns, h on the device) and nrm2[0] = ||u||^2 afterwards
+hipError_t blas_gemv_sub_norm(const void* V, size_t ld, int k, const double* h, void* u, size_t n, int f32,
+                              double* part, double* nrm2, hipStream_t st) {
+    if (k > 64) return hipErrorInvalidValue;
+    int g = blas_grid(n);
+    if (f32)
+        hipLaunchKernelGGL(gemv_sub_norm_kernel<float>, dim3(g), dim3(BLAS_THREADS), 0, st, (const float*)V, ld, k,
+                           h, (float*)u, n, part);
+    else
+        hipLaunchKernelGGL(gemv_sub_norm_kernel<double>, dim3(g), dim3(BLAS_THREADS), 0, st, (const double*)V, ld,
+                           k, h, (double*)u, n, part);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(BLAS_THREADS), 0, st, part, g, 1, nrm2, 1.0);
     return hipGetLastError();
 }
 

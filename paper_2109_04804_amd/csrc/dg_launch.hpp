@@ -12,7 +12,8 @@ struct GeomHost {
     int D, NP, NV, nE;
     int nel[3];
     double two_h[3];
-    double Dhat[8][8], lp[8], lm[8], lhp[8], lhm[8];
+    const double* basis64;   // device copies of the 1-D operators (dg_ops.hpp layout)
+    const float* basis32;
     double adv[3], lam, nu, gamma, eps;
     int flux;
 };
@@ -30,17 +31,9 @@ struct LaunchReq {
     hipStream_t stream;
 };
 
-template <typename T, int NP> Basis<T, NP> make_basis(const GeomHost& g) {
-    Basis<T, NP> b;
-    for (int i = 0; i < NP; ++i) {
-        for (int j = 0; j < NP; ++j) b.Dhat[i][j] = (T)g.Dhat[i][j];
-        b.lp[i] = (T)g.lp[i];
-        b.lm[i] = (T)g.lm[i];
-        b.lhp[i] = (T)g.lhp[i];
-        b.lhm[i] = (T)g.lhm[i];
-    }
-    return b;
-}
+template <typename T> const T* basis_ptr(const GeomHost& g);
+template <> inline const double* basis_ptr<double>(const GeomHost& g) { return g.basis64; }
+template <> inline const float* basis_ptr<float>(const GeomHost& g) { return g.basis32; }
 
 template <typename T> EqParams<T> make_eq(const GeomHost& g) {
     EqParams<T> p;
@@ -66,6 +59,7 @@ template <typename T> OpArgs<T> make_args(const GeomHost& g, const LaunchReq& r)
     }
     a.out[0] = (T*)r.out[0];
     a.out[1] = (T*)r.out[1];
+    a.basis = basis_ptr<T>(g);
     a.c0 = (T)r.c0;
     a.c1 = (T)r.c1;
     a.col = r.col;
@@ -86,8 +80,8 @@ hipError_t launch_op(const GeomHost& g, const LaunchReq& r) {
     OpArgs<T> a = make_args<T>(g, r);
     int grid = (a.e_end - a.e_begin + EPB - 1) / EPB;
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL((dg_op_kernel<D, NP, EQ, OP, T>), dim3(grid), dim3(EPB * NN), 0, r.stream,
-                       a, make_basis<T, NP>(g), make_eq<T>(g));
+    dim3 gd(grid, r.op == OPK_KCOL ? EQ::NV * NN : 1);   // KCOL: one grid row per column of K
+    hipLaunchKernelGGL((dg_op_kernel<D, NP, EQ, OP, T>), gd, dim3(EPB * NN), 0, r.stream, a, make_eq<T>(g));
     return hipGetLastError();
 }
 
@@ -100,7 +94,7 @@ template <int D, int NP, class EQ, typename T> hipError_t launch_family_np(const
         int grid = (g.nE + EPB - 1) / EPB;
         if (grid == 0) return hipSuccess;
         hipLaunchKernelGGL((trace_kernel<D, NP, NV, T>), dim3(grid), dim3(EPB * NN), 0, r.stream,
-                           (const T*)r.fld[0], (T*)r.out[0], g.nE, make_basis<T, NP>(g));
+                           (const T*)r.fld[0], (T*)r.out[0], g.nE, basis_ptr<T>(g));
         return hipGetLastError();
     }
     case OPK_R1: return launch_op<D, NP, EQ, OpR1<T>, T>(g, r);
@@ -110,6 +104,15 @@ template <int D, int NP, class EQ, typename T> hipError_t launch_family_np(const
     case OPK_JVP_NOHESS: return launch_op<D, NP, EQ, OpJvp<T, false>, T>(g, r);
     case OPK_KCOL: return launch_op<D, NP, EQ, OpKcol<T, NV * NN>, T>(g, r);
     case OPK_PCPRE: return launch_op<D, NP, EQ, OpPcPre<T>, T>(g, r);
+    case OPK_LIFT: {
+        if (!EQ::VISC) return hipErrorInvalidValue;
+        constexpr int EPB = 256 / NN > 0 ? 256 / NN : 1;
+        int grid = (g.nE + EPB - 1) / EPB;
+        if (grid == 0) return hipSuccess;
+        hipLaunchKernelGGL((lift_trace_kernel<D, NP, T>), dim3(grid), dim3(EPB * NN), 0, r.stream,
+                           (const T*)r.fld[0], (const T*)r.trc[0], (T*)r.out[0], make_args<T>(g, r));
+        return hipGetLastError();
+    }
     default: return hipErrorInvalidValue;
     }
 }

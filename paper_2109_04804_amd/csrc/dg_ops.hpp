@@ -25,10 +25,12 @@
 
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
-template <typename T, int NP> struct Basis {
-    T Dhat[NP][NP];
-    T lp[NP], lm[NP];     // l_i(+1), l_i(-1)
-    T lhp[NP], lhm[NP];   // l_i(+-1) / omega_i
+// 1-D operators in device memory, copied to LDS by every block:
+//   Dhat[NP*NP] (Dhat[i*NP+lam]), lp[NP] = l_i(+1), lm[NP] = l_i(-1),
+//   lhp[NP] = l_i(+1)/omega_i, lhm[NP] = l_i(-1)/omega_i
+template <int NP> constexpr int basis_len() { return NP * NP + 4 * NP; }
+template <int NP> struct BOff {
+    static constexpr int D = 0, LP = NP * NP, LM = LP + NP, LHP = LM + NP, LHM = LHP + NP;
 };
 
 template <typename T> struct OpArgs {
@@ -37,6 +39,7 @@ template <typename T> struct OpArgs {
     const T* q[4][3];     // BR1: lifted gradient of jet field j, direction m
     const T* qtr[4];      // BR1: traces of q (face 2m+s holds q_m)
     T* out[2];
+    const T* basis;       // 1-D operators (layout above)
     T c0, c1;             // a1dt, bcoef
     int col;              // KCOL: local column
     int nE;               // elements in the mesh (neighbour indexing)
@@ -127,17 +130,17 @@ template <typename T, bool HESS> struct OpJvp {   // fld: w, sigma, dw, dsigma
     }
 };
 
-template <typename T, int NE> struct OpKcol {   // fld: w; writes K^T[e][col][row] (column-major K)
+template <typename T, int NE> struct OpKcol {   // fld: w; column = blockIdx.y; writes K^T[e][col][row]
     using S = Dual<T>;
     static constexpr int NJ = 2, NC = 1;
     static constexpr bool LOCAL = true;
     HD static T load(const OpArgs<T>& a, int j, size_t g, int loc) {
-        return j == 0 ? a.fld[0][g] : (loc == a.col ? T(1) : T(0));
+        return j == 0 ? a.fld[0][g] : (loc == (int)blockIdx.y ? T(1) : T(0));
     }
     HD static S make(const T* x, const OpArgs<T>& a) { return {x[0], x[1]}; }
     HD static void combo(const S& f, T* c, const OpArgs<T>& a) { c[0] = f.b; }
     HD static void output(const OpArgs<T>& a, size_t g, int e, int loc, const T* gv) {
-        a.out[0][((size_t)(e - a.e_begin) * NE + a.col) * NE + loc] = gv[0];
+        a.out[0][((size_t)(e - a.e_begin) * NE + blockIdx.y) * NE + loc] = gv[0];
     }
 };
 
@@ -161,7 +164,7 @@ template <typename T> struct OpPcPre {   // fld: w, vw, vs
 // elements per block: as many as fit 256 threads and ~64 KB of LDS
 template <int D, int NP, int NV, int NJ, int NC, typename T> constexpr int op_epb() {
     constexpr int NN = ipow(NP, D), NFP = ipow(NP, D - 1);
-    constexpr int bytes = (NJ * NV * NN + NC * D * NV * NN + NC * 2 * D * NV * NFP) * (int)sizeof(T);
+    constexpr int bytes = (NJ * NV * NN + NC * D * NV * NN + NC * 2 * D * NV * NFP) * (int)sizeof(T) + 64;
     constexpr int by_lds = 65536 / bytes;
     constexpr int by_thr = 256 / NN;
     constexpr int e = by_lds < by_thr ? by_lds : by_thr;
@@ -171,16 +174,18 @@ template <int D, int NP, int NV, int NJ, int NC, typename T> constexpr int op_ep
 // ----------------------------------------------------------------- trace kernel
 template <int D, int NP, int NV, typename T>
 __global__ void __launch_bounds__(256) trace_kernel(const T* __restrict__ x, T* __restrict__ tr, int nE,
-                                                     Basis<T, NP> bs) {
+                                                     const T* __restrict__ basis) {
     constexpr int NN = ipow(NP, D), NFP = ipow(NP, D - 1);
     constexpr int EPB = 256 / NN > 0 ? 256 / NN : 1;
     constexpr int NT = EPB * NN;
     constexpr int PER_E = 2 * D * NV * NFP;
     __shared__ T s[EPB * NV * NN];
+    __shared__ T s_l[2][NP];      // l(-1), l(+1)
     const int tid = threadIdx.x;
     const int e0 = blockIdx.x * EPB;
     const int nloc = min(EPB, nE - e0);
     const size_t base = (size_t)e0 * NV * NN;
+    if (tid < 2 * NP) s_l[tid / NP][tid % NP] = basis[(tid < NP ? BOff<NP>::LM : BOff<NP>::LP) + tid % NP];
     for (int i = tid; i < nloc * NV * NN; i += NT) s[i] = x[base + i];
     __syncthreads();
     for (int i = tid; i < nloc * PER_E; i += NT) {
@@ -188,7 +193,7 @@ __global__ void __launch_bounds__(256) trace_kernel(const T* __restrict__ x, T* 
         int face = r / (NV * NFP), r2 = r % (NV * NFP);
         int v = r2 / NFP, fp = r2 % NFP;
         int m = face >> 1;
-        const T* l = (face & 1) ? bs.lp : bs.lm;
+        const T* l = s_l[face & 1];
         const T* src = s + (el * NV + v) * NN;
         T acc = T(0);
 #pragma unroll
@@ -197,9 +202,126 @@ __global__ void __launch_bounds__(256) trace_kernel(const T* __restrict__ x, T* 
     }
 }
 
+// ----------------------------------------------------------------- BR1 lift traces
+// Traces of the BR1-lifted gradient of a scalar field u (NV = 1):
+//   q_m = (2/h_m)[Dhat u + lhat(+1) u*_+ - lhat(-1) u*_-], u* = (u_own + u_nbr)/2,
+// qtr[e][2m+side][fp] = sum_i l_i(+-1) q_m(line through fp).  Faces of other
+// directions are not written (never read).
+template <int D, int NP, typename T>
+__global__ void __launch_bounds__(256) lift_trace_kernel(const T* __restrict__ u, const T* __restrict__ tru,
+                                                          T* __restrict__ qtr, OpArgs<T> a) {
+    constexpr int NN = ipow(NP, D), NFP = ipow(NP, D - 1);
+    constexpr int EPB = 256 / NN > 0 ? 256 / NN : 1;
+    constexpr int NT = EPB * NN;
+    __shared__ T s_u[EPB][NN];
+    __shared__ T s_us[EPB][2 * D][NFP];
+    __shared__ T s_q[D][EPB][NN];
+    __shared__ T s_b[basis_len<NP>()];
+    const int tid = threadIdx.x;
+    const int e0 = blockIdx.x * EPB;
+    const int nloc = min(EPB, a.nE - e0);
+    for (int i = tid; i < basis_len<NP>(); i += NT) s_b[i] = a.basis[i];
+    for (int i = tid; i < nloc * NN; i += NT) (&s_u[0][0])[i] = u[(size_t)e0 * NN + i];
+    __syncthreads();
+    for (int i = tid; i < nloc * 2 * D * NFP; i += NT) {
+        const int fel = i / (2 * D * NFP), r = i % (2 * D * NFP);
+        const int face = r / NFP, fp = r % NFP;
+        const int m = face >> 1, side = face & 1;
+        const T* l = s_b + (side ? BOff<NP>::LP : BOff<NP>::LM);
+        T own = T(0);
+        for (int q = 0; q < NP; ++q) own += l[q] * s_u[fel][node_on_line<D, NP>(fp, m, q)];
+        const int enb = nbr_elem<D>(e0 + fel, m, side ? 1 : -1, a.nel);
+        s_us[fel][face][fp] = T(0.5) * (own + tru[((size_t)enb * 2 * D + (2 * m + 1 - side)) * NFP + fp]);
+    }
+    __syncthreads();
+    const int el = tid / NN, node = tid % NN;
+    if (el < nloc) {
+        const int id3[3] = {node % NP, (node / NP) % NP, node / (NP * NP)};
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+            const int im = id3[m];
+            const int stride = m == 0 ? 1 : (m == 1 ? NP : NP * NP);
+            const int b0 = node - im * stride;
+            const T* Drow = s_b + BOff<NP>::D + im * NP;
+            T sv = T(0);
+            for (int q = 0; q < NP; ++q) sv += Drow[q] * s_u[el][b0 + q * stride];
+            const int fpm = fp_of_node<D, NP>(node, m);
+            sv += s_b[BOff<NP>::LHP + im] * s_us[el][2 * m + 1][fpm] - s_b[BOff<NP>::LHM + im] * s_us[el][2 * m][fpm];
+            s_q[m][el][node] = a.two_h[m] * sv;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < nloc * 2 * D * NFP; i += NT) {
+        const int fel = i / (2 * D * NFP), r = i % (2 * D * NFP);
+        const int face = r / NFP, fp = r % NFP;
+        const int m = face >> 1, side = face & 1;
+        const T* l = s_b + (side ? BOff<NP>::LP : BOff<NP>::LM);
+        T acc = T(0);
+        for (int q = 0; q < NP; ++q) acc += l[q] * s_q[m][fel][node_on_line<D, NP>(fp, m, q)];
+        qtr[((size_t)(e0 + fel) * 2 * D + face) * NFP + fp] = acc;
+    }
+}
+
 // ----------------------------------------------------------------- operator kernel
+// numerical flux at one face point; face = 2m + side is a compile-time constant
+// so that the state components indexed by m stay in registers
+template <int D, int NP, int FACE, class EQ, class OP, typename T, int EPB, int NN, int NFP>
+__device__ __forceinline__ void face_point(const OpArgs<T>& a, const EqParams<T>& ep, const T* s_b,
+                                           T (*s_fld)[EPB][EQ::NV][NN], T (*s_fs)[EPB][2 * D][EQ::NV][NFP],
+                                           const T* s_q, int fel, int fe, int fp) {
+    constexpr int NV = EQ::NV, NJ = OP::NJ, NC = OP::NC;
+    constexpr int M = FACE >> 1, SIDE = FACE & 1;
+    using S = typename OP::S;
+    const T* l = s_b + (SIDE ? BOff<NP>::LP : BOff<NP>::LM);
+    S own[NV], nb[NV];
+    const int enb = nbr_elem<D>(fe, M, SIDE ? 1 : -1, a.nel);
+    const size_t nbase = ((size_t)enb * 2 * D + (2 * M + 1 - SIDE)) * NV * NFP + fp;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        T x[NJ], y[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            T acc = T(0);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) acc += l[q] * s_fld[j][fel][v][node_on_line<D, NP>(fp, M, q)];
+            x[j] = acc;
+            const T* t = (OP::LOCAL && j > 0) ? nullptr : a.trc[j];
+            y[j] = t ? t[nbase + (size_t)v * NFP] : T(0);
+        }
+        own[v] = OP::make(x, a);
+        nb[v] = OP::make(y, a);
+    }
+    S f[NV];
+    if (SIDE) numerical_flux<EQ>(own, nb, M, f, ep);
+    else numerical_flux<EQ>(nb, own, M, f, ep);
+    if constexpr (EQ::VISC) {
+        // BR1 viscous surface flux -nu (q_L + q_R)/2 of the lifted gradient q_M
+        // (s_q[j][m][el][node], NV = 1); neighbour traces of q from a.qtr
+        T x[NJ], y[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const T* qj = s_q + ((j * D + M) * EPB + fel) * NN;
+            T acc = T(0);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) acc += l[q] * qj[node_on_line<D, NP>(fp, M, q)];
+            x[j] = acc;
+            const T* t = (OP::LOCAL && j > 0) ? nullptr : a.qtr[j];
+            y[j] = t ? t[((size_t)enb * 2 * D + (2 * M + 1 - SIDE)) * NFP + fp] : T(0);
+        }
+        S qo = OP::make(x, a), qn = OP::make(y, a);
+        f[0] = f[0] - (qo + qn) * (T(0.5) * ep.nu);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        T c[NC];
+        OP::combo(f[v], c, a);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) s_fs[k][fel][FACE][v][fp] = c[k];
+    }
+}
+
 template <int D, int NP, class EQ, class OP, typename T>
-__global__ void __launch_bounds__(256) dg_op_kernel(OpArgs<T> a, Basis<T, NP> bs, EqParams<T> ep) {
+__global__ void __launch_bounds__(256) dg_op_kernel(OpArgs<T> a, EqParams<T> ep) {
     constexpr int NN = ipow(NP, D), NFP = ipow(NP, D - 1);
     constexpr int NV = EQ::NV, NJ = OP::NJ, NC = OP::NC;
     constexpr int EPB = op_epb<D, NP, NV, NJ, NC, T>();
@@ -209,23 +331,67 @@ __global__ void __launch_bounds__(256) dg_op_kernel(OpArgs<T> a, Basis<T, NP> bs
     __shared__ T s_fld[NJ][EPB][NV][NN];
     __shared__ T s_flx[NC][D][EPB][NV][NN];
     __shared__ T s_fs[NC][EPB][2 * D][NV][NFP];
+    __shared__ T s_b[basis_len<NP>()];
+    constexpr int NQ = EQ::VISC ? NJ : 0;                 // BR1: lifted gradients of the jet fields
+    __shared__ T s_q[NQ > 0 ? NQ * D * EPB * NN : 1];     // [j][m][el][node]
+    __shared__ T s_us[NQ > 0 ? NQ * EPB * 2 * D * NFP : 1];   // u* = (u_own + u_nbr)/2 at face points
 
     const int tid = threadIdx.x;
     const int e0 = a.e_begin + blockIdx.x * EPB;
     const int nloc = min(EPB, a.e_end - e0);
 
-    // 1) stage the jet fields of EPB consecutive elements (contiguous in memory)
+    // 1) stage the 1-D operators and the jet fields of EPB consecutive elements
+    for (int i = tid; i < basis_len<NP>(); i += NT) s_b[i] = a.basis[i];
     for (int i = tid; i < nloc * NV * NN; i += NT) {
-        int el = i / (NV * NN), loc = i % (NV * NN);
+        int loc = i % (NV * NN);
         size_t g = (size_t)e0 * NV * NN + i;
 #pragma unroll
         for (int j = 0; j < NJ; ++j) (&s_fld[j][0][0][0])[i] = OP::load(a, j, g, loc);
-        (void)el;
     }
     __syncthreads();
 
     const int el = tid / NN, node = tid % NN;
     const bool valid = el < nloc;
+
+    if constexpr (EQ::VISC) {
+        // 1b) BR1 lifting q_m = (2/h_m)[Dhat u + lhat(+1) u*_+ - lhat(-1) u*_-], u* central
+        for (int i = tid; i < nloc * 2 * D * NFP; i += NT) {
+            const int fel = i / (2 * D * NFP), r = i % (2 * D * NFP);
+            const int face = r / NFP, fp = r % NFP;
+            const int m = face >> 1, side = face & 1;
+            const T* l = s_b + (side ? BOff<NP>::LP : BOff<NP>::LM);
+            const int enb = nbr_elem<D>(e0 + fel, m, side ? 1 : -1, a.nel);
+            const size_t nb = ((size_t)enb * 2 * D + (2 * m + 1 - side)) * NFP + fp;
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                T own = T(0);
+                for (int q = 0; q < NP; ++q) own += l[q] * s_fld[j][fel][0][node_on_line<D, NP>(fp, m, q)];
+                const T* t = (OP::LOCAL && j > 0) ? nullptr : a.trc[j];
+                const T nbv = t ? t[nb] : T(0);
+                s_us[((j * EPB + fel) * 2 * D + face) * NFP + fp] = T(0.5) * (own + nbv);
+            }
+        }
+        __syncthreads();
+        if (valid) {
+            const int id3[3] = {node % NP, (node / NP) % NP, node / (NP * NP)};
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                for (int m = 0; m < D; ++m) {
+                    const int im = id3[m];
+                    const int stride = m == 0 ? 1 : (m == 1 ? NP : NP * NP);
+                    const int b0 = node - im * stride;
+                    const T* Drow = s_b + BOff<NP>::D + im * NP;
+                    T sv = T(0);
+                    for (int q = 0; q < NP; ++q) sv += Drow[q] * s_fld[j][el][0][b0 + q * stride];
+                    const int fpm = fp_of_node<D, NP>(node, m);
+                    const T* us = s_us + ((j * EPB + el) * 2 * D + 2 * m) * NFP;
+                    sv += s_b[BOff<NP>::LHP + im] * us[NFP + fpm] - s_b[BOff<NP>::LHM + im] * us[fpm];
+                    s_q[((j * D + m) * EPB + el) * NN + node] = a.two_h[m] * sv;
+                }
+        }
+        __syncthreads();
+    }
 
     // 2) jet-valued volume fluxes at this node
     if (valid) {
@@ -239,6 +405,15 @@ __global__ void __launch_bounds__(256) dg_op_kernel(OpArgs<T> a, Basis<T, NP> bs
         }
         S F[D][NV];
         EQ::flux_all(wn, F, ep);
+        if constexpr (EQ::VISC) {
+#pragma unroll
+            for (int m = 0; m < D; ++m) {
+                T x[NJ];
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) x[j] = s_q[((j * D + m) * EPB + el) * NN + node];
+                F[m][0] = F[m][0] - OP::make(x, a) * ep.nu;
+            }
+        }
 #pragma unroll
         for (int m = 0; m < D; ++m)
 #pragma unroll
@@ -252,45 +427,31 @@ __global__ void __launch_bounds__(256) dg_op_kernel(OpArgs<T> a, Basis<T, NP> bs
 
     // 3) numerical fluxes at the face points (own trace from LDS, neighbour trace from HBM)
     for (int i = tid; i < nloc * 2 * D * NFP; i += NT) {
-        int fel = i / (2 * D * NFP), r = i % (2 * D * NFP);
-        int face = r / NFP, fp = r % NFP;
-        int m = face >> 1, side = face & 1;
-        int fe = e0 + fel;
-        const T* l = side ? bs.lp : bs.lm;
-        S own[NV], nb[NV];
-        int enb = nbr_elem<D>(fe, m, side ? 1 : -1, a.nel);
-        size_t nbase = ((size_t)enb * 2 * D + (2 * m + 1 - side)) * NV * NFP + fp;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            T x[NJ], y[NJ];
-#pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-                T acc = T(0);
-#pragma unroll
-                for (int q = 0; q < NP; ++q) acc += l[q] * s_fld[j][fel][v][node_on_line<D, NP>(fp, m, q)];
-                x[j] = acc;
-                const T* t = (OP::LOCAL && j > 0) ? nullptr : a.trc[j];
-                y[j] = t ? t[nbase + (size_t)v * NFP] : T(0);
-            }
-            own[v] = OP::make(x, a);
-            nb[v] = OP::make(y, a);
-        }
-        S f[NV];
-        if (side) numerical_flux<EQ>(own, nb, m, f, ep);
-        else numerical_flux<EQ>(nb, own, m, f, ep);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            T c[NC];
-            OP::combo(f[v], c, a);
-#pragma unroll
-            for (int k = 0; k < NC; ++k) s_fs[k][fel][face][v][fp] = c[k];
+        const int fel = i / (2 * D * NFP), r = i % (2 * D * NFP);
+        const int face = r / NFP, fp = r % NFP;
+        const int fe = e0 + fel;
+        switch (face) {
+        case 0: face_point<D, NP, 0, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, fel, fe, fp); break;
+        case 1: face_point<D, NP, 1, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, fel, fe, fp); break;
+        case 2:
+            if (D > 1) face_point<D, NP, 2 % (2 * D), EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, fel, fe, fp);
+            break;
+        case 3:
+            if (D > 1) face_point<D, NP, 3 % (2 * D), EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, fel, fe, fp);
+            break;
+        case 4:
+            if (D > 2) face_point<D, NP, 4 % (2 * D), EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, fel, fe, fp);
+            break;
+        default:
+            if (D > 2) face_point<D, NP, 5 % (2 * D), EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, fel, fe, fp);
+            break;
         }
     }
     __syncthreads();
     if (!valid) return;
 
     // 4) volume sweep + surface lifting, DG[.] per combination and variable
-    int idx[3] = {node % NP, (node / NP) % NP, node / (NP * NP)};
+    const int idx[3] = {node % NP, (node / NP) % NP, node / (NP * NP)};
     T gv[NC];
     const int e = e0 + el;
 #pragma unroll
@@ -303,11 +464,13 @@ __global__ void __launch_bounds__(256) dg_op_kernel(OpArgs<T> a, Basis<T, NP> bs
                 const int im = idx[m];
                 const int stride = m == 0 ? 1 : (m == 1 ? NP : NP * NP);
                 const int b0 = node - im * stride;
+                const T* Drow = s_b + BOff<NP>::D + im * NP;
                 T s = T(0);
 #pragma unroll
-                for (int q = 0; q < NP; ++q) s += bs.Dhat[im][q] * s_flx[k][m][el][v][b0 + q * stride];
+                for (int q = 0; q < NP; ++q) s += Drow[q] * s_flx[k][m][el][v][b0 + q * stride];
                 const int fp = fp_of_node<D, NP>(node, m);
-                s += bs.lhp[im] * s_fs[k][el][2 * m + 1][v][fp] - bs.lhm[im] * s_fs[k][el][2 * m][v][fp];
+                s += s_b[BOff<NP>::LHP + im] * s_fs[k][el][2 * m + 1][v][fp] -
+                     s_b[BOff<NP>::LHM + im] * s_fs[k][el][2 * m][v][fp];
                 acc += a.two_h[m] * s;
             }
             gv[k] = -acc;

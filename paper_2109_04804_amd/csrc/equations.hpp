@@ -38,7 +38,7 @@ template <int D> struct AdvectionEq {
     }
 };
 
-template <int D> struct BurgersEq {   // inviscid part u^2/2 per direction; viscous terms added by the operator
+template <int D> struct BurgersEq {   // inviscid part u^2/2 per direction; the operator adds -nu q (BR1)
     static constexpr int NV = 1;
     static constexpr bool VISC = true;
     template <class S, class T> HD static void flux_dir(const S* w, int m, S* F, const EqParams<T>& p) {

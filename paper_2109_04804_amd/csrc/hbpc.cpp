@@ -103,8 +103,8 @@ double now_ms() {
 }  // namespace
 
 // ------------------------------------------------------------------ kernel timing
-static const char* KC_NAMES[KC_COUNT] = {"trace", "r1", "r2", "res", "jvp", "kcol", "pcpre", "bj_apply",
-                                         "bj_invert", "mdot", "gemv", "vec"};
+static const char* KC_NAMES[KC_COUNT] = {"trace", "r1",       "r2",   "res",  "jvp", "kcol",   "pcpre",
+                                         "bj_apply", "bj_invert", "mdot", "gemv", "vec", "gs_dot", "gs_update"};
 
 static long prof_begin(hbpc_ctx* c) {
     if (!c->prof) return -1;
@@ -166,7 +166,7 @@ int op_launch(hbpc_ctx* c, const LaunchReq& r, int f32) {
     case OPK_RES: cls = KC_RES; bytes = 5 * n * esz; break;
     case OPK_JVP:
     case OPK_JVP_NOHESS: cls = KC_JVP; bytes = 6 * n * esz; break;
-    case OPK_KCOL: cls = KC_KCOL; bytes = 2.0 * (r.e_end - r.e_begin) * c->NE * 8.0; break;
+    case OPK_KCOL: cls = KC_KCOL; bytes = (double)(r.e_end - r.e_begin) * c->NE * (8.0 + c->NE * 8.0); break;
     case OPK_PCPRE: cls = KC_PCPRE; bytes = 5 * n * esz; break;
     }
     long pi = prof_begin(c);
@@ -183,12 +183,24 @@ static void op_trace(hbpc_ctx* c, const void* x, void* tr, int f32) {
     op_launch(c, r, f32);
 }
 
+// BR1: traces of the lifted gradient of field x (needs the traces of x) into slot `slot`
+static const void* op_lift(hbpc_ctx* c, const void* x, const void* trx, int slot, int f32) {
+    if (!c->visc) return nullptr;
+    LaunchReq r = op_req(c, OPK_LIFT);
+    r.fld[0] = x;
+    r.trc[0] = trx;
+    r.out[0] = c->qtr[f32][slot];
+    op_launch(c, r, f32);
+    return c->qtr[f32][slot];
+}
+
 // R1(w) -> out; traces of w written to trw (FP64)
 static void op_r1(hbpc_ctx* c, const double* w, double* out, double* trw) {
     op_trace(c, w, trw, 0);
     LaunchReq r = op_req(c, OPK_R1);
     r.fld[0] = w;
     r.trc[0] = trw;
+    r.qtr[0] = op_lift(c, w, trw, 0, 0);
     r.out[0] = out;
     op_launch(c, r, 0);
 }
@@ -201,6 +213,8 @@ static void op_r2_tr(hbpc_ctx* c, const double* w, const double* s, const double
     r.fld[1] = s;
     r.trc[0] = trw;
     r.trc[1] = trs;
+    r.qtr[0] = op_lift(c, w, trw, 0, 0);
+    r.qtr[1] = op_lift(c, s, trs, 1, 0);
     r.out[0] = out;
     op_launch(c, r, 0);
 }
@@ -220,6 +234,8 @@ static void op_res(hbpc_ctx* c, const double* X, const double* b, double a1dt, d
     r.fld[2] = b;
     r.trc[0] = c->trw;
     r.trc[1] = c->trs;
+    r.qtr[0] = op_lift(c, X, c->trw, 0, 0);
+    r.qtr[1] = op_lift(c, X + c->ndof, c->trs, 1, 0);
     r.out[0] = G;
     r.out[1] = G + c->ndof;
     r.c0 = a1dt;
@@ -246,6 +262,10 @@ static void op_jvp(hbpc_ctx* c, const void* w, const void* s, const void* trw, c
     r.trc[1] = trs;
     r.trc[2] = t1;
     r.trc[3] = t2;
+    r.qtr[0] = op_lift(c, w, trw, 0, f32);
+    r.qtr[1] = op_lift(c, s, trs, 1, f32);
+    r.qtr[2] = op_lift(c, dx, t1, 2, f32);
+    r.qtr[3] = op_lift(c, dx + c->ndof * esz, t2, 3, f32);
     r.out[0] = y;
     r.out[1] = y + c->ndof * esz;
     r.c0 = a1dt;
@@ -287,12 +307,12 @@ static void pc_build(hbpc_ctx* c, const double* w, double a1dt, double bc, int f
     const size_t esz = f32 ? 4 : 8;
     for (size_t eb = 0; eb < (size_t)c->nE; eb += c->kt_chunk) {
         size_t ee = std::min((size_t)c->nE, eb + c->kt_chunk);
-        for (int col = 0; col < c->NE; ++col) {
-            LaunchReq r = op_req(c, OPK_KCOL);
+        {
+            LaunchReq r = op_req(c, OPK_KCOL);   // all NE columns of K in one launch
             r.fld[0] = w;
             r.trc[0] = c->trw;
+            r.qtr[0] = op_lift(c, w, c->trw, 0, 0);
             r.out[0] = c->KT;
-            r.col = col;
             r.e_begin = (int)eb;
             r.e_end = (int)ee;
             op_launch(c, r, 0);
@@ -321,6 +341,7 @@ static void pc_apply(hbpc_ctx* c, const void* w, const void* trw, const void* X,
     r.fld[1] = X;
     r.fld[2] = (const char*)X + c->ndof * esz;
     r.trc[0] = trw;
+    r.qtr[0] = op_lift(c, w, trw, 0, f32);
     r.out[0] = kv;
     r.out[1] = kv + c->ndof * esz;
     r.c0 = c->pc_a1dt;
@@ -435,30 +456,40 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
             if (use_pc) pc_apply(c, w, trw, Vj(j), zj, f32);
             void* u = Vj(j + 1);
             jvp(zj, u);
-            // CGS2 against V_0..V_j
+            // classical Gram-Schmidt against V_0..V_j with a second pass when the
+            // first one cancels more than half of ||u||^2 (Daniel-Gragg-Kaufman-Stewart)
             double* h1 = c->dres;
             double* h2 = c->dres + 64;
+            double* nb = c->dres + 130;
             double* hn = c->dres + 128;
             const double vb = (double)n2 * esz;
             long pi = prof_begin(c);
-            hipchk(c, blas_mdot(V, n2, j + 1, u, n2, f32, c->part, h1, c->stream), "mdot");
-            prof_end(c, pi, KC_MDOT, (j + 2) * vb);
+            hipchk(c, blas_mdot(V, n2, j + 1, u, n2, f32, c->part, h1, c->stream), "gs dot");
+            prof_end(c, pi, KC_GSDOT, (j + 2) * vb);
             pi = prof_begin(c);
-            hipchk(c, blas_gemv_sub(V, n2, j + 1, h1, u, n2, f32, c->stream), "gemv");
-            prof_end(c, pi, KC_GEMV, (j + 3) * vb);
-            pi = prof_begin(c);
-            hipchk(c, blas_mdot(V, n2, j + 1, u, n2, f32, c->part, h2, c->stream), "mdot");
-            prof_end(c, pi, KC_MDOT, (j + 2) * vb);
-            pi = prof_begin(c);
-            hipchk(c, blas_gemv_sub(V, n2, j + 1, h2, u, n2, f32, c->stream), "gemv");
-            prof_end(c, pi, KC_GEMV, (j + 3) * vb);
-            pi = prof_begin(c);
-            hipchk(c, blas_mdot(u, 0, 1, u, n2, f32, c->part, hn, c->stream), "norm");
+            hipchk(c, blas_mdot(u, 0, 1, u, n2, f32, c->part, nb, c->stream), "norm");
             prof_end(c, pi, KC_MDOT, vb);
-            hipchk(c, hipMemcpyAsync(c->hres, c->dres, 129 * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+            pi = prof_begin(c);
+            hipchk(c, blas_gemv_sub_norm(V, n2, j + 1, h1, u, n2, f32, c->part, hn, c->stream), "gs update");
+            prof_end(c, pi, KC_GSUPD, (j + 3) * vb);
+            hipchk(c, hipMemcpyAsync(c->hres, c->dres, 131 * sizeof(double), hipMemcpyDeviceToHost, c->stream),
                    "copy");
             hipchk(c, hipStreamSynchronize(c->stream), "sync");
-            for (int i = 0; i <= j; ++i) Hc(i, j) = c->hres[i] + c->hres[64 + i];
+            for (int i = 0; i <= j; ++i) Hc(i, j) = c->hres[i];
+            if (c->hres[128] < 0.5 * c->hres[130]) {
+                pi = prof_begin(c);
+                hipchk(c, blas_mdot(V, n2, j + 1, u, n2, f32, c->part, h2, c->stream), "gs dot");
+                prof_end(c, pi, KC_GSDOT, (j + 2) * vb);
+                pi = prof_begin(c);
+                hipchk(c, blas_gemv_sub_norm(V, n2, j + 1, h2, u, n2, f32, c->part, hn, c->stream), "gs update");
+                prof_end(c, pi, KC_GSUPD, (j + 3) * vb);
+                hipchk(c, hipMemcpyAsync(c->hres + 64, c->dres + 64, 65 * sizeof(double), hipMemcpyDeviceToHost,
+                                         c->stream),
+                       "copy");
+                hipchk(c, hipStreamSynchronize(c->stream), "sync");
+                for (int i = 0; i <= j; ++i) Hc(i, j) += c->hres[64 + i];
+                c->st_reorth++;
+            }
             double hnrm = std::sqrt(c->hres[128]);
             Hc(j + 1, j) = hnrm;
             if (!std::isfinite(hnrm)) set_err(c, HBPC_ERR_NONFINITE, "non-finite Arnoldi vector");
@@ -620,9 +651,13 @@ static void ctx_free(hbpc_ctx* c) {
     }
     void* bufs[] = {c->R1all, c->R2all, c->X, c->b, c->G, c->dX, c->rhs, c->trw, c->trs, c->trd1, c->trd2,
                     c->X32, c->trw32, c->trs32, c->trd1_32, c->trd2_32, c->V, c->Z, c->kv, c->KT, c->Sinv,
-                    c->part, c->dres, c->dstatus};
+                    c->part, c->dres, c->dstatus, c->basis64, c->basis32};
     for (void* p : bufs) dfree(p);
     for (int i = 0; i < 6; ++i) dfree(c->fd[i]);
+    for (int j = 0; j < 4; ++j) {
+        dfree(c->qtr[0][j]);
+        dfree(c->qtr[1][j]);
+    }
     if (c->hres) (void)hipHostFree(c->hres);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
@@ -649,7 +684,10 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
         c->NV = c->D + 2;
         c->launch = dg_launch_euler;
     } else if (equation == HBPC_EQ_BURGERS_BR1) {
-        set_err(c, HBPC_ERR_UNSUPPORTED, "viscous Burgers is not compiled in this build");
+        if (c->D > 2) set_err(c, HBPC_ERR_UNSUPPORTED, "viscous Burgers is compiled for dim 1 and 2");
+        c->NV = 1;
+        c->visc = 1;
+        c->launch = dg_launch_burgers;
     } else {
         set_err(c, HBPC_ERR_ARG, "unknown equation");
     }
@@ -658,6 +696,7 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
         set_err(c, HBPC_ERR_ARG, "Rusanov flux needs the Euler equations");
     if (prm->flux == HBPC_FLUX_UPWIND && equation != HBPC_EQ_ADVECTION)
         set_err(c, HBPC_ERR_ARG, "upwind flux needs advection");
+    if (equation == HBPC_EQ_BURGERS_BR1 && !(prm->nu >= 0)) set_err(c, HBPC_ERR_ARG, "nu must be >= 0");
     if (prm->gmres_restart < 1 || prm->gmres_restart > 64) set_err(c, HBPC_ERR_ARG, "gmres_restart must be 1..64");
     if (prm->q != 4 && prm->q != 6 && prm->q != 8) set_err(c, HBPC_ERR_ARG, "q must be 4, 6 or 8");
     if (prm->kmax < 0) set_err(c, HBPC_ERR_ARG, "kmax must be >= 0");
@@ -686,13 +725,6 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
         g.two_h[m] = m < c->D ? 2.0 * mesh->nelem[m] / mesh->length[m] : 0.0;
         g.adv[m] = prm->adv[m];
     }
-    for (int i = 0; i < c->NP; ++i) {
-        for (int j = 0; j < c->NP; ++j) g.Dhat[i][j] = c->basis.Dhat[i * c->NP + j];
-        g.lp[i] = c->basis.lp[i];
-        g.lm[i] = c->basis.lm[i];
-        g.lhp[i] = c->basis.lhp[i];
-        g.lhm[i] = c->basis.lhm[i];
-    }
     g.lam = prm->lambda;
     g.nu = prm->nu;
     g.gamma = equation == HBPC_EQ_EULER ? prm->gamma : 1.4;
@@ -700,6 +732,23 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
     g.flux = prm->flux;
 
     const size_t n = c->ndof;
+    {   // 1-D operators: Dhat, l(+1), l(-1), lhat(+1), lhat(-1)
+        const int NP = c->NP;
+        std::vector<double> hb;
+        hb.insert(hb.end(), c->basis.Dhat.begin(), c->basis.Dhat.end());
+        hb.insert(hb.end(), c->basis.lp.begin(), c->basis.lp.end());
+        hb.insert(hb.end(), c->basis.lm.begin(), c->basis.lm.end());
+        hb.insert(hb.end(), c->basis.lhp.begin(), c->basis.lhp.end());
+        hb.insert(hb.end(), c->basis.lhm.begin(), c->basis.lhm.end());
+        std::vector<float> hf(hb.begin(), hb.end());
+        c->basis64 = dalloc<double>(c, hb.size());
+        c->basis32 = dalloc<float>(c, hf.size());
+        hipchk(c, hipMemcpy(c->basis64, hb.data(), hb.size() * 8, hipMemcpyHostToDevice), "copy basis");
+        hipchk(c, hipMemcpy(c->basis32, hf.data(), hf.size() * 4, hipMemcpyHostToDevice), "copy basis");
+        g.basis64 = c->basis64;
+        g.basis32 = c->basis32;
+        (void)NP;
+    }
     for (int i = 0; i < 4; ++i) {
         c->W[i] = dalloc<double>(c, n);
         c->Wn[i] = dalloc<double>(c, n);
@@ -721,6 +770,11 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
     c->trs32 = dalloc<float>(c, c->tsz);
     c->trd1_32 = dalloc<float>(c, c->tsz);
     c->trd2_32 = dalloc<float>(c, c->tsz);
+    if (c->visc)
+        for (int j = 0; j < 4; ++j) {
+            c->qtr[0][j] = dalloc<double>(c, c->tsz);
+            c->qtr[1][j] = dalloc<float>(c, c->tsz);
+        }
     c->m_alloc = prm->gmres_restart;
     c->kr_f32 = prm->precision == HBPC_MIXED;
     size_t ksz = c->kr_f32 ? 4 : 8;
@@ -853,6 +907,8 @@ int hbpc_newton_residual(hbpc_ctx* c, const double* w, const double* sigma, cons
         r.fld[2] = b;
         r.trc[0] = c->trw;
         r.trc[1] = c->trs;
+        r.qtr[0] = op_lift(c, w, c->trw, 0, 0);
+        r.qtr[1] = op_lift(c, sigma, c->trs, 1, 0);
         r.out[0] = G;
         r.out[1] = G + c->ndof;
         r.c0 = a1dt;

@@ -18,6 +18,8 @@ hipError_t bj_apply(const void* SinvT, int m_f32, const void* xa, const void* xc
 int blas_mdot_grid(size_t n);
 hipError_t blas_mdot(const void* V, size_t ld, int k, const void* w, size_t n, int f32, double* part, double* h,
                      hipStream_t st);
+hipError_t blas_gemv_sub_norm(const void* V, size_t ld, int k, const double* h, void* u, size_t n, int f32,
+                              double* part, double* nrm2, hipStream_t st);
 hipError_t blas_gemv_sub(const void* V, size_t ld, int k, const double* h, void* w, size_t n, int f32,
                          hipStream_t st);
 hipError_t blas_axpby(double a, const void* x, int tx, double b, void* y, int ty, size_t n, hipStream_t st);
@@ -46,6 +48,8 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+constexpr int KC_MAXCLS = 16;
+
 struct hbpc_ctx {
     hbpc_mesh mesh;
     hbpc_params prm;
@@ -69,6 +73,9 @@ struct hbpc_ctx {
     double* rhs;              // 2 ndof
     double* tmp[4];           // ndof scratch
     double* trw; double* trs; double* trd1; double* trd2;   // FP64 traces
+    double* basis64; float* basis32;                         // 1-D operators on the device
+    int visc;                                                // BR1 viscous terms (Burgers)
+    void* qtr[2][4];                                         // BR1 lifted-gradient traces [f32][field]
     // FP32 snapshots
     float* X32;               // 2 ndof
     float* trw32; float* trs32; float* trd1_32; float* trd2_32;
@@ -94,18 +101,19 @@ struct hbpc_ctx {
     hbpc_stats st;
     int cur_solve;
     int verbose;              // HBPC_VERBOSE=1: Newton progress on stderr
+    long st_reorth;           // Gram-Schmidt second passes taken
     // kernel timing
     int prof;
     std::vector<hipEvent_t> ev;          // pairs (start, stop)
     std::vector<int> ev_class;
     std::vector<double> ev_bytes, ev_flops;
     size_t ev_used;
-    int kp_launch[16];
-    double kp_ms[16], kp_bytes[16], kp_flops[16];
+    int kp_launch[KC_MAXCLS];
+    double kp_ms[KC_MAXCLS], kp_bytes[KC_MAXCLS], kp_flops[KC_MAXCLS];
 };
 
 enum { KC_TRACE = 0, KC_R1, KC_R2, KC_RES, KC_JVP, KC_KCOL, KC_PCPRE, KC_BJAPPLY, KC_BJINV, KC_MDOT, KC_GEMV,
-       KC_VEC, KC_COUNT };
+       KC_VEC, KC_GSDOT, KC_GSUPD, KC_COUNT };
 
 // helpers implemented in ops.cpp
 int op_launch(hbpc_ctx* c, const LaunchReq& r, int f32);

@@ -29,6 +29,11 @@ CASES = {
     # 3-D eps-scaled Euler (eps = 0.1), N = 3 as in the Taylor-Green workload
     "euler3_n3": dict(dim=3, nelem=[3, 4, 5], length=[TWO_PI] * 3, N=3, equation="euler", nodes="gauss",
                       flux="rusanov", eps_ref=0.1),
+    # viscous Burgers with BR1 lifting (2-D workload shape N = 4; 1-D on Lobatto nodes)
+    "burgers2": dict(dim=2, nelem=[5, 4], length=[TWO_PI, TWO_PI], N=4, equation="burgers", nodes="gauss",
+                     flux="lf", nu=0.01, **{"lambda": 1.0}),
+    "burgers1_lobatto": dict(dim=1, nelem=[7], length=[TWO_PI], N=3, equation="burgers", nodes="lobatto",
+                             flux="lf", nu=0.05, **{"lambda": 1.0}),
     # degenerate: one element per direction (every neighbour is the element itself)
     "euler2_single": dict(dim=2, nelem=[1, 1], length=[10.0, 10.0], N=5, equation="euler", nodes="gauss",
                           flux="rusanov"),

@@ -69,6 +69,24 @@ def test_euler_vortex_step(precision, rtol, tol):
     assert rel(host(wg), ref) < tol
 
 
+@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-12, 1e-10), ("mixed", 1e-8, 1e-8)])
+def test_burgers_br1_step(precision, rtol, tol):
+    """2-D viscous Burgers (BR1), 8x8 elements, N = 4, LF lambda = 1, nu = 0.01,
+    HBPC(6,2), dt = 0.1, BJ_ext; initial data of the Burgers workload (seed 2109)."""
+    case = dict(CASES["burgers2"])
+    case.update(nelem=[8, 8])
+    dg = oracle_for(case)
+    X = dg.node_coords()
+    w0 = inputs.burgers(X[0], X[1])
+    ctx = ctx_for(case, q=6, kmax=2, newton_rtol=rtol, gmres_rtol=1e-5, precision=precision)
+    sol = StageSolver(dg, newton_rtol=rtol, gmres_rtol=1e-5)
+    wg = dev(w0)
+    stats = ctx.step(wg, 0.1)
+    print(precision, stats, flush=True)
+    ref = dg_hbpc_step(dg, w0, 0.1, 6, 2, sol)
+    assert rel(host(wg), ref) < tol
+
+
 def test_constant_state_is_unchanged():
     case = dict(CASES["euler2_n5"])
     dg = oracle_for(case)
