@@ -32,6 +32,9 @@ WORKLOADS = {
     "euler_vortex_128x128_N5": dict(dim=2, nelem=[128, 128], length=[10.0, 10.0], N=5, dt=0.1),
     # small variant for quick checks
     "euler_vortex_32x32_N5": dict(dim=2, nelem=[32, 32], length=[10.0, 10.0], N=5, dt=0.1),
+    # viscous Burgers with BR1: u0 = 0.5 + 0.25 sin(x+y) + seeded noise, nu = 0.01, LF lambda = 1
+    "burgers_64x64_N4": dict(dim=2, nelem=[64, 64], length=[2 * 3.141592653589793] * 2, N=4, dt=0.1,
+                             equation="burgers"),
 }
 
 
@@ -40,6 +43,8 @@ def vortex_state(ctx, wl):
     from paper_2109_04804_amd import inputs
     xi, _ = ctx.nodes()
     X = inputs.node_coords(2, wl["nelem"], wl["length"], [0.0, 0.0], xi)
+    if wl.get("equation") == "burgers":
+        return inputs.burgers(X[0], X[1], seed=inputs.DEFAULT_SEED)
     xc, yc, beta = inputs.vortex_params(inputs.DEFAULT_SEED, beta=5.0)
     return inputs.isentropic_vortex(X[0], X[1], xc, yc, beta, mach=0.5, gamma=1.4, box=wl["length"][0])
 
@@ -48,9 +53,13 @@ def run_form(wl, precision, steps, warmup):
     import numpy as np
     import torch
     from paper_2109_04804_amd.hbpc import Context
-    ctx = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], "euler", flux="rusanov", gamma=1.4, eps_ref=1.0,
-                  q=6, kmax=4, newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=30, gmres_maxit=7000,
-                  precond="bjext", precision=precision)
+    if wl.get("equation") == "burgers":
+        eqkw = dict(flux="lf", nu=0.01, **{"lambda": 1.0})
+    else:
+        eqkw = dict(flux="rusanov", gamma=1.4, eps_ref=1.0)
+    ctx = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], wl.get("equation", "euler"), q=6, kmax=4,
+                  newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=30, gmres_maxit=7000, precond="bjext",
+                  precision=precision, **eqkw)
     w0 = vortex_state(ctx, wl)
     w = torch.tensor(np.ascontiguousarray(w0).reshape(-1), dtype=torch.float64, device="cuda")
     for i in range(warmup):
