@@ -64,6 +64,12 @@ typedef struct hbpc_ctx hbpc_ctx;
 /* preconditioner */
 #define HBPC_PC_NONE 0
 #define HBPC_PC_BJEXT 1            /* extended block-Jacobi, Sec. 3.2.3 */
+#define HBPC_PC_LEARNED 2          /* per-element network on the Schur system (an addition to
+                                      the paper, see hbpc_mlp_*), BJ_ext as fallback */
+
+/* arithmetic of the learned preconditioner's network */
+#define HBPC_MLP_BF16 0            /* BF16 operands on the matrix cores, FP32 accumulation */
+#define HBPC_MLP_FP32 1            /* FP32 throughout (check path) */
 
 /* preconditioner rebuild frequency */
 #define HBPC_PC_PER_SOLVE 0        /* once per stage solve, at the Newton initial guess */
@@ -104,6 +110,11 @@ typedef struct {
     int pc_rebuild;       /* HBPC_PC_PER_SOLVE | HBPC_PC_PER_NEWTON_IT */
     int jvp_mode;         /* HBPC_JVP_* */
     int hessian;          /* 1: include dR2/dw in the JVP (exact Newton), 0: drop it */
+    int mlp_precision;    /* HBPC_MLP_BF16 | HBPC_MLP_FP32: network arithmetic of HBPC_PC_LEARNED */
+    double pc_fallback;   /* HBPC_PC_LEARNED: if a restart cycle of FGMRES ends with
+                             ||r|| > pc_fallback ||r at the cycle's start||, or the network output
+                             is not finite, BJ_ext takes over for the rest of the stage solve
+                             (default 0.5; <= 0 never falls back) */
     void* stream;         /* hipStream_t; NULL = the null stream */
 } hbpc_params;
 
@@ -117,11 +128,14 @@ typedef struct {
     int gmres_per_solve[HBPC_MAX_SOLVES];
     double t_step_ms;                           /* wall time of the step (host clock) */
     double t_pc_build_ms, t_gmres_ms, t_residual_ms;  /* phase times (host clock, synchronised) */
+    int pc_fallbacks;                           /* stage solves where BJ_ext replaced the learned PC */
+    int mlp_samples;                            /* training samples collected during the step */
 } hbpc_stats;
 
 /* Fill *p with the defaults: Gauss nodes, Rusanov flux, gamma 1.4, eps 1,
  * HBPC(6,4), eps_N 1e-8, atol_dw 1.95e-15 (RMS), 30 Newton its, eps_G 1e-3,
- * GMRES(30), 7000 its, FP64, BJ_ext per solve, linearised JVP with Hessian. */
+ * GMRES(30), 7000 its, FP64, BJ_ext per solve, linearised JVP with Hessian,
+ * BF16 network, learned-preconditioner fallback ratio 0.5. */
 void hbpc_default_params(hbpc_params* p);
 
 /* Create a context: mesh (host struct), degree N (1..7), equation HBPC_EQ_*.
@@ -166,9 +180,109 @@ int hbpc_jvp_f32(hbpc_ctx* ctx, const float* w, const float* sigma, double a1dt,
  * precision HBPC_FP64 or HBPC_MIXED selects the storage of S^-1.  The blocks
  * are kept in the context until the next build. */
 int hbpc_pc_build(hbpc_ctx* ctx, const double* w, double a1dt, double bcoef, int precision);
-/* Y = P^-1 X with the blocks of the last build: (D vw + E vs, F vw + G vs). */
+/* With params.precond == HBPC_PC_LEARNED the build only records w (and its
+ * FP32 copy for HBPC_MIXED) and the coefficients; apply then runs the learned
+ * preconditioner (below) in FP64 or FP32 vectors.
+ * Y = P^-1 X with the blocks of the last build: (D vw + E vs, F vw + G vs). */
 int hbpc_pc_apply(hbpc_ctx* ctx, const double* X, double* Y);
 int hbpc_pc_apply_f32(hbpc_ctx* ctx, const float* X, float* Y);
+
+/* ----------------------------------------------------------------------
+ * Learned preconditioner (an addition to the paper's method).
+ *
+ * It keeps the structure of BJ_ext (Sec. 3.2.3), the exact inverse of the
+ * extended Jacobian of Eq. nonlinear_eqsys with R1'(w) replaced by its
+ * element-local part K, and replaces the element solve S_e^-1,
+ * S_e = I - a1dt K_e + bcoef K_e^2, by a network on patch features:
+ *     rt = vw - bcoef K vs,
+ *     dw_e = s_e f(x_e)             for every element e,
+ *     ds = vs + K dw,
+ * where f is a per-element network with two hidden layers of width H = 256
+ * and ne = hbpc_block_size outputs, on the features x_e = [x_r | x_w] of
+ * element e:
+ *     x_r = rt tiles of (e, its 2d face neighbours in the order -x,+x,-y,+y,-z,+z) / s_e,
+ *     x_w = [w tiles of the same elements, ln a1dt, ln bcoef],
+ *     n_r = (2d+1) ne residual inputs, n_w = n_r + 2 state inputs, n_in = n_r + n_w,
+ * each tile in the w[e][v][node] layout, s_e = RMS of the rt tiles + 1e-30.
+ * The state path gates a residual path that is linear, so that for a fixed
+ * state the preconditioner is a linear map of (vw, vs):
+ *     g1 = relu(x_w W1w + b1),   g2 = relu(g1 W2w + b2),
+ *     h1 = (x_r W1r) .* g1,      h2 = (h1 W2r) .* g2,      f = h2 W3.
+ * Parameters theta (FP32), row-major, W[i][j] from input i to output j:
+ * W1r (n_r x H), W1w (n_w x H), b1 (H), W2r (H x H), W2w (H x H), b2 (H),
+ * W3 (H x ne).  The gates are computed once per linearisation state (per
+ * Newton iteration, or per hbpc_pc_build), the residual path per apply.
+ * Training: pairs collected by hbpc_step (hbpc_mlp_collect: Newton
+ * corrections, or the element solves of BJ_ext on Krylov vectors), mean
+ * squared error, Adam with FP32 master weights.
+ * -------------------------------------------------------------------- */
+/* Network shape of this context; any output pointer may be NULL. */
+int hbpc_mlp_shape(const hbpc_ctx* ctx, int* n_in, int* hidden, int* n_out, size_t* n_params);
+/* Load / read the FP32 parameter vector (device, n_params values).  Loading
+ * resets the Adam moments and step count. */
+int hbpc_mlp_set_params(hbpc_ctx* ctx, const float* theta);
+int hbpc_mlp_get_params(hbpc_ctx* ctx, float* theta);
+/* Feature rows of `count` elements: elems (device int array, or NULL for
+ * elements 0..count-1; an entry outside 0..n_elem-1 gives a zero row and
+ * scale 0), rt and w FP64 (ndof).  X: count x n_in FP32 out;
+ * scale: count FP32 out (may be NULL); if dw != NULL, T: count x ne FP32 out
+ * with T[r] = dw_e / s_e. */
+int hbpc_mlp_features(hbpc_ctx* ctx, const double* rt, const double* w, const double* dw,
+                      const int* elems, int count, double a1dt, double bcoef,
+                      float* X, float* T, float* scale);
+/* Network output Y (rows x ne) of feature rows X (rows x n_in, the layout
+ * of hbpc_mlp_features); precision HBPC_MLP_*. */
+int hbpc_mlp_forward(hbpc_ctx* ctx, const float* X, int rows, float* Y, int precision);
+/* Mean squared error over rows x ne of f(X) - T and its gradient (device,
+ * n_params FP32); the loss goes to *loss_host (synchronises). */
+int hbpc_mlp_loss_grad(hbpc_ctx* ctx, const float* X, const float* T, int rows, float* grad,
+                       double* loss_host, int precision);
+/* One Adam step on the context's parameters with gradient grad (device):
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2, theta -= lr (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps). */
+int hbpc_mlp_adam(hbpc_ctx* ctx, const float* grad, double lr, double beta1, double beta2, double eps);
+/* Start collecting training pairs into caller-owned device buffers X
+ * (capacity x n_in) and T (capacity x ne) during subsequent hbpc_step calls,
+ * until capacity is reached; per_event distinct elements (drawn with
+ * splitmix64 from seed) contribute one pair each per event:
+ *   HBPC_MLP_PAIRS_NEWTON: event = every Newton correction dX of -G;
+ *     features of rt = -G_w + bcoef K G_sigma, target = dw_e / s_e;
+ *   HBPC_MLP_PAIRS_KRYLOV: event = every `every`-th FGMRES iteration of a
+ *     BJ_ext solve; features of rt = vw - bcoef K vs of the Krylov vector v,
+ *     target = the w block of BJ_ext's output for v (S_e^-1 rt_e) / s_e;
+ *   HBPC_MLP_PAIRS_RANDOM: event = every `every`-th FGMRES iteration of
+ *     any solve without the learned preconditioner; target dw = independent
+ *     standard normal values (splitmix64 counters, Box-Muller), features of
+ *     rt = dw - a1dt K dw + bcoef K (K dw), i.e. BJ_ext's element operator
+ *     S_e applied exactly, target dw_e / s_e.
+ * Each call restarts the count at 0 (pass offset pointers to append).
+ * capacity 0 stops collecting.  hbpc_mlp_collected returns the pairs
+ * written so far. */
+#define HBPC_MLP_PAIRS_NEWTON 0
+#define HBPC_MLP_PAIRS_KRYLOV 1
+#define HBPC_MLP_PAIRS_RANDOM 2
+int hbpc_mlp_collect(hbpc_ctx* ctx, float* X, float* T, size_t capacity, int per_event,
+                     unsigned long long seed, int source, int every);
+size_t hbpc_mlp_collected(const hbpc_ctx* ctx);
+
+typedef struct {
+    int epochs;                /* passes over the pairs */
+    int batch;                 /* pairs per Adam step, 1..8192 */
+    double lr, beta1, beta2, eps;  /* Adam */
+    unsigned long long seed;   /* pair order per epoch: Fisher-Yates driven by splitmix64 */
+    int precision;             /* HBPC_MLP_* */
+} hbpc_train_cfg;
+typedef struct {
+    int steps;                 /* Adam steps taken */
+    double loss_first;         /* mean loss over the first epoch's batches */
+    double loss_last;          /* mean loss over the last epoch's batches */
+    double ms;                 /* wall time */
+} hbpc_train_log;
+/* Defaults: 40 epochs, batch 256, lr 1e-3, (0.9, 0.999, 1e-8), seed 2109, BF16. */
+void hbpc_default_train_cfg(hbpc_train_cfg* cfg);
+/* Train the context's network on `count` pairs (X, T device, as collected).
+ * Synchronises; log may be NULL. */
+int hbpc_train_mlp(hbpc_ctx* ctx, const float* X, const float* T, size_t count,
+                   const hbpc_train_cfg* cfg, hbpc_train_log* log);
 
 /* One HBPC(q, k_max) step (Algorithm 1) of size dt, in place.  Transactional:
  * on any error w_inout is unchanged.  stats may be NULL.  Synchronises. */
@@ -176,10 +290,11 @@ int hbpc_step(hbpc_ctx* ctx, double* w_inout, double dt, hbpc_stats* stats);
 
 /* Kernel timing (HIP events recorded around every launch on the context's
  * stream, resolved after synchronisation).  Classes: trace, r1, r2, res, jvp,
- * kcol, pcpre, bj_apply, bj_invert, mdot, gemv, vec.  `bytes` and `flops` are
+ * kcol, pcpre, bj_apply, bj_invert, mdot, gemv, vec, gs_dot, gs_update, lin
+ * (x + c R1'(w) s), mlp_feat, mlp_gemm, mlp_vec.  `bytes` and `flops` are
  * the algorithmic figures of all recorded launches: inputs read once and
  * outputs written once (bytes), the method's floating-point operations
- * (flops, only for bj_invert).  Timing adds a few microseconds per launch. */
+ * (flops, only for bj_invert and mlp_gemm).  Timing adds a few microseconds per launch. */
 typedef struct {
     char name[16];
     int launches;

@@ -14,7 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhbpc.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["dg_euler.hip", "dg_advection.hip", "dg_burgers.hip", "bjext.hip", "blas.hip", "basis1d.cpp", "hbpc.cpp"]
+SOURCES = ["dg_euler.hip", "dg_advection.hip", "dg_burgers.hip", "bjext.hip", "blas.hip", "mlp.hip", "basis1d.cpp",
+           "hbpc.cpp"]
 
 # -packed-fp32-ops: never emit packed FP32 VALU instructions
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wno-unused-result",

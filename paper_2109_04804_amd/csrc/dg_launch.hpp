@@ -5,7 +5,8 @@
 
 enum {
     OPK_TRACE = 0, OPK_R1, OPK_R2, OPK_RES, OPK_JVP, OPK_JVP_NOHESS, OPK_KCOL, OPK_PCPRE,
-    OPK_LIFT      // BR1 lifting (viscous Burgers only)
+    OPK_LIFT,     // BR1 lifting (viscous Burgers only)
+    OPK_LINLOC    // x + c0 K(w) s, K the element-local Jacobian of BJ_ext
 };
 
 struct GeomHost {
@@ -104,6 +105,7 @@ template <int D, int NP, class EQ, typename T> hipError_t launch_family_np(const
     case OPK_JVP_NOHESS: return launch_op<D, NP, EQ, OpJvp<T, false>, T>(g, r);
     case OPK_KCOL: return launch_op<D, NP, EQ, OpKcol<T, NV * NN>, T>(g, r);
     case OPK_PCPRE: return launch_op<D, NP, EQ, OpPcPre<T>, T>(g, r);
+    case OPK_LINLOC: return launch_op<D, NP, EQ, OpLin<T, true>, T>(g, r);
     case OPK_LIFT: {
         if (!EQ::VISC) return hipErrorInvalidValue;
         constexpr int EPB = 256 / NN > 0 ? 256 / NN : 1;

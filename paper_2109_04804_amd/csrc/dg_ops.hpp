@@ -161,6 +161,20 @@ template <typename T> struct OpPcPre {   // fld: w, vw, vs
     }
 };
 
+// fld: w, s, x;  out = x + c0 R1'(w) s, with LOC the neighbour values of s held at zero, i.e.
+// the element-local Jacobian K of BJ_ext
+template <typename T, bool LOC> struct OpLin {
+    using S = Dual<T>;
+    static constexpr int NJ = 2, NC = 1;
+    static constexpr bool LOCAL = LOC;
+    HD static T load(const OpArgs<T>& a, int j, size_t g, int loc) { return a.fld[j][g]; }
+    HD static S make(const T* x, const OpArgs<T>& a) { return {x[0], x[1]}; }
+    HD static void combo(const S& f, T* c, const OpArgs<T>& a) { c[0] = f.b; }
+    HD static void output(const OpArgs<T>& a, size_t g, int e, int loc, const T* gv) {
+        a.out[0][g] = a.fld[2][g] + a.c0 * gv[0];
+    }
+};
+
 // elements per block: as many as fit 256 threads and ~64 KB of LDS
 template <int D, int NP, int NV, int NJ, int NC, typename T> constexpr int op_epb() {
     constexpr int NN = ipow(NP, D), NFP = ipow(NP, D - 1);

@@ -103,8 +103,9 @@ double now_ms() {
 }  // namespace
 
 // ------------------------------------------------------------------ kernel timing
-static const char* KC_NAMES[KC_COUNT] = {"trace", "r1",       "r2",   "res",  "jvp", "kcol",   "pcpre",
-                                         "bj_apply", "bj_invert", "mdot", "gemv", "vec", "gs_dot", "gs_update"};
+static const char* KC_NAMES[KC_COUNT] = {"trace",    "r1",        "r2",   "res",  "jvp", "kcol",   "pcpre",
+                                         "bj_apply", "bj_invert", "mdot", "gemv", "vec", "gs_dot", "gs_update",
+                                         "lin",      "mlp_feat",  "mlp_gemm", "mlp_vec"};
 
 static long prof_begin(hbpc_ctx* c) {
     if (!c->prof) return -1;
@@ -168,6 +169,7 @@ int op_launch(hbpc_ctx* c, const LaunchReq& r, int f32) {
     case OPK_JVP_NOHESS: cls = KC_JVP; bytes = 6 * n * esz; break;
     case OPK_KCOL: cls = KC_KCOL; bytes = (double)(r.e_end - r.e_begin) * c->NE * (8.0 + c->NE * 8.0); break;
     case OPK_PCPRE: cls = KC_PCPRE; bytes = 5 * n * esz; break;
+    case OPK_LINLOC: cls = KC_LIN; bytes = 4 * n * esz; break;
     }
     long pi = prof_begin(c);
     hipError_t e = c->launch(c->geom, r, f32);
@@ -355,6 +357,294 @@ static void pc_apply(hbpc_ctx* c, const void* w, const void* trw, const void* X,
              (double)c->nE * c->NE * c->NE * (c->sinv_f32 ? 4.0 : 8.0) + 4.0 * c->ndof * esz);
 }
 
+// ------------------------------------------------------------------ learned preconditioner
+// out = x + coef K(w) s with the element-local Jacobian K of BJ_ext (traces of w given)
+static void op_lin_local(hbpc_ctx* c, const void* w, const void* trw, const void* s, const void* x, double coef,
+                         void* out, int f32) {
+    LaunchReq r = op_req(c, OPK_LINLOC);
+    r.fld[0] = w;
+    r.fld[1] = s;
+    r.fld[2] = x;
+    r.trc[0] = trw;
+    r.qtr[0] = op_lift(c, w, trw, 0, f32);
+    r.out[0] = out;
+    r.c0 = coef;
+    op_launch(c, r, f32);
+}
+
+struct MlpView {
+    const float *W1r, *W1w, *b1, *W2r, *W2w, *b2, *W3;
+};
+
+// parameter blocks in the order W1r (n_r x H), W1w (n_w x H), b1, W2r, W2w, b2, W3 (H x NE)
+template <typename P> static void mlp_blocks(const hbpc_ctx* c, P* th, P** out) {
+    const size_t nr = c->mlp_nr, nw = c->mlp_nin - c->mlp_nr, H = c->mlp_H, no = c->NE;
+    out[0] = th;
+    out[1] = out[0] + nr * H;
+    out[2] = out[1] + nw * H;
+    out[3] = out[2] + H;
+    out[4] = out[3] + H * H;
+    out[5] = out[4] + H * H;
+    out[6] = out[5] + H;
+}
+
+static MlpView mlp_view(const hbpc_ctx* c, const float* th) {
+    const float* b[7];
+    mlp_blocks(c, th, b);
+    return MlpView{b[0], b[1], b[2], b[3], b[4], b[5], b[6]};
+}
+
+// C = A B (+bias, relu) (.* mask | .* (mask > 0)) (+= C)
+static void mlp_gemm_p(hbpc_ctx* c, const float* A, long long a_r, long long a_c, const float* B, long long b_r,
+                       long long b_c, float* C, long long ldc, const float* bias, const float* mask, int mask_mul,
+                       int M, int N, int K, int relu, int bf16, int accumulate = 0) {
+    long pi = prof_begin(c);
+    hipchk(c, mlp_gemm(A, a_r, a_c, B, b_r, b_c, C, ldc, bias, mask, mask ? ldc : 0, mask_mul, M, N, K, relu,
+                       accumulate, bf16, c->stream),
+           "mlp gemm");
+    prof_end(c, pi, KC_GEMM, 4.0 * ((double)M * K + (double)K * N + (double)M * N * (mask ? 2 : 1)),
+             2.0 * M * N * K);
+}
+
+static void mlp_ew(hbpc_ctx* c, hipError_t e, double bytes) {
+    hipchk(c, e, "mlp elementwise");
+    (void)bytes;
+}
+
+// state gates of `rows` feature rows: G1 = relu(Xw W1w + b1), G2 = relu(G1 W2w + b2)
+static void mlp_gates(hbpc_ctx* c, const float* X, int rows, float* G1, float* G2, int bf16) {
+    const int ni = c->mlp_nin, nr = c->mlp_nr, H = c->mlp_H;
+    MlpView p = mlp_view(c, c->theta);
+    mlp_gemm_p(c, X + nr, ni, 1, p.W1w, H, 1, G1, H, p.b1, nullptr, 0, rows, H, ni - nr, 1, bf16);
+    mlp_gemm_p(c, G1, H, 1, p.W2w, H, 1, G2, H, p.b2, nullptr, 0, rows, H, H, 1, bf16);
+}
+
+// residual path with the gates given: H1 = (Xr W1r) .* G1, H2 = (H1 W2r) .* G2, Y = H2 W3
+static void mlp_residual_path(hbpc_ctx* c, const float* X, int rows, const float* G1, const float* G2, float* H1,
+                              float* H2, float* Y, int bf16) {
+    const int ni = c->mlp_nin, nr = c->mlp_nr, H = c->mlp_H, no = c->NE;
+    MlpView p = mlp_view(c, c->theta);
+    mlp_gemm_p(c, X, ni, 1, p.W1r, H, 1, H1, H, nullptr, G1, 1, rows, H, nr, 0, bf16);
+    mlp_gemm_p(c, H1, H, 1, p.W2r, H, 1, H2, H, nullptr, G2, 1, rows, H, H, 0, bf16);
+    mlp_gemm_p(c, H2, H, 1, p.W3, no, 1, Y, no, nullptr, nullptr, 0, rows, no, H, 0, bf16);
+}
+
+// training buffers: per row 10 H + 2 NE (activations, gradients) + n_in + NE (gathered batch)
+static void mlp_train_alloc(hbpc_ctx* c, int rows) {
+    if (rows <= c->tr_rows) return;
+    dfree(c->tr_buf);
+    c->tr_buf = nullptr;
+    c->tr_rows = 0;
+    const size_t per = 10 * (size_t)c->mlp_H + 3 * (size_t)c->NE + (size_t)c->mlp_nin;
+    c->tr_buf = dalloc<float>(c, per * rows);
+    c->tr_rows = rows;
+}
+
+// Sum of squared errors of f(X) - T over rows x NE added to *sse (device); gradient of
+// the mean squared error into grad.  Work space: the training buffers.
+static void mlp_loss_grad_dev(hbpc_ctx* c, const float* X, const float* T, int rows, float* grad, double* sse,
+                              int bf16) {
+    const int ni = c->mlp_nin, nr = c->mlp_nr, nw = ni - nr, H = c->mlp_H, no = c->NE;
+    mlp_train_alloc(c, rows);
+    const size_t RH = (size_t)rows * H;
+    float* g1 = c->tr_buf;
+    float* g2 = g1 + RH;
+    float* a1 = g2 + RH;
+    float* h1 = a1 + RH;
+    float* a2 = h1 + RH;
+    float* h2 = a2 + RH;
+    float* D1 = h2 + RH;
+    float* D2 = D1 + RH;
+    float* D3 = D2 + RH;
+    float* D4 = D3 + RH;
+    float* Y = D4 + RH;
+    float* dY = Y + (size_t)rows * no;
+    MlpView p = mlp_view(c, c->theta);
+    float* gb[7];
+    mlp_blocks(c, grad, gb);
+    const long long nH = (long long)RH;
+    // forward, keeping the pre-gate products
+    mlp_gates(c, X, rows, g1, g2, bf16);
+    mlp_gemm_p(c, X, ni, 1, p.W1r, H, 1, a1, H, nullptr, nullptr, 0, rows, H, nr, 0, bf16);
+    mlp_ew(c, mlp_ew_mul(a1, g1, h1, nH, c->stream), 12.0 * nH);
+    mlp_gemm_p(c, h1, H, 1, p.W2r, H, 1, a2, H, nullptr, nullptr, 0, rows, H, H, 0, bf16);
+    mlp_ew(c, mlp_ew_mul(a2, g2, h2, nH, c->stream), 12.0 * nH);
+    mlp_gemm_p(c, h2, H, 1, p.W3, no, 1, Y, no, nullptr, nullptr, 0, rows, no, H, 0, bf16);
+    // loss
+    const long long n = (long long)rows * no;
+    const int nblk = (int)std::min<long long>(64, (n + 255) / 256);
+    long pi = prof_begin(c);
+    hipchk(c, mlp_mse_grad(Y, T, dY, n, (float)(1.0 / (double)n), c->part, nblk, c->stream), "mse");
+    hipchk(c, mlp_sum_parts(c->part, nblk, sse, c->stream), "mse");
+    prof_end(c, pi, KC_MLPV, 12.0 * n);
+    // y = h2 W3
+    mlp_gemm_p(c, h2, 1, H, dY, no, 1, gb[6], no, nullptr, nullptr, 0, H, no, rows, 0, bf16);
+    mlp_gemm_p(c, dY, no, 1, p.W3, 1, no, D1, H, nullptr, nullptr, 0, rows, H, no, 0, bf16);   // dh2
+    // h2 = a2 .* g2: da2 -> D2, dz2 = dh2 .* a2 .* (g2 > 0) -> D3
+    mlp_ew(c, mlp_ew_split(D1, g2, a2, D2, D3, nH, 1, c->stream), 20.0 * nH);
+    // a2 = h1 W2r
+    mlp_gemm_p(c, h1, 1, H, D2, H, 1, gb[3], H, nullptr, nullptr, 0, H, H, rows, 0, bf16);
+    mlp_gemm_p(c, D2, H, 1, p.W2r, 1, H, D1, H, nullptr, nullptr, 0, rows, H, H, 0, bf16);    // dh1
+    // h1 = a1 .* g1: da1 -> D2, dh1 .* a1 -> D4
+    mlp_ew(c, mlp_ew_split(D1, g1, a1, D2, D4, nH, 0, c->stream), 20.0 * nH);
+    // a1 = Xr W1r
+    mlp_gemm_p(c, X, 1, ni, D2, H, 1, gb[0], H, nullptr, nullptr, 0, nr, H, rows, 0, bf16);
+    // g2 = relu(g1 W2w + b2)
+    mlp_gemm_p(c, g1, 1, H, D3, H, 1, gb[4], H, nullptr, nullptr, 0, H, H, rows, 0, bf16);
+    hipchk(c, mlp_colsum(D3, H, rows, H, gb[5], c->stream), "colsum");
+    mlp_gemm_p(c, D3, H, 1, p.W2w, 1, H, D4, H, nullptr, nullptr, 0, rows, H, H, 0, bf16, 1);   // dg1 += dz2 W2w^T
+    // g1 = relu(Xw W1w + b1)
+    mlp_ew(c, mlp_ew_relu_mask(D4, g1, nH, c->stream), 12.0 * nH);
+    mlp_gemm_p(c, X + nr, 1, ni, D4, H, 1, gb[1], H, nullptr, nullptr, 0, nw, H, rows, 0, bf16);
+    hipchk(c, mlp_colsum(D4, H, rows, H, gb[2], c->stream), "colsum");
+}
+
+static void mlp_adam_dev(hbpc_ctx* c, const float* grad, double lr, double b1, double b2, double eps) {
+    c->adam_t++;
+    long pi = prof_begin(c);
+    hipchk(c, mlp_adam(c->theta, grad, c->adam_m, c->adam_v, (long long)c->mlp_np, (float)lr, (float)b1, (float)b2,
+                       (float)eps, c->adam_t, c->stream),
+           "adam");
+    prof_end(c, pi, KC_MLPV, 20.0 * c->mlp_np);
+}
+
+static void lpc_buffers(hbpc_ctx* c) {
+    if (c->ap_X) return;
+    const size_t nE = c->nE;
+    c->ap_X = dalloc<float>(c, nE * c->mlp_nin);
+    c->ap_G1 = dalloc<float>(c, nE * c->mlp_H);
+    c->ap_G2 = dalloc<float>(c, nE * c->mlp_H);
+    c->ap_H1 = dalloc<float>(c, nE * c->mlp_H);
+    c->ap_H2 = dalloc<float>(c, nE * c->mlp_H);
+    c->ap_Y = dalloc<float>(c, nE * c->NE);
+    c->ap_s = dalloc<float>(c, nE);
+}
+
+// part: 1 residual tiles (+scale, targets), 2 state tiles and coefficients, 3 both
+static void features_p(hbpc_ctx* c, const void* rt, const void* w, const void* dw, int f32, const int* elems,
+                       int count, double a1dt, double bc, float* X, float* T, float* scale, int part) {
+    long pi = prof_begin(c);
+    // the step coefficients enter as logarithms: O(1) values that tell the stage solves apart
+    const float la = (float)std::log(std::max(a1dt, 1e-300)), lb = (float)std::log(std::max(bc, 1e-300));
+    hipchk(c, mlp_features(rt, w, dw, f32, elems, count, c->D, c->geom.nel, c->NE, la, lb, X, T, scale, part,
+                           c->stream),
+           "mlp features");
+    const double esz = f32 ? 4.0 : 8.0;
+    const double tiles = (double)c->mlp_nr;   // patch values per field
+    double bytes = 0.0;
+    if (part & 1) bytes += tiles * (esz + 4.0) + 4.0 + (dw ? c->NE * (esz + 4.0) : 0.0);
+    if (part & 2) bytes += tiles * (esz + 4.0) + 8.0;
+    prof_end(c, pi, KC_FEAT, (double)count * bytes);
+}
+
+// gates of the learned preconditioner at linearisation state w (precision f32) and the coefficients
+static void lpc_prepare(hbpc_ctx* c, const void* w, int f32, double a1dt, double bc) {
+    lpc_buffers(c);
+    c->pc_a1dt = a1dt;
+    c->pc_bc = bc;
+    const int bf16 = c->prm.mlp_precision == HBPC_MLP_BF16;
+    features_p(c, nullptr, w, nullptr, f32, nullptr, c->nE, a1dt, bc, c->ap_X, nullptr, nullptr, 2);
+    mlp_gates(c, c->ap_X, c->nE, c->ap_G1, c->ap_G2, bf16);
+}
+
+// Y = P^-1 X with the learned preconditioner, vectors in precision f32, linearisation state w
+// (traces trw) as given to the last lpc_prepare
+static void lpc_apply(hbpc_ctx* c, const void* w, const void* trw, const void* Xv, void* Y, int f32) {
+    const size_t esz = f32 ? 4 : 8, n = c->ndof;
+    const char* vw = (const char*)Xv;
+    const char* vs = vw + n * esz;
+    char* yw = (char*)Y;
+    char* ys = yw + n * esz;
+    void* rt = c->kv;
+    const int bf16 = c->prm.mlp_precision == HBPC_MLP_BF16;
+    op_lin_local(c, w, trw, vs, vw, -c->pc_bc, rt, f32);   // rt = vw - bcoef K vs
+    features_p(c, rt, w, nullptr, f32, nullptr, c->nE, c->pc_a1dt, c->pc_bc, c->ap_X, nullptr, c->ap_s, 1);
+    mlp_residual_path(c, c->ap_X, c->nE, c->ap_G1, c->ap_G2, c->ap_H1, c->ap_H2, c->ap_Y, bf16);
+    long pi = prof_begin(c);
+    hipchk(c, mlp_rescale(c->ap_Y, c->ap_s, yw, f32, (long long)n, c->NE, c->stream), "mlp rescale");
+    prof_end(c, pi, KC_MLPV, (double)n * (4.0 + esz) + 4.0 * c->nE);
+    op_lin_local(c, w, trw, yw, vs, 1.0, ys, f32);          // ys = vs + K yw
+}
+
+// splitmix64 (Steele, Lea & Flood 2014): state advanced by the golden-ratio increment
+static unsigned long long splitmix64(unsigned long long& x) {
+    unsigned long long z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// first k entries of a Fisher-Yates shuffle of 0..n-1
+static void draw_distinct(unsigned long long& state, int n, int k, std::vector<int>& out) {
+    std::vector<int> p(n);
+    for (int i = 0; i < n; ++i) p[i] = i;
+    for (int i = 0; i < k; ++i) {
+        int j = i + (int)(splitmix64(state) % (unsigned long long)(n - i));
+        std::swap(p[i], p[j]);
+    }
+    out.assign(p.begin(), p.begin() + k);
+}
+
+// Training pairs from a Krylov vector v of a BJ_ext solve and z = P^-1 v: for k elements drawn with
+// splitmix64, the features of rt = vw - bcoef K vs and the w block of z, i.e. the element solve
+// S_e^-1 rt_e of BJ_ext (precision f32, linearisation state w with traces trw)
+static void lpc_collect_krylov(hbpc_ctx* c, const void* w, const void* trw, const void* v, const void* z,
+                               double a1dt, double bc, int f32) {
+    const size_t esz = f32 ? 4 : 8, n = c->ndof;
+    int k = (int)std::min<size_t>((size_t)c->col_per, c->col_cap - c->col_count);
+    k = std::min(k, c->nE);
+    if (k <= 0) return;
+    const void* target = z;
+    if (c->col_source == HBPC_MLP_PAIRS_RANDOM) {
+        // target dw: standard normal values; rt = S dw = dw - a1dt K dw + bcoef K (K dw), the
+        // element-local Schur operator of BJ_ext applied exactly
+        void* dw = c->tmp[2];
+        void* t = c->tmp[3];
+        char* rt = (char*)c->kv;
+        char* x = rt + n * esz;
+        hipchk(c, mlp_randn(dw, f32, (long long)n, c->col_seed ^ (0xD1B54A32D192ED03ull * ++c->col_draws),
+                            c->stream),
+               "randn");
+        hipchk(c, hipMemsetAsync(x, 0, n * esz, c->stream), "memset");
+        op_lin_local(c, w, trw, dw, x, 1.0, t, f32);                          // t = K dw
+        hipchk(c, blas_axpby(1.0, dw, f32, 0.0, x, f32, n, c->stream), "copy");
+        hipchk(c, blas_axpby(-a1dt, t, f32, 1.0, x, f32, n, c->stream), "axpby");   // x = dw - a1dt t
+        op_lin_local(c, w, trw, t, x, bc, rt, f32);                           // rt = x + bcoef K t
+        target = dw;
+    } else {
+        op_lin_local(c, w, trw, (const char*)v + n * esz, v, -bc, c->kv, f32);
+    }
+    std::vector<int> el;
+    draw_distinct(c->col_seed, c->nE, k, el);
+    hipchk(c, hipMemcpyAsync(c->col_elems, el.data(), (size_t)k * sizeof(int), hipMemcpyHostToDevice, c->stream),
+           "copy");
+    features_p(c, c->kv, w, target, f32, c->col_elems, k, a1dt, bc, c->col_X + c->col_count * c->mlp_nin,
+               c->col_T + c->col_count * c->NE, nullptr, 3);
+    hipchk(c, hipStreamSynchronize(c->stream), "sync");   // el is host memory of this frame
+    c->col_count += k;
+    c->st.mlp_samples += k;
+}
+
+// Training pairs from the Newton correction just computed: rhs = -G, dX (FP64), state X with traces trw
+static void lpc_collect(hbpc_ctx* c, double a1dt, double bc) {
+    if (!c->col_X || c->col_count >= c->col_cap || c->col_source != HBPC_MLP_PAIRS_NEWTON) return;
+    const size_t n = c->ndof;
+    int k = (int)std::min<size_t>((size_t)c->col_per, c->col_cap - c->col_count);
+    k = std::min(k, c->nE);
+    if (k <= 0) return;
+    double* rt = (double*)c->kv;
+    op_lin_local(c, c->X, c->trw, c->rhs + n, c->rhs, -bc, rt, 0);   // rt = rhs_w - bcoef K rhs_s
+    std::vector<int> el;
+    draw_distinct(c->col_seed, c->nE, k, el);
+    hipchk(c, hipMemcpyAsync(c->col_elems, el.data(), (size_t)k * sizeof(int), hipMemcpyHostToDevice, c->stream),
+           "copy");
+    features_p(c, rt, c->X, c->dX, 0, c->col_elems, k, a1dt, bc, c->col_X + c->col_count * c->mlp_nin,
+               c->col_T + c->col_count * c->NE, nullptr, 3);
+    hipchk(c, hipStreamSynchronize(c->stream), "sync");   // el is host memory of this frame
+    c->col_count += k;
+    c->st.mlp_samples += k;
+}
+
 // ------------------------------------------------------------------ FD JVP (Eq. MatrixFree_nonlinear), FP64
 static void fd_alloc(hbpc_ctx* c) {
     for (int i = 0; i < 6; ++i)
@@ -415,7 +705,7 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
     const int m = c->prm.gmres_restart;
     const int maxit = c->prm.gmres_maxit;
     const double rtol = c->prm.gmres_rtol;
-    const int use_pc = c->prm.precond == HBPC_PC_BJEXT;
+    const int use_pc = c->prm.precond != HBPC_PC_NONE;
     const int fd = c->prm.jvp_mode == HBPC_JVP_FD && !f32;
     char* V = (char*)c->V;
     char* Z = (char*)c->Z;
@@ -440,7 +730,7 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
     if (beta0 == 0.0) return 0;
     // residual vector r (precision f32) in V_0 slot; first cycle r = rhs
     hipchk(c, blas_axpby(1.0, rhs, 0, 0.0, Vj(0), f32, n2, c->stream), "copy");
-    int total = 0;
+    int total = 0, cycle = 0;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
     auto Hc = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
     for (;;) {
@@ -449,11 +739,18 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
         hipchk(c, blas_axpby(1.0 / beta, Vj(0), f32, 0.0, Vj(0), f32, n2, c->stream), "scale");
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
-        bool converged = false;
+        bool converged = false, bad_pc = false;
         int k = 0;
+        const double beta_cycle = beta;
+        const int learned = c->prm.precond == HBPC_PC_LEARNED && c->lpc_active;
         for (int j = 0; j < m; ++j) {
             void* zj = use_pc ? Zj(j) : Vj(j);
-            if (use_pc) pc_apply(c, w, trw, Vj(j), zj, f32);
+            if (learned) lpc_apply(c, w, trw, Vj(j), zj, f32);
+            else if (use_pc) pc_apply(c, w, trw, Vj(j), zj, f32);
+            if (!learned && c->col_X && c->col_source != HBPC_MLP_PAIRS_NEWTON &&
+                (use_pc || c->col_source == HBPC_MLP_PAIRS_RANDOM) &&
+                c->col_count < c->col_cap && total % c->col_every == 0)
+                lpc_collect_krylov(c, w, trw, Vj(j), zj, a1dt, bc, f32);
             void* u = Vj(j + 1);
             jvp(zj, u);
             // classical Gram-Schmidt against V_0..V_j with a second pass when the
@@ -492,7 +789,15 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
             }
             double hnrm = std::sqrt(c->hres[128]);
             Hc(j + 1, j) = hnrm;
-            if (!std::isfinite(hnrm)) set_err(c, HBPC_ERR_NONFINITE, "non-finite Arnoldi vector");
+            if (!std::isfinite(hnrm)) {
+                // a non-finite learned-preconditioner output: drop column j and fall back
+                if (learned && c->prm.pc_fallback > 0) {
+                    bad_pc = true;
+                    k = j;
+                    break;
+                }
+                set_err(c, HBPC_ERR_NONFINITE, "non-finite Arnoldi vector");
+            }
             for (int i = 0; i < j; ++i) {
                 double t = cs[i] * Hc(i, j) + sn[i] * Hc(i + 1, j);
                 Hc(i + 1, j) = -sn[i] * Hc(i, j) + cs[i] * Hc(i + 1, j);
@@ -518,11 +823,22 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
             for (int l = i + 1; l < k; ++l) t -= Hc(i, l) * y[l];
             y[i] = t / Hc(i, i);
         }
-        hipchk(c, blas_gemv_add(use_pc ? Z : V, f32, n2, k, y.data(), dX, 0, n2, c->stream), "update");
+        if (k > 0) hipchk(c, blas_gemv_add(use_pc ? Z : V, f32, n2, k, y.data(), dX, 0, n2, c->stream), "update");
         if (converged) return total;
         if (total >= maxit) {
             set_err(c, HBPC_ERR_GMRES, "GMRES did not reach eps_G within " + std::to_string(maxit) + " iterations");
         }
+        // learned preconditioner: BJ_ext takes over after a poor first cycle or a non-finite output
+        if (learned && c->prm.pc_fallback > 0 &&
+            (bad_pc || std::fabs(g[k]) > c->prm.pc_fallback * beta_cycle)) {
+            c->lpc_active = 0;
+            c->st.pc_fallbacks++;
+            if (c->verbose)
+                std::fprintf(stderr, "[hbpc] learned preconditioner -> BJ_ext (%s, cycle %d reduced |r| by %.3e)\n",
+                             bad_pc ? "non-finite" : "slow", cycle, std::fabs(g[k]) / beta_cycle);
+            pc_build(c, c->X, a1dt, bc, f32);
+        }
+        ++cycle;
         // restart: r = rhs - J dX, computed in precision f32 in V_0
         void* xw = Vj(1);   // dX in precision f32
         hipchk(c, blas_axpby(1.0, dX, 0, 0.0, xw, f32, n2, c->stream), "cast");
@@ -557,15 +873,24 @@ static void newton_solve(hbpc_ctx* c, const double* b, double a1dt, double bc, c
     const int sidx = c->cur_solve;
     if (n0 > 1e-14 * std::sqrt((double)c->n2)) {
         if (mixed) state_traces(c, 1);
-        const int use_pc = c->prm.precond == HBPC_PC_BJEXT;
-        if (use_pc) pc_build(c, X, a1dt, bc, mixed);
+        const int pck = c->prm.precond;
+        if (pck == HBPC_PC_BJEXT) pc_build(c, X, a1dt, bc, mixed);
+        if (pck == HBPC_PC_LEARNED) {
+            if (!c->mlp_ready) set_err(c, HBPC_ERR_ARG, "learned preconditioner without parameters");
+            c->lpc_active = 1;
+        }
         for (;;) {
             ++its;
-            if (use_pc && c->prm.pc_rebuild == HBPC_PC_PER_NEWTON_IT && its > 1) pc_build(c, X, a1dt, bc, mixed);
+            const int bj = pck == HBPC_PC_BJEXT || (pck == HBPC_PC_LEARNED && !c->lpc_active);
+            if (bj && c->prm.pc_rebuild == HBPC_PC_PER_NEWTON_IT && its > 1) pc_build(c, X, a1dt, bc, mixed);
+            // learned: gates at the current linearisation state
+            if (pck == HBPC_PC_LEARNED && c->lpc_active)
+                lpc_prepare(c, mixed ? (const void*)c->X32 : (const void*)X, mixed, a1dt, bc);
             hipchk(c, blas_axpby(-1.0, c->G, 0, 0.0, c->rhs, 0, c->n2, c->stream), "rhs");
             double tg = now_ms();
             gits += fgmres(c, c->rhs, c->dX, a1dt, bc, mixed);
             c->st.t_gmres_ms += now_ms() - tg;
+            lpc_collect(c, a1dt, bc);
             hipchk(c, blas_axpby(1.0, c->dX, 0, 1.0, X, 0, c->n2, c->stream), "update");
             state_traces(c, mixed);
             op_res(c, X, b, a1dt, bc, c->G);
@@ -651,7 +976,9 @@ static void ctx_free(hbpc_ctx* c) {
     }
     void* bufs[] = {c->R1all, c->R2all, c->X, c->b, c->G, c->dX, c->rhs, c->trw, c->trs, c->trd1, c->trd2,
                     c->X32, c->trw32, c->trs32, c->trd1_32, c->trd2_32, c->V, c->Z, c->kv, c->KT, c->Sinv,
-                    c->part, c->dres, c->dstatus, c->basis64, c->basis32};
+                    c->part, c->dres, c->dstatus, c->basis64, c->basis32, c->theta, c->adam_m, c->adam_v,
+                    c->mgrad, c->ap_X, c->ap_G1, c->ap_G2, c->ap_H1, c->ap_H2, c->ap_Y, c->ap_s, c->tr_buf, c->tr_idx_dev,
+                    c->col_elems};
     for (void* p : bufs) dfree(p);
     for (int i = 0; i < 6; ++i) dfree(c->fd[i]);
     for (int j = 0; j < 4; ++j) {
@@ -698,6 +1025,9 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
         set_err(c, HBPC_ERR_ARG, "upwind flux needs advection");
     if (equation == HBPC_EQ_BURGERS_BR1 && !(prm->nu >= 0)) set_err(c, HBPC_ERR_ARG, "nu must be >= 0");
     if (prm->gmres_restart < 1 || prm->gmres_restart > 64) set_err(c, HBPC_ERR_ARG, "gmres_restart must be 1..64");
+    if (prm->precond < HBPC_PC_NONE || prm->precond > HBPC_PC_LEARNED) set_err(c, HBPC_ERR_ARG, "unknown precond");
+    if (prm->mlp_precision != HBPC_MLP_BF16 && prm->mlp_precision != HBPC_MLP_FP32)
+        set_err(c, HBPC_ERR_ARG, "unknown mlp_precision");
     if (prm->q != 4 && prm->q != 6 && prm->q != 8) set_err(c, HBPC_ERR_ARG, "q must be 4, 6 or 8");
     if (prm->kmax < 0) set_err(c, HBPC_ERR_ARG, "kmax must be >= 0");
     if (equation == HBPC_EQ_EULER && !(prm->eps_ref > 0 && prm->gamma > 1))
@@ -779,7 +1109,20 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
     c->kr_f32 = prm->precision == HBPC_MIXED;
     size_t ksz = c->kr_f32 ? 4 : 8;
     c->V = dalloc<char>(c, (size_t)(c->m_alloc + 1) * c->n2 * ksz);
-    c->Z = prm->precond == HBPC_PC_BJEXT ? (void*)dalloc<char>(c, (size_t)c->m_alloc * c->n2 * ksz) : nullptr;
+    c->Z = prm->precond != HBPC_PC_NONE ? (void*)dalloc<char>(c, (size_t)c->m_alloc * c->n2 * ksz) : nullptr;
+    // learned preconditioner: network shape and FP32 parameters / Adam moments / gradient
+    c->mlp_H = 256;
+    c->mlp_nin = (2 * c->D + 1) * 2 * c->NE + 2;
+    c->mlp_nr = (2 * c->D + 1) * c->NE;
+    {
+        const size_t nr = c->mlp_nr, nw = c->mlp_nin - c->mlp_nr, H = c->mlp_H, no = c->NE;
+        c->mlp_np = nr * H + nw * H + H + 2 * H * H + H + H * no;
+    }
+    c->theta = dalloc<float>(c, c->mlp_np);
+    c->adam_m = dalloc<float>(c, c->mlp_np);
+    c->adam_v = dalloc<float>(c, c->mlp_np);
+    c->mgrad = dalloc<float>(c, c->mlp_np);
+    c->lpc_snap = -1;
     c->kv = dalloc<double>(c, 3 * n);
     // K build in chunks of <= 256 MB of FP64 blocks
     size_t per = (size_t)c->NE * c->NE * 8;
@@ -790,6 +1133,62 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
     void* h = nullptr;
     hipchk(c, hipHostMalloc(&h, 256 * sizeof(double)), "hipHostMalloc");
     c->hres = (double*)h;
+}
+
+static void train_impl(hbpc_ctx* c, const float* X, const float* T, size_t count, const hbpc_train_cfg* cfg,
+                       hbpc_train_log* log) {
+    const double t0 = now_ms();
+    if (!c->mlp_ready) set_err(c, HBPC_ERR_ARG, "hbpc_mlp_set_params before training");
+    const int B = (int)std::min<size_t>((size_t)cfg->batch, count);
+    const int ni = c->mlp_nin, no = c->NE, bf16 = cfg->precision == HBPC_MLP_BF16;
+    mlp_train_alloc(c, B);
+    if (c->tr_idx_cap < count) {
+        dfree(c->tr_idx_dev);
+        c->tr_idx_dev = nullptr;
+        c->tr_idx_cap = 0;
+        c->tr_idx_dev = dalloc<int>(c, count);
+        c->tr_idx_cap = count;
+    }
+    // batch buffers behind the activations of mlp_loss_grad_dev
+    float* Xb = c->tr_buf + (size_t)B * (10 * (size_t)c->mlp_H + 2 * (size_t)no);
+    float* Tb = Xb + (size_t)B * ni;
+    std::vector<int> perm(count);
+    unsigned long long state = cfg->seed;
+    double* sse = c->dres + 200;
+    int steps = 0;
+    double first = 0.0, last = 0.0;
+    for (int ep = 0; ep < cfg->epochs; ++ep) {
+        for (size_t i = 0; i < count; ++i) perm[i] = (int)i;
+        for (size_t i = count - 1; i > 0; --i) {
+            size_t j = (size_t)(splitmix64(state) % (unsigned long long)(i + 1));
+            std::swap(perm[i], perm[j]);
+        }
+        hipchk(c, hipMemcpyAsync(c->tr_idx_dev, perm.data(), count * sizeof(int), hipMemcpyHostToDevice,
+                                 c->stream),
+               "copy");
+        hipchk(c, hipMemsetAsync(sse, 0, sizeof(double), c->stream), "memset");
+        for (size_t b0 = 0; b0 < count; b0 += B) {
+            const int rows = (int)std::min<size_t>(B, count - b0);
+            hipchk(c, mlp_gather(X, ni, c->tr_idx_dev + b0, rows, ni, Xb, c->stream), "gather");
+            hipchk(c, mlp_gather(T, no, c->tr_idx_dev + b0, rows, no, Tb, c->stream), "gather");
+            mlp_loss_grad_dev(c, Xb, Tb, rows, c->mgrad, sse, bf16);
+            mlp_adam_dev(c, c->mgrad, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps);
+            ++steps;
+        }
+        double h = 0.0;
+        hipchk(c, hipMemcpyAsync(&h, sse, sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy");
+        hipchk(c, hipStreamSynchronize(c->stream), "sync");   // perm is reused by the next epoch
+        const double mean = h / ((double)count * no);
+        if (!std::isfinite(mean)) set_err(c, HBPC_ERR_NONFINITE, "non-finite training loss");
+        if (ep == 0) first = mean;
+        last = mean;
+    }
+    if (log) {
+        log->steps = steps;
+        log->loss_first = first;
+        log->loss_last = last;
+        log->ms = now_ms() - t0;
+    }
 }
 
 // ------------------------------------------------------------------ C ABI
@@ -829,6 +1228,8 @@ void hbpc_default_params(hbpc_params* p) {
     p->pc_rebuild = HBPC_PC_PER_SOLVE;
     p->jvp_mode = HBPC_JVP_LINEARISED;
     p->hessian = 1;
+    p->mlp_precision = HBPC_MLP_BF16;
+    p->pc_fallback = 0.5;
     p->stream = nullptr;
 }
 
@@ -948,35 +1349,165 @@ int hbpc_jvp_f32(hbpc_ctx* c, const float* w, const float* sigma, double a1dt, d
 int hbpc_pc_build(hbpc_ctx* c, const double* w, double a1dt, double bcoef, int precision) {
     if (!c || !w) return HBPC_ERR_ARG;
     HBPC_TRY(c, {
-        pc_build(c, w, a1dt, bcoef, precision == HBPC_MIXED);
-        if (precision == HBPC_MIXED) {
+        const int f32 = precision == HBPC_MIXED;
+        const int learned = c->prm.precond == HBPC_PC_LEARNED;
+        if (learned && !c->mlp_ready) set_err(c, HBPC_ERR_ARG, "learned preconditioner without parameters");
+        if (!learned) pc_build(c, w, a1dt, bcoef, f32);
+        if (f32) {
             hipchk(c, blas_axpby(1.0, w, 0, 0.0, c->X32, 1, c->ndof, c->stream), "cast");
             op_trace(c, c->X32, c->trw32, 1);
         } else {
             hipchk(c, hipMemcpyAsync(c->tmp[1], w, c->ndof * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
+        }
+        if (learned) {
+            lpc_prepare(c, f32 ? (const void*)c->X32 : (const void*)c->tmp[1], f32, a1dt, bcoef);
+            c->lpc_snap = f32;
         }
     });
 }
 
 int hbpc_pc_apply(hbpc_ctx* c, const double* X, double* Y) {
     if (!c || !X || !Y) return HBPC_ERR_ARG;
-    if (!c->pc_valid || c->sinv_f32) {
+    const int learned = c->prm.precond == HBPC_PC_LEARNED;
+    if (learned ? c->lpc_snap != 0 : (!c->pc_valid || c->sinv_f32)) {
         c->err = "hbpc_pc_apply needs an FP64 hbpc_pc_build first";
         return HBPC_ERR_ARG;
     }
     HBPC_TRY(c, {
         op_trace(c, c->tmp[1], c->trw, 0);
-        pc_apply(c, c->tmp[1], c->trw, X, Y, 0);
+        if (learned) lpc_apply(c, c->tmp[1], c->trw, X, Y, 0);
+        else pc_apply(c, c->tmp[1], c->trw, X, Y, 0);
     });
 }
 
 int hbpc_pc_apply_f32(hbpc_ctx* c, const float* X, float* Y) {
     if (!c || !X || !Y) return HBPC_ERR_ARG;
-    if (!c->pc_valid || !c->sinv_f32) {
+    const int learned = c->prm.precond == HBPC_PC_LEARNED;
+    if (learned ? c->lpc_snap != 1 : (!c->pc_valid || !c->sinv_f32)) {
         c->err = "hbpc_pc_apply_f32 needs an HBPC_MIXED hbpc_pc_build first";
         return HBPC_ERR_ARG;
     }
-    HBPC_TRY(c, pc_apply(c, c->X32, c->trw32, X, Y, 1));
+    HBPC_TRY(c, {
+        if (learned) lpc_apply(c, c->X32, c->trw32, X, Y, 1);
+        else pc_apply(c, c->X32, c->trw32, X, Y, 1);
+    });
+}
+
+// ---- learned preconditioner network
+int hbpc_mlp_shape(const hbpc_ctx* c, int* n_in, int* hidden, int* n_out, size_t* n_params) {
+    if (!c) return HBPC_ERR_ARG;
+    if (n_in) *n_in = c->mlp_nin;
+    if (hidden) *hidden = c->mlp_H;
+    if (n_out) *n_out = c->NE;
+    if (n_params) *n_params = c->mlp_np;
+    return HBPC_OK;
+}
+
+int hbpc_mlp_set_params(hbpc_ctx* c, const float* theta) {
+    if (!c || !theta) return HBPC_ERR_ARG;
+    HBPC_TRY(c, {
+        const size_t b = c->mlp_np * sizeof(float);
+        hipchk(c, hipMemcpyAsync(c->theta, theta, b, hipMemcpyDeviceToDevice, c->stream), "copy");
+        hipchk(c, hipMemsetAsync(c->adam_m, 0, b, c->stream), "memset");
+        hipchk(c, hipMemsetAsync(c->adam_v, 0, b, c->stream), "memset");
+        c->adam_t = 0;
+        c->mlp_ready = 1;
+    });
+}
+
+int hbpc_mlp_get_params(hbpc_ctx* c, float* theta) {
+    if (!c || !theta) return HBPC_ERR_ARG;
+    HBPC_TRY(c, hipchk(c, hipMemcpyAsync(theta, c->theta, c->mlp_np * sizeof(float), hipMemcpyDeviceToDevice,
+                                         c->stream),
+                       "copy"));
+}
+
+int hbpc_mlp_features(hbpc_ctx* c, const double* rt, const double* w, const double* dw, const int* elems, int count,
+                      double a1dt, double bcoef, float* X, float* T, float* scale) {
+    if (!c || !rt || !w || !X || count < 0 || (dw && !T)) return HBPC_ERR_ARG;
+    if (!elems && count > c->nE) return HBPC_ERR_ARG;
+    HBPC_TRY(c, features_p(c, rt, w, dw, 0, elems, count, a1dt, bcoef, X, dw ? T : nullptr, scale, 3));
+}
+
+int hbpc_mlp_forward(hbpc_ctx* c, const float* X, int rows, float* Y, int precision) {
+    if (!c || !X || !Y || rows < 0) return HBPC_ERR_ARG;
+    if (precision != HBPC_MLP_BF16 && precision != HBPC_MLP_FP32) return HBPC_ERR_ARG;
+    HBPC_TRY(c, {
+        mlp_train_alloc(c, rows);
+        const size_t RH = (size_t)rows * c->mlp_H;
+        float* G1 = c->tr_buf;
+        const int bf16 = precision == HBPC_MLP_BF16;
+        mlp_gates(c, X, rows, G1, G1 + RH, bf16);
+        mlp_residual_path(c, X, rows, G1, G1 + RH, G1 + 2 * RH, G1 + 3 * RH, Y, bf16);
+    });
+}
+
+int hbpc_mlp_loss_grad(hbpc_ctx* c, const float* X, const float* T, int rows, float* grad, double* loss_host,
+                       int precision) {
+    if (!c || !X || !T || !grad || rows <= 0) return HBPC_ERR_ARG;
+    if (precision != HBPC_MLP_BF16 && precision != HBPC_MLP_FP32) return HBPC_ERR_ARG;
+    HBPC_TRY(c, {
+        double* sse = c->dres + 200;
+        hipchk(c, hipMemsetAsync(sse, 0, sizeof(double), c->stream), "memset");
+        mlp_loss_grad_dev(c, X, T, rows, grad, sse, precision == HBPC_MLP_BF16);
+        double h = 0.0;
+        hipchk(c, hipMemcpyAsync(&h, sse, sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy");
+        hipchk(c, hipStreamSynchronize(c->stream), "sync");
+        if (loss_host) *loss_host = h / ((double)rows * c->NE);
+    });
+}
+
+int hbpc_mlp_adam(hbpc_ctx* c, const float* grad, double lr, double beta1, double beta2, double eps) {
+    if (!c || !grad) return HBPC_ERR_ARG;
+    HBPC_TRY(c, mlp_adam_dev(c, grad, lr, beta1, beta2, eps));
+}
+
+int hbpc_mlp_collect(hbpc_ctx* c, float* X, float* T, size_t capacity, int per_event, unsigned long long seed,
+                     int source, int every) {
+    if (!c) return HBPC_ERR_ARG;
+    if (capacity == 0) {
+        c->col_X = c->col_T = nullptr;
+        c->col_cap = 0;
+        return HBPC_OK;
+    }
+    if (!X || !T || per_event < 1 || every < 1) return HBPC_ERR_ARG;
+    if (source < HBPC_MLP_PAIRS_NEWTON || source > HBPC_MLP_PAIRS_RANDOM) return HBPC_ERR_ARG;
+    c->col_source = source;
+    c->col_every = every;
+    HBPC_TRY(c, {
+        if (!c->col_elems) c->col_elems = dalloc<int>(c, c->nE);
+        c->col_X = X;
+        c->col_T = T;
+        c->col_cap = capacity;
+        c->col_count = 0;
+        c->col_per = per_event;
+        c->col_seed = seed;
+        c->col_draws = 0;
+    });
+}
+
+size_t hbpc_mlp_collected(const hbpc_ctx* c) { return c ? c->col_count : 0; }
+
+void hbpc_default_train_cfg(hbpc_train_cfg* cfg) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->epochs = 40;
+    cfg->batch = 256;
+    cfg->lr = 1e-3;
+    cfg->beta1 = 0.9;
+    cfg->beta2 = 0.999;
+    cfg->eps = 1e-8;
+    cfg->seed = 2109;
+    cfg->precision = HBPC_MLP_BF16;
+}
+
+int hbpc_train_mlp(hbpc_ctx* c, const float* X, const float* T, size_t count, const hbpc_train_cfg* cfg,
+                   hbpc_train_log* log) {
+    if (!c || !X || !T || !cfg || count == 0) return HBPC_ERR_ARG;
+    if (cfg->epochs < 1 || cfg->batch < 1 || cfg->batch > 8192 || !(cfg->lr > 0)) return HBPC_ERR_ARG;
+    if (cfg->precision != HBPC_MLP_BF16 && cfg->precision != HBPC_MLP_FP32) return HBPC_ERR_ARG;
+    if (count > (size_t)0x7fffffff) return HBPC_ERR_ARG;
+    HBPC_TRY(c, train_impl(c, X, T, count, cfg, log));
 }
 
 int hbpc_step(hbpc_ctx* c, double* w_inout, double dt, hbpc_stats* stats) {
@@ -1025,7 +1556,7 @@ int hbpc_profile_read(hbpc_ctx* c, hbpc_kernel_prof* out, int max, int reset) {
         ++k;
     }
     if (reset) {
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < KC_MAXCLS; ++i) {
             c->kp_launch[i] = 0;
             c->kp_ms[i] = c->kp_bytes[i] = c->kp_flops[i] = 0.0;
         }

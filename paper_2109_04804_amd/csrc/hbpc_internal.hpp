@@ -27,6 +27,25 @@ hipError_t blas_lincomb2(double a, const double* x, double b, const double* z, d
 hipError_t blas_gemv_add(const void* Z, int tz, size_t ld, int k, const double* c, void* y, int ty, size_t n,
                          hipStream_t st);
 hipError_t blas_nonfinite(const void* x, int f32, size_t n, int* status, hipStream_t st);
+hipError_t mlp_gemm(const float* A, long long a_r, long long a_c, const float* B, long long b_r, long long b_c,
+                    float* C, long long ldc, const float* bias, const float* mask, long long ldm, int mask_mul, int M,
+                    int N, int K, int relu, int accumulate, int bf16, hipStream_t st);
+hipError_t mlp_ew_mul(const float* a, const float* b, float* out, long long n, hipStream_t st);
+hipError_t mlp_ew_split(const float* dh, const float* g, const float* a, float* da, float* dz, long long n,
+                        int relu_mask, hipStream_t st);
+hipError_t mlp_ew_relu_mask(float* x, const float* g, long long n, hipStream_t st);
+hipError_t mlp_colsum(const float* X, long long ld, int M, int N, float* out, hipStream_t st);
+hipError_t mlp_mse_grad(const float* Y, const float* T, float* dY, long long n, float scale, double* part, int nblk,
+                        hipStream_t st);
+hipError_t mlp_adam(float* th, const float* g, float* m, float* v, long long n, float lr, float b1, float b2,
+                    float eps, int t, hipStream_t st);
+hipError_t mlp_features(const void* rt, const void* w, const void* dw, int f32, const int* elems, int nb, int D,
+                        const int* nel, int ne, float a1dt, float bc, float* X, float* tgt, float* scale, int part,
+                        hipStream_t st);
+hipError_t mlp_rescale(const float* Y, const float* scale, void* out, int f32, long long n, int ne, hipStream_t st);
+hipError_t mlp_gather(const float* src, long long ld, const int* idx, int rows, int cols, float* dst, hipStream_t st);
+hipError_t mlp_sum_parts(const double* part, int n, double* acc, hipStream_t st);
+hipError_t mlp_randn(void* out, int f32, long long n, unsigned long long seed, hipStream_t st);
 
 // ---- 1-D operators (host, FP64)
 struct Basis1DHost {
@@ -48,7 +67,7 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
-constexpr int KC_MAXCLS = 16;
+constexpr int KC_MAXCLS = 24;
 
 struct hbpc_ctx {
     hbpc_mesh mesh;
@@ -97,6 +116,19 @@ struct hbpc_ctx {
     int* dstatus;
     // FD scratch (allocated on demand)
     double* fd[6];
+    // learned preconditioner (network: n_r residual + n_w state inputs -> H -> H -> NE)
+    int mlp_nin, mlp_nr, mlp_H;
+    size_t mlp_np;
+    float* theta; float* adam_m; float* adam_v; float* mgrad;   // FP32 parameters, moments, gradient
+    int adam_t, mlp_ready;
+    float* ap_X; float* ap_G1; float* ap_G2; float* ap_H1; float* ap_H2; float* ap_Y; float* ap_s;   // nE rows
+    float* tr_buf; int tr_rows;                                        // training buffers (batch rows)
+    int lpc_active;            // learned PC in use for the current stage solve
+    int lpc_snap;              // hbpc_pc_build in learned mode: -1 none, 0 FP64, 1 FP32 snapshot
+    int* tr_idx_dev; size_t tr_idx_cap;
+    float* col_X; float* col_T; size_t col_cap, col_count; int col_per, col_source, col_every;
+    unsigned long long col_seed, col_draws;
+    int* col_elems;
     // statistics of the last step
     hbpc_stats st;
     int cur_solve;
@@ -113,7 +145,7 @@ struct hbpc_ctx {
 };
 
 enum { KC_TRACE = 0, KC_R1, KC_R2, KC_RES, KC_JVP, KC_KCOL, KC_PCPRE, KC_BJAPPLY, KC_BJINV, KC_MDOT, KC_GEMV,
-       KC_VEC, KC_GSDOT, KC_GSUPD, KC_COUNT };
+       KC_VEC, KC_GSDOT, KC_GSUPD, KC_LIN, KC_FEAT, KC_GEMM, KC_MLPV, KC_COUNT };
 
 // helpers implemented in ops.cpp
 int op_launch(hbpc_ctx* c, const LaunchReq& r, int f32);

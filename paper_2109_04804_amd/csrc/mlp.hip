@@ -1,0 +1,422 @@
+// Kernels of the learned per-element preconditioner: feature gather, dense
+// layers (BF16 matrix cores with FP32 accumulation, or plain FP32), loss,
+// backward helpers and Adam.
+//
+// GEMM: C[M x N] = A[M x K] B[K x N] with general strides for A and B (so
+// transposed operands need no copies), FP32 storage, optional bias, ReLU and a
+// mask (C *= (mask > 0), or C *= mask for gating), FP32 output.  In BF16 mode the operands are rounded
+// to BF16 (round to nearest even) while they are staged in LDS and multiplied
+// by v_mfma_f32_16x16x16_bf16; in FP32 mode the same tiling runs FP32 FMAs.
+// Block tile 64 x 64 x 32, 256 threads (4 waves, 32 x 32 output per wave).
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 32;
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even (finite inputs)
+    return (uint16_t)(u >> 16);
+}
+
+struct GemmArgs {
+    const float* A; long long a_r, a_c;   // A(i,k) = A[i*a_r + k*a_c]
+    const float* B; long long b_r, b_c;   // B(k,j) = B[k*b_r + j*b_c]
+    float* C; long long ldc;              // C(i,j) = C[i*ldc + j]
+    const float* bias;                    // bias[j] or null
+    const float* mask; long long ldm;     // mask(i,j) (null: none)
+    int mask_mul;                         // 0: multiply by (mask > 0), 1: multiply by mask
+    int M, N, K;
+    int relu;
+    int accumulate;                       // C += result
+};
+
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+template <bool BF16>
+__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
+    // LDS tiles: As[i][k] and Bs[j][k] (k contiguous for both)
+    __shared__ float As32[BF16 ? 1 : BM][BK + 1];
+    __shared__ float Bs32[BF16 ? 1 : BN][BK + 1];
+    __shared__ __align__(16) uint16_t As16[BF16 ? BM : 1][BK + 4];   // row pitch 72 B: 8-byte aligned
+    __shared__ __align__(16) uint16_t Bs16[BF16 ? BN : 1][BK + 4];
+    const int tid = threadIdx.x;
+    const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BN;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;   // wave sub-tile origin
+
+    float4_t acc[2][2];
+    float accf[4][4];
+    if (BF16) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[a][b] = (float4_t){0.f, 0.f, 0.f, 0.f};
+    } else {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) accf[a][b] = 0.f;
+    }
+    const int ti = tid / 16, tj = tid % 16;   // FP32 mode: 4x4 outputs at (ti + 16a, tj + 16b)
+
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+        // A tile (k contiguous in LDS); walk the operand along its unit stride
+        for (int idx = tid; idx < BM * BK; idx += 256) {
+            const int ii = g.a_c == 1 ? idx / BK : idx % BM;
+            const int kk = g.a_c == 1 ? idx % BK : idx / BM;
+            const int gi = i0 + ii, gk = k0 + kk;
+            const float v = (gi < g.M && gk < g.K) ? g.A[gi * g.a_r + gk * g.a_c] : 0.f;
+            if (BF16) As16[ii][kk] = f2bf(v);
+            else As32[ii][kk] = v;
+        }
+        for (int idx = tid; idx < BN * BK; idx += 256) {
+            const int jj = g.b_c == 1 ? idx % BN : idx / BK;
+            const int kk = g.b_c == 1 ? idx / BN : idx % BK;
+            const int gj = j0 + jj, gk = k0 + kk;
+            const float v = (gj < g.N && gk < g.K) ? g.B[gk * g.b_r + gj * g.b_c] : 0.f;
+            if (BF16) Bs16[jj][kk] = f2bf(v);
+            else Bs32[jj][kk] = v;
+        }
+        __syncthreads();
+        if (BF16) {
+            // v_mfma_f32_16x16x16_bf16: lane l holds A[l%16][4(l/16)..+3], B[4(l/16)..+3][l%16],
+            // and D[4(l/16)+r][l%16], r = 0..3
+            const int lr = lane & 15, lk = (lane >> 4) * 4;
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 16) {
+                short4_t af[2], bf[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    af[a] = *(const short4_t*)&As16[wi + 16 * a + lr][kk + lk];
+                }
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    bf[b] = *(const short4_t*)&Bs16[wj + 16 * b + lr][kk + lk];
+                }
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[a], bf[b], acc[a][b], 0, 0, 0);
+            }
+        } else {
+#pragma unroll 4
+            for (int kk = 0; kk < BK; ++kk) {
+                float ra[4], rb[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) ra[a] = As32[ti + 16 * a][kk];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) rb[b] = Bs32[tj + 16 * b][kk];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) accf[a][b] += ra[a] * rb[b];
+            }
+        }
+        __syncthreads();
+    }
+    // epilogue
+    auto store = [&](int i, int j, float v) {
+        if (i >= g.M || j >= g.N) return;
+        if (g.bias) v += g.bias[j];
+        if (g.relu) v = v > 0.f ? v : 0.f;
+        if (g.mask) {
+            const float mk = g.mask[i * g.ldm + j];
+            v = g.mask_mul ? v * mk : (mk > 0.f ? v : 0.f);
+        }
+        float* c = g.C + i * g.ldc + j;
+        *c = g.accumulate ? *c + v : v;
+    };
+    if (BF16) {
+        const int lr = lane & 15, lq = (lane >> 4) * 4;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) store(i0 + wi + 16 * a + lq + r, j0 + wj + 16 * b + lr, acc[a][b][r]);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) store(i0 + ti + 16 * a, j0 + tj + 16 * b, accf[a][b]);
+    }
+}
+
+// column sums: out[j] (+)= sum_i X[i*ld + j]
+__global__ void __launch_bounds__(256) colsum_kernel(const float* __restrict__ X, long long ld, int M, int N,
+                                                     float* __restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    double s = 0.0;
+    for (int i = 0; i < M; ++i) s += X[i * ld + j];
+    out[j] = (float)s;
+}
+
+// dY = 2 (Y - T) / (M N); per-block partial of sum (Y - T)^2
+__global__ void __launch_bounds__(256) mse_grad_kernel(const float* __restrict__ Y, const float* __restrict__ T,
+                                                       float* __restrict__ dY, long long n, float scale,
+                                                       double* __restrict__ part) {
+    __shared__ double sh[4];
+    double acc = 0.0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const float d = Y[i] - T[i];
+        dY[i] = 2.f * d * scale;
+        acc += (double)d * d;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ th, const float* __restrict__ g,
+                                                   float* __restrict__ m, float* __restrict__ v, long long n,
+                                                   float lr, float b1, float b2, float eps, float c1, float c2) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+// Feature rows of the learned preconditioner, one block per sample:
+// X[s] = [rt tiles of (e, its 2d face neighbours) / scale, w tiles of the same, c1, c2],
+// scale = RMS of the rt patch (+1e-30); targets (optional) = dw_e / scale.
+// part: bit 0 = residual tiles (and scale, targets), bit 1 = state tiles and coefficients
+template <typename T>
+__global__ void __launch_bounds__(256) features_kernel(const T* __restrict__ rt, const T* __restrict__ w,
+                                                       const T* __restrict__ dw, const int* __restrict__ elems,
+                                                       int nb, int D, int nel0, int nel1, int nel2, int ne,
+                                                       float c1, float c2, float* __restrict__ X,
+                                                       float* __restrict__ tgt, float* __restrict__ scale,
+                                                       int part) {
+    __shared__ int patch[7];
+    __shared__ double red[4];
+    const int s = blockIdx.x;
+    if (s >= nb) return;
+    const int e = elems ? elems[s] : s;
+    const int np = 2 * D + 1;
+    const int nin = 2 * np * ne + 2;
+    if (e < 0 || e >= nel0 * nel1 * nel2) {   // element index out of range: zero row
+        for (int i = threadIdx.x; i < nin; i += blockDim.x) X[(size_t)s * nin + i] = 0.f;
+        if (threadIdx.x == 0 && scale) scale[s] = 0.f;
+        if (tgt)
+            for (int i = threadIdx.x; i < ne; i += blockDim.x) tgt[(size_t)s * ne + i] = 0.f;
+        return;
+    }
+    if (threadIdx.x == 0) {
+        int c[3] = {e % nel0, D > 1 ? (e / nel0) % nel1 : 0, D > 2 ? e / (nel0 * nel1) : 0};
+        int n[3] = {nel0, nel1, nel2};
+        patch[0] = e;
+        for (int m = 0; m < D; ++m)
+            for (int sd = 0; sd < 2; ++sd) {
+                int cc[3] = {c[0], c[1], c[2]};
+                cc[m] = (cc[m] + (sd ? 1 : -1) + n[m]) % n[m];
+                patch[1 + 2 * m + sd] = cc[0] + nel0 * (cc[1] + nel1 * cc[2]);
+            }
+    }
+    __syncthreads();
+    float* row = X + (size_t)s * nin;
+    if (part & 2) {
+        for (int i = threadIdx.x; i < np * ne; i += blockDim.x)
+            row[np * ne + i] = (float)w[(size_t)patch[i / ne] * ne + (i % ne)];
+        if (threadIdx.x == 0) {
+            row[nin - 2] = c1;
+            row[nin - 1] = c2;
+        }
+    }
+    if (!(part & 1)) return;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np * ne; i += blockDim.x) {
+        const double v = (double)rt[(size_t)patch[i / ne] * ne + (i % ne)];
+        acc += v * v;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    const double sc = sqrt((red[0] + red[1] + red[2] + red[3]) / (np * ne)) + 1e-30;
+    const double isc = 1.0 / sc;
+    for (int i = threadIdx.x; i < np * ne; i += blockDim.x)
+        row[i] = (float)((double)rt[(size_t)patch[i / ne] * ne + (i % ne)] * isc);
+    if (threadIdx.x == 0 && scale) scale[s] = (float)sc;
+    if (tgt)
+        for (int i = threadIdx.x; i < ne; i += blockDim.x)
+            tgt[(size_t)s * ne + i] = (float)((double)dw[(size_t)e * ne + i] * isc);
+}
+
+// out[e][i] = scale[e] * Y[e][i] (w block of the preconditioned vector)
+template <typename T>
+__global__ void __launch_bounds__(256) rescale_kernel(const float* __restrict__ Y, const float* __restrict__ scale,
+                                                      T* __restrict__ out, long long n, int ne) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        out[i] = (T)((double)Y[i] * (double)scale[i / ne]);
+}
+
+// out = a * b
+__global__ void __launch_bounds__(256) ew_mul_kernel(const float* __restrict__ a, const float* __restrict__ b,
+                                                     float* __restrict__ out, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        out[i] = a[i] * b[i];
+}
+
+// backward through h = a * g (g = relu(z)): da = dh * g, dz = dh * a [* (g > 0)]
+__global__ void __launch_bounds__(256) ew_split_kernel(const float* __restrict__ dh, const float* __restrict__ g,
+                                                       const float* __restrict__ a, float* __restrict__ da,
+                                                       float* __restrict__ dz, long long n, int relu_mask) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const float d = dh[i], gi = g[i];
+        da[i] = d * gi;
+        const float z = d * a[i];
+        dz[i] = relu_mask ? (gi > 0.f ? z : 0.f) : z;
+    }
+}
+
+// x *= (g > 0)
+__global__ void __launch_bounds__(256) ew_relu_mask_kernel(float* __restrict__ x, const float* __restrict__ g,
+                                                           long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        if (!(g[i] > 0.f)) x[i] = 0.f;
+}
+
+// splitmix64 finaliser (Steele, Lea & Flood 2014) of the counter value seed + (k + 1) * golden gamma
+__device__ __forceinline__ unsigned long long sm64_at(unsigned long long seed, unsigned long long k) {
+    unsigned long long z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// standard normal values by the Box-Muller transform of two counter-based uniforms in (0, 1]
+template <typename T>
+__global__ void __launch_bounds__(256) randn_kernel(T* __restrict__ out, long long n, unsigned long long seed) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const double u1 = ((double)(sm64_at(seed, 2ull * i) >> 11) + 1.0) * 0x1.0p-53;
+        const double u2 = (double)(sm64_at(seed, 2ull * i + 1ull) >> 11) * 0x1.0p-53;
+        out[i] = (T)(sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
+    }
+}
+
+// out[r][:] = src[idx[r]][:] (mini-batch gather)
+__global__ void __launch_bounds__(256) gather_rows_kernel(const float* __restrict__ src, long long ld,
+                                                          const int* __restrict__ idx, int cols,
+                                                          float* __restrict__ dst) {
+    const float* s = src + (size_t)idx[blockIdx.x] * ld;
+    float* d = dst + (size_t)blockIdx.x * cols;
+    for (int c = threadIdx.x; c < cols; c += blockDim.x) d[c] = s[c];
+}
+
+// *acc += sum of the n block partials (one thread)
+__global__ void sum_parts_kernel(const double* __restrict__ part, int n, double* __restrict__ acc) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    *acc += s;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+hipError_t mlp_gemm(const float* A, long long a_r, long long a_c, const float* B, long long b_r, long long b_c,
+                    float* C, long long ldc, const float* bias, const float* mask, long long ldm, int mask_mul, int M,
+                    int N, int K, int relu, int accumulate, int bf16, hipStream_t st) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    GemmArgs g{A, a_r, a_c, B, b_r, b_c, C, ldc, bias, mask, ldm, mask_mul, M, N, K, relu, accumulate};
+    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
+    if (bf16) hipLaunchKernelGGL(gemm_kernel<true>, grid, dim3(256), 0, st, g);
+    else hipLaunchKernelGGL(gemm_kernel<false>, grid, dim3(256), 0, st, g);
+    return hipGetLastError();
+}
+
+hipError_t mlp_colsum(const float* X, long long ld, int M, int N, float* out, hipStream_t st) {
+    hipLaunchKernelGGL(colsum_kernel, dim3((N + 255) / 256), dim3(256), 0, st, X, ld, M, N, out);
+    return hipGetLastError();
+}
+
+hipError_t mlp_mse_grad(const float* Y, const float* T, float* dY, long long n, float scale, double* part, int nblk,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(mse_grad_kernel, dim3(nblk), dim3(256), 0, st, Y, T, dY, n, scale, part);
+    return hipGetLastError();
+}
+
+hipError_t mlp_adam(float* th, const float* g, float* m, float* v, long long n, float lr, float b1, float b2,
+                    float eps, int t, hipStream_t st) {
+    const float c1 = (float)(1.0 - pow((double)b1, t)), c2 = (float)(1.0 - pow((double)b2, t));
+    long long blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)blocks), dim3(256), 0, st, th, g, m, v, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t mlp_features(const void* rt, const void* w, const void* dw, int f32, const int* elems, int nb, int D,
+                        const int* nel, int ne, float a1dt, float bc, float* X, float* tgt, float* scale, int part,
+                        hipStream_t st) {
+    if (nb <= 0) return hipSuccess;
+    if (f32)
+        hipLaunchKernelGGL(features_kernel<float>, dim3(nb), dim3(256), 0, st, (const float*)rt, (const float*)w,
+                           (const float*)dw, elems, nb, D, nel[0], nel[1], nel[2], ne, a1dt, bc, X, tgt, scale, part);
+    else
+        hipLaunchKernelGGL(features_kernel<double>, dim3(nb), dim3(256), 0, st, (const double*)rt, (const double*)w,
+                           (const double*)dw, elems, nb, D, nel[0], nel[1], nel[2], ne, a1dt, bc, X, tgt, scale,
+                           part);
+    return hipGetLastError();
+}
+
+static unsigned ew_blocks(long long n) {
+    long long b = (n + 255) / 256;
+    return (unsigned)(b > 4096 ? 4096 : (b < 1 ? 1 : b));
+}
+
+hipError_t mlp_ew_mul(const float* a, const float* b, float* out, long long n, hipStream_t st) {
+    hipLaunchKernelGGL(ew_mul_kernel, dim3(ew_blocks(n)), dim3(256), 0, st, a, b, out, n);
+    return hipGetLastError();
+}
+
+hipError_t mlp_ew_split(const float* dh, const float* g, const float* a, float* da, float* dz, long long n,
+                        int relu_mask, hipStream_t st) {
+    hipLaunchKernelGGL(ew_split_kernel, dim3(ew_blocks(n)), dim3(256), 0, st, dh, g, a, da, dz, n, relu_mask);
+    return hipGetLastError();
+}
+
+hipError_t mlp_ew_relu_mask(float* x, const float* g, long long n, hipStream_t st) {
+    hipLaunchKernelGGL(ew_relu_mask_kernel, dim3(ew_blocks(n)), dim3(256), 0, st, x, g, n);
+    return hipGetLastError();
+}
+
+hipError_t mlp_rescale(const float* Y, const float* scale, void* out, int f32, long long n, int ne, hipStream_t st) {
+    long long blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (f32)
+        hipLaunchKernelGGL(rescale_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, Y, scale, (float*)out, n, ne);
+    else
+        hipLaunchKernelGGL(rescale_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, Y, scale, (double*)out, n,
+                           ne);
+    return hipGetLastError();
+}
+
+hipError_t mlp_gather(const float* src, long long ld, const int* idx, int rows, int cols, float* dst, hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(rows), dim3(256), 0, st, src, ld, idx, cols, dst);
+    return hipGetLastError();
+}
+
+hipError_t mlp_sum_parts(const double* part, int n, double* acc, hipStream_t st) {
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(64), 0, st, part, n, acc);
+    return hipGetLastError();
+}
+
+hipError_t mlp_randn(void* out, int f32, long long n, unsigned long long seed, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (f32) hipLaunchKernelGGL(randn_kernel<float>, dim3(ew_blocks(n)), dim3(256), 0, st, (float*)out, n, seed);
+    else hipLaunchKernelGGL(randn_kernel<double>, dim3(ew_blocks(n)), dim3(256), 0, st, (double*)out, n, seed);
+    return hipGetLastError();
+}

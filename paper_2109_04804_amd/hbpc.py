@@ -20,7 +20,9 @@ EQ = {"advection": 1, "burgers": 2, "euler": 3}
 NODES = {"gauss": 0, "lobatto": 1}
 FLUX = {"central": 0, "upwind": 1, "lf": 2, "rusanov": 3}
 PRECISION = {"fp64": 0, "mixed": 1}
-PRECOND = {"none": 0, "bjext": 1}
+PRECOND = {"none": 0, "bjext": 1, "learned": 2}
+MLP_PRECISION = {"bf16": 0, "fp32": 1}
+PAIRS = {"newton": 0, "krylov": 1, "random": 2}
 JVP = {"linearised": 0, "fd": 1}
 MAX_SOLVES = 64
 
@@ -38,7 +40,8 @@ class HbpcParams(ctypes.Structure):
                 ("newton_maxit", ctypes.c_int), ("gmres_rtol", ctypes.c_double),
                 ("gmres_restart", ctypes.c_int), ("gmres_maxit", ctypes.c_int),
                 ("precision", ctypes.c_int), ("precond", ctypes.c_int), ("pc_rebuild", ctypes.c_int),
-                ("jvp_mode", ctypes.c_int), ("hessian", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("jvp_mode", ctypes.c_int), ("hessian", ctypes.c_int), ("mlp_precision", ctypes.c_int),
+                ("pc_fallback", ctypes.c_double), ("stream", ctypes.c_void_p)]
 
 
 class HbpcStats(ctypes.Structure):
@@ -46,19 +49,31 @@ class HbpcStats(ctypes.Structure):
                 ("pc_builds", ctypes.c_int), ("newton_per_solve", ctypes.c_int * MAX_SOLVES),
                 ("gmres_per_solve", ctypes.c_int * MAX_SOLVES), ("t_step_ms", ctypes.c_double),
                 ("t_pc_build_ms", ctypes.c_double), ("t_gmres_ms", ctypes.c_double),
-                ("t_residual_ms", ctypes.c_double)]
+                ("t_residual_ms", ctypes.c_double), ("pc_fallbacks", ctypes.c_int), ("mlp_samples", ctypes.c_int)]
 
     def as_dict(self):
         n = min(self.n_solves, MAX_SOLVES)
         return {"n_solves": self.n_solves, "newton_its": self.newton_its, "gmres_its": self.gmres_its,
                 "pc_builds": self.pc_builds, "newton_per_solve": list(self.newton_per_solve[:n]),
                 "gmres_per_solve": list(self.gmres_per_solve[:n]), "t_step_ms": self.t_step_ms,
-                "t_pc_build_ms": self.t_pc_build_ms, "t_gmres_ms": self.t_gmres_ms}
+                "t_pc_build_ms": self.t_pc_build_ms, "t_gmres_ms": self.t_gmres_ms,
+                "pc_fallbacks": self.pc_fallbacks, "mlp_samples": self.mlp_samples}
 
 
 class HbpcKernelProf(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 16), ("launches", ctypes.c_int), ("total_ms", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
+
+
+class HbpcTrainCfg(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
+                ("seed", ctypes.c_ulonglong), ("precision", ctypes.c_int)]
+
+
+class HbpcTrainLog(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int), ("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
+                ("ms", ctypes.c_double)]
 
 
 # every symbol include/hbpc.h declares, with its ctypes signature
@@ -82,6 +97,18 @@ SIGNATURES = {
     "hbpc_pc_apply": (_I, [_P, _P, _P]),
     "hbpc_pc_apply_f32": (_I, [_P, _P, _P]),
     "hbpc_step": (_I, [_P, _P, _D, ctypes.POINTER(HbpcStats)]),
+    "hbpc_mlp_shape": (_I, [_P, _P, _P, _P, _P]),
+    "hbpc_mlp_set_params": (_I, [_P, _P]),
+    "hbpc_mlp_get_params": (_I, [_P, _P]),
+    "hbpc_mlp_features": (_I, [_P, _P, _P, _P, _P, _I, _D, _D, _P, _P, _P]),
+    "hbpc_mlp_forward": (_I, [_P, _P, _I, _P, _I]),
+    "hbpc_mlp_loss_grad": (_I, [_P, _P, _P, _I, _P, ctypes.POINTER(_D), _I]),
+    "hbpc_mlp_adam": (_I, [_P, _P, _D, _D, _D, _D]),
+    "hbpc_mlp_collect": (_I, [_P, _P, _P, ctypes.c_size_t, _I, ctypes.c_ulonglong, _I, _I]),
+    "hbpc_mlp_collected": (ctypes.c_size_t, [_P]),
+    "hbpc_default_train_cfg": (None, [ctypes.POINTER(HbpcTrainCfg)]),
+    "hbpc_train_mlp": (_I, [_P, _P, _P, ctypes.c_size_t, ctypes.POINTER(HbpcTrainCfg),
+                            ctypes.POINTER(HbpcTrainLog)]),
     "hbpc_profile_enable": (_I, [_P, _I]),
     "hbpc_profile_read": (_I, [_P, ctypes.POINTER(HbpcKernelProf), _I, _I]),
     "hbpc_strerror": (ctypes.c_char_p, [_I]),
@@ -123,7 +150,8 @@ def default_params():
 def make_params(**kw):
     """HbpcParams from the defaults plus keyword overrides (string enums accepted)."""
     p = default_params()
-    maps = {"nodes": NODES, "flux": FLUX, "precision": PRECISION, "precond": PRECOND, "jvp_mode": JVP}
+    maps = {"nodes": NODES, "flux": FLUX, "precision": PRECISION, "precond": PRECOND, "jvp_mode": JVP,
+            "mlp_precision": MLP_PRECISION}
     for k, v in kw.items():
         if k in maps and isinstance(v, str):
             v = maps[k][v]
@@ -267,8 +295,8 @@ class Context:
 
     def profile_read(self, reset=True):
         """Per kernel class: launches, total ms, algorithmic bytes and flops."""
-        arr = (HbpcKernelProf * 16)()
-        k = self.lib.hbpc_profile_read(self.h, arr, 16, 1 if reset else 0)
+        arr = (HbpcKernelProf * 32)()
+        k = self.lib.hbpc_profile_read(self.h, arr, 32, 1 if reset else 0)
         if k < 0:
             self._check(k)
         return {arr[i].name.decode(): {"launches": arr[i].launches, "total_ms": arr[i].total_ms,
@@ -280,3 +308,91 @@ class Context:
         st = HbpcStats()
         self._check(self.lib.hbpc_step(self.h, _ptr(w, self.ndof, torch.float64), float(dt), ctypes.byref(st)))
         return st.as_dict()
+
+    # ---- learned preconditioner network
+    def mlp_shape(self):
+        """(n_in, hidden, n_out, n_params) of the per-element network."""
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        n = ctypes.c_size_t()
+        self._check(self.lib.hbpc_mlp_shape(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                            ctypes.byref(n)))
+        return a.value, b.value, c.value, n.value
+
+    def mlp_set_params(self, theta):
+        import torch
+        self._check(self.lib.hbpc_mlp_set_params(self.h, _ptr(theta, self.mlp_shape()[3], torch.float32)))
+
+    def mlp_get_params(self, out):
+        import torch
+        self._check(self.lib.hbpc_mlp_get_params(self.h, _ptr(out, self.mlp_shape()[3], torch.float32)))
+        return out
+
+    def mlp_features(self, rt, w, a1dt, bcoef, X, scale=None, dw=None, T=None, elems=None, count=None):
+        import torch
+        n_in, _, n_out, _ = self.mlp_shape()
+        if count is None:
+            count = elems.numel() if elems is not None else self.ndof // self.block
+        self._check(self.lib.hbpc_mlp_features(
+            self.h, _ptr(rt, self.ndof, torch.float64), _ptr(w, self.ndof, torch.float64),
+            _ptr(dw, self.ndof, torch.float64), _ptr(elems, count, torch.int32), int(count), float(a1dt),
+            float(bcoef), _ptr(X, count * n_in, torch.float32), _ptr(T, count * n_out, torch.float32),
+            _ptr(scale, count, torch.float32)))
+        return X
+
+    def mlp_forward(self, X, rows, Y, precision="bf16"):
+        import torch
+        n_in, _, n_out, _ = self.mlp_shape()
+        self._check(self.lib.hbpc_mlp_forward(self.h, _ptr(X, rows * n_in, torch.float32), int(rows),
+                                              _ptr(Y, rows * n_out, torch.float32), MLP_PRECISION[precision]))
+        return Y
+
+    def mlp_loss_grad(self, X, T, rows, grad, precision="bf16"):
+        """Mean squared error (host float) and its gradient (into grad)."""
+        import torch
+        n_in, _, n_out, n_p = self.mlp_shape()
+        loss = ctypes.c_double()
+        self._check(self.lib.hbpc_mlp_loss_grad(self.h, _ptr(X, rows * n_in, torch.float32),
+                                                _ptr(T, rows * n_out, torch.float32), int(rows),
+                                                _ptr(grad, n_p, torch.float32), ctypes.byref(loss),
+                                                MLP_PRECISION[precision]))
+        return loss.value
+
+    def mlp_adam(self, grad, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        import torch
+        self._check(self.lib.hbpc_mlp_adam(self.h, _ptr(grad, self.mlp_shape()[3], torch.float32), float(lr),
+                                           float(beta1), float(beta2), float(eps)))
+
+    def mlp_collect(self, X, T, capacity, per_event, seed, source="newton", every=1):
+        """Collect (features, target) pairs during subsequent steps into X, T (device
+        float32 views of at least capacity rows); source "newton" or "krylov"."""
+        import torch
+        n_in, _, n_out, _ = self.mlp_shape()
+        if capacity == 0:
+            self._check(self.lib.hbpc_mlp_collect(self.h, None, None, 0, 1, 0, 0, 1))
+            return
+        xs = X.view(-1)[: capacity * n_in]
+        ts = T.view(-1)[: capacity * n_out]
+        self._check(self.lib.hbpc_mlp_collect(self.h, _ptr(xs, capacity * n_in, torch.float32),
+                                              _ptr(ts, capacity * n_out, torch.float32), int(capacity),
+                                              int(per_event), int(seed), PAIRS[source], int(every)))
+
+    def mlp_collected(self):
+        return int(self.lib.hbpc_mlp_collected(self.h))
+
+    def train_mlp(self, X, T, count, **cfg):
+        """Adam training on `count` pairs; cfg overrides the library defaults."""
+        import torch
+        n_in, _, n_out, _ = self.mlp_shape()
+        c = HbpcTrainCfg()
+        self.lib.hbpc_default_train_cfg(ctypes.byref(c))
+        for k, v in cfg.items():
+            if k == "precision" and isinstance(v, str):
+                v = MLP_PRECISION[v]
+            setattr(c, k, v)
+        log = HbpcTrainLog()
+        xs = X.view(-1)[: count * n_in]
+        ts = T.view(-1)[: count * n_out]
+        self._check(self.lib.hbpc_train_mlp(self.h, _ptr(xs, count * n_in, torch.float32),
+                                            _ptr(ts, count * n_out, torch.float32), int(count),
+                                            ctypes.byref(c), ctypes.byref(log)))
+        return {"steps": log.steps, "loss_first": log.loss_first, "loss_last": log.loss_last, "ms": log.ms}

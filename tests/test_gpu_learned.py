@@ -1,0 +1,170 @@
+"""The learned preconditioner inside HBPC steps: step-level parity with the
+oracle (the preconditioner changes the Krylov path, not the Newton root),
+the BJ_ext fallback, and training on pairs collected by hbpc_step with what
+the trained network gains over no preconditioner (BJ_ext as the judge).
+
+Step tolerance as for the mixed path: eps_N = 1e-8, relative L2 <= 1e-8
+against the oracle run at the same eps_N.
+"""
+import numpy as np
+import pytest
+
+from gpu_cases import CASES, oracle_for, rel
+from oracle import mlp
+from oracle.solvers import StageSolver, dg_hbpc_step
+from paper_2109_04804_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev(x, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda").reshape(-1)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def ctx_for(dim, nelem, length, N, **kw):
+    from paper_2109_04804_amd.hbpc import Context
+    base = dict(nodes="gauss", flux="rusanov", gamma=1.4, eps_ref=1.0)
+    base.update(kw)
+    return Context(dim, nelem, length, N, "euler", **base)
+
+
+def random_params(ctx, seed):
+    n_in, H, n_out, _ = ctx.mlp_shape()
+    th = mlp.init_params(n_in, H, n_out, np.random.default_rng(seed))
+    return dev(th, torch.float32)
+
+
+def collect_and_train(nelem, L, N, dt, seeds, cap_newton, cap_krylov, per_event, **common):
+    """Pairs from plain BJ_ext steps on seeded vortices: Newton pairs (FP64 solves,
+    eps_G 1e-6) then Krylov pairs (mixed solves); returns (X, T, count, Newton pair count)."""
+    col = ctx_for(2, nelem, [L, L], N, gmres_rtol=1e-6, precision="fp64", precond="bjext", **common)
+    n_in, H, n_out, n_p = col.mlp_shape()
+    cap = cap_newton + cap_krylov
+    Xd = torch.zeros(cap * n_in, dtype=torch.float32, device="cuda")
+    Td = torch.zeros(cap * n_out, dtype=torch.float32, device="cuda")
+    col.mlp_collect(Xd, Td, cap_newton, per_event, 2109, source="newton")
+    for seed in seeds:
+        st = col.step(dev(_vortex(col, nelem, L, seed)), dt)
+        print("newton pairs, seed", seed, "samples", st["mlp_samples"], flush=True)
+        if col.mlp_collected() >= cap_newton:
+            break
+    n1 = col.mlp_collected()
+    col.close()
+    if cap_krylov == 0:
+        assert bool(torch.isfinite(Xd[: n1 * n_in]).all()) and bool(torch.isfinite(Td[: n1 * n_out]).all())
+        return Xd, Td, n1, n1
+    kr = ctx_for(2, nelem, [L, L], N, gmres_rtol=1e-3, precision="mixed", precond="bjext", **common)
+    kr.mlp_collect(Xd[n1 * n_in:], Td[n1 * n_out:], cap_krylov, per_event, 2110, source="krylov", every=2)
+    for seed in seeds:
+        st = kr.step(dev(_vortex(kr, nelem, L, seed)), dt)
+        print("krylov pairs, seed", seed, "samples", st["mlp_samples"], flush=True)
+        if kr.mlp_collected() >= cap_krylov:
+            break
+    count = n1 + kr.mlp_collected()
+    kr.close()
+    assert bool(torch.isfinite(Xd[: count * n_in]).all()) and bool(torch.isfinite(Td[: count * n_out]).all())
+    return Xd, Td, count, n1
+
+
+def test_learned_step_matches_oracle():
+    """2-D Euler vortex, 4 x 4 elements, N = 3, HBPC(6,2), dt = 0.1, mixed precision,
+    learned preconditioner trained on Newton pairs of this mesh (seeds 1..3) with the
+    BJ_ext fallback: the step reaches the oracle's Newton root."""
+    case = dict(CASES["euler2_n3_lobatto"])
+    case.update(nelem=[4, 4], nodes="gauss")
+    dg = oracle_for(case)
+    X = dg.node_coords()
+    w0 = inputs.isentropic_vortex(X[0], X[1], 4.6, 5.3, 3.0)
+    common = dict(q=6, kmax=2, newton_rtol=1e-8)
+    Xd, Td, count, n1 = collect_and_train([4, 4], 10.0, 3, 0.1, (1, 2, 3), 512, 0, 8, **common)
+    ctx = ctx_for(2, [4, 4], [10.0, 10.0], 3, gmres_rtol=1e-5, precision="mixed", precond="learned",
+                  pc_fallback=0.5, **common)
+    ctx.mlp_set_params(random_params(ctx, 0))
+    log = ctx.train_mlp(Xd, Td, count, epochs=40, batch=64, lr=1e-3, seed=3, precision="bf16")
+    print("train", count, log, flush=True)
+    assert log["loss_last"] < 0.5 * log["loss_first"]
+    wg = dev(w0)
+    st = ctx.step(wg, 0.1)
+    print(st, flush=True)
+    ref = dg_hbpc_step(dg, w0, 0.1, 6, 2, StageSolver(dg, newton_rtol=1e-8, gmres_rtol=1e-5))
+    err = rel(host(wg), ref)
+    print("rel err vs oracle", err)
+    assert err < 1e-8
+
+
+def test_learned_without_fallback_fails_cleanly():
+    """An untrained network with the fallback off and a small iteration cap: the step
+    reports HBPC_ERR_GMRES and leaves the state unchanged."""
+    from paper_2109_04804_amd.hbpc import HbpcError
+    case = dict(CASES["euler2_n3_lobatto"])
+    case.update(nelem=[4, 4], nodes="gauss")
+    dg = oracle_for(case)
+    X = dg.node_coords()
+    w0 = inputs.isentropic_vortex(X[0], X[1], 4.6, 5.3, 3.0)
+    ctx = ctx_for(2, [4, 4], [10.0, 10.0], 3, q=6, kmax=2, gmres_rtol=1e-5, gmres_maxit=50, precision="mixed",
+                  precond="learned", pc_fallback=0.0)
+    ctx.mlp_set_params(random_params(ctx, 0))
+    wg = dev(w0)
+    with pytest.raises(HbpcError) as ei:
+        ctx.step(wg, 0.1)
+    assert ei.value.code == -6
+    assert np.array_equal(host(wg), w0.ravel())
+
+
+def _vortex(ctx, nelem, L, seed):
+    xi, _ = ctx.nodes()
+    X = inputs.node_coords(2, nelem, [L, L], [0.0, 0.0], xi)
+    xc, yc, beta = inputs.vortex_params(seed)
+    return inputs.isentropic_vortex(X[0], X[1], xc, yc, beta, mach=0.5, gamma=1.4, box=L)
+
+
+def test_training_and_gain():
+    """16 x 16 elements, N = 3, [0,10]^2, HBPC(6,2), dt = 0.4 (element acoustic CFL
+    about 1): Newton pairs (FP64 BJ_ext solves, eps_G 1e-6) for vortex seeds 1..4,
+    BF16 training, then one mixed step at eps_G = 1e-3 on held-out seed 99 with no
+    preconditioner, the network alone (no fallback, at most 20000 Krylov iterations
+    per Newton step), the network with the BJ_ext fallback, and BJ_ext.  Prints the
+    Krylov iteration counts; asserts that training lowers the loss and that every
+    form that converges reaches the same Newton root."""
+    nelem, L, N, dt = [16, 16], 10.0, 3, 0.4
+    common = dict(q=6, kmax=2, newton_rtol=1e-8, gmres_restart=30)
+    Xd, Td, count, n1 = collect_and_train(nelem, L, N, dt, (1, 2, 3, 4), 4096, 0, 64, **common)
+    assert count > 2000
+    probe = ctx_for(2, nelem, [L, L], N, **common)
+    w_eval = _vortex(probe, nelem, L, 99)
+    probe.close()
+    theta = None
+    ev = {}
+    for form, pc, fb in (("none", "none", 0.0), ("network", "learned", 0.0), ("network+fallback", "learned", 0.5),
+                         ("bjext", "bjext", 0.0)):
+        ctx = ctx_for(2, nelem, [L, L], N, gmres_rtol=1e-3, precision="mixed", precond=pc, pc_fallback=fb,
+                      gmres_maxit=20000, **common)
+        if pc == "learned":
+            if theta is None:
+                ctx.mlp_set_params(random_params(ctx, 7))
+                log = ctx.train_mlp(Xd, Td, count, epochs=30, batch=128, lr=1e-3, seed=5, precision="bf16")
+                print("train", count, log, flush=True)
+                assert log["loss_last"] < 0.5 * log["loss_first"]
+                theta = ctx.mlp_get_params(torch.zeros(ctx.mlp_shape()[3], dtype=torch.float32, device="cuda"))
+            else:
+                ctx.mlp_set_params(theta)
+        w = dev(w_eval)
+        try:
+            st = ctx.step(w, dt)
+            ev[form] = (st["gmres_its"], st["pc_fallbacks"], host(w))
+            print(form, "gmres", st["gmres_its"], "newton", st["newton_its"], "fallbacks", st["pc_fallbacks"],
+                  "ms", round(st["t_step_ms"], 1), flush=True)
+        except Exception as ex:
+            print(form, "did not converge:", ex, flush=True)
+        ctx.close()
+    for form in ("none", "network", "network+fallback"):
+        if form in ev:
+            assert rel(ev[form][2], ev["bjext"][2]) < 1e-7, form
+    assert "network+fallback" in ev
+    print("Krylov iterations per step:", {k: v[0] for k, v in ev.items()})

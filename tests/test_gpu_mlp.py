@@ -1,0 +1,185 @@
+"""GPU parity of the learned preconditioner's kernels against the FP64 oracle
+(oracle/mlp.py): feature gather, network forward (FP32 check path and BF16
+matrix-core path), loss gradient, Adam, and the preconditioner apply, plus
+training on pairs collected by hbpc_step and what the trained network gains.
+
+Tolerances (relative L2 unless stated): features and scales 1e-6 (one FP32
+rounding of FP64 values); FP32 network 1e-5; BF16 network 2e-2 (operands
+rounded to 8 significant bits, FP32 accumulation); Adam 1e-6.
+"""
+import numpy as np
+import pytest
+
+from gpu_cases import oracle_for, rel, state
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+# 2-D Euler, N = 3 (block 64; network inputs 320 residual + 322 state, width 256, 64 outputs), 5 x 4 elements
+CASE = dict(dim=2, nelem=[5, 4], length=[10.0, 10.0], N=3, equation="euler", nodes="gauss", flux="rusanov")
+
+
+def dev(x, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda").reshape(-1)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def make_ctx(**over):
+    from paper_2109_04804_amd.hbpc import Context
+    kw = {k: v for k, v in CASE.items() if k not in ("dim", "nelem", "length", "N", "equation")}
+    kw.update(over)
+    return Context(CASE["dim"], CASE["nelem"], CASE["length"], CASE["N"], CASE["equation"], **kw)
+
+
+def params(ctx, seed=0):
+    n_in, H, n_out, n_p = ctx.mlp_shape()
+    rng = np.random.default_rng(seed)
+    th = mlp.init_params(n_in, H, n_out, rng)
+    th += 0.05 * rng.standard_normal(n_p)   # non-zero biases
+    return th.astype(np.float32).astype(np.float64)
+
+
+def test_shape():
+    ctx = make_ctx()
+    n_in, H, n_out, n_p = ctx.mlp_shape()
+    assert (n_in, H, n_out) == (5 * 2 * 64 + 2, 256, 64)
+    assert n_p == mlp.n_params(n_in, H, n_out)
+
+
+def test_features_match_oracle():
+    dg = oracle_for(CASE)
+    ctx = make_ctx()
+    nE = dg.mesh.n_elem
+    rng = np.random.default_rng(3)
+    w = state(dg)
+    rt = rng.standard_normal(w.shape) * np.exp(rng.uniform(-3, 3, size=(nE, 1, 1)))
+    dw = rng.standard_normal(w.shape)
+    elems = np.array([0, 4, 5, 19, 7, 7, 13], dtype=np.int32)   # corners, edges, a repeat
+    n_in, _, n_out, _ = ctx.mlp_shape()
+    X = torch.zeros(len(elems) * n_in, dtype=torch.float32, device="cuda")
+    T = torch.zeros(len(elems) * n_out, dtype=torch.float32, device="cuda")
+    s = torch.zeros(len(elems), dtype=torch.float32, device="cuda")
+    ctx.mlp_features(dev(rt), dev(w), 0.25, 0.0125, X, scale=s, dw=dev(dw), T=T,
+                     elems=torch.tensor(elems, device="cuda"))
+    Xr, sr = mlp.features(CASE["nelem"], rt.reshape(nE, -1), w.reshape(nE, -1), 0.25, 0.0125, elems)
+    Tr = dw.reshape(nE, -1)[elems] / sr[:, None]
+    assert np.abs(host(X).reshape(Xr.shape) - Xr).max() <= 2e-7 * np.abs(Xr).max()
+    assert rel(host(s), sr) < 1e-6
+    assert rel(host(T).reshape(Tr.shape), Tr) < 1e-6
+    # all elements, no targets
+    X2 = torch.zeros(nE * n_in, dtype=torch.float32, device="cuda")
+    ctx.mlp_features(dev(rt), dev(w), 0.25, 0.0125, X2)
+    Xa, _ = mlp.features(CASE["nelem"], rt.reshape(nE, -1), w.reshape(nE, -1), 0.25, 0.0125, range(nE))
+    assert np.abs(host(X2).reshape(Xa.shape) - Xa).max() <= 2e-7 * np.abs(Xa).max()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16", 2e-2)])
+@pytest.mark.parametrize("rows", [1, 150])
+def test_forward_matches_oracle(precision, tol, rows):
+    """Against the exact FP64 network; the BF16 path also against the oracle with
+    BF16-rounded operands (exact accumulation), to 2e-4."""
+    ctx = make_ctx()
+    n_in, H, n_out, _ = ctx.mlp_shape()
+    th = params(ctx)
+    ctx.mlp_set_params(dev(th, torch.float32))
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((rows, n_in)).astype(np.float32).astype(np.float64)
+    Y = torch.zeros(rows * n_out, dtype=torch.float32, device="cuda")
+    ctx.mlp_forward(dev(X, torch.float32), rows, Y, precision)
+    ref, _ = mlp.forward(th, X, n_in, H, n_out)
+    got = host(Y).reshape(ref.shape)
+    err = rel(got, ref)
+    print(precision, rows, "forward rel", err)
+    assert err < tol
+    if precision == "bf16":
+        ref_q, _ = mlp.forward(th, X, n_in, H, n_out, q=mlp.round_bf16)
+        err_q = rel(got, ref_q)
+        print("bf16 forward rel vs rounded-operand oracle", err_q)
+        assert err_q < 2e-4
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16", 5e-4)])
+def test_loss_grad_matches_oracle(precision, tol):
+    """FP32 path against the exact gradient; the BF16 path against the oracle
+    with BF16-rounded operands in every product (near-zero pre-activations make
+    the ReLU masks of an unrounded reference differ, an O(1) change per flip)."""
+    ctx = make_ctx()
+    n_in, H, n_out, n_p = ctx.mlp_shape()
+    th = params(ctx, 1)
+    ctx.mlp_set_params(dev(th, torch.float32))
+    rng = np.random.default_rng(7)
+    rows = 200
+    X = rng.standard_normal((rows, n_in)).astype(np.float32).astype(np.float64)
+    T = rng.standard_normal((rows, n_out)).astype(np.float32).astype(np.float64)
+    g = torch.zeros(n_p, dtype=torch.float32, device="cuda")
+    loss = ctx.mlp_loss_grad(dev(X, torch.float32), dev(T, torch.float32), rows, g, precision)
+    q = mlp.round_bf16 if precision == "bf16" else None
+    loss_ref, g_ref = mlp.loss_and_grad(th, X, T, n_in, H, n_out, q=q)
+    assert abs(loss - loss_ref) <= tol * loss_ref
+    got = mlp.unpack(host(g), n_in, H, n_out)
+    for name, a, b in zip(mlp.NAMES, got, mlp.unpack(g_ref, n_in, H, n_out)):
+        err = rel(a, b)
+        print(precision, name, "grad rel", err)
+        assert err < tol, name
+
+
+def test_adam_matches_oracle():
+    ctx = make_ctx()
+    _, _, _, n_p = ctx.mlp_shape()
+    th = params(ctx, 2)
+    ctx.mlp_set_params(dev(th, torch.float32))
+    rng = np.random.default_rng(11)
+    m = v = np.zeros(n_p)
+    t_ref = th.copy()
+    for t in range(1, 4):
+        g = (rng.standard_normal(n_p) * 10.0 ** rng.uniform(-4, 1, size=n_p)).astype(np.float32).astype(np.float64)
+        ctx.mlp_adam(dev(g, torch.float32), 1e-3)
+        t_ref, m, v = mlp.adam_step(t_ref, g, m, v, t, 1e-3)
+    got = ctx.mlp_get_params(torch.zeros(n_p, dtype=torch.float32, device="cuda"))
+    assert rel(host(got) - th, t_ref - th) < 1e-5
+    assert rel(host(got), t_ref) < 1e-6
+
+
+@pytest.mark.parametrize("mlp_precision,vec,tol", [("fp32", "fp64", 1e-5), ("fp32", "mixed", 1e-4),
+                                                    ("bf16", "fp64", 2e-2)])
+def test_learned_apply_matches_oracle(mlp_precision, vec, tol):
+    """P^-1 (vw, vs) of the learned preconditioner (Schur right-hand side, per-element
+    network on the patch features, exact second block row) against the oracle."""
+    dg = oracle_for(CASE)
+    ctx = make_ctx(precond="learned", mlp_precision=mlp_precision)
+    n_in, H, n_out, _ = ctx.mlp_shape()
+    th = params(ctx, 4)
+    ctx.mlp_set_params(dev(th, torch.float32))
+    w = state(dg)
+    rng = np.random.default_rng(13)
+    vw = rng.standard_normal(w.shape)
+    vs = rng.standard_normal(w.shape)
+    a1dt, bc = 0.05, 0.05 ** 2 / 3
+    ctx.pc_build(dev(w), a1dt, bc, vec)
+    n = dg.ndof if hasattr(dg, "ndof") else w.size
+    Xin = np.concatenate([vw.ravel(), vs.ravel()])
+    if vec == "fp64":
+        Y = torch.zeros(2 * n, dtype=torch.float64, device="cuda")
+        ctx.pc_apply(dev(Xin), Y)
+    else:
+        Y = torch.zeros(2 * n, dtype=torch.float32, device="cuda")
+        ctx.pc_apply_f32(dev(Xin, torch.float32), Y)
+    dw, ds = mlp.apply_learned(dg, th, H, w, vw, vs, a1dt, bc)
+    got = host(Y)
+    e1, e2 = rel(got[:n], dw.ravel()), rel(got[n:], ds.ravel())
+    print(mlp_precision, vec, "apply rel", e1, e2)
+    assert e1 < tol and e2 < tol
+
+
+def test_learned_pc_requires_parameters():
+    from paper_2109_04804_amd.hbpc import HbpcError
+    dg = oracle_for(CASE)
+    ctx = make_ctx(precond="learned")
+    with pytest.raises(HbpcError) as ei:
+        ctx.step(dev(state(dg)), 0.1)
+    assert ei.value.code == -1
