@@ -5,15 +5,20 @@ Workload (default): 2-D compressible Euler isentropic vortex on the periodic
 [0,10]^2, gamma 1.4, background Mach 0.5, strength 5, seeded centre
 (seed 2109), DGSEM N = 5 on Gauss nodes, 128 x 128 elements (2,359,296 DOF),
 Rusanov flux, HBPC(6,4) (3 nodes c = 0, 1/2, 1; 4 corrector sweeps), dt = 0.1,
-Newton tolerance 1e-8, FGMRES(30) with eps_G = 1e-3, BJ_ext preconditioner.
-Two forms are timed: all-FP64, and FP64 Newton with FP32 Krylov vectors, JVP
-and BJ_ext ("mixed").  A step is one full HBPC step (all stage solves) on the
-state resident in HBM; inputs are synthetic.
+Newton tolerance 1e-8, FGMRES(30) with eps_G = 1e-3.  Three forms are timed:
+  fp64     all-FP64, BJ_ext;
+  mixed    FP64 Newton, FP32 Krylov vectors, JVP and BJ_ext;
+  learned  as mixed with the learned preconditioner (BF16 network, BJ_ext as
+           fallback), trained before timing on Newton pairs of FP64 solves of
+           seeded vortices on the same mesh.
+A step is one full HBPC step (all stage solves) on the state resident in HBM;
+inputs are synthetic.
 
-Prints ONE JSON line: value = DOF-steps/s of the headline (mixed) form, the
-FP64 form beside it, the roofline of the dominant kernel (HIP events around
-every launch on the library's stream, algorithmic bytes per launch), and the
-FP64 NumPy oracle timed on the host on a bounded sample of the workload.
+Prints ONE JSON line: value = DOF-steps/s of the headline form (learned, as
+the metric names it), the other forms beside it, the roofline of the dominant
+kernel (HIP events around every launch on the library's stream, algorithmic
+bytes per launch), and the FP64 NumPy oracle timed on the host on a bounded
+sample of the workload.
 """
 import argparse
 import json
@@ -49,23 +54,76 @@ def vortex_state(ctx, wl):
     return inputs.isentropic_vortex(X[0], X[1], xc, yc, beta, mach=0.5, gamma=1.4, box=wl["length"][0])
 
 
-def run_form(wl, precision, steps, warmup):
+def _eqkw(wl):
+    if wl.get("equation") == "burgers":
+        return dict(flux="lf", nu=0.01, **{"lambda": 1.0})
+    return dict(flux="rusanov", gamma=1.4, eps_ref=1.0)
+
+
+def train_learned(wl, samples=20480, per_correction=512, seeds=(1, 2), epochs=20):
+    """Training of the learned preconditioner on the workload's mesh: Newton pairs
+    from FP64 BJ_ext solves at eps_G 1e-6 of vortices with seeded centres in
+    [3,7]^2 and strengths in [3,7] (one HBPC(6,4) step per seed), then BF16 Adam.
+    Returns (parameters, report)."""
+    import numpy as np
+    import torch
+    from paper_2109_04804_amd import inputs
+    from paper_2109_04804_amd.hbpc import Context
+    t0 = time.perf_counter()
+    col = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], "euler", q=6, kmax=4, newton_rtol=1e-8,
+                  gmres_rtol=1e-6, gmres_restart=30, gmres_maxit=7000, precond="bjext", precision="fp64",
+                  **_eqkw(wl))
+    n_in, H, n_out, n_p = col.mlp_shape()
+    X = torch.zeros(samples * n_in, dtype=torch.float32, device="cuda")
+    T = torch.zeros(samples * n_out, dtype=torch.float32, device="cuda")
+    col.mlp_collect(X, T, samples, per_correction, 2109, source="newton")
+    xi, _ = col.nodes()
+    Xc = inputs.node_coords(2, wl["nelem"], wl["length"], [0.0, 0.0], xi)
+    for seed in seeds:
+        xc, yc, beta = inputs.vortex_params(seed)
+        w0 = inputs.isentropic_vortex(Xc[0], Xc[1], xc, yc, beta, mach=0.5, gamma=1.4, box=wl["length"][0])
+        w = torch.tensor(np.ascontiguousarray(w0).reshape(-1), dtype=torch.float64, device="cuda")
+        st = col.step(w, wl["dt"])
+        print("[bench] learned: collected %d pairs (seed %d, %d Krylov iterations)" % (col.mlp_collected(), seed,
+              st["gmres_its"]), file=sys.stderr, flush=True)
+        if col.mlp_collected() >= samples:
+            break
+    count = col.mlp_collected()
+    col.close()
+    t_collect = time.perf_counter() - t0
+    tr = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], "euler", precond="learned", precision="mixed",
+                 **_eqkw(wl))
+    tr.mlp_init(7)
+    log = tr.train_mlp(X, T, count, epochs=epochs, batch=256, lr=1e-3, seed=5, precision="bf16")
+    out = torch.zeros(n_p, dtype=torch.float32, device="cuda")
+    tr.mlp_get_params(out)
+    tr.close()
+    del X, T
+    print("[bench] learned: trained on %d pairs, loss %.4g -> %.4g, %.1f s" % (count, log["loss_first"],
+          log["loss_last"], log["ms"] * 1e-3), file=sys.stderr, flush=True)
+    return out, {"pairs": count, "source": "Newton corrections of FP64 BJ_ext solves, eps_G 1e-6",
+                 "seeds": list(seeds), "collect_s": round(t_collect, 2), "train_ms": round(log["ms"], 1),
+                 "adam_steps": log["steps"], "loss_first_epoch": log["loss_first"],
+                 "loss_last_epoch": log["loss_last"]}
+
+
+def run_form(wl, form, steps, warmup, theta=None):
     import numpy as np
     import torch
     from paper_2109_04804_amd.hbpc import Context
-    if wl.get("equation") == "burgers":
-        eqkw = dict(flux="lf", nu=0.01, **{"lambda": 1.0})
-    else:
-        eqkw = dict(flux="rusanov", gamma=1.4, eps_ref=1.0)
+    precision = "fp64" if form == "fp64" else "mixed"
+    pc = "learned" if form == "learned" else "bjext"
     ctx = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], wl.get("equation", "euler"), q=6, kmax=4,
-                  newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=30, gmres_maxit=7000, precond="bjext",
-                  precision=precision, **eqkw)
+                  newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=30, gmres_maxit=7000, precond=pc,
+                  precision=precision, pc_fallback=0.5, **_eqkw(wl))
+    if pc == "learned":
+        ctx.mlp_set_params(theta)
     w0 = vortex_state(ctx, wl)
     w = torch.tensor(np.ascontiguousarray(w0).reshape(-1), dtype=torch.float64, device="cuda")
     for i in range(warmup):
         st = ctx.step(w, wl["dt"])
-        print("[bench] %s warmup %d: newton %d gmres %d  %.1f ms" % (precision, i, st["newton_its"],
-              st["gmres_its"], st["t_step_ms"]), file=sys.stderr, flush=True)
+        print("[bench] %s warmup %d: newton %d gmres %d fallbacks %d  %.1f ms" % (form, i, st["newton_its"],
+              st["gmres_its"], st["pc_fallbacks"], st["t_step_ms"]), file=sys.stderr, flush=True)
     ctx.profile_read(reset=True)
     ctx.profile_enable(True)
     stats = []
@@ -76,8 +134,8 @@ def run_form(wl, precision, steps, warmup):
     for i in range(steps):
         st = ctx.step(w, wl["dt"])
         stats.append(st)
-        print("[bench] %s step %d: newton %d gmres %d  %.1f ms" % (precision, i, st["newton_its"],
-              st["gmres_its"], st["t_step_ms"]), file=sys.stderr, flush=True)
+        print("[bench] %s step %d: newton %d gmres %d fallbacks %d  %.1f ms" % (form, i, st["newton_its"],
+              st["gmres_its"], st["pc_fallbacks"], st["t_step_ms"]), file=sys.stderr, flush=True)
     t_end.record()
     torch.cuda.synchronize()
     ms = t_start.elapsed_time(t_end)
@@ -87,7 +145,8 @@ def run_form(wl, precision, steps, warmup):
     ctx.close()
     return {"ms_total": ms, "ms_per_step": ms / steps, "dof": ctx.ndof,
             "newton_its": [s["newton_its"] for s in stats], "gmres_its": [s["gmres_its"] for s in stats],
-            "pc_builds": [s["pc_builds"] for s in stats], "kernels": prof, "finite": finite}
+            "pc_builds": [s["pc_builds"] for s in stats], "pc_fallbacks": [s["pc_fallbacks"] for s in stats],
+            "n_solves": [s["n_solves"] for s in stats], "kernels": prof, "finite": finite}
 
 
 SINGLE_KERNEL_CLASSES = ("bj_apply", "bj_invert", "jvp", "pcpre", "kcol", "trace", "res", "r1", "r2", "gs_update")
@@ -142,7 +201,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="euler_vortex_128x128_N5", choices=sorted(WORKLOADS))
-    ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--forms", default="fp64,mixed,learned",
+                    help="comma list of fp64 (BJ_ext FP64), mixed (BJ_ext, FP32 Krylov), learned "
+                         "(learned preconditioner with BJ_ext fallback, FP32 Krylov, BF16 network)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -156,10 +217,15 @@ def main():
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
     wl = WORKLOADS[a.workload]
     forms = [f for f in a.forms.split(",") if f]
+    if wl.get("equation") == "burgers":
+        forms = [f for f in forms if f != "learned"]   # the network is trained on Euler vortices
     res = {}
+    theta, train_report = None, None
+    if "learned" in forms:
+        theta, train_report = train_learned(wl)
     for f in forms:
-        res[f] = run_form(wl, f, a.steps, a.warmup)
-    head = "mixed" if "mixed" in res else forms[0]
+        res[f] = run_form(wl, f, a.steps, a.warmup, theta)
+    head = "learned" if "learned" in res else ("mixed" if "mixed" in res else forms[0])
     h = res[head]
     dof = h["dof"]
     value = dof * a.steps / (h["ms_total"] * 1e-3)
@@ -174,13 +240,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64+f32" if head == "mixed" else "f64",
+        "dtype": {"learned": "f64+f32+bf16", "mixed": "f64+f32", "fp64": "f64"}[head],
         "data": "synthetic",
         "config": {"workload": a.workload, "dof": dof, "scheme": "HBPC(6,4)", "dt": wl["dt"],
-                   "newton_rtol": 1e-8, "krylov": "FGMRES(30), eps_G 1e-3", "precond": "BJ_ext",
-                   "form": head, "learned_preconditioner": "not built"},
+                   "newton_rtol": 1e-8, "krylov": "FGMRES(30), eps_G 1e-3",
+                   "precond": {"learned": "learned (BJ_ext fallback 0.5)", "mixed": "BJ_ext",
+                               "fp64": "BJ_ext"}[head], "form": head},
         "forms": {f: {"dof_steps_per_s": dof * a.steps / (r["ms_total"] * 1e-3), "ms_per_step": r["ms_per_step"],
-                      "newton_its": r["newton_its"], "gmres_its": r["gmres_its"], "finite": r["finite"]}
+                      "newton_its": r["newton_its"], "gmres_its": r["gmres_its"], "pc_fallbacks": r["pc_fallbacks"],
+                      "n_solves": r["n_solves"], "finite": r["finite"]}
                   for f, r in res.items()},
         "roofline": roofline_of(h["kernels"]),
         "kernels": {f: {k: {"launches": v["launches"], "total_ms": round(v["total_ms"], 3),
@@ -189,6 +257,8 @@ def main():
     }
     if "fp64" in res and head != "fp64":
         out["speedup_vs_fp64"] = res["fp64"]["ms_per_step"] / h["ms_per_step"]
+    if train_report:
+        out["learned_training"] = train_report
     if not a.no_cpu_baseline:
         cb = cpu_baseline()
         out["cpu_baseline"] = cb

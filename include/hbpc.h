@@ -222,6 +222,10 @@ int hbpc_mlp_shape(const hbpc_ctx* ctx, int* n_in, int* hidden, int* n_out, size
  * resets the Adam moments and step count. */
 int hbpc_mlp_set_params(hbpc_ctx* ctx, const float* theta);
 int hbpc_mlp_get_params(hbpc_ctx* ctx, float* theta);
+/* Seeded initial parameters: weights uniform in +-sqrt(g / fan_in), g = 6 on
+ * the ReLU state path (W1w, W2w) and 3 on the linear residual path (W1r,
+ * W2r, W3), from splitmix64 counters; zero biases; Adam state reset. */
+int hbpc_mlp_init(hbpc_ctx* ctx, unsigned long long seed);
 /* Feature rows of `count` elements: elems (device int array, or NULL for
  * elements 0..count-1; an entry outside 0..n_elem-1 gives a zero row and
  * scale 0), rt and w FP64 (ndof).  X: count x n_in FP32 out;

@@ -192,14 +192,18 @@ __global__ void __launch_bounds__(TGR* TGC) bj_invert_kernel(const T* __restrict
 }
 
 // y = S^-1 x for the two right-hand sides (w block, sigma block); one thread per row.
-template <typename TM, typename T>
+// yw = S^-1 xa, ys = S^-1 xc per element; S^-1 stored transposed (column-major blocks, SinvT[e][c][r]),
+// each thread owns VR consecutive rows (one 16-byte load per column when VR * sizeof(TM) == 16),
+// NE / VR threads per element, several elements per block; the two right-hand sides staged in LDS
+template <typename TM, typename T, int VR>
 __global__ void __launch_bounds__(256) bj_apply_kernel(const TM* __restrict__ SinvT, const T* __restrict__ xa,
                                                       const T* __restrict__ xc, T* __restrict__ yw,
                                                       T* __restrict__ ys, int NE, int nE) {
     extern __shared__ unsigned char smem_raw[];
     T* sx = reinterpret_cast<T*>(smem_raw);
-    const int epb = blockDim.x / NE;
-    const int el = threadIdx.x / NE, r = threadIdx.x % NE;
+    const int tpe = NE / VR;
+    const int epb = blockDim.x / tpe;
+    const int el = threadIdx.x / tpe, r0 = (threadIdx.x % tpe) * VR;
     const int e0 = blockIdx.x * epb;
     for (int i = threadIdx.x; i < epb * NE; i += blockDim.x) {
         int le = i / NE;
@@ -211,23 +215,27 @@ __global__ void __launch_bounds__(256) bj_apply_kernel(const TM* __restrict__ Si
     __syncthreads();
     const int e = e0 + el;
     if (el >= epb || e >= nE) return;
-    const TM* M = SinvT + (size_t)e * NE * NE + r;
+    typedef TM VT __attribute__((ext_vector_type(VR)));
+    const TM* M = SinvT + (size_t)e * NE * NE + r0;
     const T* x = sx + 2 * el * NE;
-    T s0 = T(0), s1 = T(0);
-    int c = 0;
-    for (; c + 4 <= NE; c += 4) {
-        T m0 = (T)M[(size_t)(c + 0) * NE], m1 = (T)M[(size_t)(c + 1) * NE];
-        T m2 = (T)M[(size_t)(c + 2) * NE], m3 = (T)M[(size_t)(c + 3) * NE];
-        s0 += m0 * x[2 * c + 0] + m1 * x[2 * c + 2] + m2 * x[2 * c + 4] + m3 * x[2 * c + 6];
-        s1 += m0 * x[2 * c + 1] + m1 * x[2 * c + 3] + m2 * x[2 * c + 5] + m3 * x[2 * c + 7];
+    T s0[VR], s1[VR];
+#pragma unroll
+    for (int q = 0; q < VR; ++q) s0[q] = s1[q] = T(0);
+#pragma unroll 4
+    for (int c = 0; c < NE; ++c) {
+        const VT m = *reinterpret_cast<const VT*>(M + (size_t)c * NE);
+        const T xa_c = x[2 * c], xc_c = x[2 * c + 1];
+#pragma unroll
+        for (int q = 0; q < VR; ++q) {
+            s0[q] += (T)m[q] * xa_c;
+            s1[q] += (T)m[q] * xc_c;
+        }
     }
-    for (; c < NE; ++c) {
-        T m = (T)M[(size_t)c * NE];
-        s0 += m * x[2 * c];
-        s1 += m * x[2 * c + 1];
+#pragma unroll
+    for (int q = 0; q < VR; ++q) {
+        yw[(size_t)e * NE + r0 + q] = s0[q];
+        ys[(size_t)e * NE + r0 + q] = s1[q];
     }
-    yw[(size_t)e * NE + r] = s0;
-    ys[(size_t)e * NE + r] = s1;
 }
 
 template <int TGR, int TGC, int RR, int RC, typename TO>
@@ -252,31 +260,40 @@ hipError_t bj_invert(const double* KT, void* SinvT, int f32, int NE, int nE, dou
     return hipErrorInvalidValue;
 }
 
+template <typename TM, typename T, int VR>
+static void launch_apply(const TM* SinvT, const T* xa, const T* xc, T* yw, T* ys, int NE, int nE, hipStream_t st) {
+    const int tpe = NE / VR;
+    const int epb = tpe >= 256 ? 1 : 256 / tpe;
+    const int threads = epb * tpe;
+    const int grid = (nE + epb - 1) / epb;
+    const size_t sh = (size_t)2 * epb * NE * sizeof(T);
+    hipLaunchKernelGGL((bj_apply_kernel<TM, T, VR>), dim3(grid), dim3(threads), sh, st, SinvT, xa, xc, yw, ys, NE, nE);
+}
+
+// rows per thread: a 16-byte load of S^-1 when NE allows it
+template <typename TM, typename T>
+static void apply_vr(const void* SinvT, const void* xa, const void* xc, void* yw, void* ys, int NE, int nE,
+                     hipStream_t st) {
+    constexpr int V = 16 / sizeof(TM);
+    const TM* M = (const TM*)SinvT;
+    if (NE % V == 0)
+        launch_apply<TM, T, V>(M, (const T*)xa, (const T*)xc, (T*)yw, (T*)ys, NE, nE, st);
+    else if (NE % 2 == 0)
+        launch_apply<TM, T, 2>(M, (const T*)xa, (const T*)xc, (T*)yw, (T*)ys, NE, nE, st);
+    else
+        launch_apply<TM, T, 1>(M, (const T*)xa, (const T*)xc, (T*)yw, (T*)ys, NE, nE, st);
+}
+
 hipError_t bj_apply(const void* SinvT, int m_f32, const void* xa, const void* xc, void* yw, void* ys, int v_f32,
                     int NE, int nE, hipStream_t st) {
     if (nE == 0) return hipSuccess;
-    int epb = NE >= 256 ? 1 : 256 / NE;
-    int threads = epb * NE;
-    if (threads > 1024) return hipErrorInvalidValue;
-    int grid = (nE + epb - 1) / epb;
-    size_t sh = (size_t)2 * epb * NE * (v_f32 ? sizeof(float) : sizeof(double));
+    if (NE > 1024) return hipErrorInvalidValue;
     if (v_f32) {
-        if (m_f32)
-            hipLaunchKernelGGL((bj_apply_kernel<float, float>), dim3(grid), dim3(threads), sh, st,
-                               (const float*)SinvT, (const float*)xa, (const float*)xc, (float*)yw, (float*)ys, NE, nE);
-        else
-            hipLaunchKernelGGL((bj_apply_kernel<double, float>), dim3(grid), dim3(threads), sh, st,
-                               (const double*)SinvT, (const float*)xa, (const float*)xc, (float*)yw, (float*)ys, NE,
-                               nE);
+        if (m_f32) apply_vr<float, float>(SinvT, xa, xc, yw, ys, NE, nE, st);
+        else apply_vr<double, float>(SinvT, xa, xc, yw, ys, NE, nE, st);
     } else {
-        if (m_f32)
-            hipLaunchKernelGGL((bj_apply_kernel<float, double>), dim3(grid), dim3(threads), sh, st,
-                               (const float*)SinvT, (const double*)xa, (const double*)xc, (double*)yw, (double*)ys,
-                               NE, nE);
-        else
-            hipLaunchKernelGGL((bj_apply_kernel<double, double>), dim3(grid), dim3(threads), sh, st,
-                               (const double*)SinvT, (const double*)xa, (const double*)xc, (double*)yw, (double*)ys,
-                               NE, nE);
+        if (m_f32) apply_vr<float, double>(SinvT, xa, xc, yw, ys, NE, nE, st);
+        else apply_vr<double, double>(SinvT, xa, xc, yw, ys, NE, nE, st);
     }
     return hipGetLastError();
 }

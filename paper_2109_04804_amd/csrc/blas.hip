@@ -5,9 +5,10 @@
 // one block in a fixed tree, so two runs give bitwise equal results.
 #include <hip/hip_runtime.h>
 #include <cstddef>
+#include <cstdint>
 
 constexpr int BLAS_THREADS = 256;
-constexpr int MDOT_CHUNK = 8;
+constexpr int MDOT_CHUNK = 16;
 
 template <typename T> __device__ __forceinline__ double block_sum(double v, double* sh) {
     // wave64 shuffle tree, then LDS across the 4 waves
@@ -24,8 +25,35 @@ template <typename T> __device__ __forceinline__ double block_sum(double v, doub
     return r;
 }
 
-// part[blockIdx.x * ldp + j] = sum_{i in block} V_j[i] * w[i], j < kc (<= MDOT_CHUNK)
-template <typename T>
+// VEC consecutive values of type T as one 16-byte (or scalar) load/store
+template <typename T, int VEC> struct Vec { T v[VEC]; };
+template <typename T, int VEC> __device__ __forceinline__ Vec<T, VEC> vload(const T* p) {
+    Vec<T, VEC> r;
+    if constexpr (VEC == 1) {
+        r.v[0] = *p;
+    } else {
+        typedef T VT __attribute__((ext_vector_type(VEC)));
+        const VT x = *reinterpret_cast<const VT*>(p);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) r.v[i] = x[i];
+    }
+    return r;
+}
+template <typename T, int VEC> __device__ __forceinline__ void vstore(T* p, const Vec<T, VEC>& r) {
+    if constexpr (VEC == 1) {
+        *p = r.v[0];
+    } else {
+        typedef T VT __attribute__((ext_vector_type(VEC)));
+        VT x;
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) x[i] = r.v[i];
+        *reinterpret_cast<VT*>(p) = x;
+    }
+}
+
+// part[blockIdx.x * ldp + j] = sum_{i in block} V_j[i] * w[i], j < kc (<= MDOT_CHUNK); VEC values per
+// load (n and ld multiples of VEC)
+template <typename T, int VEC>
 __global__ void __launch_bounds__(BLAS_THREADS) mdot_kernel(const T* __restrict__ V, size_t ld, int kc,
                                                             const T* __restrict__ w, size_t n,
                                                             double* __restrict__ part, int ldp) {
@@ -34,11 +62,18 @@ __global__ void __launch_bounds__(BLAS_THREADS) mdot_kernel(const T* __restrict_
 #pragma unroll
     for (int j = 0; j < MDOT_CHUNK; ++j) acc[j] = 0.0;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        double wi = (double)w[i];
+    const size_t nv = n / VEC;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
+        const Vec<T, VEC> wv = vload<T, VEC>(w + i * VEC);
 #pragma unroll
         for (int j = 0; j < MDOT_CHUNK; ++j)
-            if (j < kc) acc[j] += (double)V[j * ld + i] * wi;
+            if (j < kc) {
+                const Vec<T, VEC> vv = vload<T, VEC>(V + j * ld + i * VEC);
+                double s = 0.0;
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) s += (double)vv.v[q] * (double)wv.v[q];
+                acc[j] += s;
+            }
     }
     for (int j = 0; j < kc; ++j) {
         double s = block_sum<T>(acc[j], sh);
@@ -122,8 +157,9 @@ __global__ void __launch_bounds__(BLAS_THREADS) nonfinite_kernel(const T* __rest
 }
 
 // ------------------------------------------------------------------ Gram-Schmidt passes
-// w[i] -= sum_j h[j] V_j[i] and a per-block partial of ||w||^2 (part[blockIdx.x])
-template <typename T>
+// w[i] -= sum_j h[j] V_j[i] and a per-block partial of ||w||^2 (part[blockIdx.x]); VEC values per
+// load (n and ld multiples of VEC)
+template <typename T, int VEC>
 __global__ void __launch_bounds__(BLAS_THREADS) gemv_sub_norm_kernel(const T* __restrict__ V, size_t ld, int k,
                                                                      const double* __restrict__ h,
                                                                      T* __restrict__ w, size_t n,
@@ -134,12 +170,24 @@ __global__ void __launch_bounds__(BLAS_THREADS) gemv_sub_norm_kernel(const T* __
     __syncthreads();
     double nrm = 0.0;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        double acc = 0.0;
-        for (int j = 0; j < k; ++j) acc += sh[j] * (double)V[j * ld + i];
-        const T wn = (T)((double)w[i] - acc);
-        w[i] = wn;
-        nrm += (double)wn * (double)wn;
+    const size_t nv = n / VEC;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
+        double acc[VEC];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc[q] = 0.0;
+        for (int j = 0; j < k; ++j) {
+            const Vec<T, VEC> vv = vload<T, VEC>(V + j * ld + i * VEC);
+            const double hj = sh[j];
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[q] += hj * (double)vv.v[q];
+        }
+        Vec<T, VEC> wv = vload<T, VEC>(w + i * VEC);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+            wv.v[q] = (T)((double)wv.v[q] - acc[q]);
+            nrm += (double)wv.v[q] * (double)wv.v[q];
+        }
+        vstore<T, VEC>(w + i * VEC, wv);
     }
     double t = block_sum<double>(nrm, red);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
@@ -155,17 +203,31 @@ static int blas_grid(size_t n) {
 
 int blas_mdot_grid(size_t n) { return blas_grid(n); }
 
+// 16-byte loads when the vector length, the basis stride and both base addresses allow them
+static int vec_of(size_t n, size_t ld, int f32, const void* a, const void* b) {
+    const size_t v = f32 ? 4 : 2;
+    const bool aligned = ((uintptr_t)a % 16 == 0) && ((uintptr_t)b % 16 == 0);
+    return (aligned && n % v == 0 && ld % v == 0) ? (int)v : 1;
+}
+
 // h[j] = V_j . w for j < k; part must hold grid * k doubles.
 hipError_t blas_mdot(const void* V, size_t ld, int k, const void* w, size_t n, int f32, double* part, double* h,
                      hipStream_t st) {
-    int g = blas_grid(n);
+    const int vec = vec_of(n, ld, f32, V, w);
+    int g = blas_grid(n / vec);
     for (int j0 = 0; j0 < k; j0 += MDOT_CHUNK) {
         int kc = k - j0 < MDOT_CHUNK ? k - j0 : MDOT_CHUNK;
-        if (f32)
-            hipLaunchKernelGGL(mdot_kernel<float>, dim3(g), dim3(BLAS_THREADS), 0, st,
+        if (f32 && vec == 4)
+            hipLaunchKernelGGL((mdot_kernel<float, 4>), dim3(g), dim3(BLAS_THREADS), 0, st,
                                (const float*)V + j0 * ld, ld, kc, (const float*)w, n, part + j0, k);
+        else if (f32)
+            hipLaunchKernelGGL((mdot_kernel<float, 1>), dim3(g), dim3(BLAS_THREADS), 0, st,
+                               (const float*)V + j0 * ld, ld, kc, (const float*)w, n, part + j0, k);
+        else if (vec == 2)
+            hipLaunchKernelGGL((mdot_kernel<double, 2>), dim3(g), dim3(BLAS_THREADS), 0, st,
+                               (const double*)V + j0 * ld, ld, kc, (const double*)w, n, part + j0, k);
         else
-            hipLaunchKernelGGL(mdot_kernel<double>, dim3(g), dim3(BLAS_THREADS), 0, st,
+            hipLaunchKernelGGL((mdot_kernel<double, 1>), dim3(g), dim3(BLAS_THREADS), 0, st,
                                (const double*)V + j0 * ld, ld, kc, (const double*)w, n, part + j0, k);
     }
     hipLaunchKernelGGL(reduce_parts_kernel, dim3(k), dim3(BLAS_THREADS), 0, st, part, g, k, h, 1.0);
@@ -176,13 +238,20 @@ hipError_t blas_mdot(const void* V, size_t ld, int k, const void* w, size_t n, i
 hipError_t blas_gemv_sub_norm(const void* V, size_t ld, int k, const double* h, void* u, size_t n, int f32,
                               double* part, double* nrm2, hipStream_t st) {
     if (k > 64) return hipErrorInvalidValue;
-    int g = blas_grid(n);
-    if (f32)
-        hipLaunchKernelGGL(gemv_sub_norm_kernel<float>, dim3(g), dim3(BLAS_THREADS), 0, st, (const float*)V, ld, k,
-                           h, (float*)u, n, part);
+    const int vec = vec_of(n, ld, f32, V, u);
+    int g = blas_grid(n / vec);
+    if (f32 && vec == 4)
+        hipLaunchKernelGGL((gemv_sub_norm_kernel<float, 4>), dim3(g), dim3(BLAS_THREADS), 0, st, (const float*)V, ld,
+                           k, h, (float*)u, n, part);
+    else if (f32)
+        hipLaunchKernelGGL((gemv_sub_norm_kernel<float, 1>), dim3(g), dim3(BLAS_THREADS), 0, st, (const float*)V, ld,
+                           k, h, (float*)u, n, part);
+    else if (vec == 2)
+        hipLaunchKernelGGL((gemv_sub_norm_kernel<double, 2>), dim3(g), dim3(BLAS_THREADS), 0, st, (const double*)V,
+                           ld, k, h, (double*)u, n, part);
     else
-        hipLaunchKernelGGL(gemv_sub_norm_kernel<double>, dim3(g), dim3(BLAS_THREADS), 0, st, (const double*)V, ld,
-                           k, h, (double*)u, n, part);
+        hipLaunchKernelGGL((gemv_sub_norm_kernel<double, 1>), dim3(g), dim3(BLAS_THREADS), 0, st, (const double*)V,
+                           ld, k, h, (double*)u, n, part);
     hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(BLAS_THREADS), 0, st, part, g, 1, nrm2, 1.0);
     return hipGetLastError();
 }

@@ -1191,6 +1191,28 @@ static void train_impl(hbpc_ctx* c, const float* X, const float* T, size_t count
     }
 }
 
+static void mlp_init_impl(hbpc_ctx* c, unsigned long long seed) {
+    float* b[7];
+    mlp_blocks(c, c->theta, b);
+    const long long nr = c->mlp_nr, nw = c->mlp_nin - c->mlp_nr, H = c->mlp_H, no = c->NE;
+    const long long rows[7] = {nr, nw, 0, H, H, 0, H}, cols[7] = {H, H, H, H, H, H, no};
+    for (int k = 0; k < 7; ++k) {
+        if (rows[k] == 0) {   // biases
+            hipchk(c, hipMemsetAsync(b[k], 0, cols[k] * sizeof(float), c->stream), "memset");
+            continue;
+        }
+        const double gain = (k == 1 || k == 4) ? 6.0 : 3.0;   // W1w, W2w feed a ReLU
+        hipchk(c, mlp_uniform(b[k], rows[k] * cols[k], (float)std::sqrt(gain / (double)rows[k]),
+                              seed ^ (0x632BE59BD9B4E019ull * (unsigned long long)(k + 1)), c->stream),
+               "init");
+    }
+    const size_t bytes = c->mlp_np * sizeof(float);
+    hipchk(c, hipMemsetAsync(c->adam_m, 0, bytes, c->stream), "memset");
+    hipchk(c, hipMemsetAsync(c->adam_v, 0, bytes, c->stream), "memset");
+    c->adam_t = 0;
+    c->mlp_ready = 1;
+}
+
 // ------------------------------------------------------------------ C ABI
 #define HBPC_TRY(ctx, body)                              \
     try {                                                \
@@ -1413,6 +1435,11 @@ int hbpc_mlp_set_params(hbpc_ctx* c, const float* theta) {
         c->adam_t = 0;
         c->mlp_ready = 1;
     });
+}
+
+int hbpc_mlp_init(hbpc_ctx* c, unsigned long long seed) {
+    if (!c) return HBPC_ERR_ARG;
+    HBPC_TRY(c, mlp_init_impl(c, seed));
 }
 
 int hbpc_mlp_get_params(hbpc_ctx* c, float* theta) {

@@ -46,6 +46,7 @@ hipError_t mlp_rescale(const float* Y, const float* scale, void* out, int f32, l
 hipError_t mlp_gather(const float* src, long long ld, const int* idx, int rows, int cols, float* dst, hipStream_t st);
 hipError_t mlp_sum_parts(const double* part, int n, double* acc, hipStream_t st);
 hipError_t mlp_randn(void* out, int f32, long long n, unsigned long long seed, hipStream_t st);
+hipError_t mlp_uniform(float* out, long long n, float lim, unsigned long long seed, hipStream_t st);
 
 // ---- 1-D operators (host, FP64)
 struct Basis1DHost {

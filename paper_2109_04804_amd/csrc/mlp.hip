@@ -306,6 +306,15 @@ __global__ void __launch_bounds__(256) randn_kernel(T* __restrict__ out, long lo
     }
 }
 
+// out[i] = lim (2u - 1), u uniform in [0, 1) from the top 24 bits of a splitmix64 counter value
+__global__ void __launch_bounds__(256) uniform_kernel(float* __restrict__ out, long long n, float lim,
+                                                      unsigned long long seed) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const float u = (float)(sm64_at(seed, (unsigned long long)i) >> 40) * 0x1.0p-24f;
+        out[i] = lim * (2.f * u - 1.f);
+    }
+}
+
 // out[r][:] = src[idx[r]][:] (mini-batch gather)
 __global__ void __launch_bounds__(256) gather_rows_kernel(const float* __restrict__ src, long long ld,
                                                           const int* __restrict__ idx, int cols,
@@ -418,5 +427,11 @@ hipError_t mlp_randn(void* out, int f32, long long n, unsigned long long seed, h
     if (n <= 0) return hipSuccess;
     if (f32) hipLaunchKernelGGL(randn_kernel<float>, dim3(ew_blocks(n)), dim3(256), 0, st, (float*)out, n, seed);
     else hipLaunchKernelGGL(randn_kernel<double>, dim3(ew_blocks(n)), dim3(256), 0, st, (double*)out, n, seed);
+    return hipGetLastError();
+}
+
+hipError_t mlp_uniform(float* out, long long n, float lim, unsigned long long seed, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(uniform_kernel, dim3(ew_blocks(n)), dim3(256), 0, st, out, n, lim, seed);
     return hipGetLastError();
 }

@@ -100,6 +100,7 @@ SIGNATURES = {
     "hbpc_mlp_shape": (_I, [_P, _P, _P, _P, _P]),
     "hbpc_mlp_set_params": (_I, [_P, _P]),
     "hbpc_mlp_get_params": (_I, [_P, _P]),
+    "hbpc_mlp_init": (_I, [_P, ctypes.c_ulonglong]),
     "hbpc_mlp_features": (_I, [_P, _P, _P, _P, _P, _I, _D, _D, _P, _P, _P]),
     "hbpc_mlp_forward": (_I, [_P, _P, _I, _P, _I]),
     "hbpc_mlp_loss_grad": (_I, [_P, _P, _P, _I, _P, ctypes.POINTER(_D), _I]),
@@ -321,6 +322,10 @@ class Context:
     def mlp_set_params(self, theta):
         import torch
         self._check(self.lib.hbpc_mlp_set_params(self.h, _ptr(theta, self.mlp_shape()[3], torch.float32)))
+
+    def mlp_init(self, seed):
+        """Seeded initial parameters (library generator)."""
+        self._check(self.lib.hbpc_mlp_init(self.h, int(seed)))
 
     def mlp_get_params(self, out):
         import torch
