@@ -205,6 +205,9 @@ def main():
                     help="comma list of fp64 (BJ_ext FP64), mixed (BJ_ext, FP32 Krylov), learned "
                          "(learned preconditioner with BJ_ext fallback, FP32 Krylov, BF16 network)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="first run a plain device copy of this many bytes three times (reference dispatch "
+                         "for scaling hardware byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
@@ -215,6 +218,14 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
+    if a.copy_bytes > 0:
+        src = torch.ones(a.copy_bytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print("[bench] reference copy of %d bytes done" % a.copy_bytes, file=sys.stderr, flush=True)
     wl = WORKLOADS[a.workload]
     forms = [f for f in a.forms.split(",") if f]
     if wl.get("equation") == "burgers":

@@ -1,9 +1,10 @@
 // BJ_ext preconditioner kernels (Sec. 3.2.3).
 //
 // Build: from the element-local Jacobians K_i (stored column-major, KT[e][c][r]
-// = K_i[r][c], produced column by column by the KCOL operator kernel), form
+// = K_i[r][c], FP64, produced column by column by the KCOL operator kernel), form
 // S_i = I - a1dt K_i + bcoef K_i^2 in registers and invert it by Gauss-Jordan
-// elimination with partial pivoting; store S_i^-1 column-major (SinvT[e][c][r]).
+// elimination with partial pivoting, in the precision S_i^-1 is stored in;
+// store S_i^-1 column-major (SinvT[e][c][r]).
 // One workgroup of TG x TG threads per element; thread (tr, tc) owns rows
 // tr + TG a and columns tc + TG b (a, b < R), so blocks up to R*TG fit.
 //
@@ -15,7 +16,7 @@
 #include <cstdint>
 
 template <int TGR, int TGC, int RR, int RC, typename T, typename TO>
-__global__ void __launch_bounds__(TGR* TGC) bj_invert_kernel(const T* __restrict__ KT, TO* __restrict__ SinvT,
+__global__ void __launch_bounds__(TGR* TGC) bj_invert_kernel(const double* __restrict__ KT, TO* __restrict__ SinvT,
                                                             int NE, T a1dt, T bc, int* __restrict__ status) {
     // thread (tr, tc), tid = tr + TGR tc, owns rows tr + TGR a (a < RR) and
     // columns tc + TGC b (b < RC); a column group (fixed tc) is TGR
@@ -37,7 +38,7 @@ __global__ void __launch_bounds__(TGR* TGC) bj_invert_kernel(const T* __restrict
     const int tid = threadIdx.x;
     const int tr = tid % TGR, tc = tid / TGR;
     const size_t e = blockIdx.x;
-    const T* K = KT + e * (size_t)NE * NE;
+    const double* K = KT + e * (size_t)NE * NE;
 
     T acc[RR][RC];
 #pragma unroll
@@ -50,12 +51,12 @@ __global__ void __launch_bounds__(TGR* TGC) bj_invert_kernel(const T* __restrict
         for (int i = tid; i < KC * NE; i += NT) {
             int t = i / NE, x = i % NE;
             int k = kk + t;
-            sA[t][x] = k < NE ? K[(size_t)k * NE + x] : T(0);   // K[x][k] = KT[k][x]
+            sA[t][x] = k < NE ? (T)K[(size_t)k * NE + x] : T(0);   // K[x][k] = KT[k][x]
         }
         for (int i = tid; i < KC * NE; i += NT) {
             int x = i / KC, t = i % KC;                      // consecutive threads: consecutive k
             int k = kk + t;
-            sB[t][x] = k < NE ? K[(size_t)x * NE + k] : T(0);   // K[k][x] = KT[x][k]
+            sB[t][x] = k < NE ? (T)K[(size_t)x * NE + k] : T(0);   // K[k][x] = KT[x][k]
         }
         __syncthreads();
 #pragma unroll
@@ -80,7 +81,7 @@ __global__ void __launch_bounds__(TGR* TGC) bj_invert_kernel(const T* __restrict
         for (int b = 0; b < RC; ++b) {
             int r = tr + TGR * a, c = tc + TGC * b;
             T v = (r == c) ? T(1) : T(0);
-            if (r < NE && c < NE) v += -a1dt * K[(size_t)c * NE + r] + bc * acc[a][b];
+            if (r < NE && c < NE) v += -a1dt * (T)K[(size_t)c * NE + r] + bc * acc[a][b];
             acc[a][b] = v;
         }
 
@@ -238,11 +239,13 @@ __global__ void __launch_bounds__(256) bj_apply_kernel(const TM* __restrict__ Si
     }
 }
 
+// the arithmetic follows the storage of S^-1: FP64 blocks are formed and inverted in FP64, FP32
+// blocks (mixed precision) in FP32 from the FP64 K
 template <int TGR, int TGC, int RR, int RC, typename TO>
 static hipError_t launch_inv(const double* KT, TO* SinvT, int NE, int nE, double a1dt, double bc, int* status,
                              hipStream_t st) {
-    hipLaunchKernelGGL((bj_invert_kernel<TGR, TGC, RR, RC, double, TO>), dim3(nE), dim3(TGR * TGC), 0, st, KT,
-                       SinvT, NE, a1dt, bc, status);
+    hipLaunchKernelGGL((bj_invert_kernel<TGR, TGC, RR, RC, TO, TO>), dim3(nE), dim3(TGR * TGC), 0, st, KT, SinvT,
+                       NE, (TO)a1dt, (TO)bc, status);
     return hipGetLastError();
 }
 

@@ -51,13 +51,24 @@ template <typename T, int VEC> __device__ __forceinline__ void vstore(T* p, cons
     }
 }
 
+// Second Gram-Schmidt pass wanted: the first pass removed more than half of ||u||^2
+// (cond[0] = ||u - V h||^2, cond[2] = ||u||^2).  A null cond means "always".
+__device__ __forceinline__ bool gs_second_pass(const double* cond) {
+    return !cond || cond[0] < 0.5 * cond[2];
+}
+
 // part[blockIdx.x * ldp + j] = sum_{i in block} V_j[i] * w[i], j < kc (<= MDOT_CHUNK); VEC values per
-// load (n and ld multiples of VEC)
+// load (n and ld multiples of VEC); zeros when cond says no second pass
 template <typename T, int VEC>
 __global__ void __launch_bounds__(BLAS_THREADS) mdot_kernel(const T* __restrict__ V, size_t ld, int kc,
                                                             const T* __restrict__ w, size_t n,
-                                                            double* __restrict__ part, int ldp) {
-    __shared__ double sh[BLAS_THREADS / 64];
+                                                            double* __restrict__ part, int ldp,
+                                                            const double* __restrict__ cond) {
+    __shared__ double shw[BLAS_THREADS / 64][MDOT_CHUNK];
+    if (!gs_second_pass(cond)) {
+        for (int j = threadIdx.x; j < kc; j += blockDim.x) part[(size_t)blockIdx.x * ldp + j] = 0.0;
+        return;
+    }
     double acc[MDOT_CHUNK];
 #pragma unroll
     for (int j = 0; j < MDOT_CHUNK; ++j) acc[j] = 0.0;
@@ -75,16 +86,31 @@ __global__ void __launch_bounds__(BLAS_THREADS) mdot_kernel(const T* __restrict_
                 acc[j] += s;
             }
     }
-    for (int j = 0; j < kc; ++j) {
-        double s = block_sum<T>(acc[j], sh);
-        if (threadIdx.x == 0) part[(size_t)blockIdx.x * ldp + j] = s;
+    // all kc sums at once: wave shuffle trees, then one LDS exchange across the waves
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < MDOT_CHUNK; ++j) {
+        if (j < kc) {
+            double v = acc[j];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            if (lane == 0) shw[wid][j] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kc) {
+        double r = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += shw[i][threadIdx.x];
+        part[(size_t)blockIdx.x * ldp + threadIdx.x] = r;
     }
 }
 
-// out[j] = scale * sum_b part[b * ldp + j]; one block per j
+// out[j] = scale * sum_b part[b * ldp + j]; one block per j; nothing when skip_if says no second pass
 __global__ void __launch_bounds__(BLAS_THREADS) reduce_parts_kernel(const double* __restrict__ part, int nb, int ldp,
-                                                                    double* __restrict__ out, double scale) {
+                                                                    double* __restrict__ out, double scale,
+                                                                    const double* __restrict__ skip_if) {
     __shared__ double sh[BLAS_THREADS / 64];
+    if (!gs_second_pass(skip_if)) return;
     const int j = blockIdx.x;
     double s = 0.0;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(size_t)b * ldp + j];
@@ -163,9 +189,11 @@ template <typename T, int VEC>
 __global__ void __launch_bounds__(BLAS_THREADS) gemv_sub_norm_kernel(const T* __restrict__ V, size_t ld, int k,
                                                                      const double* __restrict__ h,
                                                                      T* __restrict__ w, size_t n,
-                                                                     double* __restrict__ part) {
+                                                                     double* __restrict__ part,
+                                                                     const double* __restrict__ cond) {
     __shared__ double sh[64];
     __shared__ double red[BLAS_THREADS / 64];
+    if (!gs_second_pass(cond)) return;
     for (int j = threadIdx.x; j < k; j += blockDim.x) sh[j] = h[j];
     __syncthreads();
     double nrm = 0.0;
@@ -193,6 +221,18 @@ __global__ void __launch_bounds__(BLAS_THREADS) gemv_sub_norm_kernel(const T* __
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
+// v = u / sqrt(hn) with hn = sel[1] after a second pass, else sel[0] (sel: the pass norms and
+// ||u||^2 as above); u unchanged when hn is 0
+template <typename T>
+__global__ void __launch_bounds__(BLAS_THREADS) scale_inv_norm_kernel(T* __restrict__ u, size_t n,
+                                                                      const double* __restrict__ sel) {
+    const double hn = gs_second_pass(sel) ? sel[1] : sel[0];
+    if (!(hn > 0.0)) return;
+    const double s = 1.0 / sqrt(hn);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) u[i] = (T)(s * (double)u[i]);
+}
+
 // ------------------------------------------------------------------ launchers
 static int blas_grid(size_t n) {
     size_t g = (n + BLAS_THREADS - 1) / BLAS_THREADS;
@@ -210,49 +250,76 @@ static int vec_of(size_t n, size_t ld, int f32, const void* a, const void* b) {
     return (aligned && n % v == 0 && ld % v == 0) ? (int)v : 1;
 }
 
-// h[j] = V_j . w for j < k; part must hold grid * k doubles.
+// h[j] = V_j . w for j < k; part must hold grid * k doubles.  cond (device, may be null): only when
+// cond[0] < 0.5 cond[2] (a second Gram-Schmidt pass), else h is left unchanged.
+hipError_t blas_mdot_cond(const void* V, size_t ld, int k, const void* w, size_t n, int f32, double* part, double* h,
+                          const double* cond, hipStream_t st);
+
 hipError_t blas_mdot(const void* V, size_t ld, int k, const void* w, size_t n, int f32, double* part, double* h,
                      hipStream_t st) {
+    return blas_mdot_cond(V, ld, k, w, n, f32, part, h, nullptr, st);
+}
+
+hipError_t blas_mdot_cond(const void* V, size_t ld, int k, const void* w, size_t n, int f32, double* part, double* h,
+                          const double* cond, hipStream_t st) {
     const int vec = vec_of(n, ld, f32, V, w);
     int g = blas_grid(n / vec);
     for (int j0 = 0; j0 < k; j0 += MDOT_CHUNK) {
         int kc = k - j0 < MDOT_CHUNK ? k - j0 : MDOT_CHUNK;
         if (f32 && vec == 4)
             hipLaunchKernelGGL((mdot_kernel<float, 4>), dim3(g), dim3(BLAS_THREADS), 0, st,
-                               (const float*)V + j0 * ld, ld, kc, (const float*)w, n, part + j0, k);
+                               (const float*)V + j0 * ld, ld, kc, (const float*)w, n, part + j0, k, cond);
         else if (f32)
             hipLaunchKernelGGL((mdot_kernel<float, 1>), dim3(g), dim3(BLAS_THREADS), 0, st,
-                               (const float*)V + j0 * ld, ld, kc, (const float*)w, n, part + j0, k);
+                               (const float*)V + j0 * ld, ld, kc, (const float*)w, n, part + j0, k, cond);
         else if (vec == 2)
             hipLaunchKernelGGL((mdot_kernel<double, 2>), dim3(g), dim3(BLAS_THREADS), 0, st,
-                               (const double*)V + j0 * ld, ld, kc, (const double*)w, n, part + j0, k);
+                               (const double*)V + j0 * ld, ld, kc, (const double*)w, n, part + j0, k, cond);
         else
             hipLaunchKernelGGL((mdot_kernel<double, 1>), dim3(g), dim3(BLAS_THREADS), 0, st,
-                               (const double*)V + j0 * ld, ld, kc, (const double*)w, n, part + j0, k);
+                               (const double*)V + j0 * ld, ld, kc, (const double*)w, n, part + j0, k, cond);
     }
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(k), dim3(BLAS_THREADS), 0, st, part, g, k, h, 1.0);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(k), dim3(BLAS_THREADS), 0, st, part, g, k, h, 1.0, cond);
     return hipGetLastError();
 }
 
-// u -= V h (k columns, h on the device) and nrm2[0] = ||u||^2 afterwards
+// u -= V h (k columns, h on the device) and nrm2[0] = ||u||^2 afterwards; with cond as for
+// blas_mdot_cond (nothing happens without a second pass)
+hipError_t blas_gemv_sub_norm_cond(const void* V, size_t ld, int k, const double* h, void* u, size_t n, int f32,
+                                   double* part, double* nrm2, const double* cond, hipStream_t st);
+
 hipError_t blas_gemv_sub_norm(const void* V, size_t ld, int k, const double* h, void* u, size_t n, int f32,
                               double* part, double* nrm2, hipStream_t st) {
+    return blas_gemv_sub_norm_cond(V, ld, k, h, u, n, f32, part, nrm2, nullptr, st);
+}
+
+hipError_t blas_gemv_sub_norm_cond(const void* V, size_t ld, int k, const double* h, void* u, size_t n, int f32,
+                                   double* part, double* nrm2, const double* cond, hipStream_t st) {
     if (k > 64) return hipErrorInvalidValue;
     const int vec = vec_of(n, ld, f32, V, u);
     int g = blas_grid(n / vec);
     if (f32 && vec == 4)
         hipLaunchKernelGGL((gemv_sub_norm_kernel<float, 4>), dim3(g), dim3(BLAS_THREADS), 0, st, (const float*)V, ld,
-                           k, h, (float*)u, n, part);
+                           k, h, (float*)u, n, part, cond);
     else if (f32)
         hipLaunchKernelGGL((gemv_sub_norm_kernel<float, 1>), dim3(g), dim3(BLAS_THREADS), 0, st, (const float*)V, ld,
-                           k, h, (float*)u, n, part);
+                           k, h, (float*)u, n, part, cond);
     else if (vec == 2)
         hipLaunchKernelGGL((gemv_sub_norm_kernel<double, 2>), dim3(g), dim3(BLAS_THREADS), 0, st, (const double*)V,
-                           ld, k, h, (double*)u, n, part);
+                           ld, k, h, (double*)u, n, part, cond);
     else
         hipLaunchKernelGGL((gemv_sub_norm_kernel<double, 1>), dim3(g), dim3(BLAS_THREADS), 0, st, (const double*)V,
-                           ld, k, h, (double*)u, n, part);
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(BLAS_THREADS), 0, st, part, g, 1, nrm2, 1.0);
+                           ld, k, h, (double*)u, n, part, cond);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(BLAS_THREADS), 0, st, part, g, 1, nrm2, 1.0, cond);
+    return hipGetLastError();
+}
+
+hipError_t blas_scale_inv_norm(void* u, size_t n, int f32, const double* sel, hipStream_t st) {
+    int g = blas_grid(n);
+    if (f32)
+        hipLaunchKernelGGL(scale_inv_norm_kernel<float>, dim3(g), dim3(BLAS_THREADS), 0, st, (float*)u, n, sel);
+    else
+        hipLaunchKernelGGL(scale_inv_norm_kernel<double>, dim3(g), dim3(BLAS_THREADS), 0, st, (double*)u, n, sel);
     return hipGetLastError();
 }
 

@@ -105,7 +105,7 @@ double now_ms() {
 // ------------------------------------------------------------------ kernel timing
 static const char* KC_NAMES[KC_COUNT] = {"trace",    "r1",        "r2",   "res",  "jvp", "kcol",   "pcpre",
                                          "bj_apply", "bj_invert", "mdot", "gemv", "vec", "gs_dot", "gs_update",
-                                         "lin",      "mlp_feat",  "mlp_gemm", "mlp_vec"};
+                                         "lin",      "mlp_feat",  "mlp_gemm", "mlp_vec", "gs_pass2"};
 
 static long prof_begin(hbpc_ctx* c) {
     if (!c->prof) return -1;
@@ -286,10 +286,11 @@ static int status_read(hbpc_ctx* c) {
 
 // ||x||_2 (FP64 or FP32 vector of length n), synchronising
 static double dnorm(hbpc_ctx* c, const void* x, size_t n, int f32) {
-    hipchk(c, blas_mdot(x, 0, 1, x, n, f32, c->part, c->dres, c->stream), "norm");
-    hipchk(c, hipMemcpyAsync(c->hres, c->dres, sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy");
+    // own result slots: the Arnoldi copies of an iteration in flight use hres[0..386]
+    hipchk(c, blas_mdot(x, 0, 1, x, n, f32, c->part, c->dres + 250, c->stream), "norm");
+    hipchk(c, hipMemcpyAsync(c->hres + 500, c->dres + 250, sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy");
     hipchk(c, hipStreamSynchronize(c->stream), "sync");
-    return std::sqrt(c->hres[0]);
+    return std::sqrt(c->hres[500]);
 }
 
 // ------------------------------------------------------------------ BJ_ext
@@ -743,51 +744,57 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
         int k = 0;
         const double beta_cycle = beta;
         const int learned = c->prm.precond == HBPC_PC_LEARNED && c->lpc_active;
-        for (int j = 0; j < m; ++j) {
+        // Arnoldi iteration j, enqueued without waiting for the host: z_j = P^-1 v_j, u = J z_j,
+        // classical Gram-Schmidt against V_0..V_j with a second pass when the first one removes
+        // more than half of ||u||^2 (Daniel-Gragg-Kaufman-Stewart, decided on the device),
+        // v_{j+1} = u / ||u||, results (h, pass norms) copied to host slot j % 2
+        auto enqueue = [&](int j) {
             void* zj = use_pc ? Zj(j) : Vj(j);
             if (learned) lpc_apply(c, w, trw, Vj(j), zj, f32);
             else if (use_pc) pc_apply(c, w, trw, Vj(j), zj, f32);
             if (!learned && c->col_X && c->col_source != HBPC_MLP_PAIRS_NEWTON &&
-                (use_pc || c->col_source == HBPC_MLP_PAIRS_RANDOM) &&
-                c->col_count < c->col_cap && total % c->col_every == 0)
+                (use_pc || c->col_source == HBPC_MLP_PAIRS_RANDOM) && c->col_count < c->col_cap &&
+                (total + j) % c->col_every == 0)
                 lpc_collect_krylov(c, w, trw, Vj(j), zj, a1dt, bc, f32);
             void* u = Vj(j + 1);
             jvp(zj, u);
-            // classical Gram-Schmidt against V_0..V_j with a second pass when the
-            // first one cancels more than half of ||u||^2 (Daniel-Gragg-Kaufman-Stewart)
             double* h1 = c->dres;
             double* h2 = c->dres + 64;
-            double* nb = c->dres + 130;
-            double* hn = c->dres + 128;
+            double* sel = c->dres + 128;   // first-pass ||u - V h1||^2, second-pass norm^2, ||u||^2
             const double vb = (double)n2 * esz;
             long pi = prof_begin(c);
             hipchk(c, blas_mdot(V, n2, j + 1, u, n2, f32, c->part, h1, c->stream), "gs dot");
             prof_end(c, pi, KC_GSDOT, (j + 2) * vb);
             pi = prof_begin(c);
-            hipchk(c, blas_mdot(u, 0, 1, u, n2, f32, c->part, nb, c->stream), "norm");
+            hipchk(c, blas_mdot(u, 0, 1, u, n2, f32, c->part, sel + 2, c->stream), "norm");
             prof_end(c, pi, KC_MDOT, vb);
             pi = prof_begin(c);
-            hipchk(c, blas_gemv_sub_norm(V, n2, j + 1, h1, u, n2, f32, c->part, hn, c->stream), "gs update");
+            hipchk(c, blas_gemv_sub_norm(V, n2, j + 1, h1, u, n2, f32, c->part, sel, c->stream), "gs update");
             prof_end(c, pi, KC_GSUPD, (j + 3) * vb);
-            hipchk(c, hipMemcpyAsync(c->hres, c->dres, 131 * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+            pi = prof_begin(c);
+            hipchk(c, blas_mdot_cond(V, n2, j + 1, u, n2, f32, c->part, h2, sel, c->stream), "gs dot");
+            hipchk(c, blas_gemv_sub_norm_cond(V, n2, j + 1, h2, u, n2, f32, c->part, sel + 1, sel, c->stream),
+                   "gs update");
+            prof_end(c, pi, KC_GS2, 0.0);
+            pi = prof_begin(c);
+            hipchk(c, blas_scale_inv_norm(u, n2, f32, sel, c->stream), "scale");
+            prof_end(c, pi, KC_VEC, 2 * vb);
+            hipchk(c, hipMemcpyAsync(c->hres + 256 * (j & 1), c->dres, 131 * sizeof(double), hipMemcpyDeviceToHost,
+                                     c->stream),
                    "copy");
-            hipchk(c, hipStreamSynchronize(c->stream), "sync");
-            for (int i = 0; i <= j; ++i) Hc(i, j) = c->hres[i];
-            if (c->hres[128] < 0.5 * c->hres[130]) {
-                pi = prof_begin(c);
-                hipchk(c, blas_mdot(V, n2, j + 1, u, n2, f32, c->part, h2, c->stream), "gs dot");
-                prof_end(c, pi, KC_GSDOT, (j + 2) * vb);
-                pi = prof_begin(c);
-                hipchk(c, blas_gemv_sub_norm(V, n2, j + 1, h2, u, n2, f32, c->part, hn, c->stream), "gs update");
-                prof_end(c, pi, KC_GSUPD, (j + 3) * vb);
-                hipchk(c, hipMemcpyAsync(c->hres + 64, c->dres + 64, 65 * sizeof(double), hipMemcpyDeviceToHost,
-                                         c->stream),
-                       "copy");
-                hipchk(c, hipStreamSynchronize(c->stream), "sync");
-                for (int i = 0; i <= j; ++i) Hc(i, j) += c->hres[64 + i];
-                c->st_reorth++;
-            }
-            double hnrm = std::sqrt(c->hres[128]);
+            hipchk(c, hipEventRecord(c->arn_ev[j & 1], c->stream), "event");
+        };
+        enqueue(0);
+        for (int j = 0; j < m; ++j) {
+            // the next iteration goes to the GPU before this one's results are read (it is
+            // discarded if this one ends the cycle)
+            if (j + 1 < m && total + 1 < maxit) enqueue(j + 1);
+            hipchk(c, hipEventSynchronize(c->arn_ev[j & 1]), "sync");
+            const double* hr = c->hres + 256 * (j & 1);
+            const bool second = hr[128] < 0.5 * hr[130];
+            for (int i = 0; i <= j; ++i) Hc(i, j) = hr[i] + (second ? hr[64 + i] : 0.0);
+            if (second) c->st_reorth++;
+            double hnrm = std::sqrt(second ? hr[129] : hr[128]);
             Hc(j + 1, j) = hnrm;
             if (!std::isfinite(hnrm)) {
                 // a non-finite learned-preconditioner output: drop column j and fall back
@@ -815,7 +822,6 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
             if (std::fabs(g[j + 1]) <= rtol * beta0) { converged = true; break; }
             if (total >= maxit) break;
             if (hnrm == 0.0) { converged = true; break; }
-            hipchk(c, blas_axpby(1.0 / hnrm, u, f32, 0.0, u, f32, n2, c->stream), "scale");
         }
         // y = H^-1 g (upper triangular), dX += Z y
         for (int i = k - 1; i >= 0; --i) {
@@ -986,6 +992,8 @@ static void ctx_free(hbpc_ctx* c) {
         dfree(c->qtr[1][j]);
     }
     if (c->hres) (void)hipHostFree(c->hres);
+    for (int i = 0; i < 2; ++i)
+        if (c->arn_ev[i]) (void)hipEventDestroy(c->arn_ev[i]);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
 }
@@ -1131,8 +1139,9 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
     c->dres = dalloc<double>(c, 256);
     c->dstatus = dalloc<int>(c, 1);
     void* h = nullptr;
-    hipchk(c, hipHostMalloc(&h, 256 * sizeof(double)), "hipHostMalloc");
+    hipchk(c, hipHostMalloc(&h, 512 * sizeof(double)), "hipHostMalloc");
     c->hres = (double*)h;
+    for (int i = 0; i < 2; ++i) hipchk(c, hipEventCreateWithFlags(&c->arn_ev[i], hipEventDisableTiming), "event");
 }
 
 static void train_impl(hbpc_ctx* c, const float* X, const float* T, size_t count, const hbpc_train_cfg* cfg,

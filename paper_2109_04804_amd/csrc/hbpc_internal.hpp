@@ -22,6 +22,11 @@ hipError_t blas_gemv_sub_norm(const void* V, size_t ld, int k, const double* h, 
                               double* part, double* nrm2, hipStream_t st);
 hipError_t blas_gemv_sub(const void* V, size_t ld, int k, const double* h, void* w, size_t n, int f32,
                          hipStream_t st);
+hipError_t blas_mdot_cond(const void* V, size_t ld, int k, const void* w, size_t n, int f32, double* part, double* h,
+                          const double* cond, hipStream_t st);
+hipError_t blas_gemv_sub_norm_cond(const void* V, size_t ld, int k, const double* h, void* u, size_t n, int f32,
+                                   double* part, double* nrm2, const double* cond, hipStream_t st);
+hipError_t blas_scale_inv_norm(void* u, size_t n, int f32, const double* sel, hipStream_t st);
 hipError_t blas_axpby(double a, const void* x, int tx, double b, void* y, int ty, size_t n, hipStream_t st);
 hipError_t blas_lincomb2(double a, const double* x, double b, const double* z, double* y, size_t n, hipStream_t st);
 hipError_t blas_gemv_add(const void* Z, int tz, size_t ld, int k, const double* c, void* y, int ty, size_t n,
@@ -113,7 +118,8 @@ struct hbpc_ctx {
     // reductions
     double* part;             // blas partials
     double* dres;             // device results (256)
-    double* hres;             // pinned host copy (256)
+    double* hres;             // pinned host copies (512: two Arnoldi result slots of 256)
+    hipEvent_t arn_ev[2];     // Arnoldi results of iteration j copied to slot j % 2
     int* dstatus;
     // FD scratch (allocated on demand)
     double* fd[6];
@@ -146,7 +152,7 @@ struct hbpc_ctx {
 };
 
 enum { KC_TRACE = 0, KC_R1, KC_R2, KC_RES, KC_JVP, KC_KCOL, KC_PCPRE, KC_BJAPPLY, KC_BJINV, KC_MDOT, KC_GEMV,
-       KC_VEC, KC_GSDOT, KC_GSUPD, KC_LIN, KC_FEAT, KC_GEMM, KC_MLPV, KC_COUNT };
+       KC_VEC, KC_GSDOT, KC_GSUPD, KC_LIN, KC_FEAT, KC_GEMM, KC_MLPV, KC_GS2, KC_COUNT };
 
 // helpers implemented in ops.cpp
 int op_launch(hbpc_ctx* c, const LaunchReq& r, int f32);
