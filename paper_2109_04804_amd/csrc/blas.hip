@@ -1,6 +1,7 @@
 // Vector kernels of the Newton-Krylov solver: block-partial dot products with
-// several basis vectors at once (classical Gram-Schmidt), the update
-// w -= V h, norms, axpby, casts.  Reductions are deterministic: each block sums
+// several basis vectors at once (classical Gram-Schmidt, twice, the second
+// pass from the Gram matrix of the basis), the update w -= V h, norms,
+// axpby, casts.  Reductions are deterministic: each block sums
 // a fixed set of indices in a fixed order, partial results are combined by
 // one block in a fixed tree, so two runs give bitwise equal results.
 #include <hip/hip_runtime.h>
@@ -9,6 +10,7 @@
 
 constexpr int BLAS_THREADS = 256;
 constexpr int MDOT_CHUNK = 16;
+constexpr int MDOT2_CHUNK = 8;
 
 template <typename T> __device__ __forceinline__ double block_sum(double v, double* sh) {
     // wave64 shuffle tree, then LDS across the 4 waves
@@ -51,24 +53,13 @@ template <typename T, int VEC> __device__ __forceinline__ void vstore(T* p, cons
     }
 }
 
-// Second Gram-Schmidt pass wanted: the first pass removed more than half of ||u||^2
-// (cond[0] = ||u - V h||^2, cond[2] = ||u||^2).  A null cond means "always".
-__device__ __forceinline__ bool gs_second_pass(const double* cond) {
-    return !cond || cond[0] < 0.5 * cond[2];
-}
-
 // part[blockIdx.x * ldp + j] = sum_{i in block} V_j[i] * w[i], j < kc (<= MDOT_CHUNK); VEC values per
-// load (n and ld multiples of VEC); zeros when cond says no second pass
+// load (n and ld multiples of VEC)
 template <typename T, int VEC>
 __global__ void __launch_bounds__(BLAS_THREADS) mdot_kernel(const T* __restrict__ V, size_t ld, int kc,
                                                             const T* __restrict__ w, size_t n,
-                                                            double* __restrict__ part, int ldp,
-                                                            const double* __restrict__ cond) {
+                                                            double* __restrict__ part, int ldp) {
     __shared__ double shw[BLAS_THREADS / 64][MDOT_CHUNK];
-    if (!gs_second_pass(cond)) {
-        for (int j = threadIdx.x; j < kc; j += blockDim.x) part[(size_t)blockIdx.x * ldp + j] = 0.0;
-        return;
-    }
     double acc[MDOT_CHUNK];
 #pragma unroll
     for (int j = 0; j < MDOT_CHUNK; ++j) acc[j] = 0.0;
@@ -105,12 +96,86 @@ __global__ void __launch_bounds__(BLAS_THREADS) mdot_kernel(const T* __restrict_
     }
 }
 
-// out[j] = scale * sum_b part[b * ldp + j]; one block per j; nothing when skip_if says no second pass
+// part[b * ldp + j] = sum_{i in block b} V_j[i] w1[i] and part[b * ldp + kc2 + j] = ... V_j[i] w2[i]
+// for j < kc (<= MDOT2_CHUNK): the projections of a new vector and the Gram column of the newest
+// basis vector in one pass over V
+template <typename T, int VEC>
+__global__ void __launch_bounds__(BLAS_THREADS) mdot2_kernel(const T* __restrict__ V, size_t ld, int kc,
+                                                             const T* __restrict__ w1, const T* __restrict__ w2,
+                                                             size_t n, double* __restrict__ part, int ldp,
+                                                             int off2) {
+    __shared__ double shw[BLAS_THREADS / 64][2 * MDOT2_CHUNK];
+    double a1[MDOT2_CHUNK], a2[MDOT2_CHUNK];
+#pragma unroll
+    for (int j = 0; j < MDOT2_CHUNK; ++j) a1[j] = a2[j] = 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t nv = n / VEC;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
+        const Vec<T, VEC> x1 = vload<T, VEC>(w1 + i * VEC);
+        const Vec<T, VEC> x2 = vload<T, VEC>(w2 + i * VEC);
+#pragma unroll
+        for (int j = 0; j < MDOT2_CHUNK; ++j)
+            if (j < kc) {
+                const Vec<T, VEC> vv = vload<T, VEC>(V + j * ld + i * VEC);
+                double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) {
+                    s1 += (double)vv.v[q] * (double)x1.v[q];
+                    s2 += (double)vv.v[q] * (double)x2.v[q];
+                }
+                a1[j] += s1;
+                a2[j] += s2;
+            }
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < MDOT2_CHUNK; ++j) {
+        if (j < kc) {
+            double v1 = a1[j], v2 = a2[j];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                v1 += __shfl_down(v1, off, 64);
+                v2 += __shfl_down(v2, off, 64);
+            }
+            if (lane == 0) {
+                shw[wid][j] = v1;
+                shw[wid][MDOT2_CHUNK + j] = v2;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * kc) {
+        const int j = threadIdx.x < kc ? threadIdx.x : threadIdx.x - kc + MDOT2_CHUNK;
+        double r = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += shw[i][j];
+        const int col = threadIdx.x < kc ? threadIdx.x : off2 + threadIdx.x - kc;
+        part[(size_t)blockIdx.x * ldp + col] = r;
+    }
+}
+
+// Gram-Schmidt coefficients of the second pass from the Gram matrix: with G = V^T V (columns
+// 0..j, column j = g just computed, stored symmetric, leading dimension ldg) and h1 = V^T u,
+// the second classical pass V^T (u - V h1) = h1 - G h1, so the two passes together subtract
+// V h with h = 2 h1 - G h1.  One block.
+__global__ void __launch_bounds__(64) gram_coef_kernel(double* __restrict__ G, int ldg, int j,
+                                                       const double* __restrict__ h1, const double* __restrict__ g,
+                                                       double* __restrict__ h) {
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+        G[(size_t)i * ldg + j] = g[i];
+        G[(size_t)j * ldg + i] = g[i];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+        double s = 0.0;
+        for (int l = 0; l <= j; ++l) s += G[(size_t)i * ldg + l] * h1[l];
+        h[i] = 2.0 * h1[i] - s;
+    }
+}
+
+// out[j] = scale * sum_b part[b * ldp + j]; one block per j
 __global__ void __launch_bounds__(BLAS_THREADS) reduce_parts_kernel(const double* __restrict__ part, int nb, int ldp,
-                                                                    double* __restrict__ out, double scale,
-                                                                    const double* __restrict__ skip_if) {
+                                                                    double* __restrict__ out, double scale) {
     __shared__ double sh[BLAS_THREADS / 64];
-    if (!gs_second_pass(skip_if)) return;
     const int j = blockIdx.x;
     double s = 0.0;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(size_t)b * ldp + j];
@@ -189,11 +254,9 @@ template <typename T, int VEC>
 __global__ void __launch_bounds__(BLAS_THREADS) gemv_sub_norm_kernel(const T* __restrict__ V, size_t ld, int k,
                                                                      const double* __restrict__ h,
                                                                      T* __restrict__ w, size_t n,
-                                                                     double* __restrict__ part,
-                                                                     const double* __restrict__ cond) {
+                                                                     double* __restrict__ part) {
     __shared__ double sh[64];
     __shared__ double red[BLAS_THREADS / 64];
-    if (!gs_second_pass(cond)) return;
     for (int j = threadIdx.x; j < k; j += blockDim.x) sh[j] = h[j];
     __syncthreads();
     double nrm = 0.0;
@@ -221,12 +284,11 @@ __global__ void __launch_bounds__(BLAS_THREADS) gemv_sub_norm_kernel(const T* __
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// v = u / sqrt(hn) with hn = sel[1] after a second pass, else sel[0] (sel: the pass norms and
-// ||u||^2 as above); u unchanged when hn is 0
+// v = u / sqrt(nrm2[0]) with the squared norm on the device; u unchanged when it is 0
 template <typename T>
 __global__ void __launch_bounds__(BLAS_THREADS) scale_inv_norm_kernel(T* __restrict__ u, size_t n,
-                                                                      const double* __restrict__ sel) {
-    const double hn = gs_second_pass(sel) ? sel[1] : sel[0];
+                                                                      const double* __restrict__ nrm2) {
+    const double hn = nrm2[0];
     if (!(hn > 0.0)) return;
     const double s = 1.0 / sqrt(hn);
     const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -250,76 +312,90 @@ static int vec_of(size_t n, size_t ld, int f32, const void* a, const void* b) {
     return (aligned && n % v == 0 && ld % v == 0) ? (int)v : 1;
 }
 
-// h[j] = V_j . w for j < k; part must hold grid * k doubles.  cond (device, may be null): only when
-// cond[0] < 0.5 cond[2] (a second Gram-Schmidt pass), else h is left unchanged.
-hipError_t blas_mdot_cond(const void* V, size_t ld, int k, const void* w, size_t n, int f32, double* part, double* h,
-                          const double* cond, hipStream_t st);
-
+// h[j] = V_j . w for j < k; part must hold grid * k doubles.
 hipError_t blas_mdot(const void* V, size_t ld, int k, const void* w, size_t n, int f32, double* part, double* h,
                      hipStream_t st) {
-    return blas_mdot_cond(V, ld, k, w, n, f32, part, h, nullptr, st);
-}
-
-hipError_t blas_mdot_cond(const void* V, size_t ld, int k, const void* w, size_t n, int f32, double* part, double* h,
-                          const double* cond, hipStream_t st) {
     const int vec = vec_of(n, ld, f32, V, w);
     int g = blas_grid(n / vec);
     for (int j0 = 0; j0 < k; j0 += MDOT_CHUNK) {
         int kc = k - j0 < MDOT_CHUNK ? k - j0 : MDOT_CHUNK;
         if (f32 && vec == 4)
             hipLaunchKernelGGL((mdot_kernel<float, 4>), dim3(g), dim3(BLAS_THREADS), 0, st,
-                               (const float*)V + j0 * ld, ld, kc, (const float*)w, n, part + j0, k, cond);
+                               (const float*)V + j0 * ld, ld, kc, (const float*)w, n, part + j0, k);
         else if (f32)
             hipLaunchKernelGGL((mdot_kernel<float, 1>), dim3(g), dim3(BLAS_THREADS), 0, st,
-                               (const float*)V + j0 * ld, ld, kc, (const float*)w, n, part + j0, k, cond);
+                               (const float*)V + j0 * ld, ld, kc, (const float*)w, n, part + j0, k);
         else if (vec == 2)
             hipLaunchKernelGGL((mdot_kernel<double, 2>), dim3(g), dim3(BLAS_THREADS), 0, st,
-                               (const double*)V + j0 * ld, ld, kc, (const double*)w, n, part + j0, k, cond);
+                               (const double*)V + j0 * ld, ld, kc, (const double*)w, n, part + j0, k);
         else
             hipLaunchKernelGGL((mdot_kernel<double, 1>), dim3(g), dim3(BLAS_THREADS), 0, st,
-                               (const double*)V + j0 * ld, ld, kc, (const double*)w, n, part + j0, k, cond);
+                               (const double*)V + j0 * ld, ld, kc, (const double*)w, n, part + j0, k);
     }
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(k), dim3(BLAS_THREADS), 0, st, part, g, k, h, 1.0, cond);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(k), dim3(BLAS_THREADS), 0, st, part, g, k, h, 1.0);
     return hipGetLastError();
 }
 
-// u -= V h (k columns, h on the device) and nrm2[0] = ||u||^2 afterwards; with cond as for
-// blas_mdot_cond (nothing happens without a second pass)
-hipError_t blas_gemv_sub_norm_cond(const void* V, size_t ld, int k, const double* h, void* u, size_t n, int f32,
-                                   double* part, double* nrm2, const double* cond, hipStream_t st);
-
+// u -= V h (k columns, h on the device) and nrm2[0] = ||u||^2 afterwards
 hipError_t blas_gemv_sub_norm(const void* V, size_t ld, int k, const double* h, void* u, size_t n, int f32,
                               double* part, double* nrm2, hipStream_t st) {
-    return blas_gemv_sub_norm_cond(V, ld, k, h, u, n, f32, part, nrm2, nullptr, st);
-}
-
-hipError_t blas_gemv_sub_norm_cond(const void* V, size_t ld, int k, const double* h, void* u, size_t n, int f32,
-                                   double* part, double* nrm2, const double* cond, hipStream_t st) {
     if (k > 64) return hipErrorInvalidValue;
     const int vec = vec_of(n, ld, f32, V, u);
     int g = blas_grid(n / vec);
     if (f32 && vec == 4)
         hipLaunchKernelGGL((gemv_sub_norm_kernel<float, 4>), dim3(g), dim3(BLAS_THREADS), 0, st, (const float*)V, ld,
-                           k, h, (float*)u, n, part, cond);
+                           k, h, (float*)u, n, part);
     else if (f32)
         hipLaunchKernelGGL((gemv_sub_norm_kernel<float, 1>), dim3(g), dim3(BLAS_THREADS), 0, st, (const float*)V, ld,
-                           k, h, (float*)u, n, part, cond);
+                           k, h, (float*)u, n, part);
     else if (vec == 2)
         hipLaunchKernelGGL((gemv_sub_norm_kernel<double, 2>), dim3(g), dim3(BLAS_THREADS), 0, st, (const double*)V,
-                           ld, k, h, (double*)u, n, part, cond);
+                           ld, k, h, (double*)u, n, part);
     else
         hipLaunchKernelGGL((gemv_sub_norm_kernel<double, 1>), dim3(g), dim3(BLAS_THREADS), 0, st, (const double*)V,
-                           ld, k, h, (double*)u, n, part, cond);
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(BLAS_THREADS), 0, st, part, g, 1, nrm2, 1.0, cond);
+                           ld, k, h, (double*)u, n, part);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(BLAS_THREADS), 0, st, part, g, 1, nrm2, 1.0);
     return hipGetLastError();
 }
 
-hipError_t blas_scale_inv_norm(void* u, size_t n, int f32, const double* sel, hipStream_t st) {
+hipError_t blas_scale_inv_norm(void* u, size_t n, int f32, const double* nrm2, hipStream_t st) {
     int g = blas_grid(n);
     if (f32)
-        hipLaunchKernelGGL(scale_inv_norm_kernel<float>, dim3(g), dim3(BLAS_THREADS), 0, st, (float*)u, n, sel);
+        hipLaunchKernelGGL(scale_inv_norm_kernel<float>, dim3(g), dim3(BLAS_THREADS), 0, st, (float*)u, n, nrm2);
     else
-        hipLaunchKernelGGL(scale_inv_norm_kernel<double>, dim3(g), dim3(BLAS_THREADS), 0, st, (double*)u, n, sel);
+        hipLaunchKernelGGL(scale_inv_norm_kernel<double>, dim3(g), dim3(BLAS_THREADS), 0, st, (double*)u, n, nrm2);
+    return hipGetLastError();
+}
+
+// h1[i] = V_i . w1 and g[i] = V_i . w2 for i < k, then the combined two-pass coefficients
+// h = 2 h1 - G h1 with G's column k-1 set from g (G: device, ldg x ldg).  part: grid * 2k doubles.
+hipError_t blas_gs_gram(const void* V, size_t ld, int k, const void* w1, const void* w2, size_t n, int f32,
+                        double* part, double* h1, double* g, double* G, int ldg, double* h, hipStream_t st) {
+    if (k > 64 || k > ldg || g != h1 + k) return hipErrorInvalidValue;
+    const int vec = (vec_of(n, ld, f32, V, w1) == vec_of(n, ld, f32, V, w2)) ? vec_of(n, ld, f32, V, w1) : 1;
+    int gr = blas_grid(n / vec);
+    for (int j0 = 0; j0 < k; j0 += MDOT2_CHUNK) {
+        int kc = k - j0 < MDOT2_CHUNK ? k - j0 : MDOT2_CHUNK;
+        if (f32 && vec == 4)
+            hipLaunchKernelGGL((mdot2_kernel<float, 4>), dim3(gr), dim3(BLAS_THREADS), 0, st,
+                               (const float*)V + j0 * ld, ld, kc, (const float*)w1, (const float*)w2, n, part + j0,
+                               2 * k, k);
+        else if (f32)
+            hipLaunchKernelGGL((mdot2_kernel<float, 1>), dim3(gr), dim3(BLAS_THREADS), 0, st,
+                               (const float*)V + j0 * ld, ld, kc, (const float*)w1, (const float*)w2, n, part + j0,
+                               2 * k, k);
+        else if (vec == 2)
+            hipLaunchKernelGGL((mdot2_kernel<double, 2>), dim3(gr), dim3(BLAS_THREADS), 0, st,
+                               (const double*)V + j0 * ld, ld, kc, (const double*)w1, (const double*)w2, n,
+                               part + j0, 2 * k, k);
+        else
+            hipLaunchKernelGGL((mdot2_kernel<double, 1>), dim3(gr), dim3(BLAS_THREADS), 0, st,
+                               (const double*)V + j0 * ld, ld, kc, (const double*)w1, (const double*)w2, n,
+                               part + j0, 2 * k, k);
+    }
+    // h1 = part columns 0..k-1, g = columns k..2k-1 (h1 and g adjacent: g = h1 + k)
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(2 * k), dim3(BLAS_THREADS), 0, st, part, gr, 2 * k, h1, 1.0);
+    hipLaunchKernelGGL(gram_coef_kernel, dim3(1), dim3(64), 0, st, G, ldg, k - 1, h1, g, h);
     return hipGetLastError();
 }
 

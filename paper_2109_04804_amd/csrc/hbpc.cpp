@@ -105,7 +105,7 @@ double now_ms() {
 // ------------------------------------------------------------------ kernel timing
 static const char* KC_NAMES[KC_COUNT] = {"trace",    "r1",        "r2",   "res",  "jvp", "kcol",   "pcpre",
                                          "bj_apply", "bj_invert", "mdot", "gemv", "vec", "gs_dot", "gs_update",
-                                         "lin",      "mlp_feat",  "mlp_gemm", "mlp_vec", "gs_pass2"};
+                                         "lin",      "mlp_feat",  "mlp_gemm", "mlp_vec"};
 
 static long prof_begin(hbpc_ctx* c) {
     if (!c->prof) return -1;
@@ -745,9 +745,10 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
         const double beta_cycle = beta;
         const int learned = c->prm.precond == HBPC_PC_LEARNED && c->lpc_active;
         // Arnoldi iteration j, enqueued without waiting for the host: z_j = P^-1 v_j, u = J z_j,
-        // classical Gram-Schmidt against V_0..V_j with a second pass when the first one removes
-        // more than half of ||u||^2 (Daniel-Gragg-Kaufman-Stewart, decided on the device),
-        // v_{j+1} = u / ||u||, results (h, pass norms) copied to host slot j % 2
+        // classical Gram-Schmidt twice against V_0..V_j, the second pass taken from the Gram
+        // matrix G = V^T V (V^T (u - V h1) = h1 - G h1, so one pass over V gives V^T u and the
+        // new column of G, and one update subtracts V (2 h1 - G h1)), v_{j+1} = u / ||u||,
+        // results (h, ||u||^2) copied to host slot j % 2
         auto enqueue = [&](int j) {
             void* zj = use_pc ? Zj(j) : Vj(j);
             if (learned) lpc_apply(c, w, trw, Vj(j), zj, f32);
@@ -758,28 +759,22 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
                 lpc_collect_krylov(c, w, trw, Vj(j), zj, a1dt, bc, f32);
             void* u = Vj(j + 1);
             jvp(zj, u);
-            double* h1 = c->dres;
-            double* h2 = c->dres + 64;
-            double* sel = c->dres + 128;   // first-pass ||u - V h1||^2, second-pass norm^2, ||u||^2
+            double* h1 = c->dres;            // V^T u, then (adjacent) g = V^T v_j
+            double* hn = c->dres + 128;      // ||u - V h||^2
+            double* h = c->dres + 132;       // two-pass coefficients
             const double vb = (double)n2 * esz;
             long pi = prof_begin(c);
-            hipchk(c, blas_mdot(V, n2, j + 1, u, n2, f32, c->part, h1, c->stream), "gs dot");
-            prof_end(c, pi, KC_GSDOT, (j + 2) * vb);
+            hipchk(c, blas_gs_gram(V, n2, j + 1, u, Vj(j), n2, f32, c->part, h1, h1 + (j + 1), c->dgram, m + 1, h,
+                                   c->stream),
+                   "gs dot");
+            prof_end(c, pi, KC_GSDOT, (j + 3) * vb);
             pi = prof_begin(c);
-            hipchk(c, blas_mdot(u, 0, 1, u, n2, f32, c->part, sel + 2, c->stream), "norm");
-            prof_end(c, pi, KC_MDOT, vb);
-            pi = prof_begin(c);
-            hipchk(c, blas_gemv_sub_norm(V, n2, j + 1, h1, u, n2, f32, c->part, sel, c->stream), "gs update");
+            hipchk(c, blas_gemv_sub_norm(V, n2, j + 1, h, u, n2, f32, c->part, hn, c->stream), "gs update");
             prof_end(c, pi, KC_GSUPD, (j + 3) * vb);
             pi = prof_begin(c);
-            hipchk(c, blas_mdot_cond(V, n2, j + 1, u, n2, f32, c->part, h2, sel, c->stream), "gs dot");
-            hipchk(c, blas_gemv_sub_norm_cond(V, n2, j + 1, h2, u, n2, f32, c->part, sel + 1, sel, c->stream),
-                   "gs update");
-            prof_end(c, pi, KC_GS2, 0.0);
-            pi = prof_begin(c);
-            hipchk(c, blas_scale_inv_norm(u, n2, f32, sel, c->stream), "scale");
+            hipchk(c, blas_scale_inv_norm(u, n2, f32, hn, c->stream), "scale");
             prof_end(c, pi, KC_VEC, 2 * vb);
-            hipchk(c, hipMemcpyAsync(c->hres + 256 * (j & 1), c->dres, 131 * sizeof(double), hipMemcpyDeviceToHost,
+            hipchk(c, hipMemcpyAsync(c->hres + 256 * (j & 1), c->dres, 196 * sizeof(double), hipMemcpyDeviceToHost,
                                      c->stream),
                    "copy");
             hipchk(c, hipEventRecord(c->arn_ev[j & 1], c->stream), "event");
@@ -791,10 +786,8 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
             if (j + 1 < m && total + 1 < maxit) enqueue(j + 1);
             hipchk(c, hipEventSynchronize(c->arn_ev[j & 1]), "sync");
             const double* hr = c->hres + 256 * (j & 1);
-            const bool second = hr[128] < 0.5 * hr[130];
-            for (int i = 0; i <= j; ++i) Hc(i, j) = hr[i] + (second ? hr[64 + i] : 0.0);
-            if (second) c->st_reorth++;
-            double hnrm = std::sqrt(second ? hr[129] : hr[128]);
+            for (int i = 0; i <= j; ++i) Hc(i, j) = hr[132 + i];
+            double hnrm = std::sqrt(hr[128]);
             Hc(j + 1, j) = hnrm;
             if (!std::isfinite(hnrm)) {
                 // a non-finite learned-preconditioner output: drop column j and fall back
@@ -982,7 +975,7 @@ static void ctx_free(hbpc_ctx* c) {
     }
     void* bufs[] = {c->R1all, c->R2all, c->X, c->b, c->G, c->dX, c->rhs, c->trw, c->trs, c->trd1, c->trd2,
                     c->X32, c->trw32, c->trs32, c->trd1_32, c->trd2_32, c->V, c->Z, c->kv, c->KT, c->Sinv,
-                    c->part, c->dres, c->dstatus, c->basis64, c->basis32, c->theta, c->adam_m, c->adam_v,
+                    c->part, c->dres, c->dgram, c->dstatus, c->basis64, c->basis32, c->theta, c->adam_m, c->adam_v,
                     c->mgrad, c->ap_X, c->ap_G1, c->ap_G2, c->ap_H1, c->ap_H2, c->ap_Y, c->ap_s, c->tr_buf, c->tr_idx_dev,
                     c->col_elems};
     for (void* p : bufs) dfree(p);
@@ -1135,8 +1128,9 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
     // K build in chunks of <= 256 MB of FP64 blocks
     size_t per = (size_t)c->NE * c->NE * 8;
     c->kt_chunk = std::max<size_t>(1, std::min<size_t>(c->nE, (size_t)(256u << 20) / per));
-    c->part = dalloc<double>(c, (size_t)blas_mdot_grid(c->n2) * 65 + 64);
+    c->part = dalloc<double>(c, (size_t)blas_mdot_grid(c->n2) * 130 + 64);
     c->dres = dalloc<double>(c, 256);
+    c->dgram = dalloc<double>(c, (size_t)(c->m_alloc + 1) * (c->m_alloc + 1));
     c->dstatus = dalloc<int>(c, 1);
     void* h = nullptr;
     hipchk(c, hipHostMalloc(&h, 512 * sizeof(double)), "hipHostMalloc");

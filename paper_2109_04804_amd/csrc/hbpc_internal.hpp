@@ -22,11 +22,9 @@ hipError_t blas_gemv_sub_norm(const void* V, size_t ld, int k, const double* h, 
                               double* part, double* nrm2, hipStream_t st);
 hipError_t blas_gemv_sub(const void* V, size_t ld, int k, const double* h, void* w, size_t n, int f32,
                          hipStream_t st);
-hipError_t blas_mdot_cond(const void* V, size_t ld, int k, const void* w, size_t n, int f32, double* part, double* h,
-                          const double* cond, hipStream_t st);
-hipError_t blas_gemv_sub_norm_cond(const void* V, size_t ld, int k, const double* h, void* u, size_t n, int f32,
-                                   double* part, double* nrm2, const double* cond, hipStream_t st);
-hipError_t blas_scale_inv_norm(void* u, size_t n, int f32, const double* sel, hipStream_t st);
+hipError_t blas_scale_inv_norm(void* u, size_t n, int f32, const double* nrm2, hipStream_t st);
+hipError_t blas_gs_gram(const void* V, size_t ld, int k, const void* w1, const void* w2, size_t n, int f32,
+                        double* part, double* h1, double* g, double* G, int ldg, double* h, hipStream_t st);
 hipError_t blas_axpby(double a, const void* x, int tx, double b, void* y, int ty, size_t n, hipStream_t st);
 hipError_t blas_lincomb2(double a, const double* x, double b, const double* z, double* y, size_t n, hipStream_t st);
 hipError_t blas_gemv_add(const void* Z, int tz, size_t ld, int k, const double* c, void* y, int ty, size_t n,
@@ -118,6 +116,7 @@ struct hbpc_ctx {
     // reductions
     double* part;             // blas partials
     double* dres;             // device results (256)
+    double* dgram;            // Gram matrix V^T V of the current FGMRES cycle, (m+1) x (m+1)
     double* hres;             // pinned host copies (512: two Arnoldi result slots of 256)
     hipEvent_t arn_ev[2];     // Arnoldi results of iteration j copied to slot j % 2
     int* dstatus;
@@ -140,7 +139,6 @@ struct hbpc_ctx {
     hbpc_stats st;
     int cur_solve;
     int verbose;              // HBPC_VERBOSE=1: Newton progress on stderr
-    long st_reorth;           // Gram-Schmidt second passes taken
     // kernel timing
     int prof;
     std::vector<hipEvent_t> ev;          // pairs (start, stop)
@@ -152,7 +150,7 @@ struct hbpc_ctx {
 };
 
 enum { KC_TRACE = 0, KC_R1, KC_R2, KC_RES, KC_JVP, KC_KCOL, KC_PCPRE, KC_BJAPPLY, KC_BJINV, KC_MDOT, KC_GEMV,
-       KC_VEC, KC_GSDOT, KC_GSUPD, KC_LIN, KC_FEAT, KC_GEMM, KC_MLPV, KC_GS2, KC_COUNT };
+       KC_VEC, KC_GSDOT, KC_GSUPD, KC_LIN, KC_FEAT, KC_GEMM, KC_MLPV, KC_COUNT };
 
 // helpers implemented in ops.cpp
 int op_launch(hbpc_ctx* c, const LaunchReq& r, int f32);
