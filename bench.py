@@ -152,7 +152,7 @@ def run_form(wl, form, steps, warmup, theta=None):
 SINGLE_KERNEL_CLASSES = ("bj_apply", "bj_invert", "jvp", "pcpre", "kcol", "trace", "res", "r1", "r2", "gs_update")
 
 
-def roofline_of(prof):
+def roofline_of(prof, workload):
     """Dominant kernel (largest total time among the classes that are one
     kernel each); HBM-bound kernels against 8 TB/s, the BJ_ext inversion
     (dense FP64 arithmetic) against the FP64 vector peak."""
@@ -166,8 +166,30 @@ def roofline_of(prof):
                 "avg_launch_ms": per_launch_ms, "launches": k["launches"]}
     ach = k["bytes"] / k["launches"] / (per_launch_ms * 1e-3) / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": k["bytes"] / k["launches"],
-            "avg_launch_ms": per_launch_ms, "launches": k["launches"]}
+            "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(name, workload),
+            "bytes_per_launch": k["bytes"] / k["launches"], "avg_launch_ms": per_launch_ms,
+            "launches": k["launches"]}
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a reference copy), or None when
+    there is none for this workload or the kernel's source changed since."""
+    import glob
+    import hashlib
+    import re
+    for path in glob.glob(os.path.join(ROOT, "profiles", "%s_*_traffic.md" % kernel)):
+        m = re.search(r"<!-- traffic (\{.*\}) -->", open(path).read())
+        if not m:
+            continue
+        rec = json.loads(m.group(1))
+        if rec.get("kernel") != kernel or rec.get("workload") != workload:
+            continue
+        src = os.path.join(ROOT, rec["source"])
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["sha256"]:
+            return None
+        return float(rec["bytes_per_launch"])
+    return None
 
 
 def cpu_baseline(seconds_hint=30.0):
@@ -261,7 +283,7 @@ def main():
                       "newton_its": r["newton_its"], "gmres_its": r["gmres_its"], "pc_fallbacks": r["pc_fallbacks"],
                       "n_solves": r["n_solves"], "finite": r["finite"]}
                   for f, r in res.items()},
-        "roofline": roofline_of(h["kernels"]),
+        "roofline": roofline_of(h["kernels"], a.workload),
         "kernels": {f: {k: {"launches": v["launches"], "total_ms": round(v["total_ms"], 3),
                             "GBps": (v["bytes"] / (v["total_ms"] * 1e-3) / 1e9) if v["total_ms"] > 0 else None}
                         for k, v in r["kernels"].items()} for f, r in res.items()},
