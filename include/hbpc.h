@@ -113,8 +113,8 @@ typedef struct {
     int mlp_precision;    /* HBPC_MLP_BF16 | HBPC_MLP_FP32: network arithmetic of HBPC_PC_LEARNED */
     double pc_fallback;   /* HBPC_PC_LEARNED: if a restart cycle of FGMRES ends with
                              ||r|| > pc_fallback ||r at the cycle's start||, or the network output
-                             is not finite, BJ_ext takes over for the rest of the stage solve
-                             (default 0.5; <= 0 never falls back) */
+                             is not finite, the cycle's correction is dropped and BJ_ext takes over
+                             for the rest of the stage solve (default 0.5; <= 0 never falls back) */
     void* stream;         /* hipStream_t; NULL = the null stream */
 } hbpc_params;
 

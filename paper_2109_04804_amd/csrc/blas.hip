@@ -10,7 +10,7 @@
 
 constexpr int BLAS_THREADS = 256;
 constexpr int MDOT_CHUNK = 16;
-constexpr int MDOT2_CHUNK = 8;
+constexpr int MDOT2_CHUNK = 16;
 
 template <typename T> __device__ __forceinline__ double block_sum(double v, double* sh) {
     // wave64 shuffle tree, then LDS across the 4 waves

@@ -827,7 +827,9 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
         if (total >= maxit) {
             set_err(c, HBPC_ERR_GMRES, "GMRES did not reach eps_G within " + std::to_string(maxit) + " iterations");
         }
-        // learned preconditioner: BJ_ext takes over after a poor first cycle or a non-finite output
+        // learned preconditioner: BJ_ext takes over after a poor cycle or a non-finite output; the
+        // cycle's correction is dropped and BJ_ext starts from the right-hand side (keeping it
+        // left residuals on which BJ_ext needed more iterations than on the original one)
         if (learned && c->prm.pc_fallback > 0 &&
             (bad_pc || std::fabs(g[k]) > c->prm.pc_fallback * beta_cycle)) {
             c->lpc_active = 0;
@@ -836,6 +838,10 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
                 std::fprintf(stderr, "[hbpc] learned preconditioner -> BJ_ext (%s, cycle %d reduced |r| by %.3e)\n",
                              bad_pc ? "non-finite" : "slow", cycle, std::fabs(g[k]) / beta_cycle);
             pc_build(c, c->X, a1dt, bc, f32);
+            hipchk(c, hipMemsetAsync(dX, 0, n2 * 8, c->stream), "memset");
+            hipchk(c, blas_axpby(1.0, rhs, 0, 0.0, Vj(0), f32, n2, c->stream), "copy");
+            ++cycle;
+            continue;
         }
         ++cycle;
         // restart: r = rhs - J dX, computed in precision f32 in V_0
