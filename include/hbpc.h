@@ -307,6 +307,11 @@ typedef struct {
     double flops;
 } hbpc_kernel_prof;
 int hbpc_profile_enable(hbpc_ctx* ctx, int enable);
+/* Record only the launches of the named class (NULL: all classes again), to
+ * time one kernel without the cost of events around every other launch.
+ * Reset to all classes by hbpc_profile_enable.  HBPC_ERR_ARG for an unknown
+ * name. */
+int hbpc_profile_only(hbpc_ctx* ctx, const char* name);
 /* Copy up to max classes (those with launches) into out; reset != 0 clears
  * the counters.  Synchronises the stream.  Returns the number of classes
  * written, or a negative error code. */

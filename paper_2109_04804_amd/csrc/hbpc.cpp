@@ -107,8 +107,9 @@ static const char* KC_NAMES[KC_COUNT] = {"trace",    "r1",        "r2",   "res",
                                          "bj_apply", "bj_invert", "mdot", "gemv", "vec", "gs_dot", "gs_update",
                                          "lin",      "mlp_feat",  "mlp_gemm", "mlp_vec"};
 
-static long prof_begin(hbpc_ctx* c) {
-    if (!c->prof) return -1;
+// record a launch of class cls (all classes, or only c->prof_only when that is >= 0)
+static long prof_begin(hbpc_ctx* c, int cls) {
+    if (!c->prof || (c->prof_only >= 0 && cls != c->prof_only)) return -1;
     size_t i = c->ev_used;
     if (c->ev.size() < 2 * (i + 1)) {
         hipEvent_t a, b;
@@ -171,7 +172,7 @@ int op_launch(hbpc_ctx* c, const LaunchReq& r, int f32) {
     case OPK_PCPRE: cls = KC_PCPRE; bytes = 5 * n * esz; break;
     case OPK_LINLOC: cls = KC_LIN; bytes = 4 * n * esz; break;
     }
-    long pi = prof_begin(c);
+    long pi = prof_begin(c, cls);
     hipError_t e = c->launch(c->geom, r, f32);
     prof_end(c, pi, cls, bytes);
     if (e != hipSuccess) set_err(c, HBPC_ERR_HIP, std::string("operator kernel launch: ") + hipGetErrorString(e));
@@ -320,7 +321,7 @@ static void pc_build(hbpc_ctx* c, const double* w, double a1dt, double bc, int f
             r.e_end = (int)ee;
             op_launch(c, r, 0);
         }
-        long pi = prof_begin(c);
+        long pi = prof_begin(c, KC_BJINV);
         hipchk(c, bj_invert(c->KT, (char*)c->Sinv + eb * c->NE * c->NE * esz, f32, c->NE, (int)(ee - eb), a1dt, bc,
                             c->dstatus, c->stream),
                "bj_invert");
@@ -350,7 +351,7 @@ static void pc_apply(hbpc_ctx* c, const void* w, const void* trw, const void* X,
     r.c0 = c->pc_a1dt;
     r.c1 = c->pc_bc;
     op_launch(c, r, f32);
-    long pi = prof_begin(c);
+    long pi = prof_begin(c, KC_BJAPPLY);
     hipchk(c, bj_apply(c->Sinv, c->sinv_f32, kv, kv + c->ndof * esz, Y, (char*)Y + c->ndof * esz, f32, c->NE, c->nE,
                        c->stream),
            "bj_apply");
@@ -399,7 +400,7 @@ static MlpView mlp_view(const hbpc_ctx* c, const float* th) {
 static void mlp_gemm_p(hbpc_ctx* c, const float* A, long long a_r, long long a_c, const float* B, long long b_r,
                        long long b_c, float* C, long long ldc, const float* bias, const float* mask, int mask_mul,
                        int M, int N, int K, int relu, int bf16, int accumulate = 0) {
-    long pi = prof_begin(c);
+    long pi = prof_begin(c, KC_GEMM);
     hipchk(c, mlp_gemm(A, a_r, a_c, B, b_r, b_c, C, ldc, bias, mask, mask ? ldc : 0, mask_mul, M, N, K, relu,
                        accumulate, bf16, c->stream),
            "mlp gemm");
@@ -474,7 +475,7 @@ static void mlp_loss_grad_dev(hbpc_ctx* c, const float* X, const float* T, int r
     // loss
     const long long n = (long long)rows * no;
     const int nblk = (int)std::min<long long>(64, (n + 255) / 256);
-    long pi = prof_begin(c);
+    long pi = prof_begin(c, KC_MLPV);
     hipchk(c, mlp_mse_grad(Y, T, dY, n, (float)(1.0 / (double)n), c->part, nblk, c->stream), "mse");
     hipchk(c, mlp_sum_parts(c->part, nblk, sse, c->stream), "mse");
     prof_end(c, pi, KC_MLPV, 12.0 * n);
@@ -502,7 +503,7 @@ static void mlp_loss_grad_dev(hbpc_ctx* c, const float* X, const float* T, int r
 
 static void mlp_adam_dev(hbpc_ctx* c, const float* grad, double lr, double b1, double b2, double eps) {
     c->adam_t++;
-    long pi = prof_begin(c);
+    long pi = prof_begin(c, KC_MLPV);
     hipchk(c, mlp_adam(c->theta, grad, c->adam_m, c->adam_v, (long long)c->mlp_np, (float)lr, (float)b1, (float)b2,
                        (float)eps, c->adam_t, c->stream),
            "adam");
@@ -524,7 +525,7 @@ static void lpc_buffers(hbpc_ctx* c) {
 // part: 1 residual tiles (+scale, targets), 2 state tiles and coefficients, 3 both
 static void features_p(hbpc_ctx* c, const void* rt, const void* w, const void* dw, int f32, const int* elems,
                        int count, double a1dt, double bc, float* X, float* T, float* scale, int part) {
-    long pi = prof_begin(c);
+    long pi = prof_begin(c, KC_FEAT);
     // the step coefficients enter as logarithms: O(1) values that tell the stage solves apart
     const float la = (float)std::log(std::max(a1dt, 1e-300)), lb = (float)std::log(std::max(bc, 1e-300));
     hipchk(c, mlp_features(rt, w, dw, f32, elems, count, c->D, c->geom.nel, c->NE, la, lb, X, T, scale, part,
@@ -561,7 +562,7 @@ static void lpc_apply(hbpc_ctx* c, const void* w, const void* trw, const void* X
     op_lin_local(c, w, trw, vs, vw, -c->pc_bc, rt, f32);   // rt = vw - bcoef K vs
     features_p(c, rt, w, nullptr, f32, nullptr, c->nE, c->pc_a1dt, c->pc_bc, c->ap_X, nullptr, c->ap_s, 1);
     mlp_residual_path(c, c->ap_X, c->nE, c->ap_G1, c->ap_G2, c->ap_H1, c->ap_H2, c->ap_Y, bf16);
-    long pi = prof_begin(c);
+    long pi = prof_begin(c, KC_MLPV);
     hipchk(c, mlp_rescale(c->ap_Y, c->ap_s, yw, f32, (long long)n, c->NE, c->stream), "mlp rescale");
     prof_end(c, pi, KC_MLPV, (double)n * (4.0 + esz) + 4.0 * c->nE);
     op_lin_local(c, w, trw, yw, vs, 1.0, ys, f32);          // ys = vs + K yw
@@ -763,15 +764,15 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
             double* hn = c->dres + 128;      // ||u - V h||^2
             double* h = c->dres + 132;       // two-pass coefficients
             const double vb = (double)n2 * esz;
-            long pi = prof_begin(c);
+            long pi = prof_begin(c, KC_GSDOT);
             hipchk(c, blas_gs_gram(V, n2, j + 1, u, Vj(j), n2, f32, c->part, h1, h1 + (j + 1), c->dgram, m + 1, h,
                                    c->stream),
                    "gs dot");
             prof_end(c, pi, KC_GSDOT, (j + 3) * vb);
-            pi = prof_begin(c);
+            pi = prof_begin(c, KC_GSUPD);
             hipchk(c, blas_gemv_sub_norm(V, n2, j + 1, h, u, n2, f32, c->part, hn, c->stream), "gs update");
             prof_end(c, pi, KC_GSUPD, (j + 3) * vb);
-            pi = prof_begin(c);
+            pi = prof_begin(c, KC_VEC);
             hipchk(c, blas_scale_inv_norm(u, n2, f32, hn, c->stream), "scale");
             prof_end(c, pi, KC_VEC, 2 * vb);
             hipchk(c, hipMemcpyAsync(c->hres + 256 * (j & 1), c->dres, 196 * sizeof(double), hipMemcpyDeviceToHost,
@@ -1000,6 +1001,7 @@ static void ctx_free(hbpc_ctx* c) {
 static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, const hbpc_params* prm) {
     const char* vb = std::getenv("HBPC_VERBOSE");
     c->verbose = vb && vb[0] && vb[0] != '0';
+    c->prof_only = -1;
     c->mesh = *mesh;
     c->prm = *prm;
     c->N = N;
@@ -1574,7 +1576,23 @@ int hbpc_step(hbpc_ctx* c, double* w_inout, double dt, hbpc_stats* stats) {
 int hbpc_profile_enable(hbpc_ctx* c, int enable) {
     if (!c) return HBPC_ERR_ARG;
     c->prof = enable ? 1 : 0;
+    c->prof_only = -1;
     return HBPC_OK;
+}
+
+int hbpc_profile_only(hbpc_ctx* c, const char* name) {
+    if (!c) return HBPC_ERR_ARG;
+    if (!name) {
+        c->prof_only = -1;
+        return HBPC_OK;
+    }
+    for (int i = 0; i < KC_COUNT; ++i)
+        if (std::strcmp(name, KC_NAMES[i]) == 0) {
+            c->prof_only = i;
+            return HBPC_OK;
+        }
+    c->err = std::string("unknown kernel class ") + name;
+    return HBPC_ERR_ARG;
 }
 
 int hbpc_profile_read(hbpc_ctx* c, hbpc_kernel_prof* out, int max, int reset) {

@@ -141,6 +141,7 @@ struct hbpc_ctx {
     int verbose;              // HBPC_VERBOSE=1: Newton progress on stderr
     // kernel timing
     int prof;
+    int prof_only;            // >= 0: record only this kernel class
     std::vector<hipEvent_t> ev;          // pairs (start, stop)
     std::vector<int> ev_class;
     std::vector<double> ev_bytes, ev_flops;

@@ -111,6 +111,7 @@ SIGNATURES = {
     "hbpc_train_mlp": (_I, [_P, _P, _P, ctypes.c_size_t, ctypes.POINTER(HbpcTrainCfg),
                             ctypes.POINTER(HbpcTrainLog)]),
     "hbpc_profile_enable": (_I, [_P, _I]),
+    "hbpc_profile_only": (_I, [_P, ctypes.c_char_p]),
     "hbpc_profile_read": (_I, [_P, ctypes.POINTER(HbpcKernelProf), _I, _I]),
     "hbpc_strerror": (ctypes.c_char_p, [_I]),
     "hbpc_last_error": (ctypes.c_char_p, [_P]),
@@ -293,6 +294,10 @@ class Context:
 
     def profile_enable(self, on=True):
         self._check(self.lib.hbpc_profile_enable(self.h, 1 if on else 0))
+
+    def profile_only(self, name):
+        """Record only launches of kernel class `name` (None: all)."""
+        self._check(self.lib.hbpc_profile_only(self.h, None if name is None else name.encode()))
 
     def profile_read(self, reset=True):
         """Per kernel class: launches, total ms, algorithmic bytes and flops."""
