@@ -183,3 +183,29 @@ def test_learned_pc_requires_parameters():
     with pytest.raises(HbpcError) as ei:
         ctx.step(dev(state(dg)), 0.1)
     assert ei.value.code == -1
+
+
+def test_mlp_init_is_seeded_and_bounded():
+    """hbpc_mlp_init: same seed, same parameters; weights within +-sqrt(g / fan_in)
+    (g = 6 on the state path, 3 on the residual path) and spread over that range;
+    zero biases."""
+    ctx = make_ctx()
+    n_in, H, n_out, n_p = ctx.mlp_shape()
+    a = torch.zeros(n_p, dtype=torch.float32, device="cuda")
+    b = torch.zeros_like(a)
+    ctx.mlp_init(11)
+    ctx.mlp_get_params(a)
+    ctx.mlp_init(11)
+    ctx.mlp_get_params(b)
+    assert torch.equal(a, b)
+    ctx.mlp_init(12)
+    ctx.mlp_get_params(b)
+    assert not torch.equal(a, b)
+    parts = mlp.unpack(host(a), n_in, H, n_out)
+    for name, p, shape in zip(mlp.NAMES, parts, mlp.shapes(n_in, H, n_out)):
+        if len(shape) == 1:
+            assert np.all(p == 0.0), name
+            continue
+        lim = np.sqrt((6.0 if name in ("W1w", "W2w") else 3.0) / shape[0])
+        assert np.abs(p).max() <= lim * (1 + 1e-6), name
+        assert np.abs(p).max() > 0.99 * lim and abs(p.mean()) < 0.05 * lim, name

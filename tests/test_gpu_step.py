@@ -126,3 +126,38 @@ def test_failures_leave_state_unchanged():
     ctx = ctx_for(case)
     assert _err(lambda: ctx.step(wb, 0.2)) == -4
     assert np.array_equal(np.isnan(host(wb)), np.isnan(bad.ravel()))
+
+
+def test_euler_vortex_step_fd_jvp():
+    """The same vortex step with the finite-difference JVP of Eq. MatrixFree_nonlinear
+    (FP64): same Newton root as the oracle (eps_N 1e-12, eps_G 1e-5)."""
+    case = dict(CASES["euler2_n3_lobatto"])
+    case.update(nelem=[4, 4], nodes="gauss")
+    dg = oracle_for(case)
+    X = dg.node_coords()
+    w0 = inputs.isentropic_vortex(X[0], X[1], 4.6, 5.3, 3.0)
+    ctx = ctx_for(case, q=6, kmax=2, newton_rtol=1e-12, gmres_rtol=1e-5, precision="fp64", jvp_mode="fd")
+    wg = dev(w0)
+    stats = ctx.step(wg, 0.1)
+    print(stats, flush=True)
+    ref = dg_hbpc_step(dg, w0, 0.1, 6, 2, StageSolver(dg, newton_rtol=1e-12, gmres_rtol=1e-5))
+    assert rel(host(wg), ref) < 1e-10
+
+
+def test_profile_classes():
+    """Kernel timing: all classes, then one class only."""
+    case = dict(CASES["euler2_n3_lobatto"])
+    dg = oracle_for(case)
+    ctx = ctx_for(case, q=6, kmax=1, precision="mixed")
+    wg = dev(state(dg))
+    ctx.profile_enable(True)
+    ctx.step(wg, 0.05)
+    allp = ctx.profile_read(reset=True)
+    assert {"jvp", "bj_apply", "gs_dot", "gs_update"} <= set(allp)
+    ctx.profile_only("bj_apply")
+    ctx.step(wg, 0.05)
+    one = ctx.profile_read(reset=True)
+    assert set(one) == {"bj_apply"} and one["bj_apply"]["launches"] > 0
+    from paper_2109_04804_amd.hbpc import HbpcError
+    with pytest.raises(HbpcError):
+        ctx.profile_only("no_such_kernel")
