@@ -53,12 +53,13 @@ template <typename T, int VEC> __device__ __forceinline__ void vstore(T* p, cons
     }
 }
 
-// part[blockIdx.x * ldp + j] = sum_{i in block} V_j[i] * w[i], j < kc (<= MDOT_CHUNK); VEC values per
+// part[(c0 + j) * gridDim.x + blockIdx.x] = sum_{i in block} V_j[i] * w[i], j < kc (<= MDOT_CHUNK)
+// (block partials column by column, so that the reduction reads them contiguously); VEC values per
 // load (n and ld multiples of VEC)
 template <typename T, int VEC>
 __global__ void __launch_bounds__(BLAS_THREADS) mdot_kernel(const T* __restrict__ V, size_t ld, int kc,
                                                             const T* __restrict__ w, size_t n,
-                                                            double* __restrict__ part, int ldp) {
+                                                            double* __restrict__ part, int c0) {
     __shared__ double shw[BLAS_THREADS / 64][MDOT_CHUNK];
     double acc[MDOT_CHUNK];
 #pragma unroll
@@ -92,17 +93,17 @@ __global__ void __launch_bounds__(BLAS_THREADS) mdot_kernel(const T* __restrict_
     if (threadIdx.x < kc) {
         double r = 0.0;
         for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += shw[i][threadIdx.x];
-        part[(size_t)blockIdx.x * ldp + threadIdx.x] = r;
+        part[(size_t)(c0 + threadIdx.x) * gridDim.x + blockIdx.x] = r;
     }
 }
 
-// part[b * ldp + j] = sum_{i in block b} V_j[i] w1[i] and part[b * ldp + kc2 + j] = ... V_j[i] w2[i]
-// for j < kc (<= MDOT2_CHUNK): the projections of a new vector and the Gram column of the newest
-// basis vector in one pass over V
+// column c0 + j of the block partials (layout as for mdot_kernel): sum V_j[i] w1[i]; column
+// off2 + c0 + j: sum V_j[i] w2[i], for j < kc (<= MDOT2_CHUNK): the projections of a new vector and
+// the Gram column of the newest basis vector in one pass over V
 template <typename T, int VEC>
 __global__ void __launch_bounds__(BLAS_THREADS) mdot2_kernel(const T* __restrict__ V, size_t ld, int kc,
                                                              const T* __restrict__ w1, const T* __restrict__ w2,
-                                                             size_t n, double* __restrict__ part, int ldp,
+                                                             size_t n, double* __restrict__ part, int c0,
                                                              int off2) {
     __shared__ double shw[BLAS_THREADS / 64][2 * MDOT2_CHUNK];
     double a1[MDOT2_CHUNK], a2[MDOT2_CHUNK];
@@ -148,8 +149,8 @@ __global__ void __launch_bounds__(BLAS_THREADS) mdot2_kernel(const T* __restrict
         const int j = threadIdx.x < kc ? threadIdx.x : threadIdx.x - kc + MDOT2_CHUNK;
         double r = 0.0;
         for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += shw[i][j];
-        const int col = threadIdx.x < kc ? threadIdx.x : off2 + threadIdx.x - kc;
-        part[(size_t)blockIdx.x * ldp + col] = r;
+        const int col = c0 + (threadIdx.x < kc ? threadIdx.x : off2 + threadIdx.x - kc);
+        part[(size_t)col * gridDim.x + blockIdx.x] = r;
     }
 }
 
@@ -172,13 +173,13 @@ __global__ void __launch_bounds__(64) gram_coef_kernel(double* __restrict__ G, i
     }
 }
 
-// out[j] = scale * sum_b part[b * ldp + j]; one block per j
-__global__ void __launch_bounds__(BLAS_THREADS) reduce_parts_kernel(const double* __restrict__ part, int nb, int ldp,
+// out[j] = scale * sum_b part[j * nb + b]; one block per j
+__global__ void __launch_bounds__(BLAS_THREADS) reduce_parts_kernel(const double* __restrict__ part, int nb,
                                                                     double* __restrict__ out, double scale) {
     __shared__ double sh[BLAS_THREADS / 64];
     const int j = blockIdx.x;
     double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(size_t)b * ldp + j];
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(size_t)j * nb + b];
     s = block_sum<double>(s, sh);
     if (threadIdx.x == 0) out[j] = scale * s;
 }
@@ -296,12 +297,15 @@ __global__ void __launch_bounds__(BLAS_THREADS) scale_inv_norm_kernel(T* __restr
 }
 
 // ------------------------------------------------------------------ launchers
-static int blas_grid(size_t n) {
+static int blas_grid(size_t n, size_t cap = 2048) {
     size_t g = (n + BLAS_THREADS - 1) / BLAS_THREADS;
-    if (g > 2048) g = 2048;
+    if (g > cap) g = cap;
     if (g < 1) g = 1;
     return (int)g;
 }
+
+// multi-dot kernels carry many accumulators: fewer, longer-running blocks (4 per CU)
+constexpr size_t MDOT_GRID = 1024;
 
 int blas_mdot_grid(size_t n) { return blas_grid(n); }
 
@@ -316,23 +320,23 @@ static int vec_of(size_t n, size_t ld, int f32, const void* a, const void* b) {
 hipError_t blas_mdot(const void* V, size_t ld, int k, const void* w, size_t n, int f32, double* part, double* h,
                      hipStream_t st) {
     const int vec = vec_of(n, ld, f32, V, w);
-    int g = blas_grid(n / vec);
+    int g = blas_grid(n / vec, MDOT_GRID);
     for (int j0 = 0; j0 < k; j0 += MDOT_CHUNK) {
         int kc = k - j0 < MDOT_CHUNK ? k - j0 : MDOT_CHUNK;
         if (f32 && vec == 4)
             hipLaunchKernelGGL((mdot_kernel<float, 4>), dim3(g), dim3(BLAS_THREADS), 0, st,
-                               (const float*)V + j0 * ld, ld, kc, (const float*)w, n, part + j0, k);
+                               (const float*)V + j0 * ld, ld, kc, (const float*)w, n, part, j0);
         else if (f32)
             hipLaunchKernelGGL((mdot_kernel<float, 1>), dim3(g), dim3(BLAS_THREADS), 0, st,
-                               (const float*)V + j0 * ld, ld, kc, (const float*)w, n, part + j0, k);
+                               (const float*)V + j0 * ld, ld, kc, (const float*)w, n, part, j0);
         else if (vec == 2)
             hipLaunchKernelGGL((mdot_kernel<double, 2>), dim3(g), dim3(BLAS_THREADS), 0, st,
-                               (const double*)V + j0 * ld, ld, kc, (const double*)w, n, part + j0, k);
+                               (const double*)V + j0 * ld, ld, kc, (const double*)w, n, part, j0);
         else
             hipLaunchKernelGGL((mdot_kernel<double, 1>), dim3(g), dim3(BLAS_THREADS), 0, st,
-                               (const double*)V + j0 * ld, ld, kc, (const double*)w, n, part + j0, k);
+                               (const double*)V + j0 * ld, ld, kc, (const double*)w, n, part, j0);
     }
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(k), dim3(BLAS_THREADS), 0, st, part, g, k, h, 1.0);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(k), dim3(BLAS_THREADS), 0, st, part, g, h, 1.0);
     return hipGetLastError();
 }
 
@@ -354,7 +358,7 @@ hipError_t blas_gemv_sub_norm(const void* V, size_t ld, int k, const double* h, 
     else
         hipLaunchKernelGGL((gemv_sub_norm_kernel<double, 1>), dim3(g), dim3(BLAS_THREADS), 0, st, (const double*)V,
                            ld, k, h, (double*)u, n, part);
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(BLAS_THREADS), 0, st, part, g, 1, nrm2, 1.0);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(BLAS_THREADS), 0, st, part, g, nrm2, 1.0);
     return hipGetLastError();
 }
 
@@ -373,28 +377,28 @@ hipError_t blas_gs_gram(const void* V, size_t ld, int k, const void* w1, const v
                         double* part, double* h1, double* g, double* G, int ldg, double* h, hipStream_t st) {
     if (k > 64 || k > ldg || g != h1 + k) return hipErrorInvalidValue;
     const int vec = (vec_of(n, ld, f32, V, w1) == vec_of(n, ld, f32, V, w2)) ? vec_of(n, ld, f32, V, w1) : 1;
-    int gr = blas_grid(n / vec);
+    int gr = blas_grid(n / vec, MDOT_GRID);
     for (int j0 = 0; j0 < k; j0 += MDOT2_CHUNK) {
         int kc = k - j0 < MDOT2_CHUNK ? k - j0 : MDOT2_CHUNK;
         if (f32 && vec == 4)
             hipLaunchKernelGGL((mdot2_kernel<float, 4>), dim3(gr), dim3(BLAS_THREADS), 0, st,
-                               (const float*)V + j0 * ld, ld, kc, (const float*)w1, (const float*)w2, n, part + j0,
-                               2 * k, k);
+                               (const float*)V + j0 * ld, ld, kc, (const float*)w1, (const float*)w2, n, part, j0,
+                               k);
         else if (f32)
             hipLaunchKernelGGL((mdot2_kernel<float, 1>), dim3(gr), dim3(BLAS_THREADS), 0, st,
-                               (const float*)V + j0 * ld, ld, kc, (const float*)w1, (const float*)w2, n, part + j0,
-                               2 * k, k);
+                               (const float*)V + j0 * ld, ld, kc, (const float*)w1, (const float*)w2, n, part, j0,
+                               k);
         else if (vec == 2)
             hipLaunchKernelGGL((mdot2_kernel<double, 2>), dim3(gr), dim3(BLAS_THREADS), 0, st,
                                (const double*)V + j0 * ld, ld, kc, (const double*)w1, (const double*)w2, n,
-                               part + j0, 2 * k, k);
+                               part, j0, k);
         else
             hipLaunchKernelGGL((mdot2_kernel<double, 1>), dim3(gr), dim3(BLAS_THREADS), 0, st,
                                (const double*)V + j0 * ld, ld, kc, (const double*)w1, (const double*)w2, n,
-                               part + j0, 2 * k, k);
+                               part, j0, k);
     }
     // h1 = part columns 0..k-1, g = columns k..2k-1 (h1 and g adjacent: g = h1 + k)
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(2 * k), dim3(BLAS_THREADS), 0, st, part, gr, 2 * k, h1, 1.0);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(2 * k), dim3(BLAS_THREADS), 0, st, part, gr, h1, 1.0);
     hipLaunchKernelGGL(gram_coef_kernel, dim3(1), dim3(64), 0, st, G, ldg, k - 1, h1, g, h);
     return hipGetLastError();
 }

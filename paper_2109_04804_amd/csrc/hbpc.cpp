@@ -1133,9 +1133,10 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
     c->mgrad = dalloc<float>(c, c->mlp_np);
     c->lpc_snap = -1;
     c->kv = dalloc<double>(c, 3 * n);
-    // K build in chunks of <= 256 MB of FP64 blocks
+    // K build in chunks of <= 4 GiB of FP64 blocks (the whole 128^2 N=5 mesh in one launch, so the
+    // inversion kernel runs tens of workgroup rounds instead of three with a 16 % tail)
     size_t per = (size_t)c->NE * c->NE * 8;
-    c->kt_chunk = std::max<size_t>(1, std::min<size_t>(c->nE, (size_t)(256u << 20) / per));
+    c->kt_chunk = std::max<size_t>(1, std::min<size_t>(c->nE, ((size_t)4 << 30) / per));
     c->part = dalloc<double>(c, (size_t)blas_mdot_grid(c->n2) * 130 + 64);
     c->dres = dalloc<double>(c, 256);
     c->dgram = dalloc<double>(c, (size_t)(c->m_alloc + 1) * (c->m_alloc + 1));

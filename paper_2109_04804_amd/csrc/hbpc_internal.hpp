@@ -110,7 +110,7 @@ struct hbpc_ctx {
     double* KT;               // chunk_e x NE x NE (column-major blocks)
     void* Sinv;               // nE x NE x NE
     int sinv_f32;
-    size_t kt_chunk;          // elements per K build chunk
+    size_t kt_chunk;          // elements per K build chunk (<= 4 GiB of FP64 blocks)
     double pc_a1dt, pc_bc;
     int pc_valid;
     // reductions
