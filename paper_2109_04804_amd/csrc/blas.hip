@@ -27,6 +27,21 @@ template <typename T> __device__ __forceinline__ double block_sum(double v, doub
     return r;
 }
 
+// Grid-wide "last block" hand-over: every block publishes its result, then takes a ticket; the
+// block with the last ticket sees every published result (device-scope fences around the ticket)
+// and finishes the reduction, then rewinds the counter for the next launch.
+__device__ __forceinline__ bool last_block(unsigned* counter) {
+    __shared__ bool last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last;
+}
+
 // VEC consecutive values of type T as one 16-byte (or scalar) load/store
 template <typename T, int VEC> struct Vec { T v[VEC]; };
 template <typename T, int VEC> __device__ __forceinline__ Vec<T, VEC> vload(const T* p) {
@@ -154,23 +169,34 @@ __global__ void __launch_bounds__(BLAS_THREADS) mdot2_kernel(const T* __restrict
     }
 }
 
-// Gram-Schmidt coefficients of the second pass from the Gram matrix: with G = V^T V (columns
-// 0..j, column j = g just computed, stored symmetric, leading dimension ldg) and h1 = V^T u,
-// the second classical pass V^T (u - V h1) = h1 - G h1, so the two passes together subtract
-// V h with h = 2 h1 - G h1.  One block.
-__global__ void __launch_bounds__(64) gram_coef_kernel(double* __restrict__ G, int ldg, int j,
-                                                       const double* __restrict__ h1, const double* __restrict__ g,
-                                                       double* __restrict__ h) {
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-        G[(size_t)i * ldg + j] = g[i];
-        G[(size_t)j * ldg + i] = g[i];
+// out[j] = sum_b part[j * nb + b] for the 2k columns j = blockIdx.x (out = h1 | g); then the last
+// block forms the Gram-Schmidt coefficients of both passes: with G = V^T V (column k-1 = g, stored
+// symmetric, leading dimension ldg) and h1 = V^T u, the second classical pass V^T (u - V h1) =
+// h1 - G h1, so the two passes together subtract V h with h = 2 h1 - G h1.
+__global__ void __launch_bounds__(BLAS_THREADS) reduce_gram_kernel(const double* part, int nb, double* out, int k,
+                                                                   double* G, int ldg, double* h,
+                                                                   unsigned* counter) {
+    __shared__ double sh[BLAS_THREADS / 64];
+    const int j = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(size_t)j * nb + b];
+    s = block_sum<double>(s, sh);
+    if (threadIdx.x == 0) out[j] = s;
+    if (!last_block(counter)) return;
+    const double* h1 = out;
+    const double* g = out + k;
+    const int jj = k - 1;
+    for (int i = threadIdx.x; i <= jj; i += blockDim.x) {
+        G[(size_t)i * ldg + jj] = g[i];
+        G[(size_t)jj * ldg + i] = g[i];
     }
     __syncthreads();
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-        double s = 0.0;
-        for (int l = 0; l <= j; ++l) s += G[(size_t)i * ldg + l] * h1[l];
-        h[i] = 2.0 * h1[i] - s;
+    for (int i = threadIdx.x; i <= jj; i += blockDim.x) {
+        double t = 0.0;
+        for (int l = 0; l <= jj; ++l) t += G[(size_t)i * ldg + l] * h1[l];
+        h[i] = 2.0 * h1[i] - t;
     }
+    if (threadIdx.x == 0) *counter = 0u;
 }
 
 // out[j] = scale * sum_b part[j * nb + b]; one block per j
@@ -250,7 +276,8 @@ __global__ void __launch_bounds__(BLAS_THREADS) nonfinite_kernel(const T* __rest
 
 // ------------------------------------------------------------------ Gram-Schmidt passes
 // w[i] -= sum_j h[j] V_j[i] and a per-block partial of ||w||^2 (part[blockIdx.x]); VEC values per
-// load (n and ld multiples of VEC)
+// load (n and ld multiples of VEC).  (A last-block final sum here costs more than a second launch:
+// the device-scope release of each block writes back the freshly updated w from L2.)
 template <typename T, int VEC>
 __global__ void __launch_bounds__(BLAS_THREADS) gemv_sub_norm_kernel(const T* __restrict__ V, size_t ld, int k,
                                                                      const double* __restrict__ h,
@@ -372,9 +399,11 @@ hipError_t blas_scale_inv_norm(void* u, size_t n, int f32, const double* nrm2, h
 }
 
 // h1[i] = V_i . w1 and g[i] = V_i . w2 for i < k, then the combined two-pass coefficients
-// h = 2 h1 - G h1 with G's column k-1 set from g (G: device, ldg x ldg).  part: grid * 2k doubles.
+// h = 2 h1 - G h1 with G's column k-1 set from g (G: device, ldg x ldg).  part: grid * 2k doubles;
+// counter: a device word that is 0 between launches.
 hipError_t blas_gs_gram(const void* V, size_t ld, int k, const void* w1, const void* w2, size_t n, int f32,
-                        double* part, double* h1, double* g, double* G, int ldg, double* h, hipStream_t st) {
+                        double* part, double* h1, double* g, double* G, int ldg, double* h, unsigned* counter,
+                        hipStream_t st) {
     if (k > 64 || k > ldg || g != h1 + k) return hipErrorInvalidValue;
     const int vec = (vec_of(n, ld, f32, V, w1) == vec_of(n, ld, f32, V, w2)) ? vec_of(n, ld, f32, V, w1) : 1;
     int gr = blas_grid(n / vec, MDOT_GRID);
@@ -398,8 +427,8 @@ hipError_t blas_gs_gram(const void* V, size_t ld, int k, const void* w1, const v
                                part, j0, k);
     }
     // h1 = part columns 0..k-1, g = columns k..2k-1 (h1 and g adjacent: g = h1 + k)
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(2 * k), dim3(BLAS_THREADS), 0, st, part, gr, h1, 1.0);
-    hipLaunchKernelGGL(gram_coef_kernel, dim3(1), dim3(64), 0, st, G, ldg, k - 1, h1, g, h);
+    hipLaunchKernelGGL(reduce_gram_kernel, dim3(2 * k), dim3(BLAS_THREADS), 0, st, part, gr, h1, k, G, ldg, h,
+                       counter);
     return hipGetLastError();
 }
 

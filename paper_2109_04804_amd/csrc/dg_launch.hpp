@@ -94,7 +94,8 @@ template <int D, int NP, class EQ, typename T> hipError_t launch_family_np(const
         constexpr int EPB = 256 / NN > 0 ? 256 / NN : 1;
         int grid = (g.nE + EPB - 1) / EPB;
         if (grid == 0) return hipSuccess;
-        hipLaunchKernelGGL((trace_kernel<D, NP, NV, T>), dim3(grid), dim3(EPB * NN), 0, r.stream,
+        const int nf = r.col > 1 ? r.col : 1;   // consecutive fields (col = their number)
+        hipLaunchKernelGGL((trace_kernel<D, NP, NV, T>), dim3(grid, nf), dim3(EPB * NN), 0, r.stream,
                            (const T*)r.fld[0], (T*)r.out[0], g.nE, basis_ptr<T>(g));
         return hipGetLastError();
     }

@@ -187,7 +187,7 @@ template <int D, int NP, int NV, int NJ, int NC, typename T> constexpr int op_ep
 
 // ----------------------------------------------------------------- trace kernel
 template <int D, int NP, int NV, typename T>
-__global__ void __launch_bounds__(256) trace_kernel(const T* __restrict__ x, T* __restrict__ tr, int nE,
+__global__ void __launch_bounds__(256) trace_kernel(const T* x, T* tr, int nE,
                                                      const T* __restrict__ basis) {
     constexpr int NN = ipow(NP, D), NFP = ipow(NP, D - 1);
     constexpr int EPB = 256 / NN > 0 ? 256 / NN : 1;
@@ -199,6 +199,9 @@ __global__ void __launch_bounds__(256) trace_kernel(const T* __restrict__ x, T* 
     const int e0 = blockIdx.x * EPB;
     const int nloc = min(EPB, nE - e0);
     const size_t base = (size_t)e0 * NV * NN;
+    // field blockIdx.y of consecutive fields (stride: one state vector in, one trace array out)
+    x += (size_t)blockIdx.y * nE * NV * NN;
+    tr += (size_t)blockIdx.y * nE * PER_E;
     if (tid < 2 * NP) s_l[tid / NP][tid % NP] = basis[(tid < NP ? BOff<NP>::LM : BOff<NP>::LP) + tid % NP];
     for (int i = tid; i < nloc * NV * NN; i += NT) s[i] = x[base + i];
     __syncthreads();

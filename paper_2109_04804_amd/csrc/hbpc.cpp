@@ -162,7 +162,7 @@ int op_launch(hbpc_ctx* c, const LaunchReq& r, int f32) {
     int cls = KC_VEC;
     double bytes = 0.0;
     switch (r.op) {
-    case OPK_TRACE: cls = KC_TRACE; bytes = (n + (double)c->tsz) * esz; break;
+    case OPK_TRACE: cls = KC_TRACE; bytes = (n + (double)c->tsz) * esz * (r.col > 1 ? r.col : 1); break;
     case OPK_R1: cls = KC_R1; bytes = 2 * n * esz; break;
     case OPK_R2: cls = KC_R2; bytes = 3 * n * esz; break;
     case OPK_RES: cls = KC_RES; bytes = 5 * n * esz; break;
@@ -179,10 +179,12 @@ int op_launch(hbpc_ctx* c, const LaunchReq& r, int f32) {
     return 0;
 }
 
-static void op_trace(hbpc_ctx* c, const void* x, void* tr, int f32) {
+// traces of nf consecutive fields (x: nf x ndof, tr: nf x tsz)
+static void op_trace(hbpc_ctx* c, const void* x, void* tr, int f32, int nf = 1) {
     LaunchReq r = op_req(c, OPK_TRACE);
     r.fld[0] = x;
     r.out[0] = tr;
+    r.col = nf;
     op_launch(c, r, f32);
 }
 
@@ -254,8 +256,7 @@ static void op_jvp(hbpc_ctx* c, const void* w, const void* s, const void* trw, c
     char* y = (char*)Y;
     void* t1 = f32 ? (void*)c->trd1_32 : (void*)c->trd1;
     void* t2 = f32 ? (void*)c->trd2_32 : (void*)c->trd2;
-    op_trace(c, dx, t1, f32);
-    op_trace(c, dx + c->ndof * esz, t2, f32);
+    op_trace(c, dx, t1, f32, 2);   // t2 = t1 + tsz
     LaunchReq r = op_req(c, hess ? OPK_JVP : OPK_JVP_NOHESS);
     r.fld[0] = w;
     r.fld[1] = s;
@@ -766,7 +767,7 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
             const double vb = (double)n2 * esz;
             long pi = prof_begin(c, KC_GSDOT);
             hipchk(c, blas_gs_gram(V, n2, j + 1, u, Vj(j), n2, f32, c->part, h1, h1 + (j + 1), c->dgram, m + 1, h,
-                                   c->stream),
+                                   c->dcount, c->stream),
                    "gs dot");
             prof_end(c, pi, KC_GSDOT, (j + 3) * vb);
             pi = prof_begin(c, KC_GSUPD);
@@ -980,9 +981,9 @@ static void ctx_free(hbpc_ctx* c) {
         dfree(c->Wn[i]);
         dfree(c->tmp[i]);
     }
-    void* bufs[] = {c->R1all, c->R2all, c->X, c->b, c->G, c->dX, c->rhs, c->trw, c->trs, c->trd1, c->trd2,
-                    c->X32, c->trw32, c->trs32, c->trd1_32, c->trd2_32, c->V, c->Z, c->kv, c->KT, c->Sinv,
-                    c->part, c->dres, c->dgram, c->dstatus, c->basis64, c->basis32, c->theta, c->adam_m, c->adam_v,
+    void* bufs[] = {c->R1all, c->R2all, c->X, c->b, c->G, c->dX, c->rhs, c->trw, c->trs, c->trd1,
+                    c->X32, c->trw32, c->trs32, c->trd1_32, c->V, c->Z, c->kv, c->KT, c->Sinv,
+                    c->part, c->dres, c->dgram, c->dcount, c->dstatus, c->basis64, c->basis32, c->theta, c->adam_m, c->adam_v,
                     c->mgrad, c->ap_X, c->ap_G1, c->ap_G2, c->ap_H1, c->ap_H2, c->ap_Y, c->ap_s, c->tr_buf, c->tr_idx_dev,
                     c->col_elems};
     for (void* p : bufs) dfree(p);
@@ -1102,13 +1103,13 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
     c->rhs = dalloc<double>(c, 2 * n);
     c->trw = dalloc<double>(c, c->tsz);
     c->trs = dalloc<double>(c, c->tsz);
-    c->trd1 = dalloc<double>(c, c->tsz);
-    c->trd2 = dalloc<double>(c, c->tsz);
+    c->trd1 = dalloc<double>(c, 2 * c->tsz);   // trd2 follows trd1 (one trace launch for dX)
+    c->trd2 = c->trd1 + c->tsz;
     c->X32 = dalloc<float>(c, 2 * n);
     c->trw32 = dalloc<float>(c, c->tsz);
     c->trs32 = dalloc<float>(c, c->tsz);
-    c->trd1_32 = dalloc<float>(c, c->tsz);
-    c->trd2_32 = dalloc<float>(c, c->tsz);
+    c->trd1_32 = dalloc<float>(c, 2 * c->tsz);
+    c->trd2_32 = c->trd1_32 + c->tsz;
     if (c->visc)
         for (int j = 0; j < 4; ++j) {
             c->qtr[0][j] = dalloc<double>(c, c->tsz);
@@ -1140,6 +1141,8 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
     c->part = dalloc<double>(c, (size_t)blas_mdot_grid(c->n2) * 130 + 64);
     c->dres = dalloc<double>(c, 256);
     c->dgram = dalloc<double>(c, (size_t)(c->m_alloc + 1) * (c->m_alloc + 1));
+    c->dcount = dalloc<unsigned>(c, 4);
+    hipchk(c, hipMemset(c->dcount, 0, 4 * sizeof(unsigned)), "memset");
     c->dstatus = dalloc<int>(c, 1);
     void* h = nullptr;
     hipchk(c, hipHostMalloc(&h, 512 * sizeof(double)), "hipHostMalloc");

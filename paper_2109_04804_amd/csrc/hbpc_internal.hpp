@@ -24,7 +24,8 @@ hipError_t blas_gemv_sub(const void* V, size_t ld, int k, const double* h, void*
                          hipStream_t st);
 hipError_t blas_scale_inv_norm(void* u, size_t n, int f32, const double* nrm2, hipStream_t st);
 hipError_t blas_gs_gram(const void* V, size_t ld, int k, const void* w1, const void* w2, size_t n, int f32,
-                        double* part, double* h1, double* g, double* G, int ldg, double* h, hipStream_t st);
+                        double* part, double* h1, double* g, double* G, int ldg, double* h, unsigned* counter,
+                        hipStream_t st);
 hipError_t blas_axpby(double a, const void* x, int tx, double b, void* y, int ty, size_t n, hipStream_t st);
 hipError_t blas_lincomb2(double a, const double* x, double b, const double* z, double* y, size_t n, hipStream_t st);
 hipError_t blas_gemv_add(const void* Z, int tz, size_t ld, int k, const double* c, void* y, int ty, size_t n,
@@ -117,6 +118,7 @@ struct hbpc_ctx {
     double* part;             // blas partials
     double* dres;             // device results (256)
     double* dgram;            // Gram matrix V^T V of the current FGMRES cycle, (m+1) x (m+1)
+    unsigned* dcount;         // grid-wide hand-over counters of the fused reductions (0 between launches)
     double* hres;             // pinned host copies (512: two Arnoldi result slots of 256)
     hipEvent_t arn_ev[2];     // Arnoldi results of iteration j copied to slot j % 2
     int* dstatus;
