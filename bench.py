@@ -254,8 +254,9 @@ def main():
                          "for scaling hardware byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(the multi-GPU design is described in DESIGN.md)" % a.gpus, file=sys.stderr)
+        print("bench.py: libhbpc runs on one GPU; --gpus %d is not supported (the path would shard by "
+              "elements with a face-trace halo exchange per operator and one all-reduce per "
+              "Gram-Schmidt pass)" % a.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

@@ -71,7 +71,8 @@ def test_fullsize_residuals_and_jvp(case):
     # (d lambda . dw)(sigma_L - sigma_R) from the side the Rusanov max picks, and
     # where lambda_L = lambda_R to rounding (the nearly uniform far field) that side
     # is decided by rounding noise; a smooth sigma makes the jump, and with it the
-    # ambiguity, vanish (a rough sigma does not: see the design doc)
+    # ambiguity, vanish (a rough sigma does not: at faces where the two Rusanov speeds tie to
+    # rounding, the side the tie rule picks differs between the two implementations)
     xi, _ = ctx.nodes()
     X = inputs.node_coords(case["dim"], case["nelem"], case["length"], [0, 0, 0], xi)
     ph = sum(np.sin(2 * np.pi * X[m] / case["length"][m] + m) for m in range(case["dim"]))

@@ -1,7 +1,7 @@
 """The learned preconditioner inside HBPC steps: step-level parity with the
 oracle (the preconditioner changes the Krylov path, not the Newton root),
 the BJ_ext fallback, and training on pairs collected by hbpc_step with what
-the trained network gains over no preconditioner (BJ_ext as the judge).
+the trained network gains over no preconditioner (BJ_ext as the reference).
 
 Step tolerance as for the mixed path: eps_N = 1e-8, relative L2 <= 1e-8
 against the oracle run at the same eps_N.

@@ -61,11 +61,11 @@ def rel(a, b):
 ALL = ["adv1", "adv2", "adv3", "burgers", "burgers1", "euler2", "euler3"]
 
 
-# ------------------------------------------------------------------ P8
+# ------------------------------------------------------------------
 @pytest.mark.parametrize("kind", ALL)
 @pytest.mark.parametrize("nodes", ["gauss", "lobatto"])
 def test_free_stream(kind, nodes):
-    """P8: a constant state is a steady solution, R1 = 0 (to round-off)."""
+    """a constant state is a steady solution, R1 = 0 (to round-off)."""
     dg = make(kind, n=3, nodes=nodes)
     w = np.zeros((dg.mesh.n_elem, dg.nvar, dg.nnode))
     const = [1.3, 0.4, -0.3, 0.2, 3.0][: dg.nvar] if dg.nvar > 1 else [0.7]
@@ -76,10 +76,10 @@ def test_free_stream(kind, nodes):
     assert np.abs(dg.r1(w)).max() < 1e-12
 
 
-# ------------------------------------------------------------------ P7
+# ------------------------------------------------------------------
 @pytest.mark.parametrize("kind", ALL)
 def test_conservation(kind):
-    """P7: sum_e J sum omega (.) = 0 for R1, R2 and the Hessian term on periodic meshes."""
+    """sum_e J sum omega (.) = 0 for R1, R2 and the Hessian term on periodic meshes."""
     dg = make(kind, n=3)
     w = smooth_state(dg)
     rng = np.random.default_rng(1)
@@ -90,10 +90,10 @@ def test_conservation(kind):
         assert np.abs(dg.integral(val)).max() < 1e-12 * scale * np.prod(dg.mesh.length)
 
 
-# ------------------------------------------------------------------ P6
+# ------------------------------------------------------------------
 @pytest.mark.parametrize("nodes", ["gauss", "lobatto"])
 def test_advection_spectral_convergence(nodes):
-    """P6: R1 of the sine interpolant -> -a u_x; the pointwise error of this
+    """R1 of the sine interpolant -> -a u_x; the pointwise error of this
     derivative falls like h^N (N = 3)."""
     errs = []
     for n in (4, 8, 16):
@@ -106,7 +106,7 @@ def test_advection_spectral_convergence(nodes):
 
 
 def test_euler_density_wave_first_and_second_time_derivative():
-    """P6 for Euler: on the density wave rho = 1 + 0.3 sin(pi (x + y - 2 a t)),
+    """Euler: on the density wave rho = 1 + 0.3 sin(pi (x + y - 2 a t)),
     v = (a, a), p = 1 the exact w_t and w_tt are known; R1 -> w_t and
     R2(w, R1(w)) -> w_tt spectrally (the latter checks Eq. DGSEM_wtt)."""
     a = 0.3
@@ -128,7 +128,7 @@ def test_euler_density_wave_first_and_second_time_derivative():
 
 
 def test_burgers_viscous_rhs():
-    """P6 for BR1: u = 0.5 + 0.25 sin(x+y): u_t = -u (u_x + u_y) + nu Laplace u,
+    """BR1: u = 0.5 + 0.25 sin(x+y): u_t = -u (u_x + u_y) + nu Laplace u,
     and the viscous part alone, (R1_nu - R1_0)/nu, converges to Laplace u."""
     errs, errs_lap = [], []
     for n in (8, 16):
@@ -146,7 +146,7 @@ def test_burgers_viscous_rhs():
 
 
 def test_vortex_translation():
-    """P6: the isentropic vortex translates with the background flow, so R1 of
+    """the isentropic vortex translates with the background flow, so R1 of
     the exact solution approaches its time derivative (central difference in
     t) under refinement."""
     errs = []
@@ -162,10 +162,10 @@ def test_vortex_translation():
     assert errs[-1] < 3e-3 and errs[0] / errs[1] > 8, errs
 
 
-# ------------------------------------------------------------------ P9 / P10
+# ------------------------------------------------------------------
 @pytest.mark.parametrize("kind", ["adv1", "adv2", "adv3"])
 def test_linear_flux_closed_forms(kind):
-    """P9: for a linear flux R2(w, s) = R1(s) and the Hessian term is 0 (Sec. 3.2.1)."""
+    """for a linear flux R2(w, s) = R1(s) and the Hessian term is 0 (Sec. 3.2.1)."""
     dg = make(kind, n=3)
     rng = np.random.default_rng(3)
     w = rng.standard_normal((dg.mesh.n_elem, 1, dg.nnode))
@@ -174,10 +174,10 @@ def test_linear_flux_closed_forms(kind):
     assert np.abs(dg.hessian_term(w, s, rng.standard_normal(w.shape))).max() == 0.0
 
 
-# ------------------------------------------------------------------ P11
+# ------------------------------------------------------------------
 @pytest.mark.parametrize("kind", ALL)
 def test_complex_step_r2_and_hessian(kind):
-    """P11: Im R1(w + i h v)/h = R2(w, v) and Im R2(w + i h dw, s)/h = Hessian term."""
+    """Im R1(w + i h v)/h = R2(w, v) and Im R2(w + i h dw, s)/h = Hessian term."""
     dg = make(kind, n=3)
     w = smooth_state(dg, seed=5)
     rng = np.random.default_rng(6)
@@ -197,7 +197,7 @@ def test_complex_step_r2_and_hessian(kind):
 
 
 def test_rusanov_tie_rule_matches_complex_step_branch():
-    """Z8: at lambda_L = lambda_R the derivative takes the L branch, as the
+    """at lambda_L = lambda_R the derivative takes the L branch, as the
     complex step with real-part branching does."""
     eq = Euler(2)
     wL = [np.array([1.0]), np.array([0.3]), np.array([0.1]), np.array([2.5])]

@@ -1,11 +1,11 @@
 """Pins for the HBPC(q, k_max) driver (Algorithm 1, appendix tableaux).
 
-* P1  each tableau row is an exact Hermite-Birkhoff quadrature of order q;
-* P2  on y' = z y the step is a rational function of z whose Taylor series
+* each tableau row is an exact Hermite-Birkhoff quadrature of order q;
+* on y' = z y the step is a rational function of z whose Taylor series
       matches e^z to order min(4 + k_max, q) (remark after Algorithm 1);
-* P3  the predictor substep is the (2,2)-Pade approximant, |R(iy)| = 1;
-* P4  for q = 4 the corrector leaves the predictor result unchanged;
-* P14 temporal EOC on the 1-D advection DGSEM semi-discretisation against the
+* the predictor substep is the (2,2)-Pade approximant, |R(iy)| = 1;
+* for q = 4 the corrector leaves the predictor result unchanged;
+* temporal EOC on the 1-D advection DGSEM semi-discretisation against the
       matrix exponential.
 The power series are exact rationals, so these checks do not depend on
 floating point.
@@ -76,7 +76,7 @@ def order_of(R):
 
 @pytest.mark.parametrize("q", [4, 6, 8])
 def test_tableau_rows_are_exact_quadratures(q):
-    """P1: int_0^{c_l} t^p dt = sum_j B1 c_j^p + sum_j B2 p c_j^(p-1) for p <= q-1."""
+    """int_0^{c_l} t^p dt = sum_j B1 c_j^p + sum_j B2 p c_j^(p-1) for p <= q-1."""
     tab = tableau(q)
     for l in range(1, tab.s):
         for p in range(q):
@@ -97,13 +97,13 @@ def test_tableau_rows_are_exact_quadratures(q):
                                       (6, [4, 5, 6, 6, 6]),
                                       (8, [4, 5, 6, 7, 8, 8, 8])])
 def test_dahlquist_order(q, orders):
-    """P2: order min(4 + k_max, q)."""
+    """order min(4 + k_max, q)."""
     got = [order_of(dahlquist_step(q, k)) for k in range(len(orders))]
     assert got == orders
 
 
 def test_predictor_is_pade22():
-    """P3: one predictor substep of length c dt is (1 + x/2 + x^2/12)/(1 - x/2 + x^2/12), x = c z."""
+    """one predictor substep of length c dt is (1 + x/2 + x^2/12)/(1 - x/2 + x^2/12), x = c z."""
     R = dahlquist_step(4, 0)
     pade = (PS([1]) + Z * Fr(1, 2) + Z * Z * Fr(1, 12)).div(PS([1]) - Z * Fr(1, 2) + Z * Z * Fr(1, 12))
     assert R.c == pade.c
@@ -115,7 +115,7 @@ def test_predictor_is_pade22():
 
 
 def test_q4_corrector_is_noop():
-    """P4: for q = 4 the corrector sweeps reproduce the predictor exactly."""
+    """for q = 4 the corrector sweeps reproduce the predictor exactly."""
     R0 = dahlquist_step(4, 0)
     for k in (1, 2, 3):
         assert dahlquist_step(4, k).c == R0.c
@@ -160,7 +160,7 @@ def _advection_matrix():
 
 @pytest.mark.parametrize("q,k,expected", [(6, 0, 4), (6, 1, 5), (6, 2, 6), (6, 3, 6), (8, 4, 8)])
 def test_temporal_eoc_advection(q, k, expected):
-    """P14: error against expm(T L) u0 decays with order min(4 + k, q) (Fig. 7's claim)."""
+    """error against expm(T L) u0 decays with order min(4 + k, q) (Fig. 7's claim)."""
     Lm, u0 = _advection_matrix()
     I = np.eye(len(u0))
     T = 1.0

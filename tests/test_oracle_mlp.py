@@ -1,5 +1,5 @@
 """Pins for the reference MLP of the learned preconditioner: the manual
-backward pass against central finite differences (P17), Adam against its
+backward pass against central finite differences, Adam against its
 closed form on a quadratic, and the feature patch layout."""
 import numpy as np
 

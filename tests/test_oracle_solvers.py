@@ -41,7 +41,7 @@ def test_gmres_matches_direct_solve():
 
 
 def test_jvp_equals_complex_step_jacobian():
-    """P12: the extended Jacobian of Eq. nonlinear_eqsys (JVP) equals dG/dX
+    """the extended Jacobian of Eq. nonlinear_eqsys (JVP) equals dG/dX
     obtained column by column with the complex step on a 2x2, N = 2 Euler mesh."""
     dg, w = tiny_euler()
     n = dg.ndof
@@ -67,7 +67,7 @@ def test_jvp_equals_complex_step_jacobian():
 
 
 def test_block_inverse_identities():
-    """P16: P_i = [[A, B], [C, I]] with A = I - a1dt K, B = bcoef K, C = -K;
+    """P_i = [[A, B], [C, I]] with A = I - a1dt K, B = bcoef K, C = -K;
     A B = B A, and the D, E, F, G blocks invert P exactly (Sec. 3.2.3)."""
     dg, w = tiny_euler()
     a1dt, bc = 0.1, 0.1 ** 2 / 2
@@ -99,7 +99,7 @@ def test_bjext_is_exact_for_element_decoupled_linear_problem():
 
 
 def test_dense_newton_equals_gmres_newton():
-    """P12: a stage solve by Newton with dense LU and by Newton-GMRES(BJ_ext)
+    """a stage solve by Newton with dense LU and by Newton-GMRES(BJ_ext)
     agree to the solver tolerance (tiny 2-D Euler mesh)."""
     dg, w = tiny_euler(N=1)
     b = w + 0.05 * dg.r1(w)
@@ -126,7 +126,7 @@ def test_fd_jvp_within_fd_error_bound():
 
 
 def test_linear_step_is_matrix_rational_function():
-    """P13: for 1-D advection one HBPC(6,3) step with Newton-GMRES(BJ_ext)
+    """for 1-D advection one HBPC(6,3) step with Newton-GMRES(BJ_ext)
     equals the same step taken with exact dense solves of the stage systems."""
     dg, w, x = advection_c1()
     n = dg.ndof
@@ -144,7 +144,7 @@ def test_linear_step_is_matrix_rational_function():
 
 
 def test_central_flux_hbpc4_conserves_energy():
-    """P3: with the central flux L is skew in the DG mass inner product and the
+    """with the central flux L is skew in the DG mass inner product and the
     HBPC(4,k) step is the (2,2)-Pade map, so sum J omega w^2 is conserved."""
     dg = DGSEM(Mesh(1, [16], [1.0]), 3, Advection(1, [1.0]), nodes="lobatto", flux="central")
     x = dg.node_coords()[0]
@@ -159,7 +159,7 @@ def test_central_flux_hbpc4_conserves_energy():
 
 
 def test_constant_state_step_takes_no_newton_iterations():
-    """P8 at step level: a constant state is unchanged by an HBPC step."""
+    """At step level: a constant state is unchanged by an HBPC step."""
     dg = DGSEM(Mesh(2, [3, 3], [10.0, 10.0]), 3, Euler(2), flux="rusanov")
     w = np.zeros((9, 4, 16))
     w[:, 0], w[:, 1], w[:, 2], w[:, 3] = 1.0, 0.3, 0.2, 2.6
@@ -170,7 +170,7 @@ def test_constant_state_step_takes_no_newton_iterations():
 
 
 def test_mass_conservation_dense_and_gmres():
-    """P18: sum J omega w per variable is conserved by a step to round-off with
+    """sum J omega w per variable is conserved by a step to round-off with
     the dense Newton (1-D viscous Burgers), and to the Newton tolerance with
     Newton-GMRES (2-D Euler)."""
     dg = DGSEM(Mesh(1, [4], [2 * np.pi]), 3, Burgers(1, 0.05), flux="lf", lam=1.0)
@@ -187,7 +187,7 @@ def test_mass_conservation_dense_and_gmres():
 
 
 def test_advection_step_against_exact_solution():
-    """P15: 20 HBPC(6,3) steps of dt = 0.05 on the 1-D advection workload stay
+    """20 HBPC(6,3) steps of dt = 0.05 on the 1-D advection workload stay
     within the spatial error of the N = 3, 16-element discretisation of
     sin(2 pi (x - t)) (error at t = 1 vs. the semi-discrete bound)."""
     dg, w, x = advection_c1()
