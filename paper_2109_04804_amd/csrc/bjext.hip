@@ -5,8 +5,9 @@
 // S_i = I - a1dt K_i + bcoef K_i^2 in registers and invert it by Gauss-Jordan
 // elimination with partial pivoting, in the precision S_i^-1 is stored in;
 // store S_i^-1 column-major (SinvT[e][c][r]).
-// One workgroup of TG x TG threads per element; thread (tr, tc) owns rows
-// tr + TG a and columns tc + TG b (a, b < R), so blocks up to R*TG fit.
+// Blocks up to 144 unknowns: one workgroup of TG x TG threads per element, the
+// matrix in registers; thread (tr, tc) owns rows tr + TG a and columns tc + TG b.
+// Larger blocks (up to 1024): the blocked kernel below, matrix in the output.
 //
 // Apply: the local products K vs and K (vw - a1dt vs) come from the PCPRE
 // operator kernel (a = vw - bcoef K vs, c = vs + K (vw - a1dt vs)); since S_i
@@ -192,19 +193,271 @@ __global__ void __launch_bounds__(TGR* TGC) bj_invert_kernel(const double* __res
     }
 }
 
-// y = S^-1 x for the two right-hand sides (w block, sigma block); one thread per row.
+// ---- element blocks too large for registers (the 3-D Euler N = 3 block has 320 unknowns):
+// blocked Gauss-Jordan with the working matrix A (column-major, A[c * NE + r]) kept in the
+// element's output block.  Panels of pb columns are eliminated in LDS with the same pivot rule
+// as the register kernel (largest not-yet-pivot entry of the column, smallest row on ties).
+// A run of exchange steps on distinct rows P and columns Q composes into one block exchange:
+// with M = the panel columns after elimination and U = A[P][c] before it, every column c
+// outside the panel becomes A[r][c] <- [r not in P] A[r][c] + sum_j M[r][j] U[j][c].
+// The K^2 product and the update run in 64 x 64 output tiles; thread (tr, tc) owns rows
+// r0 + 4 tr + i (i < 4) and columns c0 + tc + 16 b (b < 4).  At the end the element's K slot
+// (no longer needed) holds a copy of A for the row/column permutation into S^-1.
+constexpr int BIG_THREADS = 256;
+constexpr int BIG_TILE = 64;
+constexpr int BIG_KC = 16;
+
+template <typename T> struct BigLds {
+    int nep, pb;                 // padded row pitch of a panel column, panel width
+    size_t off_u, off_col, off_row, off_red, off_ired, off_prow, off_pinv, bytes;
+};
+
+template <typename T> __host__ __device__ inline BigLds<T> big_lds(int NE, int pb) {
+    BigLds<T> L;
+    L.nep = (NE + 3) / 4 * 4;
+    L.pb = pb;
+    size_t p = (size_t)pb * L.nep;                               // panel, or the two K^2 staging tiles
+    const size_t stage = (size_t)BIG_KC * BIG_TILE + (size_t)BIG_KC * (BIG_TILE + 1);
+    if (p < stage) p = stage;
+    size_t off = p * sizeof(T);
+    L.off_u = off;    off += (size_t)pb * BIG_TILE * sizeof(T);
+    L.off_col = off;  off += (size_t)L.nep * sizeof(T);
+    L.off_row = off;  off += (size_t)pb * sizeof(T);
+    L.off_red = off;  off += 4 * sizeof(T);
+    L.off_ired = off; off += 8 * sizeof(int);
+    L.off_prow = off; off += (size_t)NE * sizeof(int);
+    L.off_pinv = off; off += (size_t)NE * sizeof(int);
+    L.bytes = off;
+    return L;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* __restrict__ KT, T* __restrict__ SinvT,
+                                                                   int NE, int pb_max, T a1dt, T bc,
+                                                                   int* __restrict__ status) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const BigLds<T> L = big_lds<T>(NE, pb_max);
+    const int nep = L.nep;
+    T* sP = reinterpret_cast<T*>(smem_raw);                      // panel: sP[j * nep + r]
+    T* sA = sP;                                                  // K^2 staging: sA[t * 64 + x]
+    T* sB = sP + BIG_KC * BIG_TILE;                              //              sB[t * 65 + y]
+    T* sU = reinterpret_cast<T*>(smem_raw + L.off_u);            // sU[j * 64 + y]
+    T* s_col = reinterpret_cast<T*>(smem_raw + L.off_col);
+    T* s_row = reinterpret_cast<T*>(smem_raw + L.off_row);
+    T* s_red = reinterpret_cast<T*>(smem_raw + L.off_red);
+    int* s_ired = reinterpret_cast<int*>(smem_raw + L.off_ired);
+    int* s_prow = reinterpret_cast<int*>(smem_raw + L.off_prow); // pivot row of step k
+    int* s_pinv = reinterpret_cast<int*>(smem_raw + L.off_pinv); // step at which row r was pivot, or -1
+
+    const int tid = threadIdx.x;
+    const int tr = tid % 16, tc = tid / 16;
+    const size_t e = blockIdx.x;
+    const size_t nn = (size_t)NE * NE;
+    const double* K = KT + e * nn;
+    T* A = SinvT + e * nn;
+
+    // ---- S = I - a1dt K + bc K^2 into A
+    for (int r0 = 0; r0 < NE; r0 += BIG_TILE)
+        for (int c0 = 0; c0 < NE; c0 += BIG_TILE) {
+            T acc[4][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[i][b] = T(0);
+            for (int kk = 0; kk < NE; kk += BIG_KC) {
+                for (int i = tid; i < BIG_KC * BIG_TILE; i += BIG_THREADS) {
+                    const int t = i / BIG_TILE, x = i % BIG_TILE;   // consecutive threads: consecutive rows
+                    const int k = kk + t, r = r0 + x;
+                    sA[t * BIG_TILE + x] = (k < NE && r < NE) ? (T)K[(size_t)k * NE + r] : T(0);   // K[r][k]
+                }
+                for (int i = tid; i < BIG_KC * BIG_TILE; i += BIG_THREADS) {
+                    const int y = i / BIG_KC, t = i % BIG_KC;       // consecutive threads: consecutive k
+                    const int k = kk + t, cc = c0 + y;
+                    sB[t * (BIG_TILE + 1) + y] = (k < NE && cc < NE) ? (T)K[(size_t)cc * NE + k] : T(0);   // K[k][c]
+                }
+                __syncthreads();
+#pragma unroll 4
+                for (int t = 0; t < BIG_KC; ++t) {
+                    T ra[4], cb[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) ra[i] = sA[t * BIG_TILE + 4 * tr + i];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) cb[b] = sB[t * (BIG_TILE + 1) + tc + 16 * b];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) acc[i][b] += ra[i] * cb[b];
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int cc = c0 + tc + 16 * b;
+                if (cc >= NE) continue;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = r0 + 4 * tr + i;
+                    if (r >= NE) continue;
+                    T v = (r == cc) ? T(1) : T(0);
+                    v += -a1dt * (T)K[(size_t)cc * NE + r] + bc * acc[i][b];
+                    A[(size_t)cc * NE + r] = v;
+                }
+            }
+        }
+    for (int r = tid; r < NE; r += BIG_THREADS) s_pinv[r] = -1;
+    __syncthreads();
+
+    // ---- panels
+    for (int k0 = 0; k0 < NE; k0 += pb_max) {
+        const int pb = NE - k0 < pb_max ? NE - k0 : pb_max;
+        for (int i = tid; i < pb * NE; i += BIG_THREADS) {
+            const int j = i / NE, r = i % NE;
+            sP[j * nep + r] = A[(size_t)(k0 + j) * NE + r];
+        }
+        __syncthreads();
+        for (int j = 0; j < pb; ++j) {
+            const int k = k0 + j;
+            // pivot: largest |entry| of panel column j over rows not yet pivot (NaN never wins)
+            T best = T(-1);
+            int bi = NE;
+            for (int r = tid; r < NE; r += BIG_THREADS) {
+                if (s_pinv[r] >= 0) continue;
+                T v = sP[j * nep + r];
+                v = v >= T(0) ? v : -v;
+                if (v > best) {
+                    best = v;
+                    bi = r;
+                }
+            }
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const T ob = __shfl_xor(best, off, 64);
+                const int oi = __shfl_xor(bi, off, 64);
+                if (ob > best || (ob == best && oi < bi)) {
+                    best = ob;
+                    bi = oi;
+                }
+            }
+            if ((tid & 63) == 0) {
+                s_red[tid >> 6] = best;
+                s_ired[tid >> 6] = bi;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                T b0 = s_red[0];
+                int i0 = s_ired[0];
+                for (int w = 1; w < BIG_THREADS / 64; ++w)
+                    if (s_red[w] > b0 || (s_red[w] == b0 && s_ired[w] < i0)) {
+                        b0 = s_red[w];
+                        i0 = s_ired[w];
+                    }
+                s_ired[4] = i0;
+            }
+            __syncthreads();
+            const int p = s_ired[4];
+            if (p >= NE) {                 // no finite pivot left: flag, stop
+                if (tid == 0) atomicOr(status, 1);
+                return;
+            }
+            for (int r = tid; r < NE; r += BIG_THREADS) s_col[r] = sP[j * nep + r];
+            for (int jj = tid; jj < pb; jj += BIG_THREADS) s_row[jj] = sP[jj * nep + p];
+            __syncthreads();
+            if (tid == 0) {
+                s_prow[k] = p;
+                s_pinv[p] = k;
+            }
+            const T piv = s_col[p];
+            const T ipiv = T(1) / piv;
+            if (tid == 0 && (!(piv == piv) || piv == T(0))) atomicOr(status, 1);
+            for (int i = tid; i < pb * NE; i += BIG_THREADS) {
+                const int jj = i / NE, r = i % NE;
+                T v;
+                if (jj == j) {
+                    v = (r == p) ? ipiv : -s_col[r] * ipiv;
+                } else {
+                    const T prv = s_row[jj] * ipiv;
+                    v = (r == p) ? prv : sP[jj * nep + r] - s_col[r] * prv;
+                }
+                sP[jj * nep + r] = v;
+            }
+            __syncthreads();
+        }
+        // block exchange on the columns outside the panel
+        for (int c0 = 0; c0 < NE; c0 += BIG_TILE) {
+            for (int i = tid; i < pb * BIG_TILE; i += BIG_THREADS) {
+                const int j = i / BIG_TILE, y = i % BIG_TILE;
+                const int cc = c0 + y;
+                sU[j * BIG_TILE + y] = cc < NE ? A[(size_t)cc * NE + s_prow[k0 + j]] : T(0);
+            }
+            __syncthreads();
+            for (int r0 = 0; r0 < NE; r0 += BIG_TILE) {
+                T acc[4][4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[i][b] = T(0);
+                const int rb = r0 + 4 * tr;
+                if (rb < nep) {
+                    for (int j = 0; j < pb; ++j) {
+                        T ra[4], cb[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) ra[i] = sP[j * nep + rb + i];
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) cb[b] = sU[j * BIG_TILE + tc + 16 * b];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+#pragma unroll
+                            for (int b = 0; b < 4; ++b) acc[i][b] += ra[i] * cb[b];
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int cc = c0 + tc + 16 * b;
+                    if (cc >= NE || (cc >= k0 && cc < k0 + pb)) continue;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = rb + i;
+                        if (r >= NE) continue;
+                        const int q = s_pinv[r];
+                        const bool inp = q >= k0 && q < k0 + pb;
+                        T* dst = A + (size_t)cc * NE + r;
+                        *dst = inp ? acc[i][b] : *dst + acc[i][b];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        for (int i = tid; i < pb * NE; i += BIG_THREADS) {
+            const int j = i / NE, r = i % NE;
+            A[(size_t)(k0 + j) * NE + r] = sP[j * nep + r];
+        }
+        __syncthreads();
+    }
+    // ---- S^-1[pinv[r]][prow[c]] = A[r][c], stored column-major (SinvT[col][row])
+    T* slot = reinterpret_cast<T*>(KT + e * nn);
+    for (size_t i = tid; i < nn; i += BIG_THREADS) slot[i] = A[i];
+    __syncthreads();
+    for (size_t i = tid; i < nn; i += BIG_THREADS) {
+        const int cc = (int)(i / NE), r = (int)(i % NE);
+        A[(size_t)s_prow[cc] * NE + s_pinv[r]] = slot[i];
+    }
+}
+
+// y = S^-1 x for the two right-hand sides (w block, sigma block).
 // yw = S^-1 xa, ys = S^-1 xc per element; S^-1 stored transposed (column-major blocks, SinvT[e][c][r]),
-// each thread owns VR consecutive rows (one 16-byte load per column when VR * sizeof(TM) == 16),
-// NE / VR threads per element, several elements per block; the two right-hand sides staged in LDS
+// each thread owns groups of VR consecutive rows (one 16-byte load per column when VR * sizeof(TM)
+// == 16): min(NE / VR, 256) threads per element, a thread taking every tpe-th group when there are
+// more groups than threads; several elements per block; the two right-hand sides staged in LDS
 template <typename TM, typename T, int VR>
 __global__ void __launch_bounds__(256) bj_apply_kernel(const TM* __restrict__ SinvT, const T* __restrict__ xa,
                                                       const T* __restrict__ xc, T* __restrict__ yw,
                                                       T* __restrict__ ys, int NE, int nE) {
     extern __shared__ unsigned char smem_raw[];
     T* sx = reinterpret_cast<T*>(smem_raw);
-    const int tpe = NE / VR;
+    const int ng = NE / VR;
+    const int tpe = ng < 256 ? ng : 256;
     const int epb = blockDim.x / tpe;
-    const int el = threadIdx.x / tpe, r0 = (threadIdx.x % tpe) * VR;
+    const int el = threadIdx.x / tpe;
     const int e0 = blockIdx.x * epb;
     for (int i = threadIdx.x; i < epb * NE; i += blockDim.x) {
         int le = i / NE;
@@ -217,25 +470,28 @@ __global__ void __launch_bounds__(256) bj_apply_kernel(const TM* __restrict__ Si
     const int e = e0 + el;
     if (el >= epb || e >= nE) return;
     typedef TM VT __attribute__((ext_vector_type(VR)));
-    const TM* M = SinvT + (size_t)e * NE * NE + r0;
     const T* x = sx + 2 * el * NE;
-    T s0[VR], s1[VR];
+    for (int gr = threadIdx.x % tpe; gr < ng; gr += tpe) {
+        const int r0 = gr * VR;
+        const TM* M = SinvT + (size_t)e * NE * NE + r0;
+        T s0[VR], s1[VR];
 #pragma unroll
-    for (int q = 0; q < VR; ++q) s0[q] = s1[q] = T(0);
+        for (int q = 0; q < VR; ++q) s0[q] = s1[q] = T(0);
 #pragma unroll 4
-    for (int c = 0; c < NE; ++c) {
-        const VT m = *reinterpret_cast<const VT*>(M + (size_t)c * NE);
-        const T xa_c = x[2 * c], xc_c = x[2 * c + 1];
+        for (int c = 0; c < NE; ++c) {
+            const VT m = *reinterpret_cast<const VT*>(M + (size_t)c * NE);
+            const T xa_c = x[2 * c], xc_c = x[2 * c + 1];
+#pragma unroll
+            for (int q = 0; q < VR; ++q) {
+                s0[q] += (T)m[q] * xa_c;
+                s1[q] += (T)m[q] * xc_c;
+            }
+        }
 #pragma unroll
         for (int q = 0; q < VR; ++q) {
-            s0[q] += (T)m[q] * xa_c;
-            s1[q] += (T)m[q] * xc_c;
+            yw[(size_t)e * NE + r0 + q] = s0[q];
+            ys[(size_t)e * NE + r0 + q] = s1[q];
         }
-    }
-#pragma unroll
-    for (int q = 0; q < VR; ++q) {
-        yw[(size_t)e * NE + r0 + q] = s0[q];
-        ys[(size_t)e * NE + r0 + q] = s1[q];
     }
 }
 
@@ -249,9 +505,31 @@ static hipError_t launch_inv(const double* KT, TO* SinvT, int NE, int nE, double
     return hipGetLastError();
 }
 
-hipError_t bj_invert(const double* KT, void* SinvT, int f32, int NE, int nE, double a1dt, double bc, int* status,
+// panel width for the blocked kernel: the widest of 32, 16, 8 whose LDS fits in 64 KiB (0: none)
+template <typename T> static int big_panel(int NE) {
+    for (int pb = 32; pb >= 8; pb /= 2)
+        if (big_lds<T>(NE, pb).bytes <= 65536) return pb;
+    return 0;
+}
+
+template <typename T>
+static hipError_t launch_inv_big(double* KT, T* SinvT, int NE, int nE, double a1dt, double bc, int* status,
+                                 hipStream_t st) {
+    const int pb = big_panel<T>(NE);
+    if (pb == 0) return hipErrorInvalidValue;
+    const size_t sh = big_lds<T>(NE, pb).bytes;
+    hipLaunchKernelGGL(bj_invert_big_kernel<T>, dim3(nE), dim3(BIG_THREADS), sh, st, KT, SinvT, NE, pb, (T)a1dt,
+                       (T)bc, status);
+    return hipGetLastError();
+}
+
+// KT: the chunk's K blocks; for blocks above 144 unknowns they are overwritten (used as scratch)
+hipError_t bj_invert(double* KT, void* SinvT, int f32, int NE, int nE, double a1dt, double bc, int* status,
                      hipStream_t st) {
     if (nE == 0) return hipSuccess;
+    if (NE > 144 && NE <= 1024)
+        return f32 ? launch_inv_big<float>(KT, (float*)SinvT, NE, nE, a1dt, bc, status, st)
+                   : launch_inv_big<double>(KT, (double*)SinvT, NE, nE, a1dt, bc, status, st);
 #define HBPC_INV(TGR, TGC, RR, RC)                                                                         \
     return f32 ? launch_inv<TGR, TGC, RR, RC, float>(KT, (float*)SinvT, NE, nE, a1dt, bc, status, st)    \
                : launch_inv<TGR, TGC, RR, RC, double>(KT, (double*)SinvT, NE, nE, a1dt, bc, status, st);
@@ -265,8 +543,9 @@ hipError_t bj_invert(const double* KT, void* SinvT, int f32, int NE, int nE, dou
 
 template <typename TM, typename T, int VR>
 static void launch_apply(const TM* SinvT, const T* xa, const T* xc, T* yw, T* ys, int NE, int nE, hipStream_t st) {
-    const int tpe = NE / VR;
-    const int epb = tpe >= 256 ? 1 : 256 / tpe;
+    const int ng = NE / VR;
+    const int tpe = ng < 256 ? ng : 256;
+    const int epb = 256 / tpe;
     const int threads = epb * tpe;
     const int grid = (nE + epb - 1) / epb;
     const size_t sh = (size_t)2 * epb * NE * sizeof(T);

@@ -1,6 +1,6 @@
 // Vector kernels of the Newton-Krylov solver: block-partial dot products with
 // several basis vectors at once (classical Gram-Schmidt, twice, the second
-// pass from the Gram matrix of the basis), the update w -= V h, norms,
+// pass from the Gram matrix of the basis), the update w -= V h with the normalisation of w,
 // axpby, casts.  Reductions are deterministic: each block sums
 // a fixed set of indices in a fixed order, partial results are combined by
 // one block in a fixed tree, so two runs give bitwise equal results.
@@ -210,22 +210,6 @@ __global__ void __launch_bounds__(BLAS_THREADS) reduce_parts_kernel(const double
     if (threadIdx.x == 0) out[j] = scale * s;
 }
 
-// w[i] -= sum_j h[j] V_j[i]   (h on the device)
-template <typename T>
-__global__ void __launch_bounds__(BLAS_THREADS) gemv_sub_kernel(const T* __restrict__ V, size_t ld, int k,
-                                                                const double* __restrict__ h, T* __restrict__ w,
-                                                                size_t n) {
-    __shared__ double sh[64];
-    for (int j = threadIdx.x; j < k; j += blockDim.x) sh[j] = h[j];
-    __syncthreads();
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        double acc = 0.0;
-        for (int j = 0; j < k; ++j) acc += sh[j] * (double)V[j * ld + i];
-        w[i] = (T)((double)w[i] - acc);
-    }
-}
-
 // y[i] = a * x[i] + b * y[i] (b == 0: y is not read)
 template <typename TX, typename TY>
 __global__ void __launch_bounds__(BLAS_THREADS) axpby_kernel(double a, const TX* x, double b,
@@ -312,15 +296,27 @@ __global__ void __launch_bounds__(BLAS_THREADS) gemv_sub_norm_kernel(const T* __
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// v = u / sqrt(nrm2[0]) with the squared norm on the device; u unchanged when it is 0
+// hn = sum of the nb block partials of ||u||^2 (every block forms the same sum in the same fixed
+// order; block 0 stores it in nrm2[0]), then u /= sqrt(hn) (u unchanged when hn is 0)
 template <typename T>
-__global__ void __launch_bounds__(BLAS_THREADS) scale_inv_norm_kernel(T* __restrict__ u, size_t n,
-                                                                      const double* __restrict__ nrm2) {
-    const double hn = nrm2[0];
+__global__ void __launch_bounds__(BLAS_THREADS) sum_scale_kernel(T* __restrict__ u, size_t n,
+                                                                 const double* __restrict__ part, int nb,
+                                                                 double* __restrict__ nrm2) {
+    __shared__ double red[BLAS_THREADS / 64];
+    __shared__ double hn_s;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[b];
+    s = block_sum<double>(s, red);
+    if (threadIdx.x == 0) {
+        hn_s = s;
+        if (blockIdx.x == 0) nrm2[0] = s;
+    }
+    __syncthreads();
+    const double hn = hn_s;
     if (!(hn > 0.0)) return;
-    const double s = 1.0 / sqrt(hn);
+    const double sc = 1.0 / sqrt(hn);
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) u[i] = (T)(s * (double)u[i]);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) u[i] = (T)(sc * (double)u[i]);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -367,9 +363,10 @@ hipError_t blas_mdot(const void* V, size_t ld, int k, const void* w, size_t n, i
     return hipGetLastError();
 }
 
-// u -= V h (k columns, h on the device) and nrm2[0] = ||u||^2 afterwards
-hipError_t blas_gemv_sub_norm(const void* V, size_t ld, int k, const double* h, void* u, size_t n, int f32,
-                              double* part, double* nrm2, hipStream_t st) {
+// u -= V h (k columns, h on the device), nrm2[0] = ||u||^2, u /= ||u||: the Arnoldi update of
+// a new basis vector.  part: blas_grid(n) doubles.
+hipError_t blas_gs_update_normalize(const void* V, size_t ld, int k, const double* h, void* u, size_t n, int f32,
+                                    double* part, double* nrm2, hipStream_t st) {
     if (k > 64) return hipErrorInvalidValue;
     const int vec = vec_of(n, ld, f32, V, u);
     int g = blas_grid(n / vec);
@@ -385,16 +382,12 @@ hipError_t blas_gemv_sub_norm(const void* V, size_t ld, int k, const double* h, 
     else
         hipLaunchKernelGGL((gemv_sub_norm_kernel<double, 1>), dim3(g), dim3(BLAS_THREADS), 0, st, (const double*)V,
                            ld, k, h, (double*)u, n, part);
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(BLAS_THREADS), 0, st, part, g, nrm2, 1.0);
-    return hipGetLastError();
-}
-
-hipError_t blas_scale_inv_norm(void* u, size_t n, int f32, const double* nrm2, hipStream_t st) {
-    int g = blas_grid(n);
+    const int g2 = blas_grid(n);
     if (f32)
-        hipLaunchKernelGGL(scale_inv_norm_kernel<float>, dim3(g), dim3(BLAS_THREADS), 0, st, (float*)u, n, nrm2);
+        hipLaunchKernelGGL(sum_scale_kernel<float>, dim3(g2), dim3(BLAS_THREADS), 0, st, (float*)u, n, part, g, nrm2);
     else
-        hipLaunchKernelGGL(scale_inv_norm_kernel<double>, dim3(g), dim3(BLAS_THREADS), 0, st, (double*)u, n, nrm2);
+        hipLaunchKernelGGL(sum_scale_kernel<double>, dim3(g2), dim3(BLAS_THREADS), 0, st, (double*)u, n, part, g,
+                           nrm2);
     return hipGetLastError();
 }
 
@@ -429,18 +422,6 @@ hipError_t blas_gs_gram(const void* V, size_t ld, int k, const void* w1, const v
     // h1 = part columns 0..k-1, g = columns k..2k-1 (h1 and g adjacent: g = h1 + k)
     hipLaunchKernelGGL(reduce_gram_kernel, dim3(2 * k), dim3(BLAS_THREADS), 0, st, part, gr, h1, k, G, ldg, h,
                        counter);
-    return hipGetLastError();
-}
-
-hipError_t blas_gemv_sub(const void* V, size_t ld, int k, const double* h, void* w, size_t n, int f32,
-                         hipStream_t st) {
-    int g = blas_grid(n);
-    if (f32)
-        hipLaunchKernelGGL(gemv_sub_kernel<float>, dim3(g), dim3(BLAS_THREADS), 0, st, (const float*)V, ld, k, h,
-                           (float*)w, n);
-    else
-        hipLaunchKernelGGL(gemv_sub_kernel<double>, dim3(g), dim3(BLAS_THREADS), 0, st, (const double*)V, ld, k, h,
-                           (double*)w, n);
     return hipGetLastError();
 }
 

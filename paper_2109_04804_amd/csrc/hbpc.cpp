@@ -298,7 +298,7 @@ static double dnorm(hbpc_ctx* c, const void* x, size_t n, int f32) {
 // ------------------------------------------------------------------ BJ_ext
 static void pc_build(hbpc_ctx* c, const double* w, double a1dt, double bc, int f32) {
     double t0 = now_ms();
-    if (c->NE > 144) set_err(c, HBPC_ERR_UNSUPPORTED, "BJ_ext supports element blocks up to 144 unknowns");
+    if (c->NE > 1024) set_err(c, HBPC_ERR_UNSUPPORTED, "BJ_ext supports element blocks up to 1024 unknowns");
     if (!c->Sinv || c->sinv_f32 != f32) {
         dfree(c->Sinv);
         c->Sinv = nullptr;
@@ -771,11 +771,8 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
                    "gs dot");
             prof_end(c, pi, KC_GSDOT, (j + 3) * vb);
             pi = prof_begin(c, KC_GSUPD);
-            hipchk(c, blas_gemv_sub_norm(V, n2, j + 1, h, u, n2, f32, c->part, hn, c->stream), "gs update");
-            prof_end(c, pi, KC_GSUPD, (j + 3) * vb);
-            pi = prof_begin(c, KC_VEC);
-            hipchk(c, blas_scale_inv_norm(u, n2, f32, hn, c->stream), "scale");
-            prof_end(c, pi, KC_VEC, 2 * vb);
+            hipchk(c, blas_gs_update_normalize(V, n2, j + 1, h, u, n2, f32, c->part, hn, c->stream), "gs update");
+            prof_end(c, pi, KC_GSUPD, (j + 5) * vb);
             hipchk(c, hipMemcpyAsync(c->hres + 256 * (j & 1), c->dres, 196 * sizeof(double), hipMemcpyDeviceToHost,
                                      c->stream),
                    "copy");

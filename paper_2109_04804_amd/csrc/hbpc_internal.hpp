@@ -11,18 +11,15 @@
 hipError_t dg_launch_euler(const GeomHost& g, const LaunchReq& r, int f32);
 hipError_t dg_launch_advection(const GeomHost& g, const LaunchReq& r, int f32);
 hipError_t dg_launch_burgers(const GeomHost& g, const LaunchReq& r, int f32);
-hipError_t bj_invert(const double* KT, void* SinvT, int f32, int NE, int nE, double a1dt, double bc, int* status,
+hipError_t bj_invert(double* KT, void* SinvT, int f32, int NE, int nE, double a1dt, double bc, int* status,
                      hipStream_t st);
 hipError_t bj_apply(const void* SinvT, int m_f32, const void* xa, const void* xc, void* yw, void* ys, int v_f32,
                     int NE, int nE, hipStream_t st);
 int blas_mdot_grid(size_t n);
 hipError_t blas_mdot(const void* V, size_t ld, int k, const void* w, size_t n, int f32, double* part, double* h,
                      hipStream_t st);
-hipError_t blas_gemv_sub_norm(const void* V, size_t ld, int k, const double* h, void* u, size_t n, int f32,
-                              double* part, double* nrm2, hipStream_t st);
-hipError_t blas_gemv_sub(const void* V, size_t ld, int k, const double* h, void* w, size_t n, int f32,
-                         hipStream_t st);
-hipError_t blas_scale_inv_norm(void* u, size_t n, int f32, const double* nrm2, hipStream_t st);
+hipError_t blas_gs_update_normalize(const void* V, size_t ld, int k, const double* h, void* u, size_t n, int f32,
+                                    double* part, double* nrm2, hipStream_t st);
 hipError_t blas_gs_gram(const void* V, size_t ld, int k, const void* w1, const void* w2, size_t n, int f32,
                         double* part, double* h1, double* g, double* G, int ldg, double* h, unsigned* counter,
                         hipStream_t st);

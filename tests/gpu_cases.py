@@ -29,6 +29,12 @@ CASES = {
     # 3-D eps-scaled Euler (eps = 0.1), N = 3 as in the Taylor-Green workload
     "euler3_n3": dict(dim=3, nelem=[3, 4, 5], length=[TWO_PI] * 3, N=3, equation="euler", nodes="gauss",
                       flux="rusanov", eps_ref=0.1),
+    # element blocks above the register kernel's 144 unknowns: 216 (ragged panel and tile) and
+    # 625 (odd: padded LDS pitch)
+    "adv3_n5": dict(dim=3, nelem=[2, 3, 2], length=[1.0, 1.0, 1.0], N=5, equation="advection", nodes="gauss",
+                    flux="upwind", adv=[0.3, 0.5, -0.2]),
+    "euler3_n4": dict(dim=3, nelem=[2, 1, 2], length=[TWO_PI] * 3, N=4, equation="euler", nodes="gauss",
+                      flux="rusanov", eps_ref=0.1),
     # viscous Burgers with BR1 lifting (2-D workload shape N = 4; 1-D on Lobatto nodes)
     "burgers2": dict(dim=2, nelem=[5, 4], length=[TWO_PI, TWO_PI], N=4, equation="burgers", nodes="gauss",
                      flux="lf", nu=0.01, **{"lambda": 1.0}),

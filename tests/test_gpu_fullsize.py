@@ -11,6 +11,8 @@ Workloads: the 2-D Euler vortex, 128 x 128 elements, N = 5 (2,359,296 DOF),
 and the 3-D eps-scaled Euler Taylor-Green vortex, 48^3 elements, N = 3
 (35,389,440 DOF).  Tolerances as in test_gpu_parity.
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -139,3 +141,56 @@ def test_fullsize_bjext_apply_vortex():
         refc = np.concatenate([ref[:m].reshape(len(idx), ne)[c], ref[m:].reshape(len(idx), ne)[c]])
         got = np.concatenate([Yh[:n].reshape(nE, ne)[e], Yh[n:].reshape(nE, ne)[e]])
         assert rel(got, refc) < 1e-10
+
+
+def test_fullsize_bjext_apply_tgv():
+    """BJ_ext build + apply at 48^3, N = 3 (element blocks of 320 unknowns, the blocked
+    inversion; S^-1 of the whole mesh: 90.6 GB in FP64, 45.3 GB in FP32).
+
+    Tolerance: 1e-10 in FP64; in FP32, u_32 kappa_2(S_e) (at least 1e-4), the first-order
+    error of forming and applying an inverse in unit roundoff u_32 = 2^-24 (with eps = 0.1
+    and a1dt = 0.1 these blocks have kappa_2(S_e) about 1e5)."""
+    case = TGV
+    ctx = ctx_for(case, gmres_restart=1, precond="none")
+    ne = ctx.block
+    nE = int(np.prod(case["nelem"]))
+    w = full_state(case, ctx)
+    rng = np.random.default_rng(13)
+    X = rng.standard_normal(2 * ctx.ndof)
+    a1dt, bc = 0.1, 0.1 ** 2 / 2
+    dev = lambda x, dt=torch.float64: torch.tensor(np.ascontiguousarray(x).reshape(-1), dtype=dt, device="cuda")
+    n = ctx.ndof
+    picks = samples(nE, k=1)
+    refs, kappa = {}, {}
+    for e in picks:
+        idx = patch_indices(case["nelem"], e)
+        dgp, c = patch_oracle(case, None)
+        wp = gather(w, idx, ne).reshape(len(idx), dgp.nvar, dgp.nnode)
+        pc = BJExt(dgp, wp, a1dt, bc)
+        Xp = np.concatenate([gather(X[:n], idx, ne).ravel(), gather(X[n:], idx, ne).ravel()])
+        ref = pc.apply(Xp)
+        m = len(idx) * ne
+        refs[e] = np.concatenate([ref[:m].reshape(len(idx), ne)[c], ref[m:].reshape(len(idx), ne)[c]])
+        Ke = pc.K[c]
+        kappa[e] = np.linalg.cond(np.eye(ne) - a1dt * Ke + bc * (Ke @ Ke))
+    wd = dev(w)
+    for prec, vdt, tol in (("fp64", torch.float64, 1e-10), ("mixed", torch.float32, 1e-4)):
+        print("build", prec, flush=True)
+        t0 = time.perf_counter()
+        ctx.pc_build(wd, a1dt, bc, prec)
+        torch.cuda.synchronize()
+        print("build", prec, "%.1f ms" % (1e3 * (time.perf_counter() - t0)), flush=True)
+        Y = torch.empty(2 * n, dtype=vdt, device="cuda")
+        if prec == "fp64":
+            ctx.pc_apply(dev(X), Y)
+        else:
+            ctx.pc_apply_f32(dev(X, torch.float32), Y)
+        Yh = host(Y)
+        del Y
+        for e in picks:
+            got = np.concatenate([Yh[:n].reshape(nE, ne)[e], Yh[n:].reshape(nE, ne)[e]])
+            err = rel(got, refs[e])
+            bound = tol if prec == "fp64" else max(tol, 2.0 ** -24 * kappa[e])
+            print(prec, "element", e, "rel err", err, "kappa", kappa[e], "bound", bound, flush=True)
+            assert err < bound
+    ctx.close()

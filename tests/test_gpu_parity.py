@@ -151,12 +151,11 @@ def test_jvp_finite_difference(name):
 
 
 @pytest.mark.parametrize("name", ["euler2_n3_lobatto", "euler2_n5", "adv2_ragged", "adv1_upwind", "euler3_n3",
-                                  "burgers2", "burgers1_lobatto"])
+                                  "adv3_n5", "euler3_n4", "burgers2", "burgers1_lobatto"])
 def test_pc_apply(name):
-    """BJ_ext: GPU (explicit S^-1, commuted form) vs oracle (LU, D/E/F/G blocks)."""
+    """BJ_ext: GPU (explicit S^-1, commuted form) vs oracle (LU, D/E/F/G blocks); element
+    blocks of 16..144 unknowns take the register kernel, 216, 320 and 625 the blocked one."""
     case, dg, ctx = setup(name)
-    if ctx.block > 144:
-        pytest.skip("element block above 144 unknowns")
     w = state(dg)
     a1dt, bc = 0.1, 0.1 ** 2 / 2
     pc = BJExt(dg, w, a1dt, bc)

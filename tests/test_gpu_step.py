@@ -87,6 +87,25 @@ def test_burgers_br1_step(precision, rtol, tol):
     assert rel(host(wg), ref) < tol
 
 
+@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-12, 1e-10), ("mixed", 1e-8, 1e-8)])
+def test_euler3_taylor_green_step(precision, rtol, tol):
+    """3-D eps-scaled Euler (eps = 0.1) Taylor-Green vortex, 2x2x2 elements, N = 3 (element
+    blocks of 320 unknowns: the blocked BJ_ext inversion), HBPC(6,1), dt = 0.1 (acoustic
+    CFL about 1.5 on the node spacing)."""
+    case = dict(CASES["euler3_n3"])
+    case.update(nelem=[2, 2, 2])
+    dg = oracle_for(case)
+    X = dg.node_coords()
+    w0 = inputs.taylor_green(X[0] + 0.1234, X[1] + 0.2345, X[2] + 0.3456, eps=0.1)
+    ctx = ctx_for(case, q=6, kmax=1, newton_rtol=rtol, gmres_rtol=1e-5, precision=precision)
+    sol = StageSolver(dg, newton_rtol=rtol, gmres_rtol=1e-5)
+    wg = dev(w0)
+    stats = ctx.step(wg, 0.1)
+    print(precision, stats, flush=True)
+    ref = dg_hbpc_step(dg, w0, 0.1, 6, 1, sol)
+    assert rel(host(wg), ref) < tol
+
+
 def test_constant_state_is_unchanged():
     case = dict(CASES["euler2_n5"])
     dg = oracle_for(case)
