@@ -12,7 +12,10 @@ Newton tolerance 1e-8, FGMRES(30) with eps_G = 1e-3.  Three forms are timed:
            fallback), trained before timing on Newton pairs of FP64 solves of
            seeded vortices on the same mesh.
 A step is one full HBPC step (all stage solves) on the state resident in HBM;
-inputs are synthetic.
+inputs are synthetic.  Other workloads (--workload): a 32 x 32 vortex, 2-D
+viscous Burgers 64 x 64 N = 4, and the 3-D eps-scaled Euler Taylor-Green
+vortex (eps = 0.1) with N = 3 on 48^3 or 16^3 elements at an acoustic CFL of
+about 20 (fp64 and mixed forms).
 
 Prints ONE JSON line: value = DOF-steps/s of the headline form (learned, as
 the metric names it), the other forms beside it, the roofline of the dominant
@@ -34,6 +37,7 @@ sys.path.insert(0, ROOT)
 METRIC = "HBPC DOF-steps/s at 1e-8 Newton tol, learned+FP32 vs plain FP64; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 
 WORKLOADS = {
     "euler_vortex_128x128_N5": dict(dim=2, nelem=[128, 128], length=[10.0, 10.0], N=5, dt=0.1),
@@ -42,14 +46,23 @@ WORKLOADS = {
     # viscous Burgers with BR1: u0 = 0.5 + 0.25 sin(x+y) + seeded noise, nu = 0.01, LF lambda = 1
     "burgers_64x64_N4": dict(dim=2, nelem=[64, 64], length=[2 * 3.141592653589793] * 2, N=4, dt=0.1,
                              equation="burgers"),
+    # 3-D eps-scaled Euler (eps = 0.1, Mach 0.1) Taylor-Green vortex, N = 3 (blocks of 320 unknowns),
+    # dt at an acoustic CFL of about 20: dt (|v| + c/eps) (N+1) / h with c/eps ~ 10, |v| <= 1
+    "euler_tgv_48x48x48_N3": dict(dim=3, nelem=[48, 48, 48], length=[2 * 3.141592653589793] * 3, N=3,
+                                  dt=0.06, equation="euler", field="tgv", eps_ref=0.1),
+    # the same CFL on a 16^3 mesh (quick check of iteration counts)
+    "euler_tgv_16x16x16_N3": dict(dim=3, nelem=[16, 16, 16], length=[2 * 3.141592653589793] * 3, N=3,
+                                  dt=0.18, equation="euler", field="tgv", eps_ref=0.1),
 }
 
 
-def vortex_state(ctx, wl):
+def initial_state(ctx, wl):
     import numpy as np
     from paper_2109_04804_amd import inputs
     xi, _ = ctx.nodes()
-    X = inputs.node_coords(2, wl["nelem"], wl["length"], [0.0, 0.0], xi)
+    X = inputs.node_coords(wl["dim"], wl["nelem"], wl["length"], [0.0] * wl["dim"], xi)
+    if wl.get("field") == "tgv":
+        return inputs.taylor_green(X[0], X[1], X[2], gamma=1.4, eps=wl["eps_ref"])
     if wl.get("equation") == "burgers":
         return inputs.burgers(X[0], X[1], seed=inputs.DEFAULT_SEED)
     xc, yc, beta = inputs.vortex_params(inputs.DEFAULT_SEED, beta=5.0)
@@ -59,7 +72,7 @@ def vortex_state(ctx, wl):
 def _eqkw(wl):
     if wl.get("equation") == "burgers":
         return dict(flux="lf", nu=0.01, **{"lambda": 1.0})
-    return dict(flux="rusanov", gamma=1.4, eps_ref=1.0)
+    return dict(flux="rusanov", gamma=1.4, eps_ref=wl.get("eps_ref", 1.0))
 
 
 def train_learned(wl, samples=20480, per_correction=512, seeds=(1, 2), epochs=20):
@@ -120,7 +133,7 @@ def run_form(wl, form, steps, warmup, theta=None):
                   precision=precision, pc_fallback=0.5, **_eqkw(wl))
     if pc == "learned":
         ctx.mlp_set_params(theta)
-    w0 = vortex_state(ctx, wl)
+    w0 = initial_state(ctx, wl)
     w = torch.tensor(np.ascontiguousarray(w0).reshape(-1), dtype=torch.float64, device="cuda")
     # the last warm-up step records every launch (kernel breakdown, choice of the dominant kernel);
     # the timed steps record only the dominant kernel's launches, so that events around every other
@@ -174,17 +187,18 @@ def dominant_class(prof):
     return max(cand.items(), key=lambda kv: kv[1]["total_ms"])[0]
 
 
-def roofline_of(prof, workload):
+def roofline_of(prof, workload, form):
     """The dominant kernel's launches in the timed steps (prof: per class);
-    HBM-bound kernels against 8 TB/s, the BJ_ext inversion against the FP64
-    vector peak."""
+    HBM-bound kernels against 8 TB/s, the BJ_ext inversion against the vector
+    peak of its arithmetic (FP64 in the fp64 form, FP32 otherwise)."""
     name = dominant_class(prof)
     k = prof[name]
     per_launch_ms = k["total_ms"] / k["launches"]
     if name == "bj_invert":
+        peak = FP64_PEAK_TFLOPS if form == "fp64" else FP32_PEAK_TFLOPS
         ach = k["flops"] / k["launches"] / (per_launch_ms * 1e-3) / 1e12
-        return {"kernel": name, "bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
+        return {"kernel": name, "bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                "frac": ach / peak, "traffic": None,
                 "avg_launch_ms": per_launch_ms, "launches": k["launches"]}
     ach = k["bytes"] / k["launches"] / (per_launch_ms * 1e-3) / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -273,8 +287,8 @@ def main():
         print("[bench] reference copy of %d bytes done" % a.copy_bytes, file=sys.stderr, flush=True)
     wl = WORKLOADS[a.workload]
     forms = [f for f in a.forms.split(",") if f]
-    if wl.get("equation") == "burgers":
-        forms = [f for f in forms if f != "learned"]   # the network is trained on Euler vortices
+    if wl.get("equation") == "burgers" or wl.get("field") == "tgv":
+        forms = [f for f in forms if f != "learned"]   # the network is trained on 2-D Euler vortices
     res = {}
     theta, train_report = None, None
     if "learned" in forms:
@@ -306,7 +320,7 @@ def main():
                       "newton_its": r["newton_its"], "gmres_its": r["gmres_its"], "pc_fallbacks": r["pc_fallbacks"],
                       "n_solves": r["n_solves"], "finite": r["finite"]}
                   for f, r in res.items()},
-        "roofline": roofline_of(h["timed_kernels"], a.workload),
+        "roofline": roofline_of(h["timed_kernels"], a.workload, head),
         "kernels_from": "last warm-up step, events around every launch",
         "kernels": {f: {k: {"launches": v["launches"], "total_ms": round(v["total_ms"], 3),
                             "GBps": (v["bytes"] / (v["total_ms"] * 1e-3) / 1e9) if v["total_ms"] > 0 else None}
