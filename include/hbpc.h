@@ -100,7 +100,10 @@ typedef struct {
     double newton_atol_dw;/* ... or when ||dw^r||_2 / sqrt(ndof) <= this (default 1.95e-15):
                              the paper's absolute Newton tolerance ||dw||_2 <= 1e-12 (Sec. 5.1,
                              for 262,144 coefficients) taken per coefficient, so that it stays
-                             above the round-off floor at every problem size */
+                             above the round-off floor at every problem size; ... or, from the
+                             second iteration on, when ||G(X^r)|| > 0.5 ||G(X^(r-1))|| and
+                             ||dw^r||_2 <= 1e-12 ||w^0||_2 (the residual has reached the rounding
+                             floor of its FP64 evaluation; counted in newton_floor_stops) */
     int newton_maxit;     /* default 30 */
     double gmres_rtol;    /* eps_G: stop when ||r_j|| <= eps_G ||r_0|| */
     int gmres_restart;    /* m of GMRES(m), <= 64 */
@@ -130,6 +133,7 @@ typedef struct {
     double t_pc_build_ms, t_gmres_ms, t_residual_ms;  /* phase times (host clock, synchronised) */
     int pc_fallbacks;                           /* stage solves where BJ_ext replaced the learned PC */
     int mlp_samples;                            /* training samples collected during the step */
+    int newton_floor_stops;                     /* Newton solves ended by the rounding-floor test */
 } hbpc_stats;
 
 /* Fill *p with the defaults: Gauss nodes, Rusanov flux, gamma 1.4, eps 1,

@@ -4,7 +4,11 @@ the BJ_ext preconditioner and a dense direct solve (Secs. 3.2.1-3.2.3, 4.2).
 Stopping rules (the paper states relative tolerances without a norm; this
 reading uses the Euclidean norm over all coefficients of X = (w, sigma)):
   * Newton stops after iteration r when ||G(X^r)|| <= eps_N ||G(X^0)|| or
-    ||dw^r||_2 / sqrt(ndof) <= atol_dw.  The paper adds the absolute criterion
+    ||dw^r||_2 / sqrt(ndof) <= atol_dw, or (r >= 2) when the residual has
+    reached the rounding floor of its FP64 evaluation: ||G(X^r)|| >
+    0.5 ||G(X^(r-1))|| with ||dw^r||_2 <= 1e-12 ||w^0||_2 (a corrector stage
+    started from an accurate prediction can have eps_N ||G(X^0)|| below that
+    floor; the step is then at the state's rounding level).  The paper adds the absolute criterion
     ||dw||_2 <= 1e-12 (Sec. 5.1) because corrector solves start so close to the
     solution that round-off stalls the relative one; it is read per
     coefficient here (1e-12 over the paper's 262,144 coefficients gives
@@ -222,6 +226,9 @@ class StageSolver:
         if n0 <= 1e-14 * np.sqrt(2 * n):
             self.log.append(stats)
             return w
+        nw0 = np.linalg.norm(w)
+        nr_prev = n0
+        stats["floor_stop"] = False
         pc = None
         if self.linear == "gmres" and self.precond == "bjext":
             pc = BJExt(dg, w, a1dt, bcoef)                 # once per Newton solve, at X^0
@@ -238,10 +245,16 @@ class StageSolver:
             sigma = sigma + dX[n:].reshape(shape)
             Gr = G(w, sigma)
             stats["newton"] = it
-            if (np.linalg.norm(Gr) <= self.newton_rtol * n0
-                    or np.linalg.norm(dX[:n]) / np.sqrt(n) <= self.newton_atol_dw):
+            nr = np.linalg.norm(Gr)
+            ndw = np.linalg.norm(dX[:n])
+            if nr <= self.newton_rtol * n0 or ndw / np.sqrt(n) <= self.newton_atol_dw:
                 self.log.append(stats)
                 return w
+            if it >= 2 and nr > 0.5 * nr_prev and ndw <= 1e-12 * nw0:
+                stats["floor_stop"] = True
+                self.log.append(stats)
+                return w
+            nr_prev = nr
         raise NewtonError("Newton did not converge in %d iterations" % self.newton_maxit)
 
 

@@ -227,6 +227,69 @@ template <typename T> __host__ __device__ inline BigLds<T> big_lds(int NE, int p
     return L;
 }
 
+// argmax over the 64 lanes of a wave: largest value, smallest index on ties
+template <typename T> __device__ __forceinline__ void wave_argmax(T& best, int& bi) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const T ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+        }
+    }
+}
+
+// rows rb .. rb+3 of one column (zeros outside the block); v4: NE % 4 == 0, so the four values
+// are in range together and 16-byte aligned
+template <typename T>
+__device__ __forceinline__ void load_rows4(const T* col, int rb, int NE, bool colok, bool v4, T* out) {
+    if (!colok || rb >= NE) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[i] = T(0);
+    } else if (v4) {
+        if constexpr (sizeof(T) == 4) {
+            const float4 v = *reinterpret_cast<const float4*>(col + rb);
+            out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+        } else {
+            const double2 v0 = *reinterpret_cast<const double2*>(col + rb);
+            const double2 v1 = *reinterpret_cast<const double2*>(col + rb + 2);
+            out[0] = v0.x; out[1] = v0.y; out[2] = v1.x; out[3] = v1.y;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[i] = rb + i < NE ? col[rb + i] : T(0);
+    }
+}
+
+template <typename T> __device__ __forceinline__ void store_rows4(T* col, int rb, int NE, bool v4, const T* v) {
+    if (rb >= NE) return;
+    if (v4) {
+        if constexpr (sizeof(T) == 4) {
+            *reinterpret_cast<float4*>(col + rb) = make_float4(v[0], v[1], v[2], v[3]);
+        } else {
+            *reinterpret_cast<double2*>(col + rb) = make_double2(v[0], v[1]);
+            *reinterpret_cast<double2*>(col + rb + 2) = make_double2(v[2], v[3]);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (rb + i < NE) col[rb + i] = v[i];
+    }
+}
+
+// four consecutive LDS values at a 4-aligned offset of a 16-byte aligned array
+template <typename T> __device__ __forceinline__ void lds_rows4(const T* p, T* out) {
+    if constexpr (sizeof(T) == 4) {
+        const float4 v = *reinterpret_cast<const float4*>(p);
+        out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+    } else {
+        const double2 v0 = *reinterpret_cast<const double2*>(p);
+        const double2 v1 = *reinterpret_cast<const double2*>(p + 2);
+        out[0] = v0.x; out[1] = v0.y; out[2] = v1.x; out[3] = v1.y;
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* __restrict__ KT, T* __restrict__ SinvT,
                                                                    int NE, int pb_max, T a1dt, T bc,
@@ -252,105 +315,103 @@ __global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* __re
     const double* K = KT + e * nn;
     T* A = SinvT + e * nn;
 
-    // ---- S = I - a1dt K + bc K^2 into A
-    for (int r0 = 0; r0 < NE; r0 += BIG_TILE)
-        for (int c0 = 0; c0 < NE; c0 += BIG_TILE) {
-            T acc[4][4];
+    // ---- S = I - a1dt K + bc K^2 into A (K staged through LDS in slabs of 16, the next slab's
+    // loads issued before the current slab's products)
+    {
+        const int xa = tid % BIG_TILE, ta = tid / BIG_TILE;   // sA: t = ta + 4 q, x = xa
+        const int yb = tid / BIG_KC, tb = tid % BIG_KC;       // sB: y = yb + 16 q, t = tb
+        for (int r0 = 0; r0 < NE; r0 += BIG_TILE)
+            for (int c0 = 0; c0 < NE; c0 += BIG_TILE) {
+                T acc[4][4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) acc[i][b] = T(0);
-            for (int kk = 0; kk < NE; kk += BIG_KC) {
-                for (int i = tid; i < BIG_KC * BIG_TILE; i += BIG_THREADS) {
-                    const int t = i / BIG_TILE, x = i % BIG_TILE;   // consecutive threads: consecutive rows
-                    const int k = kk + t, r = r0 + x;
-                    sA[t * BIG_TILE + x] = (k < NE && r < NE) ? (T)K[(size_t)k * NE + r] : T(0);   // K[r][k]
-                }
-                for (int i = tid; i < BIG_KC * BIG_TILE; i += BIG_THREADS) {
-                    const int y = i / BIG_KC, t = i % BIG_KC;       // consecutive threads: consecutive k
-                    const int k = kk + t, cc = c0 + y;
-                    sB[t * (BIG_TILE + 1) + y] = (k < NE && cc < NE) ? (T)K[(size_t)cc * NE + k] : T(0);   // K[k][c]
-                }
-                __syncthreads();
+                    for (int b = 0; b < 4; ++b) acc[i][b] = T(0);
+                double ga[4], gb[4];
+                auto fetch = [&](int kk) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int k = kk + ta + 4 * q, r = r0 + xa;
+                        ga[q] = (k < NE && r < NE) ? K[(size_t)k * NE + r] : 0.0;       // K[r][k]
+                        const int k2 = kk + tb, cc = c0 + yb + 16 * q;
+                        gb[q] = (k2 < NE && cc < NE) ? K[(size_t)cc * NE + k2] : 0.0;   // K[k][c]
+                    }
+                };
+                fetch(0);
+                for (int kk = 0; kk < NE; kk += BIG_KC) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        sA[(ta + 4 * q) * BIG_TILE + xa] = (T)ga[q];
+                        sB[tb * (BIG_TILE + 1) + yb + 16 * q] = (T)gb[q];
+                    }
+                    __syncthreads();
+                    if (kk + BIG_KC < NE) fetch(kk + BIG_KC);
 #pragma unroll 4
-                for (int t = 0; t < BIG_KC; ++t) {
-                    T ra[4], cb[4];
+                    for (int t = 0; t < BIG_KC; ++t) {
+                        T ra[4], cb[4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) ra[i] = sA[t * BIG_TILE + 4 * tr + i];
+                        for (int i = 0; i < 4; ++i) ra[i] = sA[t * BIG_TILE + 4 * tr + i];
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) cb[b] = sB[t * (BIG_TILE + 1) + tc + 16 * b];
+                        for (int b = 0; b < 4; ++b) cb[b] = sB[t * (BIG_TILE + 1) + tc + 16 * b];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i)
+                        for (int i = 0; i < 4; ++i)
 #pragma unroll
-                        for (int b = 0; b < 4; ++b) acc[i][b] += ra[i] * cb[b];
+                            for (int b = 0; b < 4; ++b) acc[i][b] += ra[i] * cb[b];
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
-            }
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int cc = c0 + tc + 16 * b;
-                if (cc >= NE) continue;
+                for (int b = 0; b < 4; ++b) {
+                    const int cc = c0 + tc + 16 * b;
+                    if (cc >= NE) continue;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = r0 + 4 * tr + i;
-                    if (r >= NE) continue;
-                    T v = (r == cc) ? T(1) : T(0);
-                    v += -a1dt * (T)K[(size_t)cc * NE + r] + bc * acc[i][b];
-                    A[(size_t)cc * NE + r] = v;
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = r0 + 4 * tr + i;
+                        if (r >= NE) continue;
+                        T v = (r == cc) ? T(1) : T(0);
+                        v += -a1dt * (T)K[(size_t)cc * NE + r] + bc * acc[i][b];
+                        A[(size_t)cc * NE + r] = v;
+                    }
                 }
             }
-        }
+    }
     for (int r = tid; r < NE; r += BIG_THREADS) s_pinv[r] = -1;
     __syncthreads();
 
+    const bool v4 = (NE % 4) == 0;   // 4 consecutive rows of a column: one aligned 4-value access
     // ---- panels
     for (int k0 = 0; k0 < NE; k0 += pb_max) {
         const int pb = NE - k0 < pb_max ? NE - k0 : pb_max;
-        for (int i = tid; i < pb * NE; i += BIG_THREADS) {
-            const int j = i / NE, r = i % NE;
-            sP[j * nep + r] = A[(size_t)(k0 + j) * NE + r];
+        // this thread's entries (jj, r) of the panel: tid, tid + 256, ... in column-major order
+        const int jj0 = tid / NE, rr0 = tid % NE;
+        for (int jj = jj0, r = rr0; jj < pb;) {
+            sP[jj * nep + r] = A[(size_t)(k0 + jj) * NE + r];
+            r += BIG_THREADS;
+            while (r >= NE) { r -= NE; ++jj; }
         }
         __syncthreads();
-        for (int j = 0; j < pb; ++j) {
-            const int k = k0 + j;
-            // pivot: largest |entry| of panel column j over rows not yet pivot (NaN never wins)
+        {   // pivot candidates of the panel's first column
             T best = T(-1);
             int bi = NE;
             for (int r = tid; r < NE; r += BIG_THREADS) {
                 if (s_pinv[r] >= 0) continue;
-                T v = sP[j * nep + r];
+                T v = sP[r];
                 v = v >= T(0) ? v : -v;
-                if (v > best) {
-                    best = v;
-                    bi = r;
-                }
+                if (v > best) { best = v; bi = r; }
             }
+            wave_argmax(best, bi);
+            if ((tid & 63) == 0) { s_red[tid >> 6] = best; s_ired[tid >> 6] = bi; }
+            __syncthreads();
+        }
+        for (int j = 0; j < pb; ++j) {
+            const int k = k0 + j;
+            // pivot: largest |entry| of panel column j over rows not yet pivot (NaN never wins;
+            // smallest row on ties)
+            T b0 = s_red[0];
+            int p = s_ired[0];
 #pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const T ob = __shfl_xor(best, off, 64);
-                const int oi = __shfl_xor(bi, off, 64);
-                if (ob > best || (ob == best && oi < bi)) {
-                    best = ob;
-                    bi = oi;
-                }
-            }
-            if ((tid & 63) == 0) {
-                s_red[tid >> 6] = best;
-                s_ired[tid >> 6] = bi;
-            }
-            __syncthreads();
-            if (tid == 0) {
-                T b0 = s_red[0];
-                int i0 = s_ired[0];
-                for (int w = 1; w < BIG_THREADS / 64; ++w)
-                    if (s_red[w] > b0 || (s_red[w] == b0 && s_ired[w] < i0)) {
-                        b0 = s_red[w];
-                        i0 = s_ired[w];
-                    }
-                s_ired[4] = i0;
-            }
-            __syncthreads();
-            const int p = s_ired[4];
+            for (int w = 1; w < BIG_THREADS / 64; ++w)
+                if (s_red[w] > b0 || (s_red[w] == b0 && s_ired[w] < p)) { b0 = s_red[w]; p = s_ired[w]; }
             if (p >= NE) {                 // no finite pivot left: flag, stop
                 if (tid == 0) atomicOr(status, 1);
                 return;
@@ -365,8 +426,11 @@ __global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* __re
             const T piv = s_col[p];
             const T ipiv = T(1) / piv;
             if (tid == 0 && (!(piv == piv) || piv == T(0))) atomicOr(status, 1);
-            for (int i = tid; i < pb * NE; i += BIG_THREADS) {
-                const int jj = i / NE, r = i % NE;
+            // exchange step on the panel, and the pivot candidates of column j + 1 (row p excluded:
+            // its pivot mark is being written)
+            T best = T(-1);
+            int bi = NE;
+            for (int jj = jj0, r = rr0; jj < pb;) {
                 T v;
                 if (jj == j) {
                     v = (r == p) ? ipiv : -s_col[r] * ipiv;
@@ -375,7 +439,15 @@ __global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* __re
                     v = (r == p) ? prv : sP[jj * nep + r] - s_col[r] * prv;
                 }
                 sP[jj * nep + r] = v;
+                if (jj == j + 1 && r != p && s_pinv[r] < 0) {
+                    const T av = v >= T(0) ? v : -v;
+                    if (av > best || (av == best && r < bi)) { best = av; bi = r; }
+                }
+                r += BIG_THREADS;
+                while (r >= NE) { r -= NE; ++jj; }
             }
+            wave_argmax(best, bi);
+            if ((tid & 63) == 0) { s_red[tid >> 6] = best; s_ired[tid >> 6] = bi; }
             __syncthreads();
         }
         // block exchange on the columns outside the panel
@@ -387,45 +459,49 @@ __global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* __re
             }
             __syncthreads();
             for (int r0 = 0; r0 < NE; r0 += BIG_TILE) {
-                T acc[4][4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) acc[i][b] = T(0);
                 const int rb = r0 + 4 * tr;
+                T base[4][4], acc[4][4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int cc = c0 + tc + 16 * b;
+                    load_rows4(A + (size_t)cc * NE, rb, NE, cc < NE, v4, base[b]);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) acc[b][i] = T(0);
+                }
                 if (rb < nep) {
                     for (int j = 0; j < pb; ++j) {
                         T ra[4], cb[4];
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) ra[i] = sP[j * nep + rb + i];
+                        lds_rows4(sP + j * nep + rb, ra);
 #pragma unroll
                         for (int b = 0; b < 4; ++b) cb[b] = sU[j * BIG_TILE + tc + 16 * b];
 #pragma unroll
-                        for (int i = 0; i < 4; ++i)
+                        for (int b = 0; b < 4; ++b)
 #pragma unroll
-                            for (int b = 0; b < 4; ++b) acc[i][b] += ra[i] * cb[b];
+                            for (int i = 0; i < 4; ++i) acc[b][i] += ra[i] * cb[b];
                     }
+                }
+                bool inp[4];   // pivot rows of this panel: B^-1 U replaces the row
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int q = rb + i < NE ? s_pinv[rb + i] : -1;
+                    inp[i] = q >= k0 && q < k0 + pb;
                 }
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     const int cc = c0 + tc + 16 * b;
                     if (cc >= NE || (cc >= k0 && cc < k0 + pb)) continue;
+                    T out[4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int r = rb + i;
-                        if (r >= NE) continue;
-                        const int q = s_pinv[r];
-                        const bool inp = q >= k0 && q < k0 + pb;
-                        T* dst = A + (size_t)cc * NE + r;
-                        *dst = inp ? acc[i][b] : *dst + acc[i][b];
-                    }
+                    for (int i = 0; i < 4; ++i) out[i] = inp[i] ? acc[b][i] : base[b][i] + acc[b][i];
+                    store_rows4(A + (size_t)cc * NE, rb, NE, v4, out);
                 }
             }
             __syncthreads();
         }
-        for (int i = tid; i < pb * NE; i += BIG_THREADS) {
-            const int j = i / NE, r = i % NE;
-            A[(size_t)(k0 + j) * NE + r] = sP[j * nep + r];
+        for (int jj = jj0, r = rr0; jj < pb;) {
+            A[(size_t)(k0 + jj) * NE + r] = sP[jj * nep + r];
+            r += BIG_THREADS;
+            while (r >= NE) { r -= NE; ++jj; }
         }
         __syncthreads();
     }

@@ -873,6 +873,8 @@ static void newton_solve(hbpc_ctx* c, const double* b, double a1dt, double bc, c
     op_res(c, X, b, a1dt, bc, c->G);
     const double n0 = dnorm(c, c->G, c->n2, 0);
     if (!std::isfinite(n0)) set_err(c, HBPC_ERR_NONFINITE, "non-finite residual at the Newton initial guess");
+    const double nw0 = dnorm(c, X, n, 0);   // ||w^0||, scale of the rounding-floor test
+    double nr_prev = n0;
     int its = 0, gits = 0;
     const int sidx = c->cur_solve;
     if (n0 > 1e-14 * std::sqrt((double)c->n2)) {
@@ -906,6 +908,12 @@ static void newton_solve(hbpc_ctx* c, const double* b, double a1dt, double bc, c
             if (!std::isfinite(nr)) set_err(c, HBPC_ERR_NONFINITE, "non-finite Newton residual");
             // absolute criterion per coefficient (RMS of dw), see hbpc_params.newton_atol_dw
             if (nr <= c->prm.newton_rtol * n0 || ndw <= c->prm.newton_atol_dw * std::sqrt((double)n)) break;
+            // rounding floor: the residual stopped falling and the update is at the state's rounding level
+            if (its >= 2 && nr > 0.5 * nr_prev && ndw <= 1e-12 * nw0) {
+                c->st.newton_floor_stops++;
+                break;
+            }
+            nr_prev = nr;
             if (its >= c->prm.newton_maxit)
                 set_err(c, HBPC_ERR_NEWTON,
                         "Newton did not converge within " + std::to_string(c->prm.newton_maxit) + " iterations");

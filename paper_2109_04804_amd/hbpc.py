@@ -49,7 +49,8 @@ class HbpcStats(ctypes.Structure):
                 ("pc_builds", ctypes.c_int), ("newton_per_solve", ctypes.c_int * MAX_SOLVES),
                 ("gmres_per_solve", ctypes.c_int * MAX_SOLVES), ("t_step_ms", ctypes.c_double),
                 ("t_pc_build_ms", ctypes.c_double), ("t_gmres_ms", ctypes.c_double),
-                ("t_residual_ms", ctypes.c_double), ("pc_fallbacks", ctypes.c_int), ("mlp_samples", ctypes.c_int)]
+                ("t_residual_ms", ctypes.c_double), ("pc_fallbacks", ctypes.c_int), ("mlp_samples", ctypes.c_int),
+                ("newton_floor_stops", ctypes.c_int)]
 
     def as_dict(self):
         n = min(self.n_solves, MAX_SOLVES)
@@ -57,7 +58,8 @@ class HbpcStats(ctypes.Structure):
                 "pc_builds": self.pc_builds, "newton_per_solve": list(self.newton_per_solve[:n]),
                 "gmres_per_solve": list(self.gmres_per_solve[:n]), "t_step_ms": self.t_step_ms,
                 "t_pc_build_ms": self.t_pc_build_ms, "t_gmres_ms": self.t_gmres_ms,
-                "pc_fallbacks": self.pc_fallbacks, "mlp_samples": self.mlp_samples}
+                "pc_fallbacks": self.pc_fallbacks, "mlp_samples": self.mlp_samples,
+                "newton_floor_stops": self.newton_floor_stops}
 
 
 class HbpcKernelProf(ctypes.Structure):

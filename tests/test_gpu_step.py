@@ -106,6 +106,25 @@ def test_euler3_taylor_green_step(precision, rtol, tol):
     assert rel(host(wg), ref) < tol
 
 
+def test_newton_rounding_floor_stop():
+    """2-D Euler vortex, 4x4 elements, N = 3, HBPC(6,2), dt = 0.1, FP64, with an
+    unreachable relative Newton tolerance (1e-30) and no absolute one: every solve ends
+    by the rounding-floor test, at the oracle's root (eps_N = 1e-12) to <= 1e-10."""
+    case = dict(CASES["euler2_n3_lobatto"])
+    case.update(nelem=[4, 4], nodes="gauss")
+    dg = oracle_for(case)
+    X = dg.node_coords()
+    w0 = inputs.isentropic_vortex(X[0], X[1], 4.6, 5.3, 3.0)
+    ctx = ctx_for(case, q=6, kmax=2, newton_rtol=1e-30, newton_atol_dw=0.0, gmres_rtol=1e-5, precision="fp64")
+    wg = dev(w0)
+    stats = ctx.step(wg, 0.1)
+    print(stats, flush=True)
+    assert stats["newton_floor_stops"] == stats["n_solves"]
+    assert max(stats["newton_per_solve"]) < 15
+    ref = dg_hbpc_step(dg, w0, 0.1, 6, 2, StageSolver(dg, newton_rtol=1e-12, gmres_rtol=1e-5))
+    assert rel(host(wg), ref) < 1e-10
+
+
 def test_constant_state_is_unchanged():
     case = dict(CASES["euler2_n5"])
     dg = oracle_for(case)

@@ -113,6 +113,24 @@ def test_dense_newton_equals_gmres_newton():
     assert np.linalg.norm(g) < 1e-10 * np.linalg.norm(b)
 
 
+def test_newton_stops_at_rounding_floor():
+    """With an unreachable relative tolerance and no absolute one, Newton still ends, by
+    the rounding-floor test (residual stalled, update at the state's rounding level),
+    within a few iterations, at the root of a tightly converged dense-LU solve."""
+    dg, w = tiny_euler(N=1)
+    b = w + 0.05 * dg.r1(w)
+    a1dt, bc = 0.25 * 0.2, 0.2 ** 2 / 48
+    ref = StageSolver(dg, newton_rtol=1e-13, linear="dense").solve(b, a1dt, bc, w)
+    s = StageSolver(dg, newton_rtol=1e-30, newton_atol_dw=0.0, linear="dense")
+    W = s.solve(b, a1dt, bc, w)
+    assert s.log[-1]["floor_stop"] and 2 <= s.log[-1]["newton"] < 10
+    assert np.linalg.norm(W - ref) < 1e-13 * np.linalg.norm(ref)
+    # a tolerance that is reached ends the solve before the floor
+    s2 = StageSolver(dg, newton_rtol=1e-6, linear="dense")
+    s2.solve(b, a1dt, bc, w)
+    assert not s2.log[-1]["floor_stop"]
+
+
 def test_fd_jvp_within_fd_error_bound():
     """Eq. MatrixFree_nonlinear agrees with the exact JVP to O(sqrt(eps_mach))."""
     dg, w = tiny_euler()
