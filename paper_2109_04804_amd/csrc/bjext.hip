@@ -205,7 +205,7 @@ constexpr int BIG_KC = 16;
 
 template <typename T> struct BigLds {
     int nep, pb;                 // padded row pitch of a panel column, panel width
-    size_t off_u, off_col, off_row, off_red, off_ired, off_prow, off_pinv, bytes;
+    size_t off_u, off_col, off_row, off_ired, off_prow, off_pinv, bytes;
 };
 
 template <typename T> __host__ __device__ inline BigLds<T> big_lds(int NE, int pb) {
@@ -219,7 +219,6 @@ template <typename T> __host__ __device__ inline BigLds<T> big_lds(int NE, int p
     L.off_u = off;    off += (size_t)pb * BIG_TILE * sizeof(T);
     L.off_col = off;  off += (size_t)L.nep * sizeof(T);
     L.off_row = off;  off += (size_t)pb * sizeof(T);
-    L.off_red = off;  off += 4 * sizeof(T);
     L.off_ired = off; off += 8 * sizeof(int);
     L.off_prow = off; off += (size_t)NE * sizeof(int);
     L.off_pinv = off; off += (size_t)NE * sizeof(int);
@@ -290,12 +289,11 @@ template <typename T> __device__ __forceinline__ void lds_rows4(const T* p, T* o
     }
 }
 
-template <typename T>
+template <typename T, int RR, int PB>
 __global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* __restrict__ KT, T* __restrict__ SinvT,
-                                                                   int NE, int pb_max, T a1dt, T bc,
-                                                                   int* __restrict__ status) {
+                                                                   int NE, T a1dt, T bc, int* __restrict__ status) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const BigLds<T> L = big_lds<T>(NE, pb_max);
+    const BigLds<T> L = big_lds<T>(NE, PB);
     const int nep = L.nep;
     T* sP = reinterpret_cast<T*>(smem_raw);                      // panel: sP[j * nep + r]
     T* sA = sP;                                                  // K^2 staging: sA[t * 64 + x]
@@ -303,7 +301,6 @@ __global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* __re
     T* sU = reinterpret_cast<T*>(smem_raw + L.off_u);            // sU[j * 64 + y]
     T* s_col = reinterpret_cast<T*>(smem_raw + L.off_col);
     T* s_row = reinterpret_cast<T*>(smem_raw + L.off_row);
-    T* s_red = reinterpret_cast<T*>(smem_raw + L.off_red);
     int* s_ired = reinterpret_cast<int*>(smem_raw + L.off_ired);
     int* s_prow = reinterpret_cast<int*>(smem_raw + L.off_prow); // pivot row of step k
     int* s_pinv = reinterpret_cast<int*>(smem_raw + L.off_pinv); // step at which row r was pivot, or -1
@@ -379,77 +376,111 @@ __global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* __re
     __syncthreads();
 
     const bool v4 = (NE % 4) == 0;   // 4 consecutive rows of a column: one aligned 4-value access
-    // ---- panels
-    for (int k0 = 0; k0 < NE; k0 += pb_max) {
-        const int pb = NE - k0 < pb_max ? NE - k0 : pb_max;
-        // this thread's entries (jj, r) of the panel: tid, tid + 256, ... in column-major order
-        const int jj0 = tid / NE, rr0 = tid % NE;
-        for (int jj = jj0, r = rr0; jj < pb;) {
-            sP[jj * nep + r] = A[(size_t)(k0 + jj) * NE + r];
-            r += BIG_THREADS;
-            while (r >= NE) { r -= NE; ++jj; }
-        }
-        __syncthreads();
-        {   // pivot candidates of the panel's first column
-            T best = T(-1);
-            int bi = NE;
-            for (int r = tid; r < NE; r += BIG_THREADS) {
-                if (s_pinv[r] >= 0) continue;
-                T v = sP[r];
-                v = v >= T(0) ? v : -v;
-                if (v > best) { best = v; bi = r; }
+    // ---- panels.  Panel phase in registers: lane pr of wave pc owns rows pr + 64 a (a < RR) and
+    // panel columns pc + 4 b (b < RC), so one wave holds whole columns and finds a pivot alone.
+    constexpr int RC = PB / 4;
+    const int pr = tid & 63, pc = tid >> 6;
+    unsigned used = 0u;   // bit a: owned row pr + 64 a has been a pivot row (any panel)
+    for (int k0 = 0; k0 < NE; k0 += PB) {
+        const int pb = NE - k0 < PB ? NE - k0 : PB;
+        T P[RR][RC];
+#pragma unroll
+        for (int b = 0; b < RC; ++b) {
+            const int jj = pc + 4 * b;
+#pragma unroll
+            for (int a = 0; a < RR; ++a) {
+                const int r = pr + 64 * a;
+                P[a][b] = (r < NE && jj < pb) ? A[(size_t)(k0 + jj) * NE + r] : T(0);
             }
-            wave_argmax(best, bi);
-            if ((tid & 63) == 0) { s_red[tid >> 6] = best; s_ired[tid >> 6] = bi; }
-            __syncthreads();
         }
         for (int j = 0; j < pb; ++j) {
             const int k = k0 + j;
-            // pivot: largest |entry| of panel column j over rows not yet pivot (NaN never wins;
-            // smallest row on ties)
-            T b0 = s_red[0];
-            int p = s_ired[0];
+            const int bk = j >> 2;
+            if (pc == (j & 3)) {           // pivot: largest |entry| of column j over rows not yet pivot
+                T best = T(-1);            // (NaN never wins; smallest row on ties)
+                int bi = NE;
 #pragma unroll
-            for (int w = 1; w < BIG_THREADS / 64; ++w)
-                if (s_red[w] > b0 || (s_red[w] == b0 && s_ired[w] < p)) { b0 = s_red[w]; p = s_ired[w]; }
+                for (int a = 0; a < RR; ++a) {
+                    const int r = pr + 64 * a;
+                    T v = T(0);
+#pragma unroll
+                    for (int b = 0; b < RC; ++b) v = (b == bk) ? P[a][b] : v;
+                    v = v >= T(0) ? v : -v;
+                    const bool take = r < NE && !((used >> a) & 1u) && v > best;
+                    best = take ? v : best;
+                    bi = take ? r : bi;
+                }
+                wave_argmax(best, bi);
+                if (pr == 0) s_ired[0] = bi;
+            }
+            __syncthreads();
+            const int p = s_ired[0];
             if (p >= NE) {                 // no finite pivot left: flag, stop
                 if (tid == 0) atomicOr(status, 1);
                 return;
             }
-            for (int r = tid; r < NE; r += BIG_THREADS) s_col[r] = sP[j * nep + r];
-            for (int jj = tid; jj < pb; jj += BIG_THREADS) s_row[jj] = sP[jj * nep + p];
-            __syncthreads();
+            const int ap = p >> 6;
+            if (pr == (p & 63)) {          // owners of row p publish it
+                used |= 1u << ap;
+#pragma unroll
+                for (int b = 0; b < RC; ++b) {
+                    T v = T(0);
+#pragma unroll
+                    for (int a = 0; a < RR; ++a) v = (a == ap) ? P[a][b] : v;
+                    if (pc + 4 * b < pb) s_row[pc + 4 * b] = v;
+                }
+            }
+            if (pc == (j & 3)) {           // owners of column j publish it
+#pragma unroll
+                for (int a = 0; a < RR; ++a) {
+                    const int r = pr + 64 * a;
+                    T v = T(0);
+#pragma unroll
+                    for (int b = 0; b < RC; ++b) v = (b == bk) ? P[a][b] : v;
+                    if (r < NE) s_col[r] = v;
+                }
+            }
             if (tid == 0) {
                 s_prow[k] = p;
                 s_pinv[p] = k;
             }
+            __syncthreads();
             const T piv = s_col[p];
             const T ipiv = T(1) / piv;
             if (tid == 0 && (!(piv == piv) || piv == T(0))) atomicOr(status, 1);
-            // exchange step on the panel, and the pivot candidates of column j + 1 (row p excluded:
-            // its pivot mark is being written)
-            T best = T(-1);
-            int bi = NE;
-            for (int jj = jj0, r = rr0; jj < pb;) {
-                T v;
-                if (jj == j) {
-                    v = (r == p) ? ipiv : -s_col[r] * ipiv;
-                } else {
-                    const T prv = s_row[jj] * ipiv;
-                    v = (r == p) ? prv : sP[jj * nep + r] - s_col[r] * prv;
+            T prv[RC], f[RR];
+#pragma unroll
+            for (int b = 0; b < RC; ++b) prv[b] = pc + 4 * b < pb ? s_row[pc + 4 * b] * ipiv : T(0);
+#pragma unroll
+            for (int a = 0; a < RR; ++a) f[a] = pr + 64 * a < NE ? s_col[pr + 64 * a] : T(0);
+            // exchange step, branch-free: pivot row / pivot column / the rest
+#pragma unroll
+            for (int a = 0; a < RR; ++a) {
+                const bool isp = (pr + 64 * a == p);
+                const T pk = isp ? ipiv : -f[a] * ipiv;
+#pragma unroll
+                for (int b = 0; b < RC; ++b) {
+                    const bool isk = (pc + 4 * b == j);
+                    const T v = isp ? prv[b] : P[a][b] - f[a] * prv[b];
+                    P[a][b] = isk ? pk : v;
                 }
-                sP[jj * nep + r] = v;
-                if (jj == j + 1 && r != p && s_pinv[r] < 0) {
-                    const T av = v >= T(0) ? v : -v;
-                    if (av > best || (av == best && r < bi)) { best = av; bi = r; }
-                }
-                r += BIG_THREADS;
-                while (r >= NE) { r -= NE; ++jj; }
             }
-            wave_argmax(best, bi);
-            if ((tid & 63) == 0) { s_red[tid >> 6] = best; s_ired[tid >> 6] = bi; }
-            __syncthreads();
         }
+        // the eliminated panel: to LDS (the update's left factor) and back to its columns of A
+#pragma unroll
+        for (int b = 0; b < RC; ++b) {
+            const int jj = pc + 4 * b;
+            if (jj >= pb) continue;
+#pragma unroll
+            for (int a = 0; a < RR; ++a) {
+                const int r = pr + 64 * a;
+                if (r < NE) {
+                    sP[jj * nep + r] = P[a][b];
+                    A[(size_t)(k0 + jj) * NE + r] = P[a][b];
+                }
+            }
+        }
+        __syncthreads();
         // block exchange on the columns outside the panel
         for (int c0 = 0; c0 < NE; c0 += BIG_TILE) {
             for (int i = tid; i < pb * BIG_TILE; i += BIG_THREADS) {
@@ -498,12 +529,6 @@ __global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* __re
             }
             __syncthreads();
         }
-        for (int jj = jj0, r = rr0; jj < pb;) {
-            A[(size_t)(k0 + jj) * NE + r] = sP[jj * nep + r];
-            r += BIG_THREADS;
-            while (r >= NE) { r -= NE; ++jj; }
-        }
-        __syncthreads();
     }
     // ---- S^-1[pinv[r]][prow[c]] = A[r][c], stored column-major (SinvT[col][row])
     T* slot = reinterpret_cast<T*>(KT + e * nn);
@@ -525,22 +550,26 @@ static hipError_t launch_inv(const double* KT, TO* SinvT, int NE, int nE, double
     return hipGetLastError();
 }
 
-// panel width for the blocked kernel: the widest of 32, 16, 8 whose LDS fits in 64 KiB (0: none)
-template <typename T> static int big_panel(int NE) {
-    for (int pb = 32; pb >= 8; pb /= 2)
-        if (big_lds<T>(NE, pb).bytes <= 65536) return pb;
-    return 0;
+// blocked kernel configurations: rows per lane RR (NE <= 64 RR) and panel width PB, chosen so that
+// the panel fits in registers and its LDS copy (PB x NE) in 64 KiB
+template <typename T, int RR, int PB>
+static hipError_t launch_big(double* KT, T* SinvT, int NE, int nE, double a1dt, double bc, int* status,
+                             hipStream_t st) {
+    const size_t sh = big_lds<T>(NE, PB).bytes;
+    if (sh > 65536) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((bj_invert_big_kernel<T, RR, PB>), dim3(nE), dim3(BIG_THREADS), sh, st, KT, SinvT, NE,
+                       (T)a1dt, (T)bc, status);
+    return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t launch_inv_big(double* KT, T* SinvT, int NE, int nE, double a1dt, double bc, int* status,
                                  hipStream_t st) {
-    const int pb = big_panel<T>(NE);
-    if (pb == 0) return hipErrorInvalidValue;
-    const size_t sh = big_lds<T>(NE, pb).bytes;
-    hipLaunchKernelGGL(bj_invert_big_kernel<T>, dim3(nE), dim3(BIG_THREADS), sh, st, KT, SinvT, NE, pb, (T)a1dt,
-                       (T)bc, status);
-    return hipGetLastError();
+    constexpr bool F = sizeof(T) == 4;
+    if (NE <= 320) return launch_big<T, 5, F ? 32 : 16>(KT, SinvT, NE, nE, a1dt, bc, status, st);
+    if (NE <= 640) return launch_big<T, 10, F ? 16 : 8>(KT, SinvT, NE, nE, a1dt, bc, status, st);
+    if (NE <= 1024) return launch_big<T, 16, F ? 8 : 4>(KT, SinvT, NE, nE, a1dt, bc, status, st);
+    return hipErrorInvalidValue;
 }
 
 // KT: the chunk's K blocks; for blocks above 144 unknowns they are overwritten (used as scratch)
