@@ -14,8 +14,8 @@ Newton tolerance 1e-8, FGMRES(30) with eps_G = 1e-3.  Three forms are timed:
 A step is one full HBPC step (all stage solves) on the state resident in HBM;
 inputs are synthetic.  Other workloads (--workload): a 32 x 32 vortex, 2-D
 viscous Burgers 64 x 64 N = 4, and the 3-D eps-scaled Euler Taylor-Green
-vortex (eps = 0.1) with N = 3 on 48^3 or 16^3 elements at an acoustic CFL of
-about 4.5 (fp64 and mixed forms).
+vortex (eps = 0.1) with N = 3 on 48^3 (acoustic CFL about 9) or 16^3 (CFL
+about 20) elements (fp64 and mixed forms).
 
 Prints ONE JSON line: value = DOF-steps/s of the headline form (learned, as
 the metric names it), the other forms beside it, the roofline of the dominant
@@ -47,13 +47,13 @@ WORKLOADS = {
     "burgers_64x64_N4": dict(dim=2, nelem=[64, 64], length=[2 * 3.141592653589793] * 2, N=4, dt=0.1,
                              equation="burgers"),
     # 3-D eps-scaled Euler (eps = 0.1, Mach 0.1) Taylor-Green vortex, N = 3 (blocks of 320 unknowns),
-    # dt at an acoustic CFL of about 4.5: dt (|v| + c/eps) (N+1) / h with c/eps ~ 10, |v| <= 1 (Newton
-    # on the stage equations stops converging between CFL 4.5 and 9 on the 16^3 mesh)
+    # dt at an acoustic CFL of about 9: dt (|v| + c/eps) (N+1) / h with c/eps ~ 10, |v| <= 1 (at CFL 20
+    # corrector stages need more than 7000 FGMRES(30) iterations per Newton step with BJ_ext on 48^3)
     "euler_tgv_48x48x48_N3": dict(dim=3, nelem=[48, 48, 48], length=[2 * 3.141592653589793] * 3, N=3,
-                                  dt=0.0134, equation="euler", field="tgv", eps_ref=0.1),
+                                  dt=0.027, equation="euler", field="tgv", eps_ref=0.1),
     # the same CFL on a 16^3 mesh
     "euler_tgv_16x16x16_N3": dict(dim=3, nelem=[16, 16, 16], length=[2 * 3.141592653589793] * 3, N=3,
-                                  dt=0.04, equation="euler", field="tgv", eps_ref=0.1),
+                                  dt=0.18, equation="euler", field="tgv", eps_ref=0.1),
 }
 
 
