@@ -18,6 +18,10 @@ torch = pytest.importorskip("torch")
 
 # 2-D Euler, N = 3 (block 64; network inputs 320 residual + 322 state, width 256, 64 outputs), 5 x 4 elements
 CASE = dict(dim=2, nelem=[5, 4], length=[10.0, 10.0], N=3, equation="euler", nodes="gauss", flux="rusanov")
+# 3-D eps-scaled Euler, N = 3 as in the Taylor-Green workload (block 320; 7-element patches: inputs
+# 2240 residual + 2242 state, 320 outputs), 3 x 2 x 2 elements
+CASE3 = dict(dim=3, nelem=[3, 2, 2], length=[6.283185307179586] * 3, N=3, equation="euler", nodes="gauss",
+             flux="rusanov", eps_ref=0.1)
 
 
 def dev(x, dtype=torch.float64):
@@ -29,11 +33,11 @@ def host(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
-def make_ctx(**over):
+def make_ctx(case=CASE, **over):
     from paper_2109_04804_amd.hbpc import Context
-    kw = {k: v for k, v in CASE.items() if k not in ("dim", "nelem", "length", "N", "equation")}
+    kw = {k: v for k, v in case.items() if k not in ("dim", "nelem", "length", "N", "equation")}
     kw.update(over)
-    return Context(CASE["dim"], CASE["nelem"], CASE["length"], CASE["N"], CASE["equation"], **kw)
+    return Context(case["dim"], case["nelem"], case["length"], case["N"], case["equation"], **kw)
 
 
 def params(ctx, seed=0):
@@ -51,22 +55,23 @@ def test_shape():
     assert n_p == mlp.n_params(n_in, H, n_out)
 
 
-def test_features_match_oracle():
-    dg = oracle_for(CASE)
-    ctx = make_ctx()
+@pytest.mark.parametrize("case", [CASE, CASE3], ids=["euler2", "euler3"])
+def test_features_match_oracle(case):
+    dg = oracle_for(case)
+    ctx = make_ctx(case)
     nE = dg.mesh.n_elem
     rng = np.random.default_rng(3)
     w = state(dg)
     rt = rng.standard_normal(w.shape) * np.exp(rng.uniform(-3, 3, size=(nE, 1, 1)))
     dw = rng.standard_normal(w.shape)
-    elems = np.array([0, 4, 5, 19, 7, 7, 13], dtype=np.int32)   # corners, edges, a repeat
+    elems = np.array([0, 4, 5, nE - 1, 7, 7, nE // 2], dtype=np.int32)   # corners, edges, a repeat
     n_in, _, n_out, _ = ctx.mlp_shape()
     X = torch.zeros(len(elems) * n_in, dtype=torch.float32, device="cuda")
     T = torch.zeros(len(elems) * n_out, dtype=torch.float32, device="cuda")
     s = torch.zeros(len(elems), dtype=torch.float32, device="cuda")
     ctx.mlp_features(dev(rt), dev(w), 0.25, 0.0125, X, scale=s, dw=dev(dw), T=T,
                      elems=torch.tensor(elems, device="cuda"))
-    Xr, sr = mlp.features(CASE["nelem"], rt.reshape(nE, -1), w.reshape(nE, -1), 0.25, 0.0125, elems)
+    Xr, sr = mlp.features(case["nelem"], rt.reshape(nE, -1), w.reshape(nE, -1), 0.25, 0.0125, elems)
     Tr = dw.reshape(nE, -1)[elems] / sr[:, None]
     assert np.abs(host(X).reshape(Xr.shape) - Xr).max() <= 2e-7 * np.abs(Xr).max()
     assert rel(host(s), sr) < 1e-6
@@ -74,7 +79,7 @@ def test_features_match_oracle():
     # all elements, no targets
     X2 = torch.zeros(nE * n_in, dtype=torch.float32, device="cuda")
     ctx.mlp_features(dev(rt), dev(w), 0.25, 0.0125, X2)
-    Xa, _ = mlp.features(CASE["nelem"], rt.reshape(nE, -1), w.reshape(nE, -1), 0.25, 0.0125, range(nE))
+    Xa, _ = mlp.features(case["nelem"], rt.reshape(nE, -1), w.reshape(nE, -1), 0.25, 0.0125, range(nE))
     assert np.abs(host(X2).reshape(Xa.shape) - Xa).max() <= 2e-7 * np.abs(Xa).max()
 
 
@@ -145,13 +150,16 @@ def test_adam_matches_oracle():
     assert rel(host(got), t_ref) < 1e-6
 
 
-@pytest.mark.parametrize("mlp_precision,vec,tol", [("fp32", "fp64", 1e-5), ("fp32", "mixed", 1e-4),
-                                                    ("bf16", "fp64", 2e-2)])
-def test_learned_apply_matches_oracle(mlp_precision, vec, tol):
+@pytest.mark.parametrize("case,mlp_precision,vec,tol", [(CASE, "fp32", "fp64", 1e-5), (CASE, "fp32", "mixed", 1e-4),
+                                                         (CASE, "bf16", "fp64", 2e-2), (CASE3, "fp32", "fp64", 1e-5),
+                                                         (CASE3, "bf16", "mixed", 2e-2)],
+                         ids=["euler2-fp32-fp64", "euler2-fp32-mixed", "euler2-bf16-fp64", "euler3-fp32-fp64",
+                              "euler3-bf16-mixed"])
+def test_learned_apply_matches_oracle(case, mlp_precision, vec, tol):
     """P^-1 (vw, vs) of the learned preconditioner (Schur right-hand side, per-element
     network on the patch features, exact second block row) against the oracle."""
-    dg = oracle_for(CASE)
-    ctx = make_ctx(precond="learned", mlp_precision=mlp_precision)
+    dg = oracle_for(case)
+    ctx = make_ctx(case, precond="learned", mlp_precision=mlp_precision)
     n_in, H, n_out, _ = ctx.mlp_shape()
     th = params(ctx, 4)
     ctx.mlp_set_params(dev(th, torch.float32))
