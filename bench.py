@@ -142,11 +142,11 @@ def run_form(wl, form, steps, warmup, theta=None):
     import torch
     from paper_2109_04804_amd.hbpc import Context
     precision = "fp64" if form == "fp64" else "mixed"
-    pc = "learned" if form == "learned" else "bjext"
+    pc = form if form in ("learned", "learned_first") else "bjext"
     ctx = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], wl.get("equation", "euler"), q=6, kmax=4,
                   newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=30, gmres_maxit=7000, precond=pc,
                   precision=precision, pc_fallback=0.5, **_eqkw(wl))
-    if pc == "learned":
+    if pc in ("learned", "learned_first"):
         ctx.mlp_set_params(theta)
     w0 = initial_state(ctx, wl)
     w = torch.tensor(np.ascontiguousarray(w0).reshape(-1), dtype=torch.float64, device="cuda")
@@ -303,10 +303,10 @@ def main():
     wl = WORKLOADS[a.workload]
     forms = [f for f in a.forms.split(",") if f]
     if wl.get("equation") == "burgers":
-        forms = [f for f in forms if f != "learned"]   # the network is trained on Euler states
+        forms = [f for f in forms if not f.startswith("learned")]   # the network is trained on Euler states
     res = {}
     theta, train_report = None, None
-    if "learned" in forms:
+    if any(f.startswith("learned") for f in forms):
         # 3-D: more pairs per Newton correction, so that one FP64 collection step suffices
         theta, train_report = train_learned(wl, per_correction=1024 if wl["dim"] == 3 else 512)
     for f in forms:

@@ -66,6 +66,12 @@ typedef struct hbpc_ctx hbpc_ctx;
 #define HBPC_PC_BJEXT 1            /* extended block-Jacobi, Sec. 3.2.3 */
 #define HBPC_PC_LEARNED 2          /* per-element network on the Schur system (an addition to
                                       the paper, see hbpc_mlp_*), BJ_ext as fallback */
+#define HBPC_PC_LEARNED_FIRST 3    /* flexible GMRES with the network for the first direction of
+                                      each Newton step (z_0 = N(v_0), v_0 the normalised Newton
+                                      residual: the network's training input) and BJ_ext for
+                                      every later one; a non-finite network output drops the
+                                      network for the rest of the stage solve (counted in
+                                      pc_fallbacks) */
 
 /* arithmetic of the learned preconditioner's network */
 #define HBPC_MLP_BF16 0            /* BF16 operands on the matrix cores, FP32 accumulation */

@@ -746,6 +746,8 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
         int k = 0;
         const double beta_cycle = beta;
         const int learned = c->prm.precond == HBPC_PC_LEARNED && c->lpc_active;
+        // network for z_0 only, in the first cycle (v_0 = the normalised Newton residual)
+        const int net_first = c->prm.precond == HBPC_PC_LEARNED_FIRST && c->lpc_active && cycle == 0;
         // Arnoldi iteration j, enqueued without waiting for the host: z_j = P^-1 v_j, u = J z_j,
         // classical Gram-Schmidt twice against V_0..V_j, the second pass taken from the Gram
         // matrix G = V^T V (V^T (u - V h1) = h1 - G h1, so one pass over V gives V^T u and the
@@ -753,7 +755,7 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
         // results (h, ||u||^2) copied to host slot j % 2
         auto enqueue = [&](int j) {
             void* zj = use_pc ? Zj(j) : Vj(j);
-            if (learned) lpc_apply(c, w, trw, Vj(j), zj, f32);
+            if (learned || (net_first && j == 0)) lpc_apply(c, w, trw, Vj(j), zj, f32);
             else if (use_pc) pc_apply(c, w, trw, Vj(j), zj, f32);
             if (!learned && c->col_X && c->col_source != HBPC_MLP_PAIRS_NEWTON &&
                 (use_pc || c->col_source == HBPC_MLP_PAIRS_RANDOM) && c->col_count < c->col_cap &&
@@ -790,7 +792,7 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
             Hc(j + 1, j) = hnrm;
             if (!std::isfinite(hnrm)) {
                 // a non-finite learned-preconditioner output: drop column j and fall back
-                if (learned && c->prm.pc_fallback > 0) {
+                if ((learned || (net_first && j == 0)) && c->prm.pc_fallback > 0) {
                     bad_pc = true;
                     k = j;
                     break;
@@ -829,14 +831,14 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
         // learned preconditioner: BJ_ext takes over after a poor cycle or a non-finite output; the
         // cycle's correction is dropped and BJ_ext starts from the right-hand side (keeping it
         // left residuals on which BJ_ext needed more iterations than on the original one)
-        if (learned && c->prm.pc_fallback > 0 &&
-            (bad_pc || std::fabs(g[k]) > c->prm.pc_fallback * beta_cycle)) {
+        if ((learned || net_first) && c->prm.pc_fallback > 0 &&
+            (bad_pc || (learned && std::fabs(g[k]) > c->prm.pc_fallback * beta_cycle))) {
             c->lpc_active = 0;
             c->st.pc_fallbacks++;
             if (c->verbose)
                 std::fprintf(stderr, "[hbpc] learned preconditioner -> BJ_ext (%s, cycle %d reduced |r| by %.3e)\n",
                              bad_pc ? "non-finite" : "slow", cycle, std::fabs(g[k]) / beta_cycle);
-            pc_build(c, c->X, a1dt, bc, f32);
+            if (learned) pc_build(c, c->X, a1dt, bc, f32);   // (built already for the first-direction form)
             hipchk(c, hipMemsetAsync(dX, 0, n2 * 8, c->stream), "memset");
             hipchk(c, blas_axpby(1.0, rhs, 0, 0.0, Vj(0), f32, n2, c->stream), "copy");
             ++cycle;
@@ -880,17 +882,18 @@ static void newton_solve(hbpc_ctx* c, const double* b, double a1dt, double bc, c
     if (n0 > 1e-14 * std::sqrt((double)c->n2)) {
         if (mixed) state_traces(c, 1);
         const int pck = c->prm.precond;
-        if (pck == HBPC_PC_BJEXT) pc_build(c, X, a1dt, bc, mixed);
-        if (pck == HBPC_PC_LEARNED) {
+        const int first = pck == HBPC_PC_LEARNED_FIRST;
+        if (pck == HBPC_PC_BJEXT || first) pc_build(c, X, a1dt, bc, mixed);
+        if (pck == HBPC_PC_LEARNED || first) {
             if (!c->mlp_ready) set_err(c, HBPC_ERR_ARG, "learned preconditioner without parameters");
             c->lpc_active = 1;
         }
         for (;;) {
             ++its;
-            const int bj = pck == HBPC_PC_BJEXT || (pck == HBPC_PC_LEARNED && !c->lpc_active);
+            const int bj = pck == HBPC_PC_BJEXT || first || (pck == HBPC_PC_LEARNED && !c->lpc_active);
             if (bj && c->prm.pc_rebuild == HBPC_PC_PER_NEWTON_IT && its > 1) pc_build(c, X, a1dt, bc, mixed);
             // learned: gates at the current linearisation state
-            if (pck == HBPC_PC_LEARNED && c->lpc_active)
+            if ((pck == HBPC_PC_LEARNED || first) && c->lpc_active)
                 lpc_prepare(c, mixed ? (const void*)c->X32 : (const void*)X, mixed, a1dt, bc);
             hipchk(c, blas_axpby(-1.0, c->G, 0, 0.0, c->rhs, 0, c->n2, c->stream), "rhs");
             double tg = now_ms();
@@ -1040,7 +1043,8 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
         set_err(c, HBPC_ERR_ARG, "upwind flux needs advection");
     if (equation == HBPC_EQ_BURGERS_BR1 && !(prm->nu >= 0)) set_err(c, HBPC_ERR_ARG, "nu must be >= 0");
     if (prm->gmres_restart < 1 || prm->gmres_restart > 64) set_err(c, HBPC_ERR_ARG, "gmres_restart must be 1..64");
-    if (prm->precond < HBPC_PC_NONE || prm->precond > HBPC_PC_LEARNED) set_err(c, HBPC_ERR_ARG, "unknown precond");
+    if (prm->precond < HBPC_PC_NONE || prm->precond > HBPC_PC_LEARNED_FIRST)
+        set_err(c, HBPC_ERR_ARG, "unknown precond");
     if (prm->mlp_precision != HBPC_MLP_BF16 && prm->mlp_precision != HBPC_MLP_FP32)
         set_err(c, HBPC_ERR_ARG, "unknown mlp_precision");
     if (prm->q != 4 && prm->q != 6 && prm->q != 8) set_err(c, HBPC_ERR_ARG, "q must be 4, 6 or 8");

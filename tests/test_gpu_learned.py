@@ -72,10 +72,12 @@ def collect_and_train(nelem, L, N, dt, seeds, cap_newton, cap_krylov, per_event,
     return Xd, Td, count, n1
 
 
-def test_learned_step_matches_oracle():
+@pytest.mark.parametrize("precond", ["learned", "learned_first"])
+def test_learned_step_matches_oracle(precond):
     """2-D Euler vortex, 4 x 4 elements, N = 3, HBPC(6,2), dt = 0.1, mixed precision,
-    learned preconditioner trained on Newton pairs of this mesh (seeds 1..3) with the
-    BJ_ext fallback: the step reaches the oracle's Newton root."""
+    learned preconditioner trained on Newton pairs of this mesh (seeds 1..3), with the
+    BJ_ext fallback (learned) or as the first FGMRES direction of each Newton step
+    before BJ_ext (learned_first): the step reaches the oracle's Newton root."""
     case = dict(CASES["euler2_n3_lobatto"])
     case.update(nelem=[4, 4], nodes="gauss")
     dg = oracle_for(case)
@@ -83,7 +85,7 @@ def test_learned_step_matches_oracle():
     w0 = inputs.isentropic_vortex(X[0], X[1], 4.6, 5.3, 3.0)
     common = dict(q=6, kmax=2, newton_rtol=1e-8)
     Xd, Td, count, n1 = collect_and_train([4, 4], 10.0, 3, 0.1, (1, 2, 3), 512, 0, 8, **common)
-    ctx = ctx_for(2, [4, 4], [10.0, 10.0], 3, gmres_rtol=1e-5, precision="mixed", precond="learned",
+    ctx = ctx_for(2, [4, 4], [10.0, 10.0], 3, gmres_rtol=1e-5, precision="mixed", precond=precond,
                   pc_fallback=0.5, **common)
     ctx.mlp_set_params(random_params(ctx, 0))
     log = ctx.train_mlp(Xd, Td, count, epochs=40, batch=64, lr=1e-3, seed=3, precision="bf16")
@@ -129,7 +131,8 @@ def test_training_and_gain():
     about 1): Newton pairs (FP64 BJ_ext solves, eps_G 1e-6) for vortex seeds 1..4,
     BF16 training, then one mixed step at eps_G = 1e-3 on held-out seed 99 with no
     preconditioner, the network alone (no fallback, at most 20000 Krylov iterations
-    per Newton step), the network with the BJ_ext fallback, and BJ_ext.  Prints the
+    per Newton step), the network with the BJ_ext fallback, the network as the first
+    FGMRES direction of each Newton step followed by BJ_ext, and BJ_ext.  Prints the
     Krylov iteration counts; asserts that training lowers the loss and that every
     form that converges reaches the same Newton root."""
     nelem, L, N, dt = [16, 16], 10.0, 3, 0.4
@@ -142,10 +145,10 @@ def test_training_and_gain():
     theta = None
     ev = {}
     for form, pc, fb in (("none", "none", 0.0), ("network", "learned", 0.0), ("network+fallback", "learned", 0.5),
-                         ("bjext", "bjext", 0.0)):
+                         ("network-first", "learned_first", 0.5), ("bjext", "bjext", 0.0)):
         ctx = ctx_for(2, nelem, [L, L], N, gmres_rtol=1e-3, precision="mixed", precond=pc, pc_fallback=fb,
                       gmres_maxit=20000, **common)
-        if pc == "learned":
+        if pc in ("learned", "learned_first"):
             if theta is None:
                 ctx.mlp_set_params(random_params(ctx, 7))
                 log = ctx.train_mlp(Xd, Td, count, epochs=30, batch=128, lr=1e-3, seed=5, precision="bf16")
@@ -163,8 +166,8 @@ def test_training_and_gain():
         except Exception as ex:
             print(form, "did not converge:", ex, flush=True)
         ctx.close()
-    for form in ("none", "network", "network+fallback"):
+    for form in ("none", "network", "network+fallback", "network-first"):
         if form in ev:
             assert rel(ev[form][2], ev["bjext"][2]) < 1e-7, form
-    assert "network+fallback" in ev
+    assert "network+fallback" in ev and "network-first" in ev
     print("Krylov iterations per step:", {k: v[0] for k, v in ev.items()})
