@@ -5,7 +5,10 @@ Workload (default): 2-D compressible Euler isentropic vortex on the periodic
 [0,10]^2, gamma 1.4, background Mach 0.5, strength 5, seeded centre
 (seed 2109), DGSEM N = 5 on Gauss nodes, 128 x 128 elements (2,359,296 DOF),
 Rusanov flux, HBPC(6,4) (3 nodes c = 0, 1/2, 1; 4 corrector sweeps), dt = 0.1,
-Newton tolerance 1e-8, FGMRES(30) with eps_G = 1e-3.  Three forms are timed:
+Newton tolerance 1e-8, FGMRES(30) with eps_G = 1e-3, BJ_ext blocks built once
+per predictor stage and once per corrector stage (reused by the later
+sweeps; --pc-rebuild per_solve builds them for every stage solve).  Three
+forms are timed:
   fp64     all-FP64, BJ_ext;
   mixed    FP64 Newton, FP32 Krylov vectors, JVP and BJ_ext;
   learned  as mixed with the learned preconditioner (BF16 network, BJ_ext as
@@ -137,7 +140,7 @@ def train_learned(wl, samples=20480, per_correction=512, seeds=(1, 2), epochs=20
                  "loss_last_epoch": log["loss_last"]}
 
 
-def run_form(wl, form, steps, warmup, theta=None):
+def run_form(wl, form, steps, warmup, theta=None, pc_rebuild="per_solve"):
     import numpy as np
     import torch
     from paper_2109_04804_amd.hbpc import Context
@@ -145,7 +148,7 @@ def run_form(wl, form, steps, warmup, theta=None):
     pc = form if form in ("learned", "learned_first") else "bjext"
     ctx = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], wl.get("equation", "euler"), q=6, kmax=4,
                   newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=30, gmres_maxit=7000, precond=pc,
-                  precision=precision, pc_fallback=0.5, **_eqkw(wl))
+                  precision=precision, pc_fallback=0.5, pc_rebuild=pc_rebuild, **_eqkw(wl))
     if pc in ("learned", "learned_first"):
         ctx.mlp_set_params(theta)
     w0 = initial_state(ctx, wl)
@@ -278,6 +281,9 @@ def main():
                     help="comma list of fp64 (BJ_ext FP64), mixed (BJ_ext, FP32 Krylov), learned "
                          "(learned preconditioner with BJ_ext fallback, FP32 Krylov, BF16 network)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pc-rebuild", default="per_stage", choices=["per_solve", "per_stage"],
+                    help="BJ_ext builds: kept per corrector stage across sweeps (default), or once per stage "
+                         "solve")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run a plain device copy of this many bytes three times (reference dispatch "
                          "for scaling hardware byte counters)")
@@ -310,7 +316,7 @@ def main():
         # 3-D: more pairs per Newton correction, so that one FP64 collection step suffices
         theta, train_report = train_learned(wl, per_correction=1024 if wl["dim"] == 3 else 512)
     for f in forms:
-        res[f] = run_form(wl, f, a.steps, a.warmup, theta)
+        res[f] = run_form(wl, f, a.steps, a.warmup, theta, a.pc_rebuild)
     head = "learned" if "learned" in res else ("mixed" if "mixed" in res else forms[0])
     h = res[head]
     dof = h["dof"]
@@ -329,7 +335,7 @@ def main():
         "dtype": {"learned": "f64+f32+bf16", "mixed": "f64+f32", "fp64": "f64"}[head],
         "data": "synthetic",
         "config": {"workload": a.workload, "dof": dof, "scheme": "HBPC(6,4)", "dt": wl["dt"],
-                   "newton_rtol": 1e-8, "krylov": "FGMRES(30), eps_G 1e-3",
+                   "newton_rtol": 1e-8, "krylov": "FGMRES(30), eps_G 1e-3", "pc_rebuild": a.pc_rebuild,
                    "precond": {"learned": "learned (BJ_ext fallback 0.5)", "mixed": "BJ_ext",
                                "fp64": "BJ_ext"}[head], "form": head},
         "forms": {f: {"dof_steps_per_s": dof * a.steps / (r["ms_total"] * 1e-3), "ms_per_step": r["ms_per_step"],

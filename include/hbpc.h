@@ -80,6 +80,11 @@ typedef struct hbpc_ctx hbpc_ctx;
 /* preconditioner rebuild frequency */
 #define HBPC_PC_PER_SOLVE 0        /* once per stage solve, at the Newton initial guess */
 #define HBPC_PC_PER_NEWTON_IT 1    /* at every Newton iterate */
+#define HBPC_PC_PER_STAGE 2        /* predictor: once per stage solve; corrector: once per stage in
+                                      the first sweep, kept and reused by the later sweeps (same
+                                      coefficients alpha1 dt = dt, alpha2 dt^2/2 = dt^2/2; the
+                                      state has moved by one sweep's correction).  Keeps s - 1
+                                      sets of S^-1 blocks. */
 
 /* Jacobian-vector product */
 #define HBPC_JVP_LINEARISED 0      /* exact directional derivatives (hyper-dual flux) */
@@ -116,7 +121,7 @@ typedef struct {
     int gmres_maxit;      /* per Newton step (default 7000) */
     int precision;        /* HBPC_FP64 | HBPC_MIXED */
     int precond;          /* HBPC_PC_* */
-    int pc_rebuild;       /* HBPC_PC_PER_SOLVE | HBPC_PC_PER_NEWTON_IT */
+    int pc_rebuild;       /* HBPC_PC_PER_SOLVE | HBPC_PC_PER_NEWTON_IT | HBPC_PC_PER_STAGE */
     int jvp_mode;         /* HBPC_JVP_* */
     int hessian;          /* 1: include dR2/dw in the JVP (exact Newton), 0: drop it */
     int mlp_precision;    /* HBPC_MLP_BF16 | HBPC_MLP_FP32: network arithmetic of HBPC_PC_LEARNED */

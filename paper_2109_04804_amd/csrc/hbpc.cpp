@@ -299,13 +299,17 @@ static double dnorm(hbpc_ctx* c, const void* x, size_t n, int f32) {
 static void pc_build(hbpc_ctx* c, const double* w, double a1dt, double bc, int f32) {
     double t0 = now_ms();
     if (c->NE > 1024) set_err(c, HBPC_ERR_UNSUPPORTED, "BJ_ext supports element blocks up to 1024 unknowns");
-    if (!c->Sinv || c->sinv_f32 != f32) {
-        dfree(c->Sinv);
-        c->Sinv = nullptr;
+    void*& S = c->Sinv_slot[c->cur_slot];
+    if (!S || c->sinv_f32_slot[c->cur_slot] != f32) {
+        dfree(S);
+        S = nullptr;
+        c->slot_valid[c->cur_slot] = 0;
         size_t cnt = (size_t)c->nE * c->NE * c->NE;
-        c->Sinv = f32 ? (void*)dalloc<float>(c, cnt) : (void*)dalloc<double>(c, cnt);
-        c->sinv_f32 = f32;
+        S = f32 ? (void*)dalloc<float>(c, cnt) : (void*)dalloc<double>(c, cnt);
+        c->sinv_f32_slot[c->cur_slot] = f32;
     }
+    c->Sinv = S;
+    c->sinv_f32 = f32;
     if (!c->KT) c->KT = dalloc<double>(c, c->kt_chunk * c->NE * c->NE);
     op_trace(c, w, c->trw, 0);
     status_reset(c);
@@ -333,8 +337,21 @@ static void pc_build(hbpc_ctx* c, const double* w, double a1dt, double bc, int f
     c->pc_a1dt = a1dt;
     c->pc_bc = bc;
     c->pc_valid = 1;
+    c->slot_a1dt[c->cur_slot] = a1dt;
+    c->slot_bc[c->cur_slot] = bc;
+    c->slot_valid[c->cur_slot] = 1;
     c->st.pc_builds++;
     c->st.t_pc_build_ms += now_ms() - t0;
+}
+
+// make S^-1 slot `slot` the active one (BJ_ext apply reads c->Sinv, c->pc_a1dt, c->pc_bc)
+static void pc_use_slot(hbpc_ctx* c, int slot) {
+    c->cur_slot = slot;
+    c->Sinv = c->Sinv_slot[slot];
+    c->sinv_f32 = c->sinv_f32_slot[slot];
+    c->pc_a1dt = c->slot_a1dt[slot];
+    c->pc_bc = c->slot_bc[slot];
+    c->pc_valid = c->slot_valid[slot];
 }
 
 // Y = P^-1 X in precision f32; the linearisation state (w, traces) in the same precision
@@ -864,8 +881,11 @@ static void state_traces(hbpc_ctx* c, int mixed) {
     }
 }
 
-// solve g(W) = b for W (a1dt = alpha1 dt, bc = alpha2 dt^2/2), initial guess `guess`; W -> out
-static void newton_solve(hbpc_ctx* c, const double* b, double a1dt, double bc, const double* guess, double* out) {
+// solve g(W) = b for W (a1dt = alpha1 dt, bc = alpha2 dt^2/2), initial guess `guess`; W -> out.
+// keep_pc: BJ_ext blocks of the active slot built for the same coefficients and precision are used
+// as they are.
+static void newton_solve(hbpc_ctx* c, const double* b, double a1dt, double bc, const double* guess, double* out,
+                         bool keep_pc = false) {
     const size_t n = c->ndof;
     const int mixed = c->prm.precision == HBPC_MIXED;
     double* X = c->X;
@@ -883,7 +903,8 @@ static void newton_solve(hbpc_ctx* c, const double* b, double a1dt, double bc, c
         if (mixed) state_traces(c, 1);
         const int pck = c->prm.precond;
         const int first = pck == HBPC_PC_LEARNED_FIRST;
-        if (pck == HBPC_PC_BJEXT || first) pc_build(c, X, a1dt, bc, mixed);
+        const bool kept = keep_pc && c->pc_valid && c->pc_a1dt == a1dt && c->pc_bc == bc && c->sinv_f32 == mixed;
+        if ((pck == HBPC_PC_BJEXT || first) && !kept) pc_build(c, X, a1dt, bc, mixed);
         if (pck == HBPC_PC_LEARNED || first) {
             if (!c->mlp_ready) set_err(c, HBPC_ERR_ARG, "learned preconditioner without parameters");
             c->lpc_active = 1;
@@ -955,6 +976,7 @@ static void hbpc_step_impl(hbpc_ctx* c, double* w_inout, double dt) {
         hipchk(c, hipMemcpyAsync(c->b, W[l - 1], n * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
         hipchk(c, blas_gemv_add(c->R1all, 0, n, s, coef1, c->b, 0, n, c->stream), "b");
         hipchk(c, blas_gemv_add(c->R2all, 0, n, s, coef2, c->b, 0, n, c->stream), "b");
+        pc_use_slot(c, 0);
         newton_solve(c, c->b, a1dt, bc, W[l - 1], W[l]);
         op_r1r2(c, W[l], R1(l), R2(l));
     }
@@ -969,7 +991,9 @@ static void hbpc_step_impl(hbpc_ctx* c, double* w_inout, double dt) {
             hipchk(c, hipMemcpyAsync(c->b, W[0], n * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
             hipchk(c, blas_gemv_add(c->R1all, 0, n, s, coef1, c->b, 0, n, c->stream), "b");
             hipchk(c, blas_gemv_add(c->R2all, 0, n, s, coef2, c->b, 0, n, c->stream), "b");
-            newton_solve(c, c->b, dt, dt * dt / 2, W[l], c->Wn[l]);
+            const bool per_stage = c->prm.pc_rebuild == HBPC_PC_PER_STAGE;
+            pc_use_slot(c, per_stage ? l - 1 : 0);
+            newton_solve(c, c->b, dt, dt * dt / 2, W[l], c->Wn[l], per_stage && k > 0);
         }
         for (int l = 1; l < s; ++l) std::swap(W[l], c->Wn[l]);
         if (k < c->prm.kmax - 1)
@@ -980,6 +1004,7 @@ static void hbpc_step_impl(hbpc_ctx* c, double* w_inout, double dt) {
     if (status_read(c)) set_err(c, HBPC_ERR_NONFINITE, "non-finite value in the new state");
     hipchk(c, hipMemcpyAsync(w_inout, W[s - 1], n * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
     hipchk(c, hipStreamSynchronize(c->stream), "sync");
+    pc_use_slot(c, 0);
 }
 
 // ------------------------------------------------------------------ context
@@ -990,11 +1015,13 @@ static void ctx_free(hbpc_ctx* c) {
         dfree(c->tmp[i]);
     }
     void* bufs[] = {c->R1all, c->R2all, c->X, c->b, c->G, c->dX, c->rhs, c->trw, c->trs, c->trd1,
-                    c->X32, c->trw32, c->trs32, c->trd1_32, c->V, c->Z, c->kv, c->KT, c->Sinv,
+                    c->X32, c->trw32, c->trs32, c->trd1_32, c->V, c->Z, c->kv, c->KT,
                     c->part, c->dres, c->dgram, c->dcount, c->dstatus, c->basis64, c->basis32, c->theta, c->adam_m, c->adam_v,
                     c->mgrad, c->ap_X, c->ap_G1, c->ap_G2, c->ap_H1, c->ap_H2, c->ap_Y, c->ap_s, c->tr_buf, c->tr_idx_dev,
                     c->col_elems};
     for (void* p : bufs) dfree(p);
+    for (int i = 0; i < 4; ++i) dfree(c->Sinv_slot[i]);
+    c->Sinv = nullptr;
     for (int i = 0; i < 6; ++i) dfree(c->fd[i]);
     for (int j = 0; j < 4; ++j) {
         dfree(c->qtr[0][j]);
@@ -1045,6 +1072,8 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
     if (prm->gmres_restart < 1 || prm->gmres_restart > 64) set_err(c, HBPC_ERR_ARG, "gmres_restart must be 1..64");
     if (prm->precond < HBPC_PC_NONE || prm->precond > HBPC_PC_LEARNED_FIRST)
         set_err(c, HBPC_ERR_ARG, "unknown precond");
+    if (prm->pc_rebuild < HBPC_PC_PER_SOLVE || prm->pc_rebuild > HBPC_PC_PER_STAGE)
+        set_err(c, HBPC_ERR_ARG, "unknown pc_rebuild");
     if (prm->mlp_precision != HBPC_MLP_BF16 && prm->mlp_precision != HBPC_MLP_FP32)
         set_err(c, HBPC_ERR_ARG, "unknown mlp_precision");
     if (prm->q != 4 && prm->q != 6 && prm->q != 8) set_err(c, HBPC_ERR_ARG, "q must be 4, 6 or 8");
@@ -1397,6 +1426,7 @@ int hbpc_pc_build(hbpc_ctx* c, const double* w, double a1dt, double bcoef, int p
     HBPC_TRY(c, {
         const int f32 = precision == HBPC_MIXED;
         const int learned = c->prm.precond == HBPC_PC_LEARNED;
+        pc_use_slot(c, 0);
         if (learned && !c->mlp_ready) set_err(c, HBPC_ERR_ARG, "learned preconditioner without parameters");
         if (!learned) pc_build(c, w, a1dt, bcoef, f32);
         if (f32) {

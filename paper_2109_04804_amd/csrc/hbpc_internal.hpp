@@ -106,11 +106,17 @@ struct hbpc_ctx {
     int m_alloc;
     // BJ_ext
     double* KT;               // chunk_e x NE x NE (column-major blocks)
-    void* Sinv;               // nE x NE x NE
+    void* Sinv;               // nE x NE x NE: the active slot's blocks
     int sinv_f32;
     size_t kt_chunk;          // elements per K build chunk (<= 4 GiB of FP64 blocks)
     double pc_a1dt, pc_bc;
     int pc_valid;
+    // S^-1 slots: 0 for the predictor (and every solve unless blocks are kept per stage), l - 1
+    // for corrector stage l when they are
+    void* Sinv_slot[4];
+    int sinv_f32_slot[4], slot_valid[4];
+    double slot_a1dt[4], slot_bc[4];
+    int cur_slot;
     // reductions
     double* part;             // blas partials
     double* dres;             // device results (256)

@@ -23,6 +23,7 @@ PRECISION = {"fp64": 0, "mixed": 1}
 PRECOND = {"none": 0, "bjext": 1, "learned": 2, "learned_first": 3}
 MLP_PRECISION = {"bf16": 0, "fp32": 1}
 PAIRS = {"newton": 0, "krylov": 1, "random": 2}
+PC_REBUILD = {"per_solve": 0, "per_newton_it": 1, "per_stage": 2}
 JVP = {"linearised": 0, "fd": 1}
 MAX_SOLVES = 64
 
@@ -155,7 +156,7 @@ def make_params(**kw):
     """HbpcParams from the defaults plus keyword overrides (string enums accepted)."""
     p = default_params()
     maps = {"nodes": NODES, "flux": FLUX, "precision": PRECISION, "precond": PRECOND, "jvp_mode": JVP,
-            "mlp_precision": MLP_PRECISION}
+            "mlp_precision": MLP_PRECISION, "pc_rebuild": PC_REBUILD}
     for k, v in kw.items():
         if k in maps and isinstance(v, str):
             v = maps[k][v]

@@ -106,6 +106,33 @@ def test_euler3_taylor_green_step(precision, rtol, tol):
     assert rel(host(wg), ref) < tol
 
 
+@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-12, 1e-10), ("mixed", 1e-8, 1e-8)])
+def test_pc_kept_per_stage(precision, rtol, tol):
+    """2-D Euler vortex, 4x4 elements, N = 3, HBPC(6,2), dt = 0.1, BJ_ext blocks kept per
+    corrector stage (built in the first sweep, reused in the second): 4 builds instead of 6,
+    the oracle's Newton root; afterwards an explicit build/apply (slot 0) still matches the
+    oracle's BJ_ext."""
+    from oracle.solvers import BJExt
+    case = dict(CASES["euler2_n3_lobatto"])
+    case.update(nelem=[4, 4], nodes="gauss")
+    dg = oracle_for(case)
+    X = dg.node_coords()
+    w0 = inputs.isentropic_vortex(X[0], X[1], 4.6, 5.3, 3.0)
+    ctx = ctx_for(case, q=6, kmax=2, newton_rtol=rtol, gmres_rtol=1e-5, precision=precision, pc_rebuild="per_stage")
+    wg = dev(w0)
+    stats = ctx.step(wg, 0.1)
+    print(precision, stats, flush=True)
+    assert stats["pc_builds"] == 4 and stats["n_solves"] == 6
+    ref = dg_hbpc_step(dg, w0, 0.1, 6, 2, StageSolver(dg, newton_rtol=rtol, gmres_rtol=1e-5))
+    assert rel(host(wg), ref) < tol
+    a1dt, bc = 0.1, 0.1 ** 2 / 2
+    ctx.pc_build(dev(w0), a1dt, bc, "fp64")
+    Xv = np.random.default_rng(5).standard_normal(2 * ctx.ndof)
+    out = torch.empty(2 * ctx.ndof, dtype=torch.float64, device="cuda")
+    ctx.pc_apply(dev(Xv), out)
+    assert rel(host(out), BJExt(dg, w0, a1dt, bc).apply(Xv)) < 1e-10
+
+
 def test_newton_rounding_floor_stop():
     """2-D Euler vortex, 4x4 elements, N = 3, HBPC(6,2), dt = 0.1, FP64, with an
     unreachable relative Newton tolerance (1e-30) and no absolute one: every solve ends
