@@ -109,7 +109,7 @@ typedef struct {
     int kmax;             /* corrector sweeps k_max */
     double newton_rtol;   /* eps_N: stop when ||G(X^r)|| <= eps_N ||G(X^0)|| */
     double newton_atol_dw;/* ... or when ||dw^r||_2 / sqrt(ndof) <= this (default 1.95e-15):
-                             the paper's absolute Newton tolerance ||dw||_2 <= 1e-12 (Sec. 5.1,
+                             the paper's absolute Newton tolerance ||dw||_2 <= 1e-12 (Sec. 5.2,
                              for 262,144 coefficients) taken per coefficient, so that it stays
                              above the round-off floor at every problem size; ... or, from the
                              second iteration on, when ||G(X^r)|| > 0.5 ||G(X^(r-1))|| and

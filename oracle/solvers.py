@@ -9,7 +9,7 @@ reading uses the Euclidean norm over all coefficients of X = (w, sigma)):
     0.5 ||G(X^(r-1))|| with ||dw^r||_2 <= 1e-12 ||w^0||_2 (a corrector stage
     started from an accurate prediction can have eps_N ||G(X^0)|| below that
     floor; the step is then at the state's rounding level).  The paper adds the absolute criterion
-    ||dw||_2 <= 1e-12 (Sec. 5.1) because corrector solves start so close to the
+    ||dw||_2 <= 1e-12 (Sec. 5.2) because corrector solves start so close to the
     solution that round-off stalls the relative one; it is read per
     coefficient here (1e-12 over the paper's 262,144 coefficients gives
     atol_dw = 1.95e-15), so that it keeps its meaning at every size.  It takes

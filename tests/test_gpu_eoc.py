@@ -1,5 +1,5 @@
 """Temporal order of HBPC(q, k_max) on the GPU for q = 4, 6, 8 (the order
-min(4 + k_max, q) the paper states for its convergence studies, Sec. 5.1 and
+min(4 + k_max, q) the paper states for its convergence studies, Sec. 4.3 and
 Fig. 7): 1-D linear advection, 16 elements, N = 3 on Lobatto nodes, upwind
 flux, u0 = sin(2 pi x), T = 1.  The error is taken against exp(T L) u0 for
 the operator L of the same semi-discretisation (assembled column by column
