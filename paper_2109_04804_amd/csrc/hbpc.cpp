@@ -855,7 +855,8 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
             if (c->verbose)
                 std::fprintf(stderr, "[hbpc] learned preconditioner -> BJ_ext (%s, cycle %d reduced |r| by %.3e)\n",
                              bad_pc ? "non-finite" : "slow", cycle, std::fabs(g[k]) / beta_cycle);
-            if (learned) pc_build(c, c->X, a1dt, bc, f32);   // (built already for the first-direction form)
+            // (built already for the first-direction form, or kept for this stage)
+            if (learned && !c->pc_kept) pc_build(c, c->X, a1dt, bc, f32);
             hipchk(c, hipMemsetAsync(dX, 0, n2 * 8, c->stream), "memset");
             hipchk(c, blas_axpby(1.0, rhs, 0, 0.0, Vj(0), f32, n2, c->stream), "copy");
             ++cycle;
@@ -904,6 +905,7 @@ static void newton_solve(hbpc_ctx* c, const double* b, double a1dt, double bc, c
         const int pck = c->prm.precond;
         const int first = pck == HBPC_PC_LEARNED_FIRST;
         const bool kept = keep_pc && c->pc_valid && c->pc_a1dt == a1dt && c->pc_bc == bc && c->sinv_f32 == mixed;
+        c->pc_kept = kept;
         if ((pck == HBPC_PC_BJEXT || first) && !kept) pc_build(c, X, a1dt, bc, mixed);
         if (pck == HBPC_PC_LEARNED || first) {
             if (!c->mlp_ready) set_err(c, HBPC_ERR_ARG, "learned preconditioner without parameters");

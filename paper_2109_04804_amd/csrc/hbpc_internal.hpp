@@ -117,6 +117,7 @@ struct hbpc_ctx {
     int sinv_f32_slot[4], slot_valid[4];
     double slot_a1dt[4], slot_bc[4];
     int cur_slot;
+    int pc_kept;              // the active slot's blocks serve the current stage solve as they are
     // reductions
     double* part;             // blas partials
     double* dres;             // device results (256)

@@ -72,12 +72,15 @@ def collect_and_train(nelem, L, N, dt, seeds, cap_newton, cap_krylov, per_event,
     return Xd, Td, count, n1
 
 
-@pytest.mark.parametrize("precond", ["learned", "learned_first"])
-def test_learned_step_matches_oracle(precond):
+@pytest.mark.parametrize("precond,rebuild", [("learned", "per_solve"), ("learned", "per_stage"),
+                                             ("learned_first", "per_solve")])
+def test_learned_step_matches_oracle(precond, rebuild):
     """2-D Euler vortex, 4 x 4 elements, N = 3, HBPC(6,2), dt = 0.1, mixed precision,
     learned preconditioner trained on Newton pairs of this mesh (seeds 1..3), with the
     BJ_ext fallback (learned) or as the first FGMRES direction of each Newton step
-    before BJ_ext (learned_first): the step reaches the oracle's Newton root."""
+    before BJ_ext (learned_first): the step reaches the oracle's Newton root.  With the BJ_ext
+    blocks kept per corrector stage, the fallbacks of the second sweep use the blocks of the
+    first (at most 4 builds for the 6 solves)."""
     case = dict(CASES["euler2_n3_lobatto"])
     case.update(nelem=[4, 4], nodes="gauss")
     dg = oracle_for(case)
@@ -86,7 +89,7 @@ def test_learned_step_matches_oracle(precond):
     common = dict(q=6, kmax=2, newton_rtol=1e-8)
     Xd, Td, count, n1 = collect_and_train([4, 4], 10.0, 3, 0.1, (1, 2, 3), 512, 0, 8, **common)
     ctx = ctx_for(2, [4, 4], [10.0, 10.0], 3, gmres_rtol=1e-5, precision="mixed", precond=precond,
-                  pc_fallback=0.5, **common)
+                  pc_fallback=0.5, pc_rebuild=rebuild, **common)
     ctx.mlp_set_params(random_params(ctx, 0))
     log = ctx.train_mlp(Xd, Td, count, epochs=40, batch=64, lr=1e-3, seed=3, precision="bf16")
     print("train", count, log, flush=True)
@@ -94,6 +97,8 @@ def test_learned_step_matches_oracle(precond):
     wg = dev(w0)
     st = ctx.step(wg, 0.1)
     print(st, flush=True)
+    if rebuild == "per_stage":
+        assert st["pc_builds"] <= 4
     ref = dg_hbpc_step(dg, w0, 0.1, 6, 2, StageSolver(dg, newton_rtol=1e-8, gmres_rtol=1e-5))
     err = rel(host(wg), ref)
     print("rel err vs oracle", err)
