@@ -1,13 +1,15 @@
 """Temporal order of HBPC(q, k_max) on the GPU for q = 4, 6, 8 (the order
 min(4 + k_max, q) the paper states for its convergence studies, Sec. 4.3 and
-Fig. 7): 1-D linear advection, 16 elements, N = 3 on Lobatto nodes, upwind
+Fig. 7), first on 1-D linear advection, 16 elements, N = 3 on Lobatto nodes, upwind
 flux, u0 = sin(2 pi x), T = 1.  The error is taken against exp(T L) u0 for
 the operator L of the same semi-discretisation (assembled column by column
 from the oracle's R1), so it is the time error alone; both rates over the
 halvings dt = 0.1 -> 0.05 -> 0.025 must be within 0.35 of the stated order
 (the oracle's own rates on this set-up: 3.97/3.99, 5.09/5.03, 6.20/6.07,
 7.83/8.01).  Stage solves: eps_N = 1e-14 (ended by the rounding-floor
-test), eps_G = 1e-12, GMRES(64)."""
+test), eps_G = 1e-12, GMRES(64).  Then on the non-linear Euler equations
+(the density wave of the paper's convergence study, against a small-step
+solution on the same mesh)."""
 import numpy as np
 import pytest
 import scipy.linalg as sla
@@ -51,3 +53,38 @@ def test_temporal_order(q, k, expected):
     rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
     print("HBPC(%d,%d)" % (q, k), "errors", errs, "rates", rates, flush=True)
     assert all(abs(r - expected) < 0.35 for r in rates), (errs, rates)
+
+
+def _density_wave_run(q, k, dt, n=8, N=5, T=0.8):
+    from paper_2109_04804_amd.hbpc import Context
+    ctx = Context(2, [n, n], [2.0, 2.0], N, "euler", origin=(-1.0, -1.0, 0.0), q=q, kmax=k, newton_rtol=1e-14,
+                  gmres_rtol=1e-12, gmres_restart=64, gmres_maxit=20000, precision="fp64", precond="bjext",
+                  flux="rusanov", gamma=1.4, eps_ref=1.0)
+    xi, _ = ctx.nodes()
+    X = inputs.node_coords(2, [n, n], [2.0, 2.0], [-1.0, -1.0], xi)
+    w = torch.tensor(inputs.density_wave(X, a=0.3).reshape(-1), dtype=torch.float64, device="cuda")
+    for _ in range(int(round(T / dt))):
+        ctx.step(w, dt)
+    torch.cuda.synchronize()
+    out = w.cpu().numpy()
+    ctx.close()
+    return out
+
+
+def test_temporal_order_euler_density_wave():
+    """The Euler convergence set-up (Sec. 4.3.2: density wave rho = 1 + 0.3 sin(pi(x + y -
+    2 a t)), v = (a, a), a = 0.3, p = 1, on [-1,1]^2, eps = 1, T = 0.8), here on 8^2 elements
+    with N = 5, against HBPC(8,4) at dt = 0.0125 on the same mesh (the time error alone).
+    HBPC(4,0): both rates over dt = 0.2 -> 0.1 -> 0.05 within 0.35 of 4; HBPC(6,2): over
+    dt = 0.4 -> 0.2 -> 0.1 within 0.35 of 6; HBPC(8,4): above 6.5 from dt = 0.4 to 0.2 (below,
+    the errors reach the 1e-12 level of the solver tolerances)."""
+    ref = _density_wave_run(8, 4, 0.0125)
+    for q, k, dts, expected in ((4, 0, (0.2, 0.1, 0.05), 4), (6, 2, (0.4, 0.2, 0.1), 6)):
+        errs = [rel(_density_wave_run(q, k, dt), ref) for dt in dts]
+        rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+        print("HBPC(%d,%d)" % (q, k), "errors", errs, "rates", rates, flush=True)
+        assert all(abs(r - expected) < 0.35 for r in rates), (q, k, errs, rates)
+    errs = [rel(_density_wave_run(8, 4, dt), ref) for dt in (0.4, 0.2)]
+    rate = np.log2(errs[0] / errs[1])
+    print("HBPC(8,4) errors", errs, "rate", rate, flush=True)
+    assert rate > 6.5 and errs[1] < 2e-10
