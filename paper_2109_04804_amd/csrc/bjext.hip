@@ -191,8 +191,10 @@ __global__ void __launch_bounds__(TGR* TGC) bj_invert_kernel(const double* __res
 
 // ---- element blocks too large for registers (the 3-D Euler N = 3 block has 320 unknowns):
 // blocked Gauss-Jordan with the working matrix A (column-major, A[c * NE + r]) kept in the
-// element's output block.  Panels of pb columns are eliminated in LDS with the same pivot rule
-// as the register kernel (largest not-yet-pivot entry of the column, smallest row on ties).
+// element's output block.  Panels of PB columns are eliminated in registers (lane pr of wave pc
+// holds rows pr + 64 a and panel columns pc + 4 b, so one wave owns whole columns and finds a
+// pivot alone) with the same pivot rule as the register kernel (largest not-yet-pivot entry of
+// the column, smallest row on ties), then copied to LDS as the update's left factor.
 // A run of exchange steps on distinct rows P and columns Q composes into one block exchange:
 // with M = the panel columns after elimination and U = A[P][c] before it, every column c
 // outside the panel becomes A[r][c] <- [r not in P] A[r][c] + sum_j M[r][j] U[j][c].

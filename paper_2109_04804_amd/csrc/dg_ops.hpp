@@ -8,8 +8,10 @@
 //   R1    jet = w                          DG[F]
 //   R2    jet = w + e sigma                DG[F.b]                    (Eq. DGSEM_wtt)
 //   RES   jet = w + e sigma                G1 = w - b + DG[-a1dt F.a + bc F.b], G2 = sigma - DG[F.a]
-//   JVP   jet = w + e_s sigma + e_d dw + e_e dsigma
-//                                          Jw = dw + DG[-a1dt F.d + bc (F.e + F.sd)], Js = dsigma - DG[F.d]
+//   JVP   jet = w + e_s sigma + e_d dw + e_s e_d dsigma   (hyper-dual; without the Hessian term:
+//               w + e1 dw + e2 dsigma)
+//                                          Jw = dw + DG[-a1dt F.d + bc F.m], Js = dsigma - DG[F.d]
+//               (F.m = F'(w) dsigma + F''(w)[sigma, dw]; without the Hessian term F'(w) dsigma)
 //   KCOL  jet = w + e unit_col   (local)   column col of K = dR1_i/dw_i
 //   PCPRE jet = w + e1 vs + e2 (vw - a1dt vs) (local)
 //                                          a = vw - bc K vs, c = vs + K (vw - a1dt vs)
@@ -114,15 +116,30 @@ template <typename T> struct OpRes {   // fld: w, sigma, b
     }
 };
 
+template <typename T, bool HESS> struct JvpJet;
+template <typename T> struct JvpJet<T, true> {   // w + e_s sigma + e_d dw + e_s e_d dsigma
+    using S = HDual<T>;
+    HD static S make(const T* x) { return {x[0], x[1], x[2], x[3]}; }
+    HD static T first(const S& f) { return f.d; }
+    HD static T second(const S& f) { return f.m; }
+};
+template <typename T> struct JvpJet<T, false> {   // w + e1 dw + e2 dsigma
+    using S = Dual2<T>;
+    HD static S make(const T* x) { return {x[0], x[2], x[3]}; }
+    HD static T first(const S& f) { return f.b; }
+    HD static T second(const S& f) { return f.c; }
+};
+
 template <typename T, bool HESS> struct OpJvp {   // fld: w, sigma, dw, dsigma
-    using S = Jet5<T>;
+    using J = JvpJet<T, HESS>;
+    using S = typename J::S;
     static constexpr int NJ = 4, NC = 2;
     static constexpr bool LOCAL = false;
     HD static T load(const OpArgs<T>& a, int j, size_t g, int loc) { return a.fld[j][g]; }
-    HD static S make(const T* x, const OpArgs<T>& a) { return {x[0], x[1], x[2], x[3], T(0)}; }
+    HD static S make(const T* x, const OpArgs<T>& a) { return J::make(x); }
     HD static void combo(const S& f, T* c, const OpArgs<T>& a) {
-        c[0] = -a.c0 * f.d + a.c1 * (HESS ? f.e + f.sd : f.e);
-        c[1] = f.d;
+        c[0] = -a.c0 * J::first(f) + a.c1 * J::second(f);
+        c[1] = J::first(f);
     }
     HD static void output(const OpArgs<T>& a, size_t g, int e, int loc, const T* gv) {
         a.out[0][g] = a.fld[2][g] + gv[0];

@@ -4,9 +4,10 @@
 //
 //   Dual<T>  a + b e                      one direction
 //   Dual2<T> a + b e1 + c e2              two independent directions, no cross term
-//   Jet5<T>  a + s e_s + d e_d + e e_e + sd e_s e_d   (e_s^2 = e_d^2 = e_e^2 = 0,
-//            e_e e_s = e_e e_d = 0): directions sigma (s), dw (d), dsigma (e)
-//            and the mixed second derivative along (sigma, dw).
+//   HDual<T> a + s e_s + d e_d + m e_s e_d (hyper-dual, e_s^2 = e_d^2 = 0): for
+//            x = w + sigma e_s + dw e_d + dsigma e_s e_d the e_d part of F(x) is
+//            F'(w) dw and the e_s e_d part F'(w) dsigma + F''(w)[sigma, dw]: both
+//            JVP terms (with the Hessian term) in four components.
 //
 // Non-smooth functions branch on the value part: |x| uses sign(a) with
 // sign(0) = +1; max(x, y) returns x when a_x >= a_y.
@@ -17,7 +18,7 @@
 
 template <typename T> struct Dual { T a, b; };
 template <typename T> struct Dual2 { T a, b, c; };
-template <typename T> struct Jet5 { T a, s, d, e, sd; };
+template <typename T> struct HDual { T a, s, d, m; };
 
 // ---------------------------------------------------------------- plain scalars
 template <typename T> HD T jrecip(T x) { return T(1) / x; }
@@ -62,40 +63,32 @@ template <typename T> HD Dual2<T> jabs(Dual2<T> x) { return x.a >= T(0) ? x : -x
 template <typename T> HD Dual2<T> jmax(Dual2<T> x, Dual2<T> y) { return x.a >= y.a ? x : y; }
 template <typename T> HD T jval(Dual2<T> x) { return x.a; }
 
-// ---------------------------------------------------------------- Jet5
-template <typename T> HD Jet5<T> operator+(Jet5<T> x, Jet5<T> y) {
-    return {x.a + y.a, x.s + y.s, x.d + y.d, x.e + y.e, x.sd + y.sd};
+// ---------------------------------------------------------------- HDual
+template <typename T> HD HDual<T> operator+(HDual<T> x, HDual<T> y) { return {x.a + y.a, x.s + y.s, x.d + y.d, x.m + y.m}; }
+template <typename T> HD HDual<T> operator-(HDual<T> x, HDual<T> y) { return {x.a - y.a, x.s - y.s, x.d - y.d, x.m - y.m}; }
+template <typename T> HD HDual<T> operator-(HDual<T> x) { return {-x.a, -x.s, -x.d, -x.m}; }
+template <typename T> HD HDual<T> operator*(HDual<T> x, HDual<T> y) {
+    return {x.a * y.a, x.a * y.s + x.s * y.a, x.a * y.d + x.d * y.a, x.a * y.m + x.s * y.d + x.d * y.s + x.m * y.a};
 }
-template <typename T> HD Jet5<T> operator-(Jet5<T> x, Jet5<T> y) {
-    return {x.a - y.a, x.s - y.s, x.d - y.d, x.e - y.e, x.sd - y.sd};
-}
-template <typename T> HD Jet5<T> operator-(Jet5<T> x) { return {-x.a, -x.s, -x.d, -x.e, -x.sd}; }
-template <typename T> HD Jet5<T> operator*(Jet5<T> x, Jet5<T> y) {
-    return {x.a * y.a,
-            x.a * y.s + x.s * y.a,
-            x.a * y.d + x.d * y.a,
-            x.a * y.e + x.e * y.a,
-            x.a * y.sd + x.s * y.d + x.d * y.s + x.sd * y.a};
-}
-template <typename T> HD Jet5<T> operator*(Jet5<T> x, T k) { return {x.a * k, x.s * k, x.d * k, x.e * k, x.sd * k}; }
-template <typename T> HD Jet5<T> operator*(T k, Jet5<T> x) { return x * k; }
-template <typename T> HD Jet5<T> operator+(Jet5<T> x, T k) { return {x.a + k, x.s, x.d, x.e, x.sd}; }
+template <typename T> HD HDual<T> operator*(HDual<T> x, T k) { return {x.a * k, x.s * k, x.d * k, x.m * k}; }
+template <typename T> HD HDual<T> operator*(T k, HDual<T> x) { return x * k; }
+template <typename T> HD HDual<T> operator+(HDual<T> x, T k) { return {x.a + k, x.s, x.d, x.m}; }
 // g(x) with g(a) = f0, g'(a) = f1, g''(a) = f2
-template <typename T> HD Jet5<T> japply(Jet5<T> x, T f0, T f1, T f2) {
-    return {f0, f1 * x.s, f1 * x.d, f1 * x.e, f1 * x.sd + f2 * x.s * x.d};
+template <typename T> HD HDual<T> japply(HDual<T> x, T f0, T f1, T f2) {
+    return {f0, f1 * x.s, f1 * x.d, f1 * x.m + f2 * x.s * x.d};
 }
-template <typename T> HD Jet5<T> jrecip(Jet5<T> x) {
+template <typename T> HD HDual<T> jrecip(HDual<T> x) {
     T r = T(1) / x.a;
     return japply(x, r, -r * r, T(2) * r * r * r);
 }
-template <typename T> HD Jet5<T> jsqrt(Jet5<T> x) {
+template <typename T> HD HDual<T> jsqrt(HDual<T> x) {
     T s = sqrt(x.a);
     T d1 = T(0.5) / s;
     return japply(x, s, d1, -T(0.5) * d1 / x.a);
 }
-template <typename T> HD Jet5<T> jabs(Jet5<T> x) { return x.a >= T(0) ? x : -x; }
-template <typename T> HD Jet5<T> jmax(Jet5<T> x, Jet5<T> y) { return x.a >= y.a ? x : y; }
-template <typename T> HD T jval(Jet5<T> x) { return x.a; }
+template <typename T> HD HDual<T> jabs(HDual<T> x) { return x.a >= T(0) ? x : -x; }
+template <typename T> HD HDual<T> jmax(HDual<T> x, HDual<T> y) { return x.a >= y.a ? x : y; }
+template <typename T> HD T jval(HDual<T> x) { return x.a; }
 
 // constant of the jet type
 template <typename S, typename T> HD S jconst(T k);
@@ -105,5 +98,5 @@ template <> HD Dual<double> jconst<Dual<double>, double>(double k) { return {k, 
 template <> HD Dual<float> jconst<Dual<float>, float>(float k) { return {k, 0.0f}; }
 template <> HD Dual2<double> jconst<Dual2<double>, double>(double k) { return {k, 0.0, 0.0}; }
 template <> HD Dual2<float> jconst<Dual2<float>, float>(float k) { return {k, 0.0f, 0.0f}; }
-template <> HD Jet5<double> jconst<Jet5<double>, double>(double k) { return {k, 0.0, 0.0, 0.0, 0.0}; }
-template <> HD Jet5<float> jconst<Jet5<float>, float>(float k) { return {k, 0.0f, 0.0f, 0.0f, 0.0f}; }
+template <> HD HDual<double> jconst<HDual<double>, double>(double k) { return {k, 0.0, 0.0, 0.0}; }
+template <> HD HDual<float> jconst<HDual<float>, float>(float k) { return {k, 0.0f, 0.0f, 0.0f}; }
