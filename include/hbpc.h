@@ -129,6 +129,10 @@ typedef struct {
                              ||r|| > pc_fallback ||r at the cycle's start||, or the network output
                              is not finite, the cycle's correction is dropped and BJ_ext takes over
                              for the rest of the stage solve (default 0.5; <= 0 never falls back) */
+    int pc_half;          /* HBPC_MIXED: 1 stores the BJ_ext blocks S^-1 in FP16 (formed and inverted
+                             in FP32, rounded once; the apply sums in FP32): half the bytes of the
+                             apply.  Element blocks of at most 144 unknowns; an entry beyond the
+                             FP16 range makes the build fail with HBPC_ERR_NONFINITE.  Default 0. */
     void* stream;         /* hipStream_t; NULL = the null stream */
 } hbpc_params;
 
@@ -191,9 +195,11 @@ int hbpc_jvp_f32(hbpc_ctx* ctx, const float* w, const float* sigma, double a1dt,
 
 /* Build BJ_ext at state w (Sec. 3.2.3): K_i = element-local dR1/dw (every
  * quantity read from a neighbour held constant), S_i = I - a1dt K_i +
- * bcoef K_i^2, S_i^-1 by Gauss-Jordan elimination with partial pivoting.
- * precision HBPC_FP64 or HBPC_MIXED selects the storage of S^-1.  The blocks
- * are kept in the context until the next build. */
+ * bcoef K_i^2, S_i^-1 by Gauss-Jordan elimination with partial pivoting
+ * (element blocks of up to 1024 unknowns; HBPC_ERR_UNSUPPORTED above).  precision HBPC_FP64 or
+ * HBPC_MIXED selects the storage (and arithmetic) of S^-1.  The blocks are
+ * kept in the context until the next build (they share storage with the
+ * first stage's blocks of hbpc_step). */
 int hbpc_pc_build(hbpc_ctx* ctx, const double* w, double a1dt, double bcoef, int precision);
 /* With params.precond == HBPC_PC_LEARNED the build only records w (and its
  * FP32 copy for HBPC_MIXED) and the coefficients; apply then runs the learned

@@ -85,15 +85,18 @@ static void apply_vr(const void* SinvT, const void* xa, const void* xc, void* yw
         launch_apply<TM, T, 1>(M, (const T*)xa, (const T*)xc, (T*)yw, (T*)ys, NE, nE, st);
 }
 
-hipError_t bj_apply(const void* SinvT, int m_f32, const void* xa, const void* xc, void* yw, void* ys, int v_f32,
+// m_type: storage of S^-1, 0 FP64, 1 FP32, 2 FP16 (FP32 vectors only); the sums run in the vector type
+hipError_t bj_apply(const void* SinvT, int m_type, const void* xa, const void* xc, void* yw, void* ys, int v_f32,
                     int NE, int nE, hipStream_t st) {
     if (nE == 0) return hipSuccess;
     if (NE > 1024) return hipErrorInvalidValue;
+    if (m_type == 2 && !v_f32) return hipErrorInvalidValue;
     if (v_f32) {
-        if (m_f32) apply_vr<float, float>(SinvT, xa, xc, yw, ys, NE, nE, st);
+        if (m_type == 2) apply_vr<_Float16, float>(SinvT, xa, xc, yw, ys, NE, nE, st);
+        else if (m_type == 1) apply_vr<float, float>(SinvT, xa, xc, yw, ys, NE, nE, st);
         else apply_vr<double, float>(SinvT, xa, xc, yw, ys, NE, nE, st);
     } else {
-        if (m_f32) apply_vr<float, double>(SinvT, xa, xc, yw, ys, NE, nE, st);
+        if (m_type == 1) apply_vr<float, double>(SinvT, xa, xc, yw, ys, NE, nE, st);
         else apply_vr<double, double>(SinvT, xa, xc, yw, ys, NE, nE, st);
     }
     return hipGetLastError();

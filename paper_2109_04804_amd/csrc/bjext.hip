@@ -11,6 +11,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <type_traits>
 
 template <int TGR, int TGC, int RR, int RC, typename T, typename TO>
 __global__ void __launch_bounds__(TGR* TGC) bj_invert_kernel(const double* __restrict__ KT, TO* __restrict__ SinvT,
@@ -184,7 +185,12 @@ __global__ void __launch_bounds__(TGR* TGC) bj_invert_kernel(const double* __res
 #pragma unroll
         for (int a = 0; a < RR; ++a) {
             const int r = tr + TGR * a;
-            if (r < NE) out[(size_t)col * NE + s_pinv[r]] = (TO)acc[a][b];
+            if (r < NE) {
+                if constexpr (sizeof(TO) == 2) {   // half storage: an entry beyond its range is flagged
+                    if (!(acc[a][b] <= T(65504) && acc[a][b] >= T(-65504))) atomicOr(status, 1);
+                }
+                out[(size_t)col * NE + s_pinv[r]] = (TO)acc[a][b];
+            }
         }
     }
 }
@@ -543,12 +549,13 @@ __global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* __re
 }
 
 // the arithmetic follows the storage of S^-1: FP64 blocks are formed and inverted in FP64, FP32
-// blocks (mixed precision) in FP32 from the FP64 K
+// blocks (mixed precision) in FP32 from the FP64 K; FP16 blocks in FP32, rounded once when stored
 template <int TGR, int TGC, int RR, int RC, typename TO>
 static hipError_t launch_inv(const double* KT, TO* SinvT, int NE, int nE, double a1dt, double bc, int* status,
                              hipStream_t st) {
-    hipLaunchKernelGGL((bj_invert_kernel<TGR, TGC, RR, RC, TO, TO>), dim3(nE), dim3(TGR * TGC), 0, st, KT, SinvT,
-                       NE, (TO)a1dt, (TO)bc, status);
+    using T = typename std::conditional<sizeof(TO) == 2, float, TO>::type;
+    hipLaunchKernelGGL((bj_invert_kernel<TGR, TGC, RR, RC, T, TO>), dim3(nE), dim3(TGR * TGC), 0, st, KT, SinvT,
+                       NE, (T)a1dt, (T)bc, status);
     return hipGetLastError();
 }
 
@@ -574,16 +581,19 @@ static hipError_t launch_inv_big(double* KT, T* SinvT, int NE, int nE, double a1
     return hipErrorInvalidValue;
 }
 
-// KT: the chunk's K blocks; for blocks above 144 unknowns they are overwritten (used as scratch)
-hipError_t bj_invert(double* KT, void* SinvT, int f32, int NE, int nE, double a1dt, double bc, int* status,
+// KT: the chunk's K blocks; for blocks above 144 unknowns they are overwritten (used as scratch).
+// type: storage of S^-1, 0 FP64, 1 FP32, 2 FP16 (blocks of at most 144 unknowns)
+hipError_t bj_invert(double* KT, void* SinvT, int type, int NE, int nE, double a1dt, double bc, int* status,
                      hipStream_t st) {
     if (nE == 0) return hipSuccess;
-    if (NE > 144 && NE <= 1024)
-        return f32 ? launch_inv_big<float>(KT, (float*)SinvT, NE, nE, a1dt, bc, status, st)
-                   : launch_inv_big<double>(KT, (double*)SinvT, NE, nE, a1dt, bc, status, st);
+    if (NE > 144 && NE <= 1024 && type != 2)
+        return type == 1 ? launch_inv_big<float>(KT, (float*)SinvT, NE, nE, a1dt, bc, status, st)
+                         : launch_inv_big<double>(KT, (double*)SinvT, NE, nE, a1dt, bc, status, st);
+    if (NE > 144) return hipErrorInvalidValue;
 #define HBPC_INV(TGR, TGC, RR, RC)                                                                         \
-    return f32 ? launch_inv<TGR, TGC, RR, RC, float>(KT, (float*)SinvT, NE, nE, a1dt, bc, status, st)    \
-               : launch_inv<TGR, TGC, RR, RC, double>(KT, (double*)SinvT, NE, nE, a1dt, bc, status, st);
+    if (type == 2) return launch_inv<TGR, TGC, RR, RC, _Float16>(KT, (_Float16*)SinvT, NE, nE, a1dt, bc, status, st); \
+    return type == 1 ? launch_inv<TGR, TGC, RR, RC, float>(KT, (float*)SinvT, NE, nE, a1dt, bc, status, st)    \
+                     : launch_inv<TGR, TGC, RR, RC, double>(KT, (double*)SinvT, NE, nE, a1dt, bc, status, st);
     if (NE <= 16) { HBPC_INV(4, 4, 4, 4) }
     if (NE <= 32) { HBPC_INV(8, 8, 4, 4) }
     if (NE <= 64) { HBPC_INV(16, 16, 4, 4) }

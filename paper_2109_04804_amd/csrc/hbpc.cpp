@@ -299,21 +299,25 @@ static double dnorm(hbpc_ctx* c, const void* x, size_t n, int f32) {
 static void pc_build(hbpc_ctx* c, const double* w, double a1dt, double bc, int f32) {
     double t0 = now_ms();
     if (c->NE > 1024) set_err(c, HBPC_ERR_UNSUPPORTED, "BJ_ext supports element blocks up to 1024 unknowns");
+    const int type = f32 ? (c->prm.pc_half ? 2 : 1) : 0;
+    if (type == 2 && c->NE > 144)
+        set_err(c, HBPC_ERR_UNSUPPORTED, "FP16 BJ_ext blocks need element blocks of at most 144 unknowns");
+    const size_t esz = type == 2 ? 2 : (type == 1 ? 4 : 8);
     void*& S = c->Sinv_slot[c->cur_slot];
-    if (!S || c->sinv_f32_slot[c->cur_slot] != f32) {
+    if (!S || c->sinv_type_slot[c->cur_slot] != type) {
         dfree(S);
         S = nullptr;
         c->slot_valid[c->cur_slot] = 0;
         size_t cnt = (size_t)c->nE * c->NE * c->NE;
-        S = f32 ? (void*)dalloc<float>(c, cnt) : (void*)dalloc<double>(c, cnt);
-        c->sinv_f32_slot[c->cur_slot] = f32;
+        S = (void*)dalloc<char>(c, cnt * esz);
+        c->sinv_type_slot[c->cur_slot] = type;
     }
     c->Sinv = S;
     c->sinv_f32 = f32;
+    c->sinv_type = type;
     if (!c->KT) c->KT = dalloc<double>(c, c->kt_chunk * c->NE * c->NE);
     op_trace(c, w, c->trw, 0);
     status_reset(c);
-    const size_t esz = f32 ? 4 : 8;
     for (size_t eb = 0; eb < (size_t)c->nE; eb += c->kt_chunk) {
         size_t ee = std::min((size_t)c->nE, eb + c->kt_chunk);
         {
@@ -327,7 +331,7 @@ static void pc_build(hbpc_ctx* c, const double* w, double a1dt, double bc, int f
             op_launch(c, r, 0);
         }
         long pi = prof_begin(c, KC_BJINV);
-        hipchk(c, bj_invert(c->KT, (char*)c->Sinv + eb * c->NE * c->NE * esz, f32, c->NE, (int)(ee - eb), a1dt, bc,
+        hipchk(c, bj_invert(c->KT, (char*)c->Sinv + eb * c->NE * c->NE * esz, type, c->NE, (int)(ee - eb), a1dt, bc,
                             c->dstatus, c->stream),
                "bj_invert");
         const double ne = c->NE, cnt = (double)(ee - eb);
@@ -348,7 +352,8 @@ static void pc_build(hbpc_ctx* c, const double* w, double a1dt, double bc, int f
 static void pc_use_slot(hbpc_ctx* c, int slot) {
     c->cur_slot = slot;
     c->Sinv = c->Sinv_slot[slot];
-    c->sinv_f32 = c->sinv_f32_slot[slot];
+    c->sinv_type = c->sinv_type_slot[slot];
+    c->sinv_f32 = c->sinv_type != 0;
     c->pc_a1dt = c->slot_a1dt[slot];
     c->pc_bc = c->slot_bc[slot];
     c->pc_valid = c->slot_valid[slot];
@@ -370,11 +375,12 @@ static void pc_apply(hbpc_ctx* c, const void* w, const void* trw, const void* X,
     r.c1 = c->pc_bc;
     op_launch(c, r, f32);
     long pi = prof_begin(c, KC_BJAPPLY);
-    hipchk(c, bj_apply(c->Sinv, c->sinv_f32, kv, kv + c->ndof * esz, Y, (char*)Y + c->ndof * esz, f32, c->NE, c->nE,
+    hipchk(c, bj_apply(c->Sinv, c->sinv_type, kv, kv + c->ndof * esz, Y, (char*)Y + c->ndof * esz, f32, c->NE, c->nE,
                        c->stream),
            "bj_apply");
     prof_end(c, pi, KC_BJAPPLY,
-             (double)c->nE * c->NE * c->NE * (c->sinv_f32 ? 4.0 : 8.0) + 4.0 * c->ndof * esz);
+             (double)c->nE * c->NE * c->NE * (c->sinv_type == 2 ? 2.0 : (c->sinv_type == 1 ? 4.0 : 8.0)) +
+                 4.0 * c->ndof * esz);
 }
 
 // ------------------------------------------------------------------ learned preconditioner

@@ -133,6 +133,23 @@ def test_pc_kept_per_stage(precision, rtol, tol):
     assert rel(host(out), BJExt(dg, w0, a1dt, bc).apply(Xv)) < 1e-10
 
 
+def test_pc_half_storage_step():
+    """2-D Euler vortex, 4x4 elements, N = 3, HBPC(6,2), dt = 0.1, mixed precision with the
+    BJ_ext blocks stored in FP16: the preconditioner changes the Krylov path only, the step
+    reaches the oracle's Newton root (relative L2 <= 1e-8 at eps_N = 1e-8)."""
+    case = dict(CASES["euler2_n3_lobatto"])
+    case.update(nelem=[4, 4], nodes="gauss")
+    dg = oracle_for(case)
+    X = dg.node_coords()
+    w0 = inputs.isentropic_vortex(X[0], X[1], 4.6, 5.3, 3.0)
+    ctx = ctx_for(case, q=6, kmax=2, newton_rtol=1e-8, gmres_rtol=1e-5, precision="mixed", pc_half=1)
+    wg = dev(w0)
+    stats = ctx.step(wg, 0.1)
+    print(stats, flush=True)
+    ref = dg_hbpc_step(dg, w0, 0.1, 6, 2, StageSolver(dg, newton_rtol=1e-8, gmres_rtol=1e-5))
+    assert rel(host(wg), ref) < 1e-8
+
+
 def test_newton_rounding_floor_stop():
     """2-D Euler vortex, 4x4 elements, N = 3, HBPC(6,2), dt = 0.1, FP64, with an
     unreachable relative Newton tolerance (1e-30) and no absolute one: every solve ends
