@@ -93,20 +93,21 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def patch_indices(nelem, e):
-    """Element indices of the 3^d patch centred on element e (periodic), in
-    the lexicographic order of a 3^d mesh (x fastest)."""
+def patch_indices(nelem, e, radius=1):
+    """Element indices of the (2 radius + 1)^d patch centred on element e
+    (periodic), in the lexicographic order of a (2 radius + 1)^d mesh (x fastest)."""
     d = len(nelem)
+    w = 2 * radius + 1
     coords = []
     r = e
     for m in range(d):
         coords.append(r % nelem[m])
         r //= nelem[m]
     idx = []
-    for k in range(3 if d > 2 else 1):
-        for j in range(3 if d > 1 else 1):
-            for i in range(3):
-                off = [i - 1, j - 1, k - 1][:d]
+    for k in range(w if d > 2 else 1):
+        for j in range(w if d > 1 else 1):
+            for i in range(w):
+                off = [i - radius, j - radius, k - radius][:d]
                 c = [(coords[m] + off[m]) % nelem[m] for m in range(d)]
                 g = 0
                 mul = 1
@@ -117,15 +118,18 @@ def patch_indices(nelem, e):
     return np.array(idx)
 
 
-def patch_oracle(case, dg_full):
-    """Oracle on a 3^d periodic patch with the full mesh's element size; the
-    centre element (index (3^d - 1)/2) sees exactly its true neighbours."""
+def patch_oracle(case, dg_full, radius=1):
+    """Oracle on a (2 radius + 1)^d periodic patch with the full mesh's element
+    size; the centre element (index ((2 radius + 1)^d - 1)/2) sees exactly the
+    elements within `radius` of it (radius 2 for BR1, whose lifted gradient of a
+    neighbour reads that neighbour's neighbours)."""
     d = case["dim"]
+    w = 2 * radius + 1
     h = [case["length"][m] / case["nelem"][m] for m in range(d)]
     sub = dict(case)
-    sub["nelem"] = [3] * d
-    sub["length"] = [3 * h[m] for m in range(d)]
-    return oracle_for(sub), (3 ** d - 1) // 2
+    sub["nelem"] = [w] * d
+    sub["length"] = [w * h[m] for m in range(d)]
+    return oracle_for(sub), (w ** d - 1) // 2
 
 
 def _rowsum(dg):

@@ -3,13 +3,15 @@
 The GPU evaluates the operators on the whole mesh (the launch configuration
 the benchmark times); the oracle evaluates each sampled element on the 3^d
 patch of elements around it (a periodic 3^d mesh with the same element size,
-so the centre element sees exactly its true neighbours), which is all the
-operators depend on.  Samples: seeded random elements plus the first and last
-element (periodic wrap in every direction).
+so the centre element sees exactly its true neighbours; 5^d for viscous
+Burgers, whose BR1 lifted gradients of the neighbours read their own
+neighbours), which is all the operators depend on.  Samples: seeded random
+elements plus the first and last element (periodic wrap in every direction).
 
 Workloads: the 2-D Euler vortex, 128 x 128 elements, N = 5 (2,359,296 DOF),
-and the 3-D eps-scaled Euler Taylor-Green vortex, 48^3 elements, N = 3
-(35,389,440 DOF).  Tolerances as in test_gpu_parity.
+the 3-D eps-scaled Euler Taylor-Green vortex, 48^3 elements, N = 3
+(35,389,440 DOF), and 2-D viscous Burgers with BR1, 64 x 64 elements, N = 4
+(102,400 DOF).  Tolerances as in test_gpu_parity.
 """
 import time
 
@@ -26,6 +28,8 @@ torch = pytest.importorskip("torch")
 VORTEX = dict(dim=2, nelem=[128, 128], length=[10.0, 10.0], N=5, equation="euler", nodes="gauss", flux="rusanov")
 TGV = dict(dim=3, nelem=[48, 48, 48], length=[2 * np.pi] * 3, N=3, equation="euler", nodes="gauss",
            flux="rusanov", eps_ref=0.1)
+BURGERS = dict(dim=2, nelem=[64, 64], length=[2 * np.pi] * 2, N=4, equation="burgers", nodes="gauss", flux="lf",
+               nu=0.01, **{"lambda": 1.0})
 
 
 def ctx_for(case, **over):
@@ -38,6 +42,8 @@ def ctx_for(case, **over):
 def full_state(case, ctx):
     xi, _ = ctx.nodes()
     X = inputs.node_coords(case["dim"], case["nelem"], case["length"], [0, 0, 0], xi)
+    if case["equation"] == "burgers":
+        return inputs.burgers(X[0], X[1])
     if case["dim"] == 2:
         xc, yc, beta = inputs.vortex_params(inputs.DEFAULT_SEED, beta=5.0)
         return inputs.isentropic_vortex(X[0], X[1], xc, yc, beta)
@@ -61,7 +67,7 @@ def host(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("case", [VORTEX, TGV], ids=["vortex128", "tgv48"])
+@pytest.mark.parametrize("case", [VORTEX, TGV, BURGERS], ids=["vortex128", "tgv48", "burgers64"])
 def test_fullsize_residuals_and_jvp(case):
     ctx = ctx_for(case, gmres_restart=1, precond="none")
     print("full-size case", case["nelem"], "ndof", ctx.ndof, flush=True)
@@ -97,9 +103,10 @@ def test_fullsize_residuals_and_jvp(case):
                 torch.cat([dev(dw).float(), dev(ds).float()]), J32)
     R1, R2, JJ, JJ32 = host(r1), host(r2), host(J), host(J32)
     n = ctx.ndof
+    radius = 2 if case["equation"] == "burgers" else 1   # BR1: neighbours' lifted gradients
     for e in samples(nE):
-        idx = patch_indices(case["nelem"], e)
-        dgp, c = patch_oracle(case, None)
+        idx = patch_indices(case["nelem"], e, radius)
+        dgp, c = patch_oracle(case, None, radius)
         wp, sp, dwp, dsp = (gather(x, idx, ne).reshape(len(idx), dgp.nvar, dgp.nnode) for x in (w, s, dw, ds))
         ref1 = dgp.r1(wp)[c]
         check(R1.reshape(nE, ne)[e], ref1, flux_scale(dgp, wp) , label="R1 e=%d" % e)
@@ -210,13 +217,14 @@ def _integral(case, ctx, w):
     return jac * np.einsum("evn,n->v", w.reshape(nE, -1, wt.size), wt)
 
 
-@pytest.mark.parametrize("case,dt", [(VORTEX, 0.1), (TGV, 0.027)], ids=["vortex128", "tgv48"])
-def test_fullsize_step_conserves(case, dt):
+@pytest.mark.parametrize("case,dt,precision", [(VORTEX, 0.1, "mixed"), (TGV, 0.027, "mixed"),
+                                              (BURGERS, 0.1, "fp64")], ids=["vortex128", "tgv48", "burgers64"])
+def test_fullsize_step_conserves(case, dt, precision):
     """One mixed-precision HBPC(6,4) step at the benchmark's sizes and settings (eps_N 1e-8,
     FGMRES(30) at eps_G 1e-3, BJ_ext): the integral of every conserved variable is kept to the
     Newton tolerance (the stage equations conserve it exactly; the inexact solves leave
     |G| <= 1e-8 |G0|), the state moves and stays finite."""
-    ctx = ctx_for(case, q=6, kmax=4, newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=30, precision="mixed",
+    ctx = ctx_for(case, q=6, kmax=4, newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=30, precision=precision,
                   precond="bjext")
     w0 = full_state(case, ctx)
     wd = torch.tensor(np.ascontiguousarray(w0).reshape(-1), dtype=torch.float64, device="cuda")
