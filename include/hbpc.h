@@ -131,8 +131,8 @@ typedef struct {
                              for the rest of the stage solve (default 0.5; <= 0 never falls back) */
     int pc_half;          /* HBPC_MIXED: 1 stores the BJ_ext blocks S^-1 in FP16 (formed and inverted
                              in FP32, rounded once; the apply sums in FP32): half the bytes of the
-                             apply.  Element blocks of at most 144 unknowns; an entry beyond the
-                             FP16 range makes the build fail with HBPC_ERR_NONFINITE.  Default 0. */
+                             apply.  An entry beyond the FP16 range makes the build fail with
+                             HBPC_ERR_NONFINITE.  Default 0. */
     void* stream;         /* hipStream_t; NULL = the null stream */
 } hbpc_params;
 

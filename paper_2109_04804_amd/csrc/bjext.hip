@@ -297,9 +297,13 @@ template <typename T> __device__ __forceinline__ void lds_rows4(const T* p, T* o
     }
 }
 
-template <typename T, int RR, int PB>
-__global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* __restrict__ KT, T* __restrict__ SinvT,
-                                                                   int NE, T a1dt, T bc, int* __restrict__ status) {
+// TO: storage of S^-1.  For FP16 storage (T = float) the working matrix cannot live in the output
+// block; the element's K slot (NE^2 doubles) then holds K converted to FP32 in its first half and
+// the working matrix in its second half, and only the final permuted store writes the output.
+template <typename T, typename TO, int RR, int PB>
+__global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* KT, TO* __restrict__ SinvT, int NE,
+                                                                   T a1dt, T bc, int* __restrict__ status) {
+    constexpr bool HALF = sizeof(TO) == 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const BigLds<T> L = big_lds<T>(NE, PB);
     const int nep = L.nep;
@@ -317,8 +321,30 @@ __global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* __re
     const int tr = tid % 16, tc = tid / 16;
     const size_t e = blockIdx.x;
     const size_t nn = (size_t)NE * NE;
-    const double* K = KT + e * nn;
-    T* A = SinvT + e * nn;
+    double* Kd = KT + e * nn;
+    float* Kf = reinterpret_cast<float*>(Kd);                   // HALF: FP32 copy of K, first half of the slot
+    T* A = HALF ? reinterpret_cast<T*>(Kf + nn) : reinterpret_cast<T*>(SinvT + e * nn);
+    auto Kat = [&](size_t i) -> double { return HALF ? (double)Kf[i] : Kd[i]; };
+    if constexpr (HALF) {
+        // in place, chunk by chunk: the floats of chunk c overwrite doubles of chunks <= c, which
+        // have been read (each chunk's loads finish at the barrier before its stores)
+        constexpr int CH = 4 * BIG_THREADS;
+        for (size_t c0 = 0; c0 < nn; c0 += CH) {
+            double v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const size_t i = c0 + tid + (size_t)q * BIG_THREADS;
+                v[q] = i < nn ? Kd[i] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const size_t i = c0 + tid + (size_t)q * BIG_THREADS;
+                if (i < nn) Kf[i] = (float)v[q];
+            }
+            __syncthreads();
+        }
+    }
 
     // ---- S = I - a1dt K + bc K^2 into A (K staged through LDS in slabs of 16, the next slab's
     // loads issued before the current slab's products)
@@ -337,9 +363,9 @@ __global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* __re
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int k = kk + ta + 4 * q, r = r0 + xa;
-                        ga[q] = (k < NE && r < NE) ? K[(size_t)k * NE + r] : 0.0;       // K[r][k]
+                        ga[q] = (k < NE && r < NE) ? Kat((size_t)k * NE + r) : 0.0;       // K[r][k]
                         const int k2 = kk + tb, cc = c0 + yb + 16 * q;
-                        gb[q] = (k2 < NE && cc < NE) ? K[(size_t)cc * NE + k2] : 0.0;   // K[k][c]
+                        gb[q] = (k2 < NE && cc < NE) ? Kat((size_t)cc * NE + k2) : 0.0;   // K[k][c]
                     }
                 };
                 fetch(0);
@@ -374,7 +400,7 @@ __global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* __re
                         const int r = r0 + 4 * tr + i;
                         if (r >= NE) continue;
                         T v = (r == cc) ? T(1) : T(0);
-                        v += -a1dt * (T)K[(size_t)cc * NE + r] + bc * acc[i][b];
+                        v += -a1dt * (T)Kat((size_t)cc * NE + r) + bc * acc[i][b];
                         A[(size_t)cc * NE + r] = v;
                     }
                 }
@@ -539,12 +565,22 @@ __global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* __re
         }
     }
     // ---- S^-1[pinv[r]][prow[c]] = A[r][c], stored column-major (SinvT[col][row])
-    T* slot = reinterpret_cast<T*>(KT + e * nn);
-    for (size_t i = tid; i < nn; i += BIG_THREADS) slot[i] = A[i];
-    __syncthreads();
-    for (size_t i = tid; i < nn; i += BIG_THREADS) {
-        const int cc = (int)(i / NE), r = (int)(i % NE);
-        A[(size_t)s_prow[cc] * NE + s_pinv[r]] = slot[i];
+    TO* out = SinvT + e * nn;
+    if constexpr (HALF) {   // A is in the K slot: one permuted, rounded store (out-of-range entries flagged)
+        for (size_t i = tid; i < nn; i += BIG_THREADS) {
+            const int cc = (int)(i / NE), r = (int)(i % NE);
+            const T v = A[i];
+            if (!(v <= T(65504) && v >= T(-65504))) atomicOr(status, 1);
+            out[(size_t)s_prow[cc] * NE + s_pinv[r]] = (TO)v;
+        }
+    } else {                // A is the output block: copy it to the K slot first
+        T* slot = reinterpret_cast<T*>(KT + e * nn);
+        for (size_t i = tid; i < nn; i += BIG_THREADS) slot[i] = A[i];
+        __syncthreads();
+        for (size_t i = tid; i < nn; i += BIG_THREADS) {
+            const int cc = (int)(i / NE), r = (int)(i % NE);
+            out[(size_t)s_prow[cc] * NE + s_pinv[r]] = (TO)slot[i];
+        }
     }
 }
 
@@ -561,12 +597,13 @@ static hipError_t launch_inv(const double* KT, TO* SinvT, int NE, int nE, double
 
 // blocked kernel configurations: rows per lane RR (NE <= 64 RR) and panel width PB, chosen so that
 // the panel fits in registers and its LDS copy (PB x NE) in 64 KiB
-template <typename T, int RR, int PB>
-static hipError_t launch_big(double* KT, T* SinvT, int NE, int nE, double a1dt, double bc, int* status,
+template <typename TO, int RR, int PB>
+static hipError_t launch_big(double* KT, TO* SinvT, int NE, int nE, double a1dt, double bc, int* status,
                              hipStream_t st) {
+    using T = typename std::conditional<sizeof(TO) == 2, float, TO>::type;
     const size_t sh = big_lds<T>(NE, PB).bytes;
     if (sh > 65536) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((bj_invert_big_kernel<T, RR, PB>), dim3(nE), dim3(BIG_THREADS), sh, st, KT, SinvT, NE,
+    hipLaunchKernelGGL((bj_invert_big_kernel<T, TO, RR, PB>), dim3(nE), dim3(BIG_THREADS), sh, st, KT, SinvT, NE,
                        (T)a1dt, (T)bc, status);
     return hipGetLastError();
 }
@@ -574,7 +611,7 @@ static hipError_t launch_big(double* KT, T* SinvT, int NE, int nE, double a1dt, 
 template <typename T>
 static hipError_t launch_inv_big(double* KT, T* SinvT, int NE, int nE, double a1dt, double bc, int* status,
                                  hipStream_t st) {
-    constexpr bool F = sizeof(T) == 4;
+    constexpr bool F = sizeof(T) <= 4;   // FP32 arithmetic (FP32 or FP16 storage)
     if (NE <= 320) return launch_big<T, 5, F ? 32 : 16>(KT, SinvT, NE, nE, a1dt, bc, status, st);
     if (NE <= 640) return launch_big<T, 10, F ? 16 : 8>(KT, SinvT, NE, nE, a1dt, bc, status, st);
     if (NE <= 1024) return launch_big<T, 16, F ? 8 : 4>(KT, SinvT, NE, nE, a1dt, bc, status, st);
@@ -582,13 +619,15 @@ static hipError_t launch_inv_big(double* KT, T* SinvT, int NE, int nE, double a1
 }
 
 // KT: the chunk's K blocks; for blocks above 144 unknowns they are overwritten (used as scratch).
-// type: storage of S^-1, 0 FP64, 1 FP32, 2 FP16 (blocks of at most 144 unknowns)
+// type: storage of S^-1, 0 FP64, 1 FP32, 2 FP16
 hipError_t bj_invert(double* KT, void* SinvT, int type, int NE, int nE, double a1dt, double bc, int* status,
                      hipStream_t st) {
     if (nE == 0) return hipSuccess;
-    if (NE > 144 && NE <= 1024 && type != 2)
+    if (NE > 144 && NE <= 1024) {
+        if (type == 2) return launch_inv_big<_Float16>(KT, (_Float16*)SinvT, NE, nE, a1dt, bc, status, st);
         return type == 1 ? launch_inv_big<float>(KT, (float*)SinvT, NE, nE, a1dt, bc, status, st)
                          : launch_inv_big<double>(KT, (double*)SinvT, NE, nE, a1dt, bc, status, st);
+    }
     if (NE > 144) return hipErrorInvalidValue;
 #define HBPC_INV(TGR, TGC, RR, RC)                                                                         \
     if (type == 2) return launch_inv<TGR, TGC, RR, RC, _Float16>(KT, (_Float16*)SinvT, NE, nE, a1dt, bc, status, st); \

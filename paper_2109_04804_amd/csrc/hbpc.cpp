@@ -300,8 +300,6 @@ static void pc_build(hbpc_ctx* c, const double* w, double a1dt, double bc, int f
     double t0 = now_ms();
     if (c->NE > 1024) set_err(c, HBPC_ERR_UNSUPPORTED, "BJ_ext supports element blocks up to 1024 unknowns");
     const int type = f32 ? (c->prm.pc_half ? 2 : 1) : 0;
-    if (type == 2 && c->NE > 144)
-        set_err(c, HBPC_ERR_UNSUPPORTED, "FP16 BJ_ext blocks need element blocks of at most 144 unknowns");
     const size_t esz = type == 2 ? 2 : (type == 1 ? 4 : 8);
     void*& S = c->Sinv_slot[c->cur_slot];
     if (!S || c->sinv_type_slot[c->cur_slot] != type) {

@@ -87,6 +87,25 @@ def perturbation(dg, seed, scale=None):
     return s * rng.standard_normal(w.shape)
 
 
+def half_storage_bound(Ks, vw, vs, a1dt, bc, ref):
+    """Relative error bound of the BJ_ext apply with every entry of S_e^-1 rounded to FP16
+    (unit roundoff 2^-11): y = (S^-1 a, S^-1 c) with a = vw - bc K vs, c = vs + K (vw - a1dt vs)
+    per element, so |dy| <= 2^-11 (|S^-1| |a|, |S^-1| |c|) componentwise; plus the FP32
+    inversion error 2^-24 kappa_2(S_e).  Ks: (nE, ne, ne); vw, vs: (nE, ne); ref: the exact
+    result (both halves)."""
+    ne = Ks.shape[1]
+    I = np.eye(ne)
+    num, kap = 0.0, 0.0
+    for K, xw, xs in zip(Ks, vw, vs):
+        S = I - a1dt * K + bc * (K @ K)
+        Si = np.abs(np.linalg.inv(S))
+        a = xw - bc * (K @ xs)
+        c = xs + K @ (xw - a1dt * xs)
+        num += np.sum((Si @ np.abs(a)) ** 2) + np.sum((Si @ np.abs(c)) ** 2)
+        kap = max(kap, np.linalg.cond(S))
+    return 2.0 ** -11 * np.sqrt(num) / np.linalg.norm(ref) + 2.0 ** -24 * kap
+
+
 def rel(a, b):
     a = np.asarray(a, dtype=np.float64).ravel()
     b = np.asarray(b, dtype=np.float64).ravel()

@@ -16,7 +16,7 @@ seeded inputs.  Tolerances:
 import numpy as np
 import pytest
 
-from gpu_cases import (CASES, check, flux_scale, lib_kwargs, lipschitz, oracle_for, patch_indices, patch_oracle,
+from gpu_cases import (half_storage_bound, CASES, check, flux_scale, lib_kwargs, lipschitz, oracle_for, patch_indices, patch_oracle,
                        perturbation, rel, state)
 from oracle.solvers import BJExt
 
@@ -150,38 +150,27 @@ def test_jvp_finite_difference(name):
     assert rel(host(out), np.concatenate([Jw.ravel(), Js.ravel()])) < 1e-6
 
 
-@pytest.mark.parametrize("name", ["euler2_n5", "adv2_ragged", "euler2_n3_lobatto"])
+@pytest.mark.parametrize("name", ["euler2_n5", "adv2_ragged", "euler2_n3_lobatto", "euler3_n3", "euler3_n4"])
 def test_pc_apply_half_storage(name):
     """BJ_ext with S^-1 stored in FP16 (inverted in FP32, FP32 sums): against the oracle within
-    max(1e-3, 2^-11 max_e kappa_2(S_e)), the first-order error of rounding every entry of
-    S^-1 to half precision (unit roundoff 2^-11)."""
+    twice the componentwise bound of rounding every entry of S^-1 to half precision
+    (gpu_cases.half_storage_bound, plus 1e-5 for the FP32 vectors); blocks of 64, 144
+    (register kernel), 320 and 625 unknowns (blocked kernel)."""
     case, dg, ctx = setup(name, pc_half=1)
     w = state(dg)
     a1dt, bc = 0.1, 0.1 ** 2 / 2
     pc = BJExt(dg, w, a1dt, bc)
     ne = ctx.block
-    kappa = max(np.linalg.cond(np.eye(ne) - a1dt * K + bc * (K @ K)) for K in pc.K)
-    X = np.concatenate([perturbation(dg, 6).ravel(), perturbation(dg, 7).ravel()])
+    vw, vs = perturbation(dg, 6), perturbation(dg, 7)
+    X = np.concatenate([vw.ravel(), vs.ravel()])
     ref = pc.apply(X)
     ctx.pc_build(dev(w), a1dt, bc, "mixed")
     out32 = torch.empty(2 * ctx.ndof, dtype=torch.float32, device="cuda")
     ctx.pc_apply_f32(dev(X, torch.float32), out32)
-    err, bound = rel(host(out32), ref), max(1e-3, 2.0 ** -11 * kappa)
-    print(name, "FP16 S^-1 apply rel err", err, "kappa", kappa, "bound", bound)
+    b = half_storage_bound(pc.K, vw.reshape(-1, ne), vs.reshape(-1, ne), a1dt, bc, ref)
+    err, bound = rel(host(out32), ref), 2 * b + 1e-5
+    print(name, "FP16 S^-1 apply rel err", err, "bound", bound)
     assert err < bound
-
-
-def test_pc_half_storage_rejects_large_blocks():
-    """FP16 blocks are built by the register kernel only: 3-D Euler N = 3 (320 unknowns) with
-    pc_half reports HBPC_ERR_UNSUPPORTED."""
-    from paper_2109_04804_amd.hbpc import HbpcError
-    case = dict(CASES["euler3_n3"])
-    case.update(nelem=[1, 1, 1])
-    ctx = make_ctx(case, pc_half=1)
-    w = torch.ones(ctx.ndof, dtype=torch.float64, device="cuda")
-    with pytest.raises(HbpcError) as ei:
-        ctx.pc_build(w, 0.1, 0.005, "mixed")
-    assert ei.value.code == -7
 
 
 def test_pc_build_rejects_blocks_above_1024():
