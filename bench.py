@@ -145,12 +145,12 @@ def run_form(wl, form, steps, warmup, theta=None, pc_rebuild="per_solve"):
     import torch
     from paper_2109_04804_amd.hbpc import Context
     precision = "fp64" if form == "fp64" else "mixed"
-    pc = form if form in ("learned", "learned_first") else "bjext"
+    pc = form if form in ("learned", "learned_first", "learned_guess") else "bjext"
     half = 1 if form == "mixed16" else 0
     ctx = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], wl.get("equation", "euler"), q=6, kmax=4,
                   newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=30, gmres_maxit=7000, precond=pc,
                   precision=precision, pc_fallback=0.5, pc_rebuild=pc_rebuild, pc_half=half, **_eqkw(wl))
-    if pc in ("learned", "learned_first"):
+    if pc.startswith("learned"):
         ctx.mlp_set_params(theta)
     w0 = initial_state(ctx, wl)
     w = torch.tensor(np.ascontiguousarray(w0).reshape(-1), dtype=torch.float64, device="cuda")
@@ -281,7 +281,8 @@ def main():
     ap.add_argument("--forms", default="fp64,mixed,learned",
                     help="comma list of fp64 (BJ_ext FP64), mixed (BJ_ext, FP32 Krylov), learned "
                          "(learned preconditioner with BJ_ext fallback, FP32 Krylov, BF16 network), "
-                         "learned_first (network for the first FGMRES direction, then BJ_ext), mixed16 "
+                         "learned_first (network for the first FGMRES direction, then BJ_ext), "
+                         "learned_guess (network correction as FGMRES initial guess, then BJ_ext), mixed16 "
                          "(as mixed with the BJ_ext blocks stored in FP16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pc-rebuild", default="per_stage", choices=["per_solve", "per_stage"],
@@ -335,13 +336,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"learned": "f64+f32+bf16", "learned_first": "f64+f32+bf16", "mixed": "f64+f32",
+        "dtype": {"learned": "f64+f32+bf16", "learned_first": "f64+f32+bf16", "learned_guess": "f64+f32+bf16",
+                  "mixed": "f64+f32",
                   "mixed16": "f64+f32+f16", "fp64": "f64"}[head],
         "data": "synthetic",
         "config": {"workload": a.workload, "dof": dof, "scheme": "HBPC(6,4)", "dt": wl["dt"],
                    "newton_rtol": 1e-8, "krylov": "FGMRES(30), eps_G 1e-3", "pc_rebuild": a.pc_rebuild,
                    "precond": {"learned": "learned (BJ_ext fallback 0.5)",
-                               "learned_first": "learned first direction, then BJ_ext", "mixed": "BJ_ext",
+                               "learned_first": "learned first direction, then BJ_ext",
+                               "learned_guess": "learned initial guess, then BJ_ext", "mixed": "BJ_ext",
                                "mixed16": "BJ_ext, FP16 blocks", "fp64": "BJ_ext"}[head], "form": head},
         "forms": {f: {"dof_steps_per_s": dof * a.steps / (r["ms_total"] * 1e-3), "ms_per_step": r["ms_per_step"],
                       "newton_its": r["newton_its"], "gmres_its": r["gmres_its"], "pc_fallbacks": r["pc_fallbacks"],

@@ -66,6 +66,9 @@ typedef struct hbpc_ctx hbpc_ctx;
 #define HBPC_PC_BJEXT 1            /* extended block-Jacobi, Sec. 3.2.3 */
 #define HBPC_PC_LEARNED 2          /* per-element network on the Schur system (an addition to
                                       the paper, see hbpc_mlp_*), BJ_ext as fallback */
+#define HBPC_PC_LEARNED_GUESS 4    /* the network's correction of the Newton residual as the
+                                      initial guess of each Newton step's FGMRES (kept only if it
+                                      lowers the residual norm), BJ_ext for every direction */
 #define HBPC_PC_LEARNED_FIRST 3    /* flexible GMRES with the network for the first direction of
                                       each Newton step (z_0 = N(v_0), v_0 the normalised Newton
                                       residual: the network's training input) and BJ_ext for

@@ -754,6 +754,25 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
     if (beta0 == 0.0) return 0;
     // residual vector r (precision f32) in V_0 slot; first cycle r = rhs
     hipchk(c, blas_axpby(1.0, rhs, 0, 0.0, Vj(0), f32, n2, c->stream), "copy");
+    if (c->prm.precond == HBPC_PC_LEARNED_GUESS && c->lpc_active) {
+        // initial guess z = N(rhs) (the network is linear in the residual): r = rhs - J z, kept
+        // when it is smaller than rhs
+        void* z = Zj(0);
+        void* u = Vj(1);
+        lpc_apply(c, w, trw, Vj(0), z, f32);
+        jvp(z, u);
+        hipchk(c, blas_axpby(-1.0, u, f32, 1.0, Vj(0), f32, n2, c->stream), "guess residual");
+        const double nr = dnorm(c, Vj(0), n2, f32);
+        if (std::isfinite(nr) && nr < beta0) {
+            hipchk(c, blas_axpby(1.0, z, f32, 1.0, dX, 0, n2, c->stream), "guess");
+            if (nr <= rtol * beta0) return 0;
+        } else {
+            c->st.pc_fallbacks++;
+            hipchk(c, blas_axpby(1.0, rhs, 0, 0.0, Vj(0), f32, n2, c->stream), "copy");
+        }
+        if (c->verbose)
+            std::fprintf(stderr, "[hbpc] learned initial guess: |r| %.3e -> %.3e\n", beta0, nr);
+    }
     int total = 0, cycle = 0;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
     auto Hc = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
@@ -907,7 +926,7 @@ static void newton_solve(hbpc_ctx* c, const double* b, double a1dt, double bc, c
     if (n0 > 1e-14 * std::sqrt((double)c->n2)) {
         if (mixed) state_traces(c, 1);
         const int pck = c->prm.precond;
-        const int first = pck == HBPC_PC_LEARNED_FIRST;
+        const int first = pck == HBPC_PC_LEARNED_FIRST || pck == HBPC_PC_LEARNED_GUESS;
         const bool kept = keep_pc && c->pc_valid && c->pc_a1dt == a1dt && c->pc_bc == bc && c->sinv_f32 == mixed;
         c->pc_kept = kept;
         if ((pck == HBPC_PC_BJEXT || first) && !kept) pc_build(c, X, a1dt, bc, mixed);
@@ -1076,7 +1095,7 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
         set_err(c, HBPC_ERR_ARG, "upwind flux needs advection");
     if (equation == HBPC_EQ_BURGERS_BR1 && !(prm->nu >= 0)) set_err(c, HBPC_ERR_ARG, "nu must be >= 0");
     if (prm->gmres_restart < 1 || prm->gmres_restart > 64) set_err(c, HBPC_ERR_ARG, "gmres_restart must be 1..64");
-    if (prm->precond < HBPC_PC_NONE || prm->precond > HBPC_PC_LEARNED_FIRST)
+    if (prm->precond < HBPC_PC_NONE || prm->precond > HBPC_PC_LEARNED_GUESS)
         set_err(c, HBPC_ERR_ARG, "unknown precond");
     if (prm->pc_rebuild < HBPC_PC_PER_SOLVE || prm->pc_rebuild > HBPC_PC_PER_STAGE)
         set_err(c, HBPC_ERR_ARG, "unknown pc_rebuild");

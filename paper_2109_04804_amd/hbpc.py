@@ -20,7 +20,7 @@ EQ = {"advection": 1, "burgers": 2, "euler": 3}
 NODES = {"gauss": 0, "lobatto": 1}
 FLUX = {"central": 0, "upwind": 1, "lf": 2, "rusanov": 3}
 PRECISION = {"fp64": 0, "mixed": 1}
-PRECOND = {"none": 0, "bjext": 1, "learned": 2, "learned_first": 3}
+PRECOND = {"none": 0, "bjext": 1, "learned": 2, "learned_first": 3, "learned_guess": 4}
 MLP_PRECISION = {"bf16": 0, "fp32": 1}
 PAIRS = {"newton": 0, "krylov": 1, "random": 2}
 PC_REBUILD = {"per_solve": 0, "per_newton_it": 1, "per_stage": 2}

@@ -73,7 +73,7 @@ def collect_and_train(nelem, L, N, dt, seeds, cap_newton, cap_krylov, per_event,
 
 
 @pytest.mark.parametrize("precond,rebuild", [("learned", "per_solve"), ("learned", "per_stage"),
-                                             ("learned_first", "per_solve")])
+                                             ("learned_first", "per_solve"), ("learned_guess", "per_solve")])
 def test_learned_step_matches_oracle(precond, rebuild):
     """2-D Euler vortex, 4 x 4 elements, N = 3, HBPC(6,2), dt = 0.1, mixed precision,
     learned preconditioner trained on Newton pairs of this mesh (seeds 1..3), with the
@@ -137,7 +137,8 @@ def test_training_and_gain():
     BF16 training, then one mixed step at eps_G = 1e-3 on held-out seed 99 with no
     preconditioner, the network alone (no fallback, at most 20000 Krylov iterations
     per Newton step), the network with the BJ_ext fallback, the network as the first
-    FGMRES direction of each Newton step followed by BJ_ext, and BJ_ext.  Prints the
+    FGMRES direction of each Newton step followed by BJ_ext, the network's correction as
+    the initial guess of each Newton step's FGMRES (BJ_ext after it), and BJ_ext.  Prints the
     Krylov iteration counts; asserts that training lowers the loss and that every
     form that converges reaches the same Newton root."""
     nelem, L, N, dt = [16, 16], 10.0, 3, 0.4
@@ -150,10 +151,11 @@ def test_training_and_gain():
     theta = None
     ev = {}
     for form, pc, fb in (("none", "none", 0.0), ("network", "learned", 0.0), ("network+fallback", "learned", 0.5),
-                         ("network-first", "learned_first", 0.5), ("bjext", "bjext", 0.0)):
+                         ("network-first", "learned_first", 0.5), ("network-guess", "learned_guess", 0.5),
+                         ("bjext", "bjext", 0.0)):
         ctx = ctx_for(2, nelem, [L, L], N, gmres_rtol=1e-3, precision="mixed", precond=pc, pc_fallback=fb,
                       gmres_maxit=20000, **common)
-        if pc in ("learned", "learned_first"):
+        if pc.startswith("learned"):
             if theta is None:
                 ctx.mlp_set_params(random_params(ctx, 7))
                 log = ctx.train_mlp(Xd, Td, count, epochs=30, batch=128, lr=1e-3, seed=5, precision="bf16")
@@ -171,8 +173,8 @@ def test_training_and_gain():
         except Exception as ex:
             print(form, "did not converge:", ex, flush=True)
         ctx.close()
-    for form in ("none", "network", "network+fallback", "network-first"):
+    for form in ("none", "network", "network+fallback", "network-first", "network-guess"):
         if form in ev:
             assert rel(ev[form][2], ev["bjext"][2]) < 1e-7, form
-    assert "network+fallback" in ev and "network-first" in ev
+    assert "network+fallback" in ev and "network-first" in ev and "network-guess" in ev
     print("Krylov iterations per step:", {k: v[0] for k, v in ev.items()})
