@@ -69,6 +69,25 @@ def test_euler_vortex_step(precision, rtol, tol):
     assert rel(host(wg), ref) < tol
 
 
+@pytest.mark.parametrize("q,kmax", [(4, 1), (8, 1), (8, 3)])
+def test_euler_vortex_step_other_tableaux(q, kmax):
+    """2-D Euler vortex, 4x4 elements, N = 3, dt = 0.1, FP64 at eps_N = 1e-12: HBPC(4,1)
+    (two nodes), HBPC(8,1) and HBPC(8,3) (four equispaced nodes; appendix tableaux) against
+    the oracle (relative L2 <= 1e-10)."""
+    case = dict(CASES["euler2_n3_lobatto"])
+    case.update(nelem=[4, 4], nodes="gauss")
+    dg = oracle_for(case)
+    X = dg.node_coords()
+    w0 = inputs.isentropic_vortex(X[0], X[1], 4.6, 5.3, 3.0)
+    ctx = ctx_for(case, q=q, kmax=kmax, newton_rtol=1e-12, gmres_rtol=1e-5, precision="fp64")
+    wg = dev(w0)
+    stats = ctx.step(wg, 0.1)
+    print(q, kmax, stats, flush=True)
+    assert stats["n_solves"] == (q // 2 - 1) * (1 + kmax)
+    ref = dg_hbpc_step(dg, w0, 0.1, q, kmax, StageSolver(dg, newton_rtol=1e-12, gmres_rtol=1e-5))
+    assert rel(host(wg), ref) < 1e-10
+
+
 @pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-12, 1e-10), ("mixed", 1e-8, 1e-8)])
 def test_burgers_br1_step(precision, rtol, tol):
     """2-D viscous Burgers (BR1), 8x8 elements, N = 4, LF lambda = 1, nu = 0.01,
