@@ -58,6 +58,15 @@ def _const(x):
     return x.a if isinstance(x, jets.HD) else x
 
 
+def _const_but_b(x):
+    """Keep the value and the b part, drop the others (neighbour data in the local
+    Hessian block: sigma of the neighbours stays, their dependence on w does not)."""
+    if isinstance(x, jets.HD):
+        z = np.zeros_like(x.a)
+        return jets.HD(x.a, x.b, z, z)
+    return x
+
+
 class DGSEM:
     def __init__(self, mesh, N, eq, nodes="gauss", flux="rusanov", lam=0.0):
         self.mesh = mesh
@@ -131,8 +140,9 @@ class DGSEM:
         nb_right = [self._roll(um[v], -1, m) for v in range(len(u))]   # minus-trace of element e+1
         nb_left = [self._roll(up[v], +1, m) for v in range(len(u))]    # plus-trace of element e-1
         if local:
-            nb_right = [_const(x) for x in nb_right]
-            nb_left = [_const(x) for x in nb_left]
+            keep = _const_but_b if local == "b" else _const
+            nb_right = [keep(x) for x in nb_right]
+            nb_left = [keep(x) for x in nb_left]
         return up, um, nb_left, nb_right
 
     def lift(self, u, local=False):
@@ -238,6 +248,23 @@ class DGSEM:
             R = self._r1_vars(self._jet(w, e.reshape(nE, self.nvar, self.nnode)), local=True)
             K[:, :, col] = self.to_flat([jets.part(x, "b") for x in R]).reshape(nE, ne)
         return K
+
+    def local_hessian(self, w, sigma):
+        """H_i = dR2_i/dw_i at (w, sigma) for every element: the element-local block of
+        R1''(w)[sigma, .], which BJ^H_ext adds to S_i (Sec. 3.2.3).
+
+        sigma is the global field, so the neighbour traces keep their value and sigma
+        parts; only the dependence on the neighbours' w is held constant.  Same shape
+        and index convention as local_jacobian."""
+        nE = self.mesh.n_elem
+        ne = self.nvar * self.nnode
+        H = np.zeros((nE, ne, ne))
+        for col in range(ne):
+            e = np.zeros((nE, ne))
+            e[:, col] = 1.0
+            R = self._r1_vars(self._jet(w, sigma, e.reshape(nE, self.nvar, self.nnode)), local="b")
+            H[:, :, col] = self.to_flat([jets.part(x, "d") for x in R]).reshape(nE, ne)
+        return H
 
     # ------------------------------------------------------------- utilities
     def node_coords(self):

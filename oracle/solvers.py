@@ -26,6 +26,12 @@ A_i = I - a1dt K_i, B_i = bcoef K_i, C_i = -K_i and S_i = A_i - B_i C_i =
 I - a1dt K_i + bcoef K_i^2, the inverse of the block-diagonal P has blocks
 D = S^-1, E = -B S^-1, F = -C S^-1, G = A S^-1, applied as
 P^-1 (vw, vs) = (D vw + E vs, F vw + G vs), S^-1 through an LU factorisation.
+
+BJ^H_ext (Sec. 3.2.3): the same P with the element-local Hessian block
+H_i = dR2_i/dw_i (dgsem.local_hessian, at the state (w, sigma)) kept in
+A^H_i = I - a1dt K_i + bcoef H_i.  S^H_i = A^H_i - B_i C_i =
+I - a1dt K_i + bcoef (H_i + K_i^2) no longer commutes with K_i, and the blocks
+of P^-1 are D^H = S^-1, E^H = -S^-1 B, F^H = -C S^-1, G^H = I + C S^-1 B.
 """
 import numpy as np
 import scipy.linalg as sla
@@ -143,6 +149,47 @@ class BJExt:
         return np.concatenate([out_w.reshape(-1), out_s.reshape(-1)])
 
 
+class BJExtH:
+    """Extended block-Jacobi preconditioner with the Hessian block, BJ^H_ext, built at
+    the state (w, sigma)."""
+
+    def __init__(self, dg, w, sigma, a1dt, bcoef):
+        self.dg = dg
+        self.a1dt = a1dt
+        self.bcoef = bcoef
+        K = dg.local_jacobian(w)
+        H = dg.local_hessian(w, sigma)
+        ne = K.shape[1]
+        I = np.eye(ne)
+        self.K = K
+        self.H = H
+        self.lu = []
+        for i in range(K.shape[0]):
+            A = I - a1dt * K[i] + bcoef * H[i]
+            B = bcoef * K[i]
+            C = -K[i]
+            self.lu.append(sla.lu_factor(A - B @ C))
+
+    def apply(self, X):
+        dg = self.dg
+        n = dg.ndof
+        nE = dg.mesh.n_elem
+        vw = X[:n].reshape(nE, -1)
+        vs = X[n:].reshape(nE, -1)
+        out_w = np.empty_like(vw)
+        out_s = np.empty_like(vs)
+        for i in range(nE):
+            B = self.bcoef * self.K[i]
+            C = -self.K[i]
+            Dw = sla.lu_solve(self.lu[i], vw[i])           # D^H vw = S^-1 vw
+            Es = -sla.lu_solve(self.lu[i], B @ vs[i])      # E^H vs = -S^-1 B vs
+            Fw = -(C @ Dw)                                 # F^H vw = -C S^-1 vw
+            Gs = vs[i] + C @ (-Es)                         # G^H vs = vs + C S^-1 B vs
+            out_w[i] = Dw + Es
+            out_s[i] = Fw + Gs
+        return np.concatenate([out_w.reshape(-1), out_s.reshape(-1)])
+
+
 class StageSolver:
     """Newton on the extended residual of one DGSEM stage equation."""
 
@@ -232,6 +279,8 @@ class StageSolver:
         pc = None
         if self.linear == "gmres" and self.precond == "bjext":
             pc = BJExt(dg, w, a1dt, bcoef)                 # once per Newton solve, at X^0
+        elif self.linear == "gmres" and self.precond == "bjext_h":
+            pc = BJExtH(dg, w, sigma, a1dt, bcoef)
         for it in range(1, self.newton_maxit + 1):
             if self.linear == "dense":
                 J = self.dense_jacobian(w, sigma, a1dt, bcoef)
