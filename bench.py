@@ -14,6 +14,9 @@ forms are timed:
   learned  as mixed with the learned preconditioner (BF16 network, BJ_ext as
            fallback), trained before timing on Newton pairs of FP64 solves of
            seeded vortices on the same mesh.
+On request (--forms) also fp64_h / mixed_h (as fp64 / mixed with BJ^H_ext, the
+element-local Hessian block kept in the preconditioner), mixed16 (S^-1 stored
+in FP16) and the learned_first / learned_guess variants.
 A step is one full HBPC step (all stage solves) on the state resident in HBM;
 inputs are synthetic.  Other workloads (--workload): a 32 x 32 vortex, 2-D
 viscous Burgers 64 x 64 N = 4, and the 3-D eps-scaled Euler Taylor-Green
@@ -144,8 +147,9 @@ def run_form(wl, form, steps, warmup, theta=None, pc_rebuild="per_solve"):
     import numpy as np
     import torch
     from paper_2109_04804_amd.hbpc import Context
-    precision = "fp64" if form == "fp64" else "mixed"
-    pc = form if form in ("learned", "learned_first", "learned_guess") else "bjext"
+    precision = "fp64" if form in ("fp64", "fp64_h") else "mixed"
+    pc = form if form in ("learned", "learned_first", "learned_guess") else ("bjext_h" if form.endswith("_h")
+                                                                             else "bjext")
     half = 1 if form == "mixed16" else 0
     ctx = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], wl.get("equation", "euler"), q=6, kmax=4,
                   newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=30, gmres_maxit=7000, precond=pc,
@@ -214,7 +218,7 @@ def roofline_of(prof, workload, form):
     k = prof[name]
     per_launch_ms = k["total_ms"] / k["launches"]
     if name == "bj_invert":
-        peak = FP64_PEAK_TFLOPS if form == "fp64" else FP32_PEAK_TFLOPS
+        peak = FP64_PEAK_TFLOPS if form in ("fp64", "fp64_h") else FP32_PEAK_TFLOPS
         ach = k["flops"] / k["launches"] / (per_launch_ms * 1e-3) / 1e12
         return {"kernel": name, "bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                 "frac": ach / peak, "traffic": None,
@@ -283,7 +287,8 @@ def main():
                          "(learned preconditioner with BJ_ext fallback, FP32 Krylov, BF16 network), "
                          "learned_first (network for the first FGMRES direction, then BJ_ext), "
                          "learned_guess (network correction as FGMRES initial guess, then BJ_ext), mixed16 "
-                         "(as mixed with the BJ_ext blocks stored in FP16)")
+                         "(as mixed with the BJ_ext blocks stored in FP16), fp64_h / mixed_h (as fp64 / mixed "
+                         "with BJ^H_ext)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pc-rebuild", default="per_stage", choices=["per_solve", "per_stage"],
                     help="BJ_ext builds: kept per corrector stage across sweeps (default), or once per stage "
@@ -338,14 +343,15 @@ def main():
         "vs_baseline": None,
         "dtype": {"learned": "f64+f32+bf16", "learned_first": "f64+f32+bf16", "learned_guess": "f64+f32+bf16",
                   "mixed": "f64+f32",
-                  "mixed16": "f64+f32+f16", "fp64": "f64"}[head],
+                  "mixed16": "f64+f32+f16", "fp64": "f64", "fp64_h": "f64", "mixed_h": "f64+f32"}[head],
         "data": "synthetic",
         "config": {"workload": a.workload, "dof": dof, "scheme": "HBPC(6,4)", "dt": wl["dt"],
                    "newton_rtol": 1e-8, "krylov": "FGMRES(30), eps_G 1e-3", "pc_rebuild": a.pc_rebuild,
                    "precond": {"learned": "learned (BJ_ext fallback 0.5)",
                                "learned_first": "learned first direction, then BJ_ext",
                                "learned_guess": "learned initial guess, then BJ_ext", "mixed": "BJ_ext",
-                               "mixed16": "BJ_ext, FP16 blocks", "fp64": "BJ_ext"}[head], "form": head},
+                               "mixed16": "BJ_ext, FP16 blocks", "fp64": "BJ_ext", "fp64_h": "BJ^H_ext",
+                               "mixed_h": "BJ^H_ext"}[head], "form": head},
         "forms": {f: {"dof_steps_per_s": dof * a.steps / (r["ms_total"] * 1e-3), "ms_per_step": r["ms_per_step"],
                       "newton_its": r["newton_its"], "gmres_its": r["gmres_its"], "pc_fallbacks": r["pc_fallbacks"],
                       "n_solves": r["n_solves"], "finite": r["finite"]}

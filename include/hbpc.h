@@ -75,6 +75,10 @@ typedef struct hbpc_ctx hbpc_ctx;
                                       every later one; a non-finite network output drops the
                                       network for the rest of the stage solve (counted in
                                       pc_fallbacks) */
+#define HBPC_PC_BJEXT_H 5          /* BJ^H_ext, Sec. 3.2.3: BJ_ext with the element-local
+                                      Hessian block dR2/dw kept in P, built at (w, sigma) of the
+                                      Newton iterate (FP64 blocks K and H; S^-1 stored as for
+                                      BJ_ext) */
 
 /* arithmetic of the learned preconditioner's network */
 #define HBPC_MLP_BF16 0            /* BF16 operands on the matrix cores, FP32 accumulation */
@@ -204,6 +208,16 @@ int hbpc_jvp_f32(hbpc_ctx* ctx, const float* w, const float* sigma, double a1dt,
  * kept in the context until the next build (they share storage with the
  * first stage's blocks of hbpc_step). */
 int hbpc_pc_build(hbpc_ctx* ctx, const double* w, double a1dt, double bcoef, int precision);
+/* Build BJ^H_ext at the state (w, sigma) (Sec. 3.2.3): in addition to K_i,
+ * H_i = element-local dR2/dw at (w, sigma), i.e. R1''(w)[sigma, .] with the
+ * neighbours' sigma read and their w held constant; S_i = I - a1dt K_i +
+ * bcoef (K_i^2 + H_i).  S_i no longer commutes with K_i, and the apply is
+ * y = S_i^-1 (vw - bcoef K_i vs), P^-1 (vw, vs) = (y, vs + K_i y).  w and
+ * sigma: ndof device values each, read only.  Same storage, limits and
+ * precision rule as hbpc_pc_build; HBPC_ERR_ARG on a context whose params.precond
+ * is HBPC_PC_LEARNED.  hbpc_pc_apply* below use whichever build came last. */
+int hbpc_pc_build_hess(hbpc_ctx* ctx, const double* w, const double* sigma, double a1dt, double bcoef,
+                       int precision);
 /* With params.precond == HBPC_PC_LEARNED the build only records w (and its
  * FP32 copy for HBPC_MIXED) and the coefficients; apply then runs the learned
  * preconditioner (below) in FP64 or FP32 vectors.

@@ -2,7 +2,9 @@
 //
 // From the element-local Jacobians K_i (stored column-major, KT[e][c][r]
 // = K_i[r][c], FP64, produced column by column by the KCOL operator kernel), form
-// S_i = I - a1dt K_i + bcoef K_i^2 and invert it by Gauss-Jordan
+// S_i = I - a1dt K_i + bcoef K_i^2 (BJ_ext), or with the element-local Hessian
+// block H_i (HT, same layout, optional) S_i = I - a1dt K_i + bcoef (K_i^2 + H_i)
+// (BJ^H_ext), and invert it by Gauss-Jordan
 // elimination with partial pivoting, in the precision S_i^-1 is stored in;
 // store S_i^-1 column-major (SinvT[e][c][r]).
 // Blocks up to 144 unknowns: one workgroup of TG x TG threads per element, the
@@ -14,7 +16,8 @@
 #include <type_traits>
 
 template <int TGR, int TGC, int RR, int RC, typename T, typename TO>
-__global__ void __launch_bounds__(TGR* TGC) bj_invert_kernel(const double* __restrict__ KT, TO* __restrict__ SinvT,
+__global__ void __launch_bounds__(TGR* TGC) bj_invert_kernel(const double* __restrict__ KT,
+                                                            const double* __restrict__ HT, TO* __restrict__ SinvT,
                                                             int NE, T a1dt, T bc, int* __restrict__ status) {
     // thread (tr, tc), tid = tr + TGR tc, owns rows tr + TGR a (a < RR) and
     // columns tc + TGC b (b < RC); a column group (fixed tc) is TGR
@@ -37,6 +40,7 @@ __global__ void __launch_bounds__(TGR* TGC) bj_invert_kernel(const double* __res
     const int tr = tid % TGR, tc = tid / TGR;
     const size_t e = blockIdx.x;
     const double* K = KT + e * (size_t)NE * NE;
+    const double* Hm = HT ? HT + e * (size_t)NE * NE : nullptr;
 
     T acc[RR][RC];
 #pragma unroll
@@ -71,7 +75,7 @@ __global__ void __launch_bounds__(TGR* TGC) bj_invert_kernel(const double* __res
         }
         __syncthreads();
     }
-    // ---- S = I - a1dt K + bc K^2 (padding rows/columns: identity, never used)
+    // ---- S = I - a1dt K + bc (K^2 + H) (padding rows/columns: identity, never used)
     unsigned used = 0u;   // bit a: owned row a has been a pivot row
 #pragma unroll
     for (int a = 0; a < RR; ++a)
@@ -79,7 +83,10 @@ __global__ void __launch_bounds__(TGR* TGC) bj_invert_kernel(const double* __res
         for (int b = 0; b < RC; ++b) {
             int r = tr + TGR * a, c = tc + TGC * b;
             T v = (r == c) ? T(1) : T(0);
-            if (r < NE && c < NE) v += -a1dt * (T)K[(size_t)c * NE + r] + bc * acc[a][b];
+            if (r < NE && c < NE) {
+                T h = Hm ? (T)Hm[(size_t)c * NE + r] : T(0);
+                v += -a1dt * (T)K[(size_t)c * NE + r] + bc * (acc[a][b] + h);
+            }
             acc[a][b] = v;
         }
 
@@ -301,7 +308,8 @@ template <typename T> __device__ __forceinline__ void lds_rows4(const T* p, T* o
 // block; the element's K slot (NE^2 doubles) then holds K converted to FP32 in its first half and
 // the working matrix in its second half, and only the final permuted store writes the output.
 template <typename T, typename TO, int RR, int PB>
-__global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* KT, TO* __restrict__ SinvT, int NE,
+__global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* KT, const double* __restrict__ HT,
+                                                                   TO* __restrict__ SinvT, int NE,
                                                                    T a1dt, T bc, int* __restrict__ status) {
     constexpr bool HALF = sizeof(TO) == 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -346,7 +354,7 @@ __global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* KT, 
         }
     }
 
-    // ---- S = I - a1dt K + bc K^2 into A (K staged through LDS in slabs of 16, the next slab's
+    // ---- S = I - a1dt K + bc (K^2 + H) into A (K staged through LDS in slabs of 16, the next slab's
     // loads issued before the current slab's products)
     {
         const int xa = tid % BIG_TILE, ta = tid / BIG_TILE;   // sA: t = ta + 4 q, x = xa
@@ -400,7 +408,8 @@ __global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* KT, 
                         const int r = r0 + 4 * tr + i;
                         if (r >= NE) continue;
                         T v = (r == cc) ? T(1) : T(0);
-                        v += -a1dt * (T)Kat((size_t)cc * NE + r) + bc * acc[i][b];
+                        const T h = HT ? (T)HT[e * nn + (size_t)cc * NE + r] : T(0);
+                        v += -a1dt * (T)Kat((size_t)cc * NE + r) + bc * (acc[i][b] + h);
                         A[(size_t)cc * NE + r] = v;
                     }
                 }
@@ -587,10 +596,10 @@ __global__ void __launch_bounds__(BIG_THREADS) bj_invert_big_kernel(double* KT, 
 // the arithmetic follows the storage of S^-1: FP64 blocks are formed and inverted in FP64, FP32
 // blocks (mixed precision) in FP32 from the FP64 K; FP16 blocks in FP32, rounded once when stored
 template <int TGR, int TGC, int RR, int RC, typename TO>
-static hipError_t launch_inv(const double* KT, TO* SinvT, int NE, int nE, double a1dt, double bc, int* status,
+static hipError_t launch_inv(const double* KT, const double* HT, TO* SinvT, int NE, int nE, double a1dt, double bc, int* status,
                              hipStream_t st) {
     using T = typename std::conditional<sizeof(TO) == 2, float, TO>::type;
-    hipLaunchKernelGGL((bj_invert_kernel<TGR, TGC, RR, RC, T, TO>), dim3(nE), dim3(TGR * TGC), 0, st, KT, SinvT,
+    hipLaunchKernelGGL((bj_invert_kernel<TGR, TGC, RR, RC, T, TO>), dim3(nE), dim3(TGR * TGC), 0, st, KT, HT, SinvT,
                        NE, (T)a1dt, (T)bc, status);
     return hipGetLastError();
 }
@@ -598,41 +607,42 @@ static hipError_t launch_inv(const double* KT, TO* SinvT, int NE, int nE, double
 // blocked kernel configurations: rows per lane RR (NE <= 64 RR) and panel width PB, chosen so that
 // the panel fits in registers and its LDS copy (PB x NE) in 64 KiB
 template <typename TO, int RR, int PB>
-static hipError_t launch_big(double* KT, TO* SinvT, int NE, int nE, double a1dt, double bc, int* status,
+static hipError_t launch_big(double* KT, const double* HT, TO* SinvT, int NE, int nE, double a1dt, double bc, int* status,
                              hipStream_t st) {
     using T = typename std::conditional<sizeof(TO) == 2, float, TO>::type;
     const size_t sh = big_lds<T>(NE, PB).bytes;
     if (sh > 65536) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((bj_invert_big_kernel<T, TO, RR, PB>), dim3(nE), dim3(BIG_THREADS), sh, st, KT, SinvT, NE,
+    hipLaunchKernelGGL((bj_invert_big_kernel<T, TO, RR, PB>), dim3(nE), dim3(BIG_THREADS), sh, st, KT, HT, SinvT, NE,
                        (T)a1dt, (T)bc, status);
     return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t launch_inv_big(double* KT, T* SinvT, int NE, int nE, double a1dt, double bc, int* status,
+static hipError_t launch_inv_big(double* KT, const double* HT, T* SinvT, int NE, int nE, double a1dt, double bc, int* status,
                                  hipStream_t st) {
     constexpr bool F = sizeof(T) <= 4;   // FP32 arithmetic (FP32 or FP16 storage)
-    if (NE <= 320) return launch_big<T, 5, F ? 32 : 16>(KT, SinvT, NE, nE, a1dt, bc, status, st);
-    if (NE <= 640) return launch_big<T, 10, F ? 16 : 8>(KT, SinvT, NE, nE, a1dt, bc, status, st);
-    if (NE <= 1024) return launch_big<T, 16, F ? 8 : 4>(KT, SinvT, NE, nE, a1dt, bc, status, st);
+    if (NE <= 320) return launch_big<T, 5, F ? 32 : 16>(KT, HT, SinvT, NE, nE, a1dt, bc, status, st);
+    if (NE <= 640) return launch_big<T, 10, F ? 16 : 8>(KT, HT, SinvT, NE, nE, a1dt, bc, status, st);
+    if (NE <= 1024) return launch_big<T, 16, F ? 8 : 4>(KT, HT, SinvT, NE, nE, a1dt, bc, status, st);
     return hipErrorInvalidValue;
 }
 
 // KT: the chunk's K blocks; for blocks above 144 unknowns they are overwritten (used as scratch).
+// HT: the chunk's Hessian blocks H (BJ^H_ext), same layout, or nullptr (BJ_ext).
 // type: storage of S^-1, 0 FP64, 1 FP32, 2 FP16
-hipError_t bj_invert(double* KT, void* SinvT, int type, int NE, int nE, double a1dt, double bc, int* status,
+hipError_t bj_invert(double* KT, const double* HT, void* SinvT, int type, int NE, int nE, double a1dt, double bc, int* status,
                      hipStream_t st) {
     if (nE == 0) return hipSuccess;
     if (NE > 144 && NE <= 1024) {
-        if (type == 2) return launch_inv_big<_Float16>(KT, (_Float16*)SinvT, NE, nE, a1dt, bc, status, st);
-        return type == 1 ? launch_inv_big<float>(KT, (float*)SinvT, NE, nE, a1dt, bc, status, st)
-                         : launch_inv_big<double>(KT, (double*)SinvT, NE, nE, a1dt, bc, status, st);
+        if (type == 2) return launch_inv_big<_Float16>(KT, HT, (_Float16*)SinvT, NE, nE, a1dt, bc, status, st);
+        return type == 1 ? launch_inv_big<float>(KT, HT, (float*)SinvT, NE, nE, a1dt, bc, status, st)
+                         : launch_inv_big<double>(KT, HT, (double*)SinvT, NE, nE, a1dt, bc, status, st);
     }
     if (NE > 144) return hipErrorInvalidValue;
 #define HBPC_INV(TGR, TGC, RR, RC)                                                                         \
-    if (type == 2) return launch_inv<TGR, TGC, RR, RC, _Float16>(KT, (_Float16*)SinvT, NE, nE, a1dt, bc, status, st); \
-    return type == 1 ? launch_inv<TGR, TGC, RR, RC, float>(KT, (float*)SinvT, NE, nE, a1dt, bc, status, st)    \
-                     : launch_inv<TGR, TGC, RR, RC, double>(KT, (double*)SinvT, NE, nE, a1dt, bc, status, st);
+    if (type == 2) return launch_inv<TGR, TGC, RR, RC, _Float16>(KT, HT, (_Float16*)SinvT, NE, nE, a1dt, bc, status, st); \
+    return type == 1 ? launch_inv<TGR, TGC, RR, RC, float>(KT, HT, (float*)SinvT, NE, nE, a1dt, bc, status, st)    \
+                     : launch_inv<TGR, TGC, RR, RC, double>(KT, HT, (double*)SinvT, NE, nE, a1dt, bc, status, st);
     if (NE <= 16) { HBPC_INV(4, 4, 4, 4) }
     if (NE <= 32) { HBPC_INV(8, 8, 4, 4) }
     if (NE <= 64) { HBPC_INV(16, 16, 4, 4) }

@@ -6,7 +6,8 @@
 enum {
     OPK_TRACE = 0, OPK_R1, OPK_R2, OPK_RES, OPK_JVP, OPK_JVP_NOHESS, OPK_KCOL, OPK_PCPRE,
     OPK_LIFT,     // BR1 lifting (viscous Burgers only)
-    OPK_LINLOC    // x + c0 K(w) s, K the element-local Jacobian of BJ_ext
+    OPK_LINLOC,   // x + c0 K(w) s, K the element-local Jacobian of BJ_ext
+    OPK_KHCOL     // columns of K and of the element-local Hessian block H (BJ^H_ext, FP64)
 };
 
 struct GeomHost {
@@ -81,7 +82,7 @@ hipError_t launch_op(const GeomHost& g, const LaunchReq& r) {
     OpArgs<T> a = make_args<T>(g, r);
     int grid = (a.e_end - a.e_begin + EPB - 1) / EPB;
     if (grid <= 0) return hipSuccess;
-    dim3 gd(grid, r.op == OPK_KCOL ? EQ::NV * NN : 1);   // KCOL: one grid row per column of K
+    dim3 gd(grid, (r.op == OPK_KCOL || r.op == OPK_KHCOL) ? EQ::NV * NN : 1);   // one grid row per column
     hipLaunchKernelGGL((dg_op_kernel<D, NP, EQ, OP, T>), gd, dim3(EPB * NN), 0, r.stream, a, make_eq<T>(g));
     return hipGetLastError();
 }
@@ -107,6 +108,9 @@ template <int D, int NP, class EQ, typename T> hipError_t launch_family_np(const
     case OPK_KCOL: return launch_op<D, NP, EQ, OpKcol<T, NV * NN>, T>(g, r);
     case OPK_PCPRE: return launch_op<D, NP, EQ, OpPcPre<T>, T>(g, r);
     case OPK_LINLOC: return launch_op<D, NP, EQ, OpLin<T, true>, T>(g, r);
+    case OPK_KHCOL:
+        if constexpr (sizeof(T) == 8) return launch_op<D, NP, EQ, OpKHcol<T, NV * NN>, T>(g, r);
+        return hipErrorInvalidValue;
     case OPK_LIFT: {
         if (!EQ::VISC) return hipErrorInvalidValue;
         constexpr int EPB = 256 / NN > 0 ? 256 / NN : 1;

@@ -13,11 +13,14 @@
 //                                          Jw = dw + DG[-a1dt F.d + bc F.m], Js = dsigma - DG[F.d]
 //               (F.m = F'(w) dsigma + F''(w)[sigma, dw]; without the Hessian term F'(w) dsigma)
 //   KCOL  jet = w + e unit_col   (local)   column col of K = dR1_i/dw_i
+//   KHCOL jet = w + e_s sigma + e_d unit_col (local in e_d)
+//                                          column col of K and of H = dR2_i/dw_i (BJ^H_ext)
 //   PCPRE jet = w + e1 vs + e2 (vw - a1dt vs) (local)
 //                                          a = vw - bc K vs, c = vs + K (vw - a1dt vs)
 // "local": every quantity read from a neighbour is held at its value (the
 // direction parts of neighbour traces are zero) -- the element-local Jacobian
-// of the BJ_ext preconditioner (Sec. 3.2.3).
+// of the BJ_ext preconditioner (Sec. 3.2.3).  Each op names NGLOB: jet fields
+// j < NGLOB read their neighbour traces, the others are zero across faces.
 //
 // Layout: fields x[e][v][node]; traces tr[e][face][v][fp], face = 2m + side
 // (side 1 = +e_m), fp enumerates the other directions in increasing order.
@@ -83,7 +86,7 @@ template <int D, int NP> HD int fp_of_node(int node, int m) {
 template <typename T> struct OpR1 {
     using S = T;
     static constexpr int NJ = 1, NC = 1;
-    static constexpr bool LOCAL = false;
+    static constexpr int NGLOB = NJ;
     HD static T load(const OpArgs<T>& a, int j, size_t g, int loc) { return a.fld[0][g]; }
     HD static S make(const T* x, const OpArgs<T>& a) { return x[0]; }
     HD static void combo(const S& f, T* c, const OpArgs<T>& a) { c[0] = f; }
@@ -93,7 +96,7 @@ template <typename T> struct OpR1 {
 template <typename T> struct OpR2 {
     using S = Dual<T>;
     static constexpr int NJ = 2, NC = 1;
-    static constexpr bool LOCAL = false;
+    static constexpr int NGLOB = NJ;
     HD static T load(const OpArgs<T>& a, int j, size_t g, int loc) { return a.fld[j][g]; }
     HD static S make(const T* x, const OpArgs<T>& a) { return {x[0], x[1]}; }
     HD static void combo(const S& f, T* c, const OpArgs<T>& a) { c[0] = f.b; }
@@ -103,7 +106,7 @@ template <typename T> struct OpR2 {
 template <typename T> struct OpRes {   // fld: w, sigma, b
     using S = Dual<T>;
     static constexpr int NJ = 2, NC = 2;
-    static constexpr bool LOCAL = false;
+    static constexpr int NGLOB = NJ;
     HD static T load(const OpArgs<T>& a, int j, size_t g, int loc) { return a.fld[j][g]; }
     HD static S make(const T* x, const OpArgs<T>& a) { return {x[0], x[1]}; }
     HD static void combo(const S& f, T* c, const OpArgs<T>& a) {
@@ -134,7 +137,7 @@ template <typename T, bool HESS> struct OpJvp {   // fld: w, sigma, dw, dsigma
     using J = JvpJet<T, HESS>;
     using S = typename J::S;
     static constexpr int NJ = 4, NC = 2;
-    static constexpr bool LOCAL = false;
+    static constexpr int NGLOB = NJ;
     HD static T load(const OpArgs<T>& a, int j, size_t g, int loc) { return a.fld[j][g]; }
     HD static S make(const T* x, const OpArgs<T>& a) { return J::make(x); }
     HD static void combo(const S& f, T* c, const OpArgs<T>& a) {
@@ -150,7 +153,7 @@ template <typename T, bool HESS> struct OpJvp {   // fld: w, sigma, dw, dsigma
 template <typename T, int NE> struct OpKcol {   // fld: w; column = blockIdx.y; writes K^T[e][col][row]
     using S = Dual<T>;
     static constexpr int NJ = 2, NC = 1;
-    static constexpr bool LOCAL = true;
+    static constexpr int NGLOB = 1;
     HD static T load(const OpArgs<T>& a, int j, size_t g, int loc) {
         return j == 0 ? a.fld[0][g] : (loc == (int)blockIdx.y ? T(1) : T(0));
     }
@@ -161,10 +164,30 @@ template <typename T, int NE> struct OpKcol {   // fld: w; column = blockIdx.y; 
     }
 };
 
+// fld: w, sigma; column = blockIdx.y; writes K^T (out[0]) and H^T (out[1]), H = dR2_i/dw_i at
+// (w, sigma): the e_s e_d part of the hyper-dual flux is F''(w)[sigma, e_col].  The neighbours'
+// sigma enters the face fluxes (NGLOB = 2); their dependence on w does not.
+template <typename T, int NE> struct OpKHcol {
+    using S = HDual<T>;
+    static constexpr int NJ = 4, NC = 2;
+    static constexpr int NGLOB = 2;
+    HD static T load(const OpArgs<T>& a, int j, size_t g, int loc) {
+        if (j < 2) return a.fld[j][g];
+        return (j == 2 && loc == (int)blockIdx.y) ? T(1) : T(0);
+    }
+    HD static S make(const T* x, const OpArgs<T>& a) { return {x[0], x[1], x[2], x[3]}; }
+    HD static void combo(const S& f, T* c, const OpArgs<T>& a) { c[0] = f.d; c[1] = f.m; }
+    HD static void output(const OpArgs<T>& a, size_t g, int e, int loc, const T* gv) {
+        const size_t i = ((size_t)(e - a.e_begin) * NE + blockIdx.y) * NE + loc;
+        a.out[0][i] = gv[0];
+        a.out[1][i] = gv[1];
+    }
+};
+
 template <typename T> struct OpPcPre {   // fld: w, vw, vs
     using S = Dual2<T>;
     static constexpr int NJ = 3, NC = 2;
-    static constexpr bool LOCAL = true;
+    static constexpr int NGLOB = 1;
     HD static T load(const OpArgs<T>& a, int j, size_t g, int loc) {
         if (j == 0) return a.fld[0][g];
         if (j == 1) return a.fld[2][g];
@@ -183,7 +206,7 @@ template <typename T> struct OpPcPre {   // fld: w, vw, vs
 template <typename T, bool LOC> struct OpLin {
     using S = Dual<T>;
     static constexpr int NJ = 2, NC = 1;
-    static constexpr bool LOCAL = LOC;
+    static constexpr int NGLOB = LOC ? 1 : NJ;
     HD static T load(const OpArgs<T>& a, int j, size_t g, int loc) { return a.fld[j][g]; }
     HD static S make(const T* x, const OpArgs<T>& a) { return {x[0], x[1]}; }
     HD static void combo(const S& f, T* c, const OpArgs<T>& a) { c[0] = f.b; }
@@ -319,7 +342,7 @@ __device__ __forceinline__ void face_point(const OpArgs<T>& a, const EqParams<T>
 #pragma unroll
             for (int q = 0; q < NP; ++q) acc += l[q] * s_fld[j][fel][v][node_on_line<D, NP>(fp, M, q)];
             x[j] = acc;
-            const T* t = (OP::LOCAL && j > 0) ? nullptr : a.trc[j];
+            const T* t = j >= OP::NGLOB ? nullptr : a.trc[j];
             y[j] = t ? t[nbase + (size_t)v * NFP] : T(0);
         }
         own[v] = OP::make(x, a);
@@ -339,7 +362,7 @@ __device__ __forceinline__ void face_point(const OpArgs<T>& a, const EqParams<T>
 #pragma unroll
             for (int q = 0; q < NP; ++q) acc += l[q] * qj[node_on_line<D, NP>(fp, M, q)];
             x[j] = acc;
-            const T* t = (OP::LOCAL && j > 0) ? nullptr : a.qtr[j];
+            const T* t = j >= OP::NGLOB ? nullptr : a.qtr[j];
             y[j] = t ? t[((size_t)enb * 2 * D + (2 * M + 1 - SIDE)) * NFP + fp] : T(0);
         }
         S qo = OP::make(x, a), qn = OP::make(y, a);
@@ -400,7 +423,7 @@ __global__ void __launch_bounds__(256) dg_op_kernel(OpArgs<T> a, EqParams<T> ep)
             for (int j = 0; j < NJ; ++j) {
                 T own = T(0);
                 for (int q = 0; q < NP; ++q) own += l[q] * s_fld[j][fel][0][node_on_line<D, NP>(fp, m, q)];
-                const T* t = (OP::LOCAL && j > 0) ? nullptr : a.trc[j];
+                const T* t = j >= OP::NGLOB ? nullptr : a.trc[j];
                 const T nbv = t ? t[nb] : T(0);
                 s_us[((j * EPB + fel) * 2 * D + face) * NFP + fp] = T(0.5) * (own + nbv);
             }

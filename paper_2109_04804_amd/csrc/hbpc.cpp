@@ -169,6 +169,7 @@ int op_launch(hbpc_ctx* c, const LaunchReq& r, int f32) {
     case OPK_JVP:
     case OPK_JVP_NOHESS: cls = KC_JVP; bytes = 6 * n * esz; break;
     case OPK_KCOL: cls = KC_KCOL; bytes = (double)(r.e_end - r.e_begin) * c->NE * (8.0 + c->NE * 8.0); break;
+    case OPK_KHCOL: cls = KC_KCOL; bytes = (double)(r.e_end - r.e_begin) * c->NE * (16.0 + c->NE * 16.0); break;
     case OPK_PCPRE: cls = KC_PCPRE; bytes = 5 * n * esz; break;
     case OPK_LINLOC: cls = KC_LIN; bytes = 4 * n * esz; break;
     }
@@ -296,7 +297,9 @@ static double dnorm(hbpc_ctx* c, const void* x, size_t n, int f32) {
 }
 
 // ------------------------------------------------------------------ BJ_ext
-static void pc_build(hbpc_ctx* c, const double* w, double a1dt, double bc, int f32) {
+// BJ_ext blocks at w, or with sigma given the BJ^H_ext blocks at (w, sigma) (Sec. 3.2.3)
+static void pc_build(hbpc_ctx* c, const double* w, const double* sigma, double a1dt, double bc, int f32) {
+    const bool hess = sigma != nullptr;
     double t0 = now_ms();
     if (c->NE > 1024) set_err(c, HBPC_ERR_UNSUPPORTED, "BJ_ext supports element blocks up to 1024 unknowns");
     const int type = f32 ? (c->prm.pc_half ? 2 : 1) : 0;
@@ -314,31 +317,41 @@ static void pc_build(hbpc_ctx* c, const double* w, double a1dt, double bc, int f
     c->sinv_f32 = f32;
     c->sinv_type = type;
     if (!c->KT) c->KT = dalloc<double>(c, c->kt_chunk * c->NE * c->NE);
+    if (hess && !c->HT) c->HT = dalloc<double>(c, c->kt_chunk * c->NE * c->NE);
     op_trace(c, w, c->trw, 0);
+    if (hess) op_trace(c, sigma, c->trs, 0);
     status_reset(c);
     for (size_t eb = 0; eb < (size_t)c->nE; eb += c->kt_chunk) {
         size_t ee = std::min((size_t)c->nE, eb + c->kt_chunk);
         {
-            LaunchReq r = op_req(c, OPK_KCOL);   // all NE columns of K in one launch
+            LaunchReq r = op_req(c, hess ? OPK_KHCOL : OPK_KCOL);   // all NE columns in one launch
             r.fld[0] = w;
             r.trc[0] = c->trw;
             r.qtr[0] = op_lift(c, w, c->trw, 0, 0);
             r.out[0] = c->KT;
+            if (hess) {
+                // the lifted gradient of sigma only reaches the e_s part, which is not written
+                r.fld[1] = sigma;
+                r.trc[1] = c->trs;
+                r.out[1] = c->HT;
+            }
             r.e_begin = (int)eb;
             r.e_end = (int)ee;
             op_launch(c, r, 0);
         }
         long pi = prof_begin(c, KC_BJINV);
-        hipchk(c, bj_invert(c->KT, (char*)c->Sinv + eb * c->NE * c->NE * esz, type, c->NE, (int)(ee - eb), a1dt, bc,
-                            c->dstatus, c->stream),
+        hipchk(c, bj_invert(c->KT, hess ? c->HT : nullptr, (char*)c->Sinv + eb * c->NE * c->NE * esz, type, c->NE,
+                            (int)(ee - eb), a1dt, bc, c->dstatus, c->stream),
                "bj_invert");
         const double ne = c->NE, cnt = (double)(ee - eb);
-        prof_end(c, pi, KC_BJINV, cnt * ne * ne * (8.0 + esz), cnt * 4.0 * ne * ne * ne);
+        prof_end(c, pi, KC_BJINV, cnt * ne * ne * ((hess ? 16.0 : 8.0) + esz), cnt * 4.0 * ne * ne * ne);
     }
     if (status_read(c)) set_err(c, HBPC_ERR_NONFINITE, "BJ_ext: singular or non-finite element block");
     c->pc_a1dt = a1dt;
     c->pc_bc = bc;
     c->pc_valid = 1;
+    c->pc_hess = hess;
+    c->slot_hess[c->cur_slot] = hess;
     c->slot_a1dt[c->cur_slot] = a1dt;
     c->slot_bc[c->cur_slot] = bc;
     c->slot_valid[c->cur_slot] = 1;
@@ -355,12 +368,29 @@ static void pc_use_slot(hbpc_ctx* c, int slot) {
     c->pc_a1dt = c->slot_a1dt[slot];
     c->pc_bc = c->slot_bc[slot];
     c->pc_valid = c->slot_valid[slot];
+    c->pc_hess = c->slot_hess[slot];
 }
+
+static void op_lin_local(hbpc_ctx* c, const void* w, const void* trw, const void* s, const void* x, double coef,
+                         void* out, int f32);
 
 // Y = P^-1 X in precision f32; the linearisation state (w, traces) in the same precision
 static void pc_apply(hbpc_ctx* c, const void* w, const void* trw, const void* X, void* Y, int f32) {
     size_t esz = f32 ? 4 : 8;
     char* kv = (char*)c->kv;   // a | c
+    if (c->pc_hess) {
+        // BJ^H_ext: S^-1 no longer commutes with K; y = S^-1 (vw - bcoef K vs), P^-1 X = (y, vs + K y)
+        const char* vs = (const char*)X + c->ndof * esz;
+        char* ys = (char*)Y + c->ndof * esz;
+        op_lin_local(c, w, trw, vs, X, -c->pc_bc, kv, f32);
+        long pi = prof_begin(c, KC_BJAPPLY);
+        hipchk(c, bj_apply(c->Sinv, c->sinv_type, kv, kv, Y, ys, f32, c->NE, c->nE, c->stream), "bj_apply");
+        prof_end(c, pi, KC_BJAPPLY,
+                 (double)c->nE * c->NE * c->NE * (c->sinv_type == 2 ? 2.0 : (c->sinv_type == 1 ? 4.0 : 8.0)) +
+                     4.0 * c->ndof * esz);
+        op_lin_local(c, w, trw, Y, vs, 1.0, ys, f32);
+        return;
+    }
     LaunchReq r = op_req(c, OPK_PCPRE);
     r.fld[0] = w;
     r.fld[1] = X;
@@ -879,7 +909,7 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
                 std::fprintf(stderr, "[hbpc] learned preconditioner -> BJ_ext (%s, cycle %d reduced |r| by %.3e)\n",
                              bad_pc ? "non-finite" : "slow", cycle, std::fabs(g[k]) / beta_cycle);
             // (built already for the first-direction form, or kept for this stage)
-            if (learned && !c->pc_kept) pc_build(c, c->X, a1dt, bc, f32);
+            if (learned && !c->pc_kept) pc_build(c, c->X, nullptr, a1dt, bc, f32);
             hipchk(c, hipMemsetAsync(dX, 0, n2 * 8, c->stream), "memset");
             hipchk(c, blas_axpby(1.0, rhs, 0, 0.0, Vj(0), f32, n2, c->stream), "copy");
             ++cycle;
@@ -929,15 +959,17 @@ static void newton_solve(hbpc_ctx* c, const double* b, double a1dt, double bc, c
         const int first = pck == HBPC_PC_LEARNED_FIRST || pck == HBPC_PC_LEARNED_GUESS;
         const bool kept = keep_pc && c->pc_valid && c->pc_a1dt == a1dt && c->pc_bc == bc && c->sinv_f32 == mixed;
         c->pc_kept = kept;
-        if ((pck == HBPC_PC_BJEXT || first) && !kept) pc_build(c, X, a1dt, bc, mixed);
+        const double* sig_h = pck == HBPC_PC_BJEXT_H ? X + n : nullptr;   // BJ^H_ext: at (w, sigma)
+        if ((pck == HBPC_PC_BJEXT || pck == HBPC_PC_BJEXT_H || first) && !kept) pc_build(c, X, sig_h, a1dt, bc, mixed);
         if (pck == HBPC_PC_LEARNED || first) {
             if (!c->mlp_ready) set_err(c, HBPC_ERR_ARG, "learned preconditioner without parameters");
             c->lpc_active = 1;
         }
         for (;;) {
             ++its;
-            const int bj = pck == HBPC_PC_BJEXT || first || (pck == HBPC_PC_LEARNED && !c->lpc_active);
-            if (bj && c->prm.pc_rebuild == HBPC_PC_PER_NEWTON_IT && its > 1) pc_build(c, X, a1dt, bc, mixed);
+            const int bj = pck == HBPC_PC_BJEXT || pck == HBPC_PC_BJEXT_H || first ||
+                           (pck == HBPC_PC_LEARNED && !c->lpc_active);
+            if (bj && c->prm.pc_rebuild == HBPC_PC_PER_NEWTON_IT && its > 1) pc_build(c, X, sig_h, a1dt, bc, mixed);
             // learned: gates at the current linearisation state
             if ((pck == HBPC_PC_LEARNED || first) && c->lpc_active)
                 lpc_prepare(c, mixed ? (const void*)c->X32 : (const void*)X, mixed, a1dt, bc);
@@ -1040,7 +1072,7 @@ static void ctx_free(hbpc_ctx* c) {
         dfree(c->tmp[i]);
     }
     void* bufs[] = {c->R1all, c->R2all, c->X, c->b, c->G, c->dX, c->rhs, c->trw, c->trs, c->trd1,
-                    c->X32, c->trw32, c->trs32, c->trd1_32, c->V, c->Z, c->kv, c->KT,
+                    c->X32, c->trw32, c->trs32, c->trd1_32, c->V, c->Z, c->kv, c->KT, c->HT,
                     c->part, c->dres, c->dgram, c->dcount, c->dstatus, c->basis64, c->basis32, c->theta, c->adam_m, c->adam_v,
                     c->mgrad, c->ap_X, c->ap_G1, c->ap_G2, c->ap_H1, c->ap_H2, c->ap_Y, c->ap_s, c->tr_buf, c->tr_idx_dev,
                     c->col_elems};
@@ -1095,7 +1127,7 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
         set_err(c, HBPC_ERR_ARG, "upwind flux needs advection");
     if (equation == HBPC_EQ_BURGERS_BR1 && !(prm->nu >= 0)) set_err(c, HBPC_ERR_ARG, "nu must be >= 0");
     if (prm->gmres_restart < 1 || prm->gmres_restart > 64) set_err(c, HBPC_ERR_ARG, "gmres_restart must be 1..64");
-    if (prm->precond < HBPC_PC_NONE || prm->precond > HBPC_PC_LEARNED_GUESS)
+    if (prm->precond < HBPC_PC_NONE || prm->precond > HBPC_PC_BJEXT_H)
         set_err(c, HBPC_ERR_ARG, "unknown precond");
     if (prm->pc_rebuild < HBPC_PC_PER_SOLVE || prm->pc_rebuild > HBPC_PC_PER_STAGE)
         set_err(c, HBPC_ERR_ARG, "unknown pc_rebuild");
@@ -1446,25 +1478,36 @@ int hbpc_jvp_f32(hbpc_ctx* c, const float* w, const float* sigma, double a1dt, d
     });
 }
 
+// sigma: nullptr for BJ_ext (or the learned snapshot), the state's sigma for BJ^H_ext
+static void pc_build_abi(hbpc_ctx* c, const double* w, const double* sigma, double a1dt, double bcoef,
+                         int precision) {
+    const int f32 = precision == HBPC_MIXED;
+    const int learned = c->prm.precond == HBPC_PC_LEARNED;
+    pc_use_slot(c, 0);
+    if (learned && sigma)
+        set_err(c, HBPC_ERR_ARG, "hbpc_pc_build_hess on a context with the learned preconditioner");
+    if (learned && !c->mlp_ready) set_err(c, HBPC_ERR_ARG, "learned preconditioner without parameters");
+    if (!learned) pc_build(c, w, sigma, a1dt, bcoef, f32);
+    if (f32) {
+        hipchk(c, blas_axpby(1.0, w, 0, 0.0, c->X32, 1, c->ndof, c->stream), "cast");
+        op_trace(c, c->X32, c->trw32, 1);
+    } else {
+        hipchk(c, hipMemcpyAsync(c->tmp[1], w, c->ndof * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
+    }
+    if (learned) {
+        lpc_prepare(c, f32 ? (const void*)c->X32 : (const void*)c->tmp[1], f32, a1dt, bcoef);
+        c->lpc_snap = f32;
+    }
+}
+
 int hbpc_pc_build(hbpc_ctx* c, const double* w, double a1dt, double bcoef, int precision) {
     if (!c || !w) return HBPC_ERR_ARG;
-    HBPC_TRY(c, {
-        const int f32 = precision == HBPC_MIXED;
-        const int learned = c->prm.precond == HBPC_PC_LEARNED;
-        pc_use_slot(c, 0);
-        if (learned && !c->mlp_ready) set_err(c, HBPC_ERR_ARG, "learned preconditioner without parameters");
-        if (!learned) pc_build(c, w, a1dt, bcoef, f32);
-        if (f32) {
-            hipchk(c, blas_axpby(1.0, w, 0, 0.0, c->X32, 1, c->ndof, c->stream), "cast");
-            op_trace(c, c->X32, c->trw32, 1);
-        } else {
-            hipchk(c, hipMemcpyAsync(c->tmp[1], w, c->ndof * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
-        }
-        if (learned) {
-            lpc_prepare(c, f32 ? (const void*)c->X32 : (const void*)c->tmp[1], f32, a1dt, bcoef);
-            c->lpc_snap = f32;
-        }
-    });
+    HBPC_TRY(c, { pc_build_abi(c, w, nullptr, a1dt, bcoef, precision); });
+}
+
+int hbpc_pc_build_hess(hbpc_ctx* c, const double* w, const double* sigma, double a1dt, double bcoef, int precision) {
+    if (!c || !w || !sigma) return HBPC_ERR_ARG;
+    HBPC_TRY(c, { pc_build_abi(c, w, sigma, a1dt, bcoef, precision); });
 }
 
 int hbpc_pc_apply(hbpc_ctx* c, const double* X, double* Y) {

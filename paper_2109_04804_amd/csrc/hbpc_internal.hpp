@@ -11,7 +11,7 @@
 hipError_t dg_launch_euler(const GeomHost& g, const LaunchReq& r, int f32);
 hipError_t dg_launch_advection(const GeomHost& g, const LaunchReq& r, int f32);
 hipError_t dg_launch_burgers(const GeomHost& g, const LaunchReq& r, int f32);
-hipError_t bj_invert(double* KT, void* SinvT, int type, int NE, int nE, double a1dt, double bc, int* status,
+hipError_t bj_invert(double* KT, const double* HT, void* SinvT, int type, int NE, int nE, double a1dt, double bc, int* status,
                      hipStream_t st);
 hipError_t bj_apply(const void* SinvT, int m_type, const void* xa, const void* xc, void* yw, void* ys, int v_f32,
                     int NE, int nE, hipStream_t st);
@@ -106,16 +106,18 @@ struct hbpc_ctx {
     int m_alloc;
     // BJ_ext
     double* KT;               // chunk_e x NE x NE (column-major blocks)
+    double* HT;               // BJ^H_ext: Hessian blocks, same layout (allocated on first use)
     void* Sinv;               // nE x NE x NE: the active slot's blocks
     int sinv_f32;             // S^-1 feeds FP32 vectors (stored FP32 or FP16)
     int sinv_type;            // storage: 0 FP64, 1 FP32, 2 FP16
     size_t kt_chunk;          // elements per K build chunk (<= 4 GiB of FP64 blocks)
     double pc_a1dt, pc_bc;
     int pc_valid;
+    int pc_hess;              // the active blocks are BJ^H_ext's (apply: y, vs + K y)
     // S^-1 slots: 0 for the predictor (and every solve unless blocks are kept per stage), l - 1
     // for corrector stage l when they are
     void* Sinv_slot[4];
-    int sinv_type_slot[4], slot_valid[4];
+    int sinv_type_slot[4], slot_valid[4], slot_hess[4];
     double slot_a1dt[4], slot_bc[4];
     int cur_slot;
     int pc_kept;              // the active slot's blocks serve the current stage solve as they are

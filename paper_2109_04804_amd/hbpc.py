@@ -20,7 +20,7 @@ EQ = {"advection": 1, "burgers": 2, "euler": 3}
 NODES = {"gauss": 0, "lobatto": 1}
 FLUX = {"central": 0, "upwind": 1, "lf": 2, "rusanov": 3}
 PRECISION = {"fp64": 0, "mixed": 1}
-PRECOND = {"none": 0, "bjext": 1, "learned": 2, "learned_first": 3, "learned_guess": 4}
+PRECOND = {"none": 0, "bjext": 1, "learned": 2, "learned_first": 3, "learned_guess": 4, "bjext_h": 5}
 MLP_PRECISION = {"bf16": 0, "fp32": 1}
 PAIRS = {"newton": 0, "krylov": 1, "random": 2}
 PC_REBUILD = {"per_solve": 0, "per_newton_it": 1, "per_stage": 2}
@@ -97,6 +97,7 @@ SIGNATURES = {
     "hbpc_jvp": (_I, [_P, _P, _P, _D, _D, _P, _P, _I]),
     "hbpc_jvp_f32": (_I, [_P, _P, _P, _D, _D, _P, _P]),
     "hbpc_pc_build": (_I, [_P, _P, _D, _D, _I]),
+    "hbpc_pc_build_hess": (_I, [_P, _P, _P, _D, _D, _I]),
     "hbpc_pc_apply": (_I, [_P, _P, _P]),
     "hbpc_pc_apply_f32": (_I, [_P, _P, _P]),
     "hbpc_step": (_I, [_P, _P, _D, ctypes.POINTER(HbpcStats)]),
@@ -282,6 +283,12 @@ class Context:
         import torch
         self._check(self.lib.hbpc_pc_build(self.h, _ptr(w, self.ndof, torch.float64), float(a1dt), float(bcoef),
                                            PRECISION[precision]))
+
+    def pc_build_hess(self, w, sigma, a1dt, bcoef, precision="fp64"):
+        import torch
+        n = self.ndof
+        self._check(self.lib.hbpc_pc_build_hess(self.h, _ptr(w, n, torch.float64), _ptr(sigma, n, torch.float64),
+                                                float(a1dt), float(bcoef), PRECISION[precision]))
 
     def pc_apply(self, X, out):
         import torch

@@ -1,0 +1,96 @@
+"""GPU parity of BJ^H_ext (Sec. 3.2.3: BJ_ext with the element-local Hessian block dR2/dw
+kept in P) against the oracle: the apply after hbpc_pc_build_hess on the same seeded
+(w, sigma), and whole HBPC steps preconditioned with it.
+
+Tolerances as for BJ_ext: FP64 apply (explicit S^-1 and the K-products of the jet
+kernels vs LU and dense blocks) relative L2 1e-10; FP32 storage and vectors 1e-4; FP64
+steps at eps_N = 1e-12 relative L2 1e-10, mixed at eps_N = 1e-8 1e-8.
+"""
+import numpy as np
+import pytest
+
+from gpu_cases import CASES, lib_kwargs, oracle_for, perturbation, rel, state
+from oracle.solvers import BJExt, BJExtH, StageSolver, dg_hbpc_step
+from paper_2109_04804_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev(x, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda").reshape(-1)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def make_ctx(case, **over):
+    from paper_2109_04804_amd.hbpc import Context
+    kw = lib_kwargs(case)
+    kw.update(over)
+    return Context(case["dim"], case["nelem"], case["length"], case["N"], case["equation"], **kw)
+
+
+def sigma_of(dg, w, seed):
+    """A Newton iterate's sigma: R1(w) plus a seeded perturbation of 5 % of its size."""
+    r1 = dg.r1(w)
+    p = perturbation(dg, seed)
+    return r1 + 0.05 * np.abs(r1).max() * p / np.abs(p).max()
+
+
+@pytest.mark.parametrize("name", ["euler2_n3_lobatto", "euler2_n5", "burgers2", "adv2_ragged", "euler3_n3"])
+def test_pc_apply_hess(name):
+    """Blocks of 64, 144 (register inversion), 320 (blocked); viscous Burgers (BR1); the
+    linear flux, where H = 0 and the result is BJ_ext's."""
+    case = CASES[name]
+    dg = oracle_for(case)
+    ctx = make_ctx(case)
+    print("case", name, "ndof", dg.ndof, flush=True)
+    w = state(dg)
+    sig = sigma_of(dg, w, 5)
+    a1dt, bc = 0.1, 0.1 ** 2 / 2
+    X = np.concatenate([perturbation(dg, 6).ravel(), perturbation(dg, 7).ravel()])
+    ref = BJExtH(dg, w, sig, a1dt, bc).apply(X)
+    ref_plain = BJExt(dg, w, a1dt, bc).apply(X)
+    ctx.pc_build_hess(dev(w), dev(sig), a1dt, bc, "fp64")
+    out = torch.empty(2 * ctx.ndof, dtype=torch.float64, device="cuda")
+    ctx.pc_apply(dev(X), out)
+    err, gap = rel(host(out), ref), rel(ref, ref_plain)
+    print(name, "BJ^H_ext FP64 rel err", err, "distance to BJ_ext", gap, flush=True)
+    assert err < 1e-10
+    if case["equation"] == "advection":
+        assert gap < 1e-13
+    else:
+        assert gap > 1e3 * err          # the Hessian block changes the result
+    ctx.pc_build_hess(dev(w), dev(sig), a1dt, bc, "mixed")
+    out32 = torch.empty(2 * ctx.ndof, dtype=torch.float32, device="cuda")
+    ctx.pc_apply_f32(dev(X, torch.float32), out32)
+    assert rel(host(out32), ref) < 1e-4
+    # a plain build afterwards is BJ_ext again
+    ctx.pc_build(dev(w), a1dt, bc, "fp64")
+    ctx.pc_apply(dev(X), out)
+    assert rel(host(out), ref_plain) < 1e-10
+
+
+@pytest.mark.parametrize("precision,rtol,tol,rebuild", [("fp64", 1e-12, 1e-10, "per_solve"),
+                                                         ("mixed", 1e-8, 1e-8, "per_solve"),
+                                                         ("mixed", 1e-8, 1e-8, "per_stage")])
+def test_euler_vortex_step_bjext_h(precision, rtol, tol, rebuild):
+    """2-D Euler vortex, 4x4 elements, N = 3, HBPC(6,2), dt = 0.1, preconditioned with
+    BJ^H_ext, against the oracle stepping with BJ^H_ext."""
+    case = dict(CASES["euler2_n3_lobatto"])
+    case.update(nelem=[4, 4], nodes="gauss")
+    dg = oracle_for(case)
+    X = dg.node_coords()
+    w0 = inputs.isentropic_vortex(X[0], X[1], 4.6, 5.3, 3.0)
+    ctx = make_ctx(case, q=6, kmax=2, newton_rtol=rtol, gmres_rtol=1e-5, precision=precision,
+                   precond="bjext_h", pc_rebuild=rebuild)
+    wg = dev(w0)
+    stats = ctx.step(wg, 0.1)
+    print(precision, rebuild, stats, flush=True)
+    sol = StageSolver(dg, newton_rtol=rtol, gmres_rtol=1e-5, precond="bjext_h")
+    ref = dg_hbpc_step(dg, w0, 0.1, 6, 2, sol)
+    assert rel(host(wg), ref) < tol
+    assert stats["pc_fallbacks"] == 0 and stats["gmres_its"] > 0
