@@ -276,6 +276,53 @@ def cpu_baseline(seconds_hint=30.0):
                       "eps_N 1e-8, GMRES(30)+BJ_ext, NumPy FP64, 1 thread, %.1f s" % (dg.ndof, dt)}
 
 
+# Preconditioner study of Sec. 4.1.2 (Figs. 4 and 5): the eps-scaled density wave of
+# Eq. euler_convtest on [-1,1]^2, 16^2 elements, N = 5, eps_G 1e-3, eps_N 1e-8, at most 7000 Krylov
+# iterations per Newton step, preconditioners rebuilt at every Newton iterate; one time step of the
+# HBPC(4,0) predictor per point.  Time steps within the ranges the paper plots for each eps.
+STUDY_DT = {1.0: [0.0125, 0.05, 0.2, 0.8], 0.1: [0.003125, 0.0125, 0.05, 0.2],
+            0.01: [0.00078125, 0.003125, 0.0125, 0.025]}
+STUDY_PC = ("none", "bjext", "bjext_h")
+
+
+def precond_study(precision):
+    """Rows (eps, dt, preconditioner, Krylov and Newton iterations, ms per step); a point
+    without convergence within the iteration cap is reported with its error code."""
+    import numpy as np
+    import torch
+    from paper_2109_04804_amd import inputs
+    from paper_2109_04804_amd.hbpc import Context, HbpcError
+    rows = []
+    for eps, dts in STUDY_DT.items():
+        for dt in dts:
+            for pc in STUDY_PC:
+                ctx = Context(2, [16, 16], [2.0, 2.0], 5, "euler", origin=(-1.0, -1.0, 0.0), q=4, kmax=0,
+                              newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=30, gmres_maxit=7000,
+                              precision=precision, precond=pc, pc_rebuild="per_newton_it", flux="rusanov",
+                              gamma=1.4, eps_ref=eps)
+                xi, _ = ctx.nodes()
+                X = inputs.node_coords(2, [16, 16], [2.0, 2.0], [-1.0, -1.0], xi)
+                w0 = torch.tensor(inputs.density_wave(X, a=0.3, eps=eps).reshape(-1), dtype=torch.float64,
+                                  device="cuda")
+                row = {"eps": eps, "dt": dt, "precond": pc}
+                try:
+                    for rep_ in range(2):   # the first step warms up, the second is timed
+                        w = w0.clone()
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        st = ctx.step(w, dt)
+                        torch.cuda.synchronize()
+                        ms = (time.perf_counter() - t0) * 1e3
+                    row.update(gmres_its=st["gmres_its"], newton_its=st["newton_its"], ms=ms,
+                               pc_builds=st.get("pc_builds"))
+                except HbpcError as e:
+                    row.update(error=e.code)
+                ctx.close()
+                print("[study] %s" % json.dumps(row), file=sys.stderr, flush=True)
+                rows.append(row)
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,6 +340,10 @@ def main():
     ap.add_argument("--pc-rebuild", default="per_stage", choices=["per_solve", "per_stage"],
                     help="BJ_ext builds: kept per corrector stage across sweeps (default), or once per stage "
                          "solve")
+    ap.add_argument("--study", choices=["precond_eps"], default=None,
+                    help="instead of the benchmark: the preconditioner study over eps and dt (none, BJ_ext, "
+                         "BJ^H_ext; one JSON line)")
+    ap.add_argument("--study-precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run a plain device copy of this many bytes three times (reference dispatch "
                          "for scaling hardware byte counters)")
@@ -307,6 +358,13 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
+    if a.study == "precond_eps":
+        rows = precond_study(a.study_precision)
+        print(json.dumps({"study": "precond_eps", "precision": a.study_precision,
+                          "setup": "density wave, [-1,1]^2, 16^2 elements, N = 5, Rusanov, HBPC(4,0) "
+                                   "predictor, eps_G 1e-3, eps_N 1e-8, FGMRES(30), cap 7000 per Newton step, "
+                                   "preconditioner rebuilt at every Newton iterate", "rows": rows}))
+        return
     if a.copy_bytes > 0:
         src = torch.ones(a.copy_bytes // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
