@@ -94,3 +94,26 @@ def test_euler_vortex_step_bjext_h(precision, rtol, tol, rebuild):
     ref = dg_hbpc_step(dg, w0, 0.1, 6, 2, sol)
     assert rel(host(wg), ref) < tol
     assert stats["pc_fallbacks"] == 0 and stats["gmres_its"] > 0
+
+
+@pytest.mark.parametrize("eps,dt", [(0.1, 0.0125), (0.01, 0.00078125)])
+def test_density_wave_predictor_step_eps(eps, dt):
+    """The setting of the preconditioner study: the eps-scaled density wave on [-1,1]^2
+    (4x4 elements, N = 3), one HBPC(4,0) predictor step, BJ^H_ext rebuilt at every Newton
+    iterate, FP64 at eps_N = 1e-12, against the oracle stepping with BJ^H_ext built once per
+    solve (the preconditioner changes the Krylov path, not the root): relative L2 <= 1e-10."""
+    from oracle.dgsem import DGSEM, Mesh
+    from oracle.equations import Euler
+    from paper_2109_04804_amd.hbpc import Context
+    dg = DGSEM(Mesh(2, [4, 4], [2.0, 2.0], [-1.0, -1.0]), 3, Euler(2, 1.4, eps), flux="rusanov")
+    w0 = inputs.density_wave(dg.node_coords(), a=0.3, eps=eps)
+    ctx = Context(2, [4, 4], [2.0, 2.0], 3, "euler", origin=(-1.0, -1.0, 0.0), q=4, kmax=0, newton_rtol=1e-12,
+                  gmres_rtol=1e-5, precision="fp64", precond="bjext_h", pc_rebuild="per_newton_it",
+                  flux="rusanov", gamma=1.4, eps_ref=eps)
+    assert ctx.ndof == dg.ndof
+    wg = dev(w0)
+    stats = ctx.step(wg, dt)
+    print(eps, dt, stats, flush=True)
+    ref = dg_hbpc_step(dg, w0, dt, 4, 0, StageSolver(dg, newton_rtol=1e-12, gmres_rtol=1e-5, precond="bjext_h"))
+    assert rel(host(wg), ref) < 1e-10
+    assert stats["pc_builds"] == stats["newton_its"]
