@@ -117,3 +117,52 @@ def test_density_wave_predictor_step_eps(eps, dt):
     ref = dg_hbpc_step(dg, w0, dt, 4, 0, StageSolver(dg, newton_rtol=1e-12, gmres_rtol=1e-5, precond="bjext_h"))
     assert rel(host(wg), ref) < 1e-10
     assert stats["pc_builds"] == stats["newton_its"]
+
+
+@pytest.mark.parametrize("name", ["euler2_n5", "euler3_n3"])
+def test_pc_apply_hess_half_storage(name):
+    """BJ^H_ext with S^-1 stored in FP16 (register inversion at 144 unknowns, blocked at 320).
+    Rounding every entry of S^-1 to half precision (unit roundoff 2^-11) moves y = S^-1 a,
+    a = vw - bcoef K vs, by at most 2^-11 |S^-1| |a| componentwise, and vs + K y by |K| times
+    that; the test allows twice this bound plus 1e-5 for the FP32 vectors."""
+    import scipy.linalg as sla
+    case = CASES[name]
+    dg = oracle_for(case)
+    ctx = make_ctx(case, pc_half=1)
+    print("case", name, "ndof", dg.ndof, flush=True)
+    w = state(dg)
+    sig = sigma_of(dg, w, 5)
+    a1dt, bc = 0.1, 0.1 ** 2 / 2
+    vw, vs = perturbation(dg, 6), perturbation(dg, 7)
+    X = np.concatenate([vw.ravel(), vs.ravel()])
+    pc = BJExtH(dg, w, sig, a1dt, bc)
+    ref = pc.apply(X)
+    ne = ctx.block
+    vw, vs = vw.reshape(-1, ne), vs.reshape(-1, ne)
+    dy = np.empty_like(vw)
+    dz = np.empty_like(vw)
+    for e in range(vw.shape[0]):
+        Sinv = sla.lu_solve(pc.lu[e], np.eye(ne))
+        a = vw[e] - bc * pc.K[e] @ vs[e]
+        dy[e] = 2.0 ** -11 * np.abs(Sinv) @ np.abs(a)
+        dz[e] = np.abs(pc.K[e]) @ dy[e]
+    bound = 2 * np.linalg.norm(np.concatenate([dy.ravel(), dz.ravel()])) / np.linalg.norm(ref) + 1e-5
+    ctx.pc_build_hess(dev(w), dev(sig), a1dt, bc, "mixed")
+    out32 = torch.empty(2 * ctx.ndof, dtype=torch.float32, device="cuda")
+    ctx.pc_apply_f32(dev(X, torch.float32), out32)
+    err = rel(host(out32), ref)
+    print(name, "BJ^H_ext FP16 S^-1 apply rel err", err, "bound", bound, flush=True)
+    assert err < bound
+
+
+def test_pc_build_hess_rejects_learned_context():
+    """On a context whose preconditioner is the learned one, hbpc_pc_apply would run the
+    network: hbpc_pc_build_hess reports HBPC_ERR_ARG instead of building."""
+    from paper_2109_04804_amd.hbpc import HbpcError
+    case = CASES["euler2_n3_lobatto"]
+    dg = oracle_for(case)
+    ctx = make_ctx(case, precond="learned")
+    w = dev(state(dg))
+    with pytest.raises(HbpcError) as ei:
+        ctx.pc_build_hess(w, w, 0.1, 0.005, "fp64")
+    assert ei.value.code == -1
