@@ -143,7 +143,7 @@ def train_learned(wl, samples=20480, per_correction=512, seeds=(1, 2), epochs=20
                  "loss_last_epoch": log["loss_last"]}
 
 
-def run_form(wl, form, steps, warmup, theta=None, pc_rebuild="per_solve"):
+def run_form(wl, form, steps, warmup, theta=None, pc_rebuild="per_solve", pc_reuse_steps=4):
     import numpy as np
     import torch
     from paper_2109_04804_amd.hbpc import Context
@@ -153,7 +153,8 @@ def run_form(wl, form, steps, warmup, theta=None, pc_rebuild="per_solve"):
     half = 1 if form == "mixed16" else 0
     ctx = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], wl.get("equation", "euler"), q=6, kmax=4,
                   newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=30, gmres_maxit=7000, precond=pc,
-                  precision=precision, pc_fallback=0.5, pc_rebuild=pc_rebuild, pc_half=half, **_eqkw(wl))
+                  precision=precision, pc_fallback=0.5, pc_rebuild=pc_rebuild, pc_half=half,
+                  pc_reuse_steps=pc_reuse_steps, **_eqkw(wl))
     if pc.startswith("learned"):
         ctx.mlp_set_params(theta)
     w0 = initial_state(ctx, wl)
@@ -337,9 +338,10 @@ def main():
                          "(as mixed with the BJ_ext blocks stored in FP16), fp64_h / mixed_h (as fp64 / mixed "
                          "with BJ^H_ext)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--pc-rebuild", default="per_stage", choices=["per_solve", "per_stage"],
-                    help="BJ_ext builds: kept per corrector stage across sweeps (default), or once per stage "
-                         "solve")
+    ap.add_argument("--pc-rebuild", default="per_stage", choices=["per_solve", "per_stage", "across_steps"],
+                    help="BJ_ext builds: kept per corrector stage across sweeps (default), once per stage "
+                         "solve, or every stage's blocks kept across --pc-reuse-steps time steps")
+    ap.add_argument("--pc-reuse-steps", type=int, default=4)
     ap.add_argument("--study", choices=["precond_eps"], default=None,
                     help="instead of the benchmark: the preconditioner study over eps and dt (none, BJ_ext, "
                          "BJ^H_ext; one JSON line)")
@@ -383,7 +385,7 @@ def main():
         # 3-D: more pairs per Newton correction, so that one FP64 collection step suffices
         theta, train_report = train_learned(wl, per_correction=1024 if wl["dim"] == 3 else 512)
     for f in forms:
-        res[f] = run_form(wl, f, a.steps, a.warmup, theta, a.pc_rebuild)
+        res[f] = run_form(wl, f, a.steps, a.warmup, theta, a.pc_rebuild, a.pc_reuse_steps)
     head = "learned" if "learned" in res else ("mixed" if "mixed" in res else forms[0])
     h = res[head]
     dof = h["dof"]
@@ -405,6 +407,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": a.workload, "dof": dof, "scheme": "HBPC(6,4)", "dt": wl["dt"],
                    "newton_rtol": 1e-8, "krylov": "FGMRES(30), eps_G 1e-3", "pc_rebuild": a.pc_rebuild,
+                   "pc_reuse_steps": a.pc_reuse_steps if a.pc_rebuild == "across_steps" else None,
                    "precond": {"learned": "learned (BJ_ext fallback 0.5)",
                                "learned_first": "learned first direction, then BJ_ext",
                                "learned_guess": "learned initial guess, then BJ_ext", "mixed": "BJ_ext",

@@ -92,6 +92,12 @@ typedef struct hbpc_ctx hbpc_ctx;
                                       coefficients alpha1 dt = dt, alpha2 dt^2/2 = dt^2/2; the
                                       state has moved by one sweep's correction).  Keeps s - 1
                                       sets of S^-1 blocks. */
+#define HBPC_PC_ACROSS_STEPS 3     /* the blocks of every predictor substep and corrector stage
+                                      kept across time steps (Sec. 4.1.2 suggests reusing the
+                                      preconditioner over several Newton steps or time steps):
+                                      built on first use, rebuilt after pc_reuse_steps steps or
+                                      when the solve's coefficients (dt) change.  Keeps 2 (s - 1)
+                                      sets of S^-1 blocks, so q <= 6. */
 
 /* Jacobian-vector product */
 #define HBPC_JVP_LINEARISED 0      /* exact directional derivatives (hyper-dual flux) */
@@ -140,6 +146,7 @@ typedef struct {
                              in FP32, rounded once; the apply sums in FP32): half the bytes of the
                              apply.  An entry beyond the FP16 range makes the build fail with
                              HBPC_ERR_NONFINITE.  Default 0. */
+    int pc_reuse_steps;   /* HBPC_PC_ACROSS_STEPS: time steps per set of blocks (>= 1, default 4) */
     void* stream;         /* hipStream_t; NULL = the null stream */
 } hbpc_params;
 

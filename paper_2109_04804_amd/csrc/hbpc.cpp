@@ -1022,6 +1022,12 @@ static void hbpc_step_impl(hbpc_ctx* c, double* w_inout, double dt) {
     auto R2 = [&](int j) { return c->R2all + (size_t)j * n; };
     hipchk(c, hipMemcpyAsync(W[0], w_inout, n * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
     op_r1r2(c, W[0], R1(0), R2(0));
+    // blocks kept across steps: every slot is rebuilt on first use after pc_reuse_steps steps
+    const bool across = c->prm.pc_rebuild == HBPC_PC_ACROSS_STEPS;
+    if (across && c->pc_steps >= c->prm.pc_reuse_steps) {
+        for (int i = 0; i < 4; ++i) c->slot_valid[i] = 0;
+        c->pc_steps = 0;
+    }
     // predictor: successive two-point Hermite-Birkhoff substeps
     for (int l = 1; l < s; ++l) {
         double dc = t.c[l] - t.c[l - 1];
@@ -1033,8 +1039,8 @@ static void hbpc_step_impl(hbpc_ctx* c, double* w_inout, double dt) {
         hipchk(c, hipMemcpyAsync(c->b, W[l - 1], n * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
         hipchk(c, blas_gemv_add(c->R1all, 0, n, s, coef1, c->b, 0, n, c->stream), "b");
         hipchk(c, blas_gemv_add(c->R2all, 0, n, s, coef2, c->b, 0, n, c->stream), "b");
-        pc_use_slot(c, 0);
-        newton_solve(c, c->b, a1dt, bc, W[l - 1], W[l]);
+        pc_use_slot(c, across ? s - 1 + (l - 1) : 0);   // across steps: slots after the correctors'
+        newton_solve(c, c->b, a1dt, bc, W[l - 1], W[l], across);
         op_r1r2(c, W[l], R1(l), R2(l));
     }
     // corrector sweeps: every stage of sweep k uses iterate [k] of all stages
@@ -1049,8 +1055,8 @@ static void hbpc_step_impl(hbpc_ctx* c, double* w_inout, double dt) {
             hipchk(c, blas_gemv_add(c->R1all, 0, n, s, coef1, c->b, 0, n, c->stream), "b");
             hipchk(c, blas_gemv_add(c->R2all, 0, n, s, coef2, c->b, 0, n, c->stream), "b");
             const bool per_stage = c->prm.pc_rebuild == HBPC_PC_PER_STAGE;
-            pc_use_slot(c, per_stage ? l - 1 : 0);
-            newton_solve(c, c->b, dt, dt * dt / 2, W[l], c->Wn[l], per_stage && k > 0);
+            pc_use_slot(c, per_stage || across ? l - 1 : 0);
+            newton_solve(c, c->b, dt, dt * dt / 2, W[l], c->Wn[l], (per_stage && k > 0) || across);
         }
         for (int l = 1; l < s; ++l) std::swap(W[l], c->Wn[l]);
         if (k < c->prm.kmax - 1)
@@ -1062,6 +1068,7 @@ static void hbpc_step_impl(hbpc_ctx* c, double* w_inout, double dt) {
     hipchk(c, hipMemcpyAsync(w_inout, W[s - 1], n * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
     hipchk(c, hipStreamSynchronize(c->stream), "sync");
     pc_use_slot(c, 0);
+    if (across) c->pc_steps++;
 }
 
 // ------------------------------------------------------------------ context
@@ -1129,8 +1136,12 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
     if (prm->gmres_restart < 1 || prm->gmres_restart > 64) set_err(c, HBPC_ERR_ARG, "gmres_restart must be 1..64");
     if (prm->precond < HBPC_PC_NONE || prm->precond > HBPC_PC_BJEXT_H)
         set_err(c, HBPC_ERR_ARG, "unknown precond");
-    if (prm->pc_rebuild < HBPC_PC_PER_SOLVE || prm->pc_rebuild > HBPC_PC_PER_STAGE)
+    if (prm->pc_rebuild < HBPC_PC_PER_SOLVE || prm->pc_rebuild > HBPC_PC_ACROSS_STEPS)
         set_err(c, HBPC_ERR_ARG, "unknown pc_rebuild");
+    if (prm->pc_rebuild == HBPC_PC_ACROSS_STEPS && prm->q > 6)
+        set_err(c, HBPC_ERR_ARG, "HBPC_PC_ACROSS_STEPS keeps 2 (s - 1) block sets: q <= 6");
+    if (prm->pc_rebuild == HBPC_PC_ACROSS_STEPS && prm->pc_reuse_steps < 1)
+        set_err(c, HBPC_ERR_ARG, "pc_reuse_steps must be >= 1");
     if (prm->mlp_precision != HBPC_MLP_BF16 && prm->mlp_precision != HBPC_MLP_FP32)
         set_err(c, HBPC_ERR_ARG, "unknown mlp_precision");
     if (prm->q != 4 && prm->q != 6 && prm->q != 8) set_err(c, HBPC_ERR_ARG, "q must be 4, 6 or 8");
@@ -1362,6 +1373,7 @@ void hbpc_default_params(hbpc_params* p) {
     p->hessian = 1;
     p->mlp_precision = HBPC_MLP_BF16;
     p->pc_fallback = 0.5;
+    p->pc_reuse_steps = 4;
     p->stream = nullptr;
 }
 
@@ -1481,6 +1493,7 @@ int hbpc_jvp_f32(hbpc_ctx* c, const float* w, const float* sigma, double a1dt, d
 // sigma: nullptr for BJ_ext (or the learned snapshot), the state's sigma for BJ^H_ext
 static void pc_build_abi(hbpc_ctx* c, const double* w, const double* sigma, double a1dt, double bcoef,
                          int precision) {
+    c->pc_steps = 1 << 30;   // slot 0 is overwritten: blocks kept across steps are rebuilt next step
     const int f32 = precision == HBPC_MIXED;
     const int learned = c->prm.precond == HBPC_PC_LEARNED;
     pc_use_slot(c, 0);

@@ -121,6 +121,7 @@ struct hbpc_ctx {
     double slot_a1dt[4], slot_bc[4];
     int cur_slot;
     int pc_kept;              // the active slot's blocks serve the current stage solve as they are
+    int pc_steps;             // HBPC_PC_ACROSS_STEPS: steps since the kept blocks were invalidated
     // reductions
     double* part;             // blas partials
     double* dres;             // device results (256)

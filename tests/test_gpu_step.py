@@ -262,3 +262,34 @@ def test_profile_classes():
     from paper_2109_04804_amd.hbpc import HbpcError
     with pytest.raises(HbpcError):
         ctx.profile_only("no_such_kernel")
+
+
+@pytest.mark.parametrize("precond", ["bjext", "bjext_h"])
+def test_pc_kept_across_steps(precond):
+    """Blocks kept across time steps (HBPC_PC_ACROSS_STEPS, pc_reuse_steps = 2): HBPC(6,2) on
+    the 4x4, N = 3 vortex, mixed at eps_N = 1e-8.  Builds: 4 in the first step (2 predictor
+    substeps, 2 corrector stages), none in the second, 4 again in the third; every step
+    matches the oracle (blocks built for every solve) within 1e-8.  q = 8 would need 6 block
+    sets and is rejected."""
+    from paper_2109_04804_amd.hbpc import HbpcError
+    case = dict(CASES["euler2_n3_lobatto"])
+    case.update(nelem=[4, 4], nodes="gauss")
+    dg = oracle_for(case)
+    X = dg.node_coords()
+    w0 = inputs.isentropic_vortex(X[0], X[1], 4.6, 5.3, 3.0)
+    ctx = ctx_for(case, q=6, kmax=2, newton_rtol=1e-8, gmres_rtol=1e-5, precision="mixed", precond=precond,
+                  pc_rebuild="across_steps", pc_reuse_steps=2)
+    sol = StageSolver(dg, newton_rtol=1e-8, gmres_rtol=1e-5, precond=precond)
+    wg = dev(w0)
+    ref = w0
+    builds = []
+    for step in range(3):
+        stats = ctx.step(wg, 0.1)
+        print(precond, step, stats, flush=True)
+        builds.append(stats["pc_builds"])
+        ref = dg_hbpc_step(dg, ref, 0.1, 6, 2, sol)
+        assert rel(host(wg), ref) < 1e-8
+    assert builds == [4, 0, 4]
+    with pytest.raises(HbpcError) as ei:
+        ctx_for(case, q=8, kmax=1, pc_rebuild="across_steps")
+    assert ei.value.code == -1
