@@ -150,6 +150,58 @@ def test_fullsize_bjext_apply_vortex():
         assert rel(got, refc) < 1e-10
 
 
+def test_fullsize_bjext_h_apply_vortex():
+    """BJ^H_ext build + apply at 128 x 128, N = 5: sigma a smooth synthetic field (a Newton
+    iterate's sigma need not equal R1(w), but is smooth like it: where the two Rusanov speeds of
+    a face tie to rounding, in the nearly uniform far field, the Hessian block carries
+    (d lambda . e)(sigma_L - sigma_R) from the side the tie rule picks, which rounding noise
+    decides, and a rough sigma turns that into an O(1) difference between two correct
+    readings).  The Hessian block of an element reads the sigma traces of its neighbours,
+    which the 3^2 patch holds.  FP64 within 1e-10; FP32 blocks and vectors within
+    max(1e-4, u32 kappa_2(S_e)), u32 = 2^-24."""
+    from oracle.solvers import BJExtH
+    case = VORTEX
+    ctx = ctx_for(case, gmres_restart=1, precond="none")
+    ne = ctx.block
+    nE = int(np.prod(case["nelem"]))
+    n = ctx.ndof
+    w = full_state(case, ctx)
+    rng = np.random.default_rng(13)
+    xi, _ = ctx.nodes()
+    Xn = inputs.node_coords(case["dim"], case["nelem"], case["length"], [0, 0, 0], xi)
+    ph = sum(np.sin(2 * np.pi * Xn[m] / case["length"][m] + m) for m in range(case["dim"]))
+    sig = 0.1 * np.stack([ph * (1 + 0.3 * v) for v in range(w.shape[1])], axis=1)
+    X = rng.standard_normal(2 * n)
+    a1dt, bc = 0.1, 0.1 ** 2 / 2
+    dev = lambda x, dt=torch.float64: torch.tensor(np.ascontiguousarray(x).reshape(-1), dtype=dt, device="cuda")
+    ctx.pc_build_hess(dev(w), dev(sig), a1dt, bc, "fp64")
+    Y = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+    ctx.pc_apply(dev(X), Y)
+    Yh = host(Y)
+    ctx.pc_build_hess(dev(w), dev(sig), a1dt, bc, "mixed")
+    Y32 = torch.empty(2 * n, dtype=torch.float32, device="cuda")
+    ctx.pc_apply_f32(dev(X, torch.float32), Y32)
+    Y32h = host(Y32)
+    for e in samples(nE, k=4):
+        idx = patch_indices(case["nelem"], e)
+        dgp, c = patch_oracle(case, None)
+        wp = gather(w, idx, ne).reshape(len(idx), dgp.nvar, dgp.nnode)
+        sp = gather(sig, idx, ne).reshape(len(idx), dgp.nvar, dgp.nnode)
+        pc = BJExtH(dgp, wp, sp, a1dt, bc)
+        Xp = np.concatenate([gather(X[:n], idx, ne).ravel(), gather(X[n:], idx, ne).ravel()])
+        ref = pc.apply(Xp)
+        m = len(idx) * ne
+        refc = np.concatenate([ref[:m].reshape(len(idx), ne)[c], ref[m:].reshape(len(idx), ne)[c]])
+        got = np.concatenate([Yh[:n].reshape(nE, ne)[e], Yh[n:].reshape(nE, ne)[e]])
+        got32 = np.concatenate([Y32h[:n].reshape(nE, ne)[e], Y32h[n:].reshape(nE, ne)[e]])
+        S = np.eye(ne) - a1dt * pc.K[c] + bc * (pc.K[c] @ pc.K[c] + pc.H[c])
+        bound32 = max(1e-4, 2.0 ** -24 * np.linalg.cond(S))
+        err, err32 = rel(got, refc), rel(got32, refc)
+        print("element", e, "FP64", err, "FP32", err32, "bound", bound32, flush=True)
+        assert err < 1e-10
+        assert err32 < bound32
+
+
 def test_fullsize_bjext_apply_tgv():
     """BJ_ext build + apply at 48^3, N = 3 (element blocks of 320 unknowns, the blocked
     inversion; S^-1 of the whole mesh: 90.6 GB in FP64, 45.3 GB in FP32).
