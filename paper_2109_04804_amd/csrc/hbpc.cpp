@@ -957,9 +957,10 @@ static void newton_solve(hbpc_ctx* c, const double* b, double a1dt, double bc, c
         if (mixed) state_traces(c, 1);
         const int pck = c->prm.precond;
         const int first = pck == HBPC_PC_LEARNED_FIRST || pck == HBPC_PC_LEARNED_GUESS;
-        const bool kept = keep_pc && c->pc_valid && c->pc_a1dt == a1dt && c->pc_bc == bc && c->sinv_f32 == mixed;
-        c->pc_kept = kept;
         const double* sig_h = pck == HBPC_PC_BJEXT_H ? X + n : nullptr;   // BJ^H_ext: at (w, sigma)
+        const bool kept = keep_pc && c->pc_valid && c->pc_a1dt == a1dt && c->pc_bc == bc && c->sinv_f32 == mixed &&
+                          c->pc_hess == (sig_h != nullptr);
+        c->pc_kept = kept;
         if ((pck == HBPC_PC_BJEXT || pck == HBPC_PC_BJEXT_H || first) && !kept) pc_build(c, X, sig_h, a1dt, bc, mixed);
         if (pck == HBPC_PC_LEARNED || first) {
             if (!c->mlp_ready) set_err(c, HBPC_ERR_ARG, "learned preconditioner without parameters");

@@ -202,6 +202,54 @@ def test_fullsize_bjext_h_apply_vortex():
         assert err32 < bound32
 
 
+def test_fullsize_bjext_h_apply_tgv():
+    """BJ^H_ext build + apply at 48^3, N = 3: blocks of 320 unknowns (blocked inversion with the
+    Hessian term), built in 22 chunks of K and H.  Smooth sigma as in the 2-D case; FP64 within
+    1e-10, FP32 within max(1e-4, u32 kappa_2(S_e))."""
+    from oracle.solvers import BJExtH
+    case = TGV
+    ctx = ctx_for(case, gmres_restart=1, precond="none")
+    ne = ctx.block
+    nE = int(np.prod(case["nelem"]))
+    n = ctx.ndof
+    w = full_state(case, ctx)
+    rng = np.random.default_rng(14)
+    xi, _ = ctx.nodes()
+    Xn = inputs.node_coords(case["dim"], case["nelem"], case["length"], [0, 0, 0], xi)
+    ph = sum(np.sin(2 * np.pi * Xn[m] / case["length"][m] + m) for m in range(case["dim"]))
+    sig = 0.1 * np.stack([ph * (1 + 0.3 * v) for v in range(w.shape[1])], axis=1)
+    X = rng.standard_normal(2 * n)
+    a1dt, bc = 0.1, 0.1 ** 2 / 2
+    dev = lambda x, dt=torch.float64: torch.tensor(np.ascontiguousarray(x).reshape(-1), dtype=dt, device="cuda")
+    refs, bounds = {}, {}
+    for e in samples(nE, k=1):
+        idx = patch_indices(case["nelem"], e)
+        dgp, c = patch_oracle(case, None)
+        wp = gather(w, idx, ne).reshape(len(idx), dgp.nvar, dgp.nnode)
+        sp = gather(sig, idx, ne).reshape(len(idx), dgp.nvar, dgp.nnode)
+        pc = BJExtH(dgp, wp, sp, a1dt, bc)
+        Xp = np.concatenate([gather(X[:n], idx, ne).ravel(), gather(X[n:], idx, ne).ravel()])
+        ref = pc.apply(Xp)
+        m = len(idx) * ne
+        refs[e] = np.concatenate([ref[:m].reshape(len(idx), ne)[c], ref[m:].reshape(len(idx), ne)[c]])
+        S = np.eye(ne) - a1dt * pc.K[c] + bc * (pc.K[c] @ pc.K[c] + pc.H[c])
+        bounds[e] = max(1e-4, 2.0 ** -24 * np.linalg.cond(S))
+    wd, sd = dev(w), dev(sig)
+    for prec, vdt in (("fp64", torch.float64), ("mixed", torch.float32)):
+        t0 = time.perf_counter()
+        ctx.pc_build_hess(wd, sd, a1dt, bc, prec)
+        Y = torch.empty(2 * n, dtype=vdt, device="cuda")
+        (ctx.pc_apply if prec == "fp64" else ctx.pc_apply_f32)(dev(X, vdt), Y)
+        Yh = host(Y)
+        print(prec, "build + apply %.1f s" % (time.perf_counter() - t0), flush=True)
+        for e in refs:
+            got = np.concatenate([Yh[:n].reshape(nE, ne)[e], Yh[n:].reshape(nE, ne)[e]])
+            err = rel(got, refs[e])
+            tol = 1e-10 if prec == "fp64" else bounds[e]
+            print(prec, "element", e, "rel err", err, "tol", tol, flush=True)
+            assert err < tol
+
+
 def test_fullsize_bjext_apply_tgv():
     """BJ_ext build + apply at 48^3, N = 3 (element blocks of 320 unknowns, the blocked
     inversion; S^-1 of the whole mesh: 90.6 GB in FP64, 45.3 GB in FP32).
