@@ -12,8 +12,9 @@ forms are timed:
   fp64     all-FP64, BJ_ext;
   mixed    FP64 Newton, FP32 Krylov vectors, JVP and BJ_ext;
   learned  as mixed with the learned preconditioner (BF16 network, BJ_ext as
-           fallback), trained before timing on Newton pairs of FP64 solves of
-           seeded vortices on the same mesh.
+           fallback after a 5-iteration probe cycle of the network in each
+           solve, --pc-probe-its), trained before timing on Newton pairs of
+           FP64 solves of seeded vortices on the same mesh.
 On request (--forms) also fp64_h / mixed_h (as fp64 / mixed with BJ^H_ext, the
 element-local Hessian block kept in the preconditioner), mixed16 (S^-1 stored
 in FP16) and the learned_first / learned_guess variants.
@@ -143,7 +144,7 @@ def train_learned(wl, samples=20480, per_correction=512, seeds=(1, 2), epochs=20
                  "loss_last_epoch": log["loss_last"]}
 
 
-def run_form(wl, form, steps, warmup, theta=None, pc_rebuild="per_solve", pc_reuse_steps=4):
+def run_form(wl, form, steps, warmup, theta=None, pc_rebuild="per_solve", pc_reuse_steps=4, pc_probe_its=0):
     import numpy as np
     import torch
     from paper_2109_04804_amd.hbpc import Context
@@ -154,7 +155,7 @@ def run_form(wl, form, steps, warmup, theta=None, pc_rebuild="per_solve", pc_reu
     ctx = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], wl.get("equation", "euler"), q=6, kmax=4,
                   newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=30, gmres_maxit=7000, precond=pc,
                   precision=precision, pc_fallback=0.5, pc_rebuild=pc_rebuild, pc_half=half,
-                  pc_reuse_steps=pc_reuse_steps, **_eqkw(wl))
+                  pc_reuse_steps=pc_reuse_steps, pc_probe_its=pc_probe_its, **_eqkw(wl))
     if pc.startswith("learned"):
         ctx.mlp_set_params(theta)
     w0 = initial_state(ctx, wl)
@@ -342,6 +343,9 @@ def main():
                     help="BJ_ext builds: kept per corrector stage across sweeps (default), once per stage "
                          "solve, or every stage's blocks kept across --pc-reuse-steps time steps")
     ap.add_argument("--pc-reuse-steps", type=int, default=4)
+    ap.add_argument("--pc-probe-its", type=int, default=5,
+                    help="learned form: length of the network's first restart cycle per solve, judged at the "
+                         "fallback's mean rate per iteration (0: the full restart cycle)")
     ap.add_argument("--study", choices=["precond_eps"], default=None,
                     help="instead of the benchmark: the preconditioner study over eps and dt (none, BJ_ext, "
                          "BJ^H_ext; one JSON line)")
@@ -385,7 +389,7 @@ def main():
         # 3-D: more pairs per Newton correction, so that one FP64 collection step suffices
         theta, train_report = train_learned(wl, per_correction=1024 if wl["dim"] == 3 else 512)
     for f in forms:
-        res[f] = run_form(wl, f, a.steps, a.warmup, theta, a.pc_rebuild, a.pc_reuse_steps)
+        res[f] = run_form(wl, f, a.steps, a.warmup, theta, a.pc_rebuild, a.pc_reuse_steps, a.pc_probe_its)
     head = "learned" if "learned" in res else ("mixed" if "mixed" in res else forms[0])
     h = res[head]
     dof = h["dof"]
@@ -408,6 +412,7 @@ def main():
         "config": {"workload": a.workload, "dof": dof, "scheme": "HBPC(6,4)", "dt": wl["dt"],
                    "newton_rtol": 1e-8, "krylov": "FGMRES(30), eps_G 1e-3", "pc_rebuild": a.pc_rebuild,
                    "pc_reuse_steps": a.pc_reuse_steps if a.pc_rebuild == "across_steps" else None,
+                   "pc_probe_its": a.pc_probe_its,
                    "precond": {"learned": "learned (BJ_ext fallback 0.5)",
                                "learned_first": "learned first direction, then BJ_ext",
                                "learned_guess": "learned initial guess, then BJ_ext", "mixed": "BJ_ext",

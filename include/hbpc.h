@@ -147,6 +147,11 @@ typedef struct {
                              apply.  An entry beyond the FP16 range makes the build fail with
                              HBPC_ERR_NONFINITE.  Default 0. */
     int pc_reuse_steps;   /* HBPC_PC_ACROSS_STEPS: time steps per set of blocks (>= 1, default 4) */
+    int pc_probe_its;     /* HBPC_PC_LEARNED: length of the network's first restart cycle in each
+                             stage solve (0, the default: gmres_restart).  A shorter probe is
+                             judged by the same mean reduction per iteration: fallback when
+                             ||r|| > pc_fallback^(pc_probe_its / gmres_restart) ||r at its start||.
+                             Later cycles have the full length. */
     void* stream;         /* hipStream_t; NULL = the null stream */
 } hbpc_params;
 

@@ -818,6 +818,10 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
         const int learned = c->prm.precond == HBPC_PC_LEARNED && c->lpc_active;
         // network for z_0 only, in the first cycle (v_0 = the normalised Newton residual)
         const int net_first = c->prm.precond == HBPC_PC_LEARNED_FIRST && c->lpc_active && cycle == 0;
+        // the network's first cycle of the solve may be a shorter probe, judged at the same mean rate
+        const int probe = c->prm.pc_probe_its;
+        const int mc = learned && cycle == 0 && probe > 0 && probe < m ? probe : m;
+        const double fall = mc < m ? std::pow(c->prm.pc_fallback, (double)mc / m) : c->prm.pc_fallback;
         // Arnoldi iteration j, enqueued without waiting for the host: z_j = P^-1 v_j, u = J z_j,
         // classical Gram-Schmidt twice against V_0..V_j, the second pass taken from the Gram
         // matrix G = V^T V (V^T (u - V h1) = h1 - G h1, so one pass over V gives V^T u and the
@@ -851,10 +855,10 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
             hipchk(c, hipEventRecord(c->arn_ev[j & 1], c->stream), "event");
         };
         enqueue(0);
-        for (int j = 0; j < m; ++j) {
+        for (int j = 0; j < mc; ++j) {
             // the next iteration goes to the GPU before this one's results are read (it is
             // discarded if this one ends the cycle)
-            if (j + 1 < m && total + 1 < maxit) enqueue(j + 1);
+            if (j + 1 < mc && total + 1 < maxit) enqueue(j + 1);
             hipchk(c, hipEventSynchronize(c->arn_ev[j & 1]), "sync");
             const double* hr = c->hres + 256 * (j & 1);
             for (int i = 0; i <= j; ++i) Hc(i, j) = hr[132 + i];
@@ -902,7 +906,7 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
         // cycle's correction is dropped and BJ_ext starts from the right-hand side (keeping it
         // left residuals on which BJ_ext needed more iterations than on the original one)
         if ((learned || net_first) && c->prm.pc_fallback > 0 &&
-            (bad_pc || (learned && std::fabs(g[k]) > c->prm.pc_fallback * beta_cycle))) {
+            (bad_pc || (learned && std::fabs(g[k]) > fall * beta_cycle))) {
             c->lpc_active = 0;
             c->st.pc_fallbacks++;
             if (c->verbose)
@@ -1143,6 +1147,7 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
         set_err(c, HBPC_ERR_ARG, "HBPC_PC_ACROSS_STEPS keeps 2 (s - 1) block sets: q <= 6");
     if (prm->pc_rebuild == HBPC_PC_ACROSS_STEPS && prm->pc_reuse_steps < 1)
         set_err(c, HBPC_ERR_ARG, "pc_reuse_steps must be >= 1");
+    if (prm->pc_probe_its < 0) set_err(c, HBPC_ERR_ARG, "pc_probe_its must be >= 0");
     if (prm->mlp_precision != HBPC_MLP_BF16 && prm->mlp_precision != HBPC_MLP_FP32)
         set_err(c, HBPC_ERR_ARG, "unknown mlp_precision");
     if (prm->q != 4 && prm->q != 6 && prm->q != 8) set_err(c, HBPC_ERR_ARG, "q must be 4, 6 or 8");
@@ -1375,6 +1380,7 @@ void hbpc_default_params(hbpc_params* p) {
     p->mlp_precision = HBPC_MLP_BF16;
     p->pc_fallback = 0.5;
     p->pc_reuse_steps = 4;
+    p->pc_probe_its = 0;
     p->stream = nullptr;
 }
 

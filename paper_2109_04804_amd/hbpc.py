@@ -43,7 +43,7 @@ class HbpcParams(ctypes.Structure):
                 ("precision", ctypes.c_int), ("precond", ctypes.c_int), ("pc_rebuild", ctypes.c_int),
                 ("jvp_mode", ctypes.c_int), ("hessian", ctypes.c_int), ("mlp_precision", ctypes.c_int),
                 ("pc_fallback", ctypes.c_double), ("pc_half", ctypes.c_int),
-                ("pc_reuse_steps", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("pc_reuse_steps", ctypes.c_int), ("pc_probe_its", ctypes.c_int), ("stream", ctypes.c_void_p)]
 
 
 class HbpcStats(ctypes.Structure):

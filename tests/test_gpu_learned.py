@@ -73,14 +73,16 @@ def collect_and_train(nelem, L, N, dt, seeds, cap_newton, cap_krylov, per_event,
 
 
 @pytest.mark.parametrize("precond,rebuild", [("learned", "per_solve"), ("learned", "per_stage"),
-                                             ("learned_first", "per_solve"), ("learned_guess", "per_solve")])
+                                             ("learned_first", "per_solve"), ("learned_guess", "per_solve"),
+                                             ("learned_probe", "per_solve")])
 def test_learned_step_matches_oracle(precond, rebuild):
     """2-D Euler vortex, 4 x 4 elements, N = 3, HBPC(6,2), dt = 0.1, mixed precision,
     learned preconditioner trained on Newton pairs of this mesh (seeds 1..3), with the
     BJ_ext fallback (learned) or as the first FGMRES direction of each Newton step
     before BJ_ext (learned_first): the step reaches the oracle's Newton root.  With the BJ_ext
     blocks kept per corrector stage, the fallbacks of the second sweep use the blocks of the
-    first (at most 4 builds for the 6 solves)."""
+    first (at most 4 builds for the 6 solves).  learned_probe: the network's first cycle of
+    each solve is a 5-iteration probe (pc_probe_its)."""
     case = dict(CASES["euler2_n3_lobatto"])
     case.update(nelem=[4, 4], nodes="gauss")
     dg = oracle_for(case)
@@ -88,8 +90,10 @@ def test_learned_step_matches_oracle(precond, rebuild):
     w0 = inputs.isentropic_vortex(X[0], X[1], 4.6, 5.3, 3.0)
     common = dict(q=6, kmax=2, newton_rtol=1e-8)
     Xd, Td, count, n1 = collect_and_train([4, 4], 10.0, 3, 0.1, (1, 2, 3), 512, 0, 8, **common)
-    ctx = ctx_for(2, [4, 4], [10.0, 10.0], 3, gmres_rtol=1e-5, precision="mixed", precond=precond,
-                  pc_fallback=0.5, pc_rebuild=rebuild, **common)
+    probe = 5 if precond == "learned_probe" else 0
+    ctx = ctx_for(2, [4, 4], [10.0, 10.0], 3, gmres_rtol=1e-5, precision="mixed",
+                  precond="learned" if probe else precond, pc_fallback=0.5, pc_rebuild=rebuild, pc_probe_its=probe,
+                  **common)
     ctx.mlp_set_params(random_params(ctx, 0))
     log = ctx.train_mlp(Xd, Td, count, epochs=40, batch=64, lr=1e-3, seed=3, precision="bf16")
     print("train", count, log, flush=True)
@@ -151,10 +155,11 @@ def test_training_and_gain():
     theta = None
     ev = {}
     for form, pc, fb in (("none", "none", 0.0), ("network", "learned", 0.0), ("network+fallback", "learned", 0.5),
+                         ("network+fallback, 5-iteration probe", "learned", 0.5),
                          ("network-first", "learned_first", 0.5), ("network-guess", "learned_guess", 0.5),
                          ("bjext", "bjext", 0.0)):
         ctx = ctx_for(2, nelem, [L, L], N, gmres_rtol=1e-3, precision="mixed", precond=pc, pc_fallback=fb,
-                      gmres_maxit=20000, **common)
+                      gmres_maxit=20000, pc_probe_its=5 if "probe" in form else 0, **common)
         if pc.startswith("learned"):
             if theta is None:
                 ctx.mlp_set_params(random_params(ctx, 7))
@@ -173,7 +178,8 @@ def test_training_and_gain():
         except Exception as ex:
             print(form, "did not converge:", ex, flush=True)
         ctx.close()
-    for form in ("none", "network", "network+fallback", "network-first", "network-guess"):
+    for form in ("none", "network", "network+fallback", "network+fallback, 5-iteration probe", "network-first",
+                 "network-guess"):
         if form in ev:
             assert rel(ev[form][2], ev["bjext"][2]) < 1e-7, form
     assert "network+fallback" in ev and "network-first" in ev and "network-guess" in ev
