@@ -6,8 +6,6 @@ flux (the Hessian contribution vanishes there)."""
 import numpy as np
 import pytest
 
-from oracle.dgsem import DGSEM, Mesh
-from oracle.equations import Burgers
 from oracle.solvers import BJExt, BJExtH, StageSolver
 from tests.test_oracle_dgsem import make, rel, smooth_state
 
