@@ -144,14 +144,26 @@ def train_learned(wl, samples=20480, per_correction=512, seeds=(1, 2), epochs=20
                  "loss_last_epoch": log["loss_last"]}
 
 
+FORMS = ("fp64", "mixed", "learned", "learned_first", "learned_guess", "mixed16", "fp64_h", "mixed_h")
+
+
+def form_settings(form):
+    """(precision, preconditioner, FP16 blocks) of a benchmark form."""
+    if form not in FORMS:
+        raise ValueError("unknown form %r (one of %s)" % (form, ", ".join(FORMS)))
+    precision = "fp64" if form in ("fp64", "fp64_h") else "mixed"
+    if form.startswith("learned"):
+        pc = form
+    else:
+        pc = "bjext_h" if form.endswith("_h") else "bjext"
+    return precision, pc, 1 if form == "mixed16" else 0
+
+
 def run_form(wl, form, steps, warmup, theta=None, pc_rebuild="per_solve", pc_reuse_steps=4, pc_probe_its=0):
     import numpy as np
     import torch
     from paper_2109_04804_amd.hbpc import Context
-    precision = "fp64" if form in ("fp64", "fp64_h") else "mixed"
-    pc = form if form in ("learned", "learned_first", "learned_guess") else ("bjext_h" if form.endswith("_h")
-                                                                             else "bjext")
-    half = 1 if form == "mixed16" else 0
+    precision, pc, half = form_settings(form)
     ctx = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], wl.get("equation", "euler"), q=6, kmax=4,
                   newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=30, gmres_maxit=7000, precond=pc,
                   precision=precision, pc_fallback=0.5, pc_rebuild=pc_rebuild, pc_half=half,
@@ -381,6 +393,8 @@ def main():
         print("[bench] reference copy of %d bytes done" % a.copy_bytes, file=sys.stderr, flush=True)
     wl = WORKLOADS[a.workload]
     forms = [f for f in a.forms.split(",") if f]
+    for f in forms:
+        form_settings(f)   # an unknown form fails before any form runs
     if wl.get("equation") == "burgers":
         forms = [f for f in forms if not f.startswith("learned")]   # the network is trained on Euler states
     res = {}

@@ -54,3 +54,17 @@ def test_measured_traffic_follows_the_source_hash(tmp_path, monkeypatch):
     assert bench.measured_traffic("bj_apply", "other") is None
     src.write_text("// the kernel changed\n")
     assert bench.measured_traffic("bj_apply", "wl") is None
+
+
+def test_form_settings():
+    """Each benchmark form maps to the precision, preconditioner and block storage it names."""
+    assert bench.form_settings("fp64") == ("fp64", "bjext", 0)
+    assert bench.form_settings("mixed") == ("mixed", "bjext", 0)
+    assert bench.form_settings("mixed16") == ("mixed", "bjext", 1)
+    assert bench.form_settings("fp64_h") == ("fp64", "bjext_h", 0)
+    assert bench.form_settings("mixed_h") == ("mixed", "bjext_h", 0)
+    for f in ("learned", "learned_first", "learned_guess"):
+        assert bench.form_settings(f) == ("mixed", f, 0)
+    with pytest.raises(ValueError):
+        bench.form_settings("fp16")
+    assert bench.STUDY_PC == ("none", "bjext", "bjext_h")
