@@ -46,7 +46,7 @@ def test_host_only_calls():
     lib = hbpc.load_library()
     p = hbpc.default_params()
     assert p.q == 6 and p.kmax == 4 and p.gmres_restart == 30 and abs(p.newton_rtol - 1e-8) < 1e-20
-    assert p.pc_reuse_steps == 4 and p.pc_rebuild == 0
+    assert p.pc_reuse_steps == 4 and p.pc_rebuild == 0 and p.pc_probe_its == 0
     assert lib.hbpc_strerror(-5) == b"Newton did not converge"
     h = ctypes.c_void_p()
     assert lib.hbpc_create(None, 3, 3, ctypes.byref(p), ctypes.byref(h)) == -1
