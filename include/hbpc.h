@@ -76,9 +76,9 @@ typedef struct hbpc_ctx hbpc_ctx;
                                       network for the rest of the stage solve (counted in
                                       pc_fallbacks) */
 #define HBPC_PC_BJEXT_H 5          /* BJ^H_ext, Sec. 3.2.3: BJ_ext with the element-local
-                                      Hessian block dR2/dw kept in P, built at (w, sigma) of the
-                                      Newton iterate (FP64 blocks K and H; S^-1 stored as for
-                                      BJ_ext) */
+                                      Hessian block dR2/dw kept in P, built at the (w, sigma) of
+                                      the Newton iterate at which pc_rebuild builds (FP64 blocks K
+                                      and H; S^-1 stored as for BJ_ext) */
 
 /* arithmetic of the learned preconditioner's network */
 #define HBPC_MLP_BF16 0            /* BF16 operands on the matrix cores, FP32 accumulation */
