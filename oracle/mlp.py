@@ -33,8 +33,10 @@ inputs and n_w = n_r + 2 state inputs.
 
 Parity unpinned: the trained weights and the iteration savings have no
 external reference; the forward/backward arithmetic is pinned by central
-finite differences, linearity in the residual by superposition, the BF16
-rounding by its tie cases and by torch's own float32 -> bfloat16 conversion
+finite differences, linearity in the residual by superposition, the block
+structure (r~ and the back-substitution) by reproducing BJ_ext's four-block
+apply when the element solve is the exact S_e^-1, the BF16 rounding by its
+tie cases and by torch's own float32 -> bfloat16 conversion
 (tests/test_oracle_mlp.py).
 """
 import numpy as np
@@ -202,15 +204,33 @@ def features(nelem, rt, w, a1dt, bcoef, elems):
     return np.array(rows), np.array(scales)
 
 
-def apply_learned(dg, theta, H, w, v_w, v_s, a1dt, bcoef):
-    """Learned preconditioner P^-1 (v_w, v_s) in FP64 (module docstring); K v
-    is the element-local linearisation dg.r2(w, v, local=True)."""
+def schur_apply(dg, w, v_w, v_s, bcoef, element_solve):
+    """The preconditioner's block structure (module docstring) with a given
+    element solve: r~ = v_w - bcoef K v_s, dw = element_solve(r~),
+    ds = v_s + K dw, K v the element-local linearisation
+    dg.r2(w, v, local=True).  With element_solve = S_e^-1 for every element
+    this is BJ_ext (Sec. 3.2.3) exactly, because S_e is a polynomial in K_e
+    and commutes with it."""
+    rt = v_w - bcoef * dg.r2(w, v_s, local=True)
+    dw = np.asarray(element_solve(rt)).reshape(w.shape)
+    ds = v_s + dg.r2(w, dw, local=True)
+    return dw, ds
+
+
+def network_solve(dg, theta, H, w, a1dt, bcoef):
+    """Element solve of the learned preconditioner: dw_e = s_e f(x_e) for every
+    element, x_e the patch features of r~ and w."""
     nE = dg.mesh.n_elem
     ne = dg.nvar * dg.nnode
     n_in = (2 * dg.d + 1) * 2 * ne + 2
-    rt = v_w - bcoef * dg.r2(w, v_s, local=True)
-    X, s = features(dg.mesh.nelem, rt, w, a1dt, bcoef, range(nE))
-    y, _ = forward(theta, X, n_in, H, ne)
-    dw = (y * s[:, None]).reshape(w.shape)
-    ds = v_s + dg.r2(w, dw, local=True)
-    return dw, ds
+
+    def solve(rt):
+        X, s = features(dg.mesh.nelem, rt, w, a1dt, bcoef, range(nE))
+        y, _ = forward(theta, X, n_in, H, ne)
+        return y * s[:, None]
+    return solve
+
+
+def apply_learned(dg, theta, H, w, v_w, v_s, a1dt, bcoef):
+    """Learned preconditioner P^-1 (v_w, v_s) in FP64 (module docstring)."""
+    return schur_apply(dg, w, v_w, v_s, bcoef, network_solve(dg, theta, H, w, a1dt, bcoef))

@@ -241,6 +241,33 @@ def test_euler_flux_jacobian_eigenvalues(d, eps):
         assert np.allclose(ev, ref, atol=1e-10)
 
 
+@pytest.mark.parametrize("d,eps", [(2, 1.0), (2, 0.3), (3, 0.1), (3, 1.0)])
+def test_wave_speed_is_flux_jacobian_spectral_radius(d, eps):
+    """Rusanov's lambda on one side, Euler.wave_speed(w, m), equals the
+    spectral radius of the flux Jacobian A_m(w) built column by column from
+    jets (Eq. Riemann with the eps-scaled system of Eq. Euler).  The states
+    include negative velocity components, so a missing |.|, a missing square
+    root or c/eps^2 in place of c/eps changes the value."""
+    eq = Euler(d, 1.4, eps)
+    rng = np.random.default_rng(100 + d)
+    for trial in range(4):
+        rho = rng.uniform(0.5, 2.0)
+        vel = rng.uniform(-0.8, 0.8, d)
+        vel[trial % d] = -abs(vel[trial % d]) - 0.1
+        p = rng.uniform(0.3, 3.0)
+        E = p / 0.4 + 0.5 * eps ** 2 * rho * vel @ vel
+        w = np.array([rho, *(rho * vel), E])
+        for m in range(d):
+            A = np.zeros((d + 2, d + 2))
+            for u in range(d + 2):
+                st = [jets.HD(np.array([w[k]]), np.array([1.0 if k == u else 0.0])) for k in range(d + 2)]
+                F = eq.flux(st, m)
+                A[:, u] = [F[k].b[0] for k in range(d + 2)]
+            radius = np.abs(np.linalg.eigvals(A)).max()
+            lam = eq.wave_speed([np.array([x]) for x in w], m)[0]
+            assert abs(lam - radius) <= 1e-10 * radius, (trial, m, lam, radius)
+
+
 def test_upwind_flux_is_upwind():
     eq = Advection(1, [0.7])
     f = numerical_flux(eq, "upwind", 0, [np.array([2.0])], [np.array([-5.0])], 0)

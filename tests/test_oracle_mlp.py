@@ -128,3 +128,34 @@ def test_learned_apply_is_linear():
     for k in range(2):
         ref = a[k] - 3 * b[k]
         assert np.linalg.norm(c[k] - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_schur_structure_with_exact_element_solve_is_bjext():
+    """The learned preconditioner's block structure (r~ = v_w - bcoef K v_s,
+    dsigma = v_s + K dw) with the network's element solve replaced by the exact
+    S_e^-1 r~ reproduces BJ_ext's apply from the paper's D, E, F, G blocks
+    (Sec. 3.2.3) to round-off: a wrong sign in r~ or in the back-substitution
+    fails it."""
+    import scipy.linalg as sla
+    from oracle.solvers import BJExt
+    from paper_2109_04804_amd import inputs
+    for nelem, N in (([3, 2], 2), ([2, 3], 3)):
+        dg = DGSEM(Mesh(2, nelem, [10.0, 10.0]), N, Euler(2), flux="rusanov")
+        X = dg.node_coords()
+        w = inputs.isentropic_vortex(X[0], X[1], 4.0, 6.0, 3.0)
+        a1dt, bcoef = 0.3, 0.02
+        pc = BJExt(dg, w, a1dt, bcoef)
+        nE, ne = dg.mesh.n_elem, dg.nvar * dg.nnode
+        K = dg.local_jacobian(w)
+        S = [np.eye(ne) - a1dt * K[i] + bcoef * (K[i] @ K[i]) for i in range(nE)]
+
+        def exact(rt):
+            rt = np.asarray(rt).reshape(nE, ne)
+            return np.array([sla.solve(S[i], rt[i]) for i in range(nE)])
+        rng = np.random.default_rng(11)
+        for _ in range(2):
+            vw, vs = rng.standard_normal(w.shape), rng.standard_normal(w.shape)
+            dw, ds = mlp.schur_apply(dg, w, vw, vs, bcoef, exact)
+            ref = pc.apply(np.concatenate([vw.ravel(), vs.ravel()]))
+            got = np.concatenate([dw.ravel(), ds.ravel()])
+            assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
