@@ -113,6 +113,11 @@ def numerical_flux(eq, kind, lam_const, wL, wR, m):
         lam = float(lam_const)
     elif kind == "rusanov":
         lam = jets.maxval(eq.wave_speed(wL, m), eq.wave_speed(wR, m))
+    elif kind == "lf_literal":
+        # Eq. Riemann as printed, without the 1/2 on the dissipation, with the diagonal
+        # lambda of the Euler set-up (Sec. 4.1.2): 1/eps on density and energy, 1 on momenta
+        lam_v = [1.0 / eq.eps] + [1.0] * (eq.nvar - 2) + [1.0 / eq.eps]
+        return [0.5 * (FL[v] + FR[v]) + lam_v[v] * (wL[v] - wR[v]) for v in range(eq.nvar)]
     else:
         raise ValueError(kind)
     return [0.5 * (FL[v] + FR[v]) + 0.5 * lam * (wL[v] - wR[v]) for v in range(eq.nvar)]
