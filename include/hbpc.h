@@ -56,6 +56,8 @@ typedef struct hbpc_ctx hbpc_ctx;
 #define HBPC_FLUX_UPWIND 1         /* lambda = |a.n| (advection) */
 #define HBPC_FLUX_LF 2             /* lambda = params.lambda, a global constant */
 #define HBPC_FLUX_RUSANOV 3        /* lambda = max(|vL.n| + cL/eps, |vR.n| + cR/eps) (Euler) */
+#define HBPC_FLUX_LF_LITERAL 4     /* Euler: Eq. Riemann as printed, lambda_v (wL - wR) without the 1/2,
+                                      lambda = diag(1/eps, 1, .., 1, 1/eps) (Sec. 4.1.2 set-up) */
 
 /* precision of the Krylov solve */
 #define HBPC_FP64 0                /* everything FP64 */
@@ -130,11 +132,14 @@ typedef struct {
                              floor of its FP64 evaluation; counted in newton_floor_stops) */
     int newton_maxit;     /* default 30 */
     double gmres_rtol;    /* eps_G: stop when ||r_j|| <= eps_G ||r_0|| */
-    int gmres_restart;    /* m of GMRES(m), <= 64 */
+    int gmres_restart;    /* m of GMRES(m), 1..HBPC_MAX_RESTART (the paper restarts after 700
+                             iterations, Sec. 4.1.2); the library keeps m + 1 basis vectors and m
+                             preconditioned ones of 2 ndof values each (FP32 in HBPC_MIXED) */
     int gmres_maxit;      /* per Newton step (default 7000) */
     int precision;        /* HBPC_FP64 | HBPC_MIXED */
     int precond;          /* HBPC_PC_* */
-    int pc_rebuild;       /* HBPC_PC_PER_SOLVE | HBPC_PC_PER_NEWTON_IT | HBPC_PC_PER_STAGE */
+    int pc_rebuild;       /* HBPC_PC_PER_SOLVE | HBPC_PC_PER_NEWTON_IT | HBPC_PC_PER_STAGE |
+                             HBPC_PC_ACROSS_STEPS */
     int jvp_mode;         /* HBPC_JVP_* */
     int hessian;          /* 1: include dR2/dw in the JVP (exact Newton), 0: drop it */
     int mlp_precision;    /* HBPC_MLP_BF16 | HBPC_MLP_FP32: network arithmetic of HBPC_PC_LEARNED */
@@ -156,6 +161,8 @@ typedef struct {
 } hbpc_params;
 
 #define HBPC_MAX_SOLVES 64
+/* largest FGMRES restart length (hbpc_params.gmres_restart) */
+#define HBPC_MAX_RESTART 1024
 typedef struct {
     int n_solves;                               /* stage solves in the last step */
     int newton_its;                             /* total Newton iterations */
@@ -176,7 +183,8 @@ typedef struct {
  * BF16 network, learned-preconditioner fallback ratio 0.5. */
 void hbpc_default_params(hbpc_params* p);
 
-/* Create a context: mesh (host struct), degree N (1..7), equation HBPC_EQ_*.
+/* Create a context: mesh (host struct), degree N (2..7 in 1-D and 2-D, 2..5 in 3-D; other
+ * degrees return HBPC_ERR_UNSUPPORTED), equation HBPC_EQ_*.
  * Computes the 1-D operators (Sec. 3.1.1) on the host and allocates all
  * device work space (stage vectors, Krylov bases, BJ_ext blocks).  *out is
  * owned by the caller and released by hbpc_destroy.

@@ -11,6 +11,8 @@
 constexpr int BLAS_THREADS = 256;
 constexpr int MDOT_CHUNK = 16;
 constexpr int MDOT2_CHUNK = 16;
+// most basis vectors of one Gram-Schmidt pass (the FGMRES restart length)
+constexpr int GS_MAXK = 1024;
 
 template <typename T> __device__ __forceinline__ double block_sum(double v, double* sh) {
     // wave64 shuffle tree, then LDS across the 4 waves
@@ -267,7 +269,7 @@ __global__ void __launch_bounds__(BLAS_THREADS) gemv_sub_norm_kernel(const T* __
                                                                      const double* __restrict__ h,
                                                                      T* __restrict__ w, size_t n,
                                                                      double* __restrict__ part) {
-    __shared__ double sh[64];
+    __shared__ double sh[GS_MAXK];
     __shared__ double red[BLAS_THREADS / 64];
     for (int j = threadIdx.x; j < k; j += blockDim.x) sh[j] = h[j];
     __syncthreads();
@@ -279,7 +281,7 @@ __global__ void __launch_bounds__(BLAS_THREADS) gemv_sub_norm_kernel(const T* __
 #pragma unroll
         for (int q = 0; q < VEC; ++q) acc[q] = 0.0;
         for (int j = 0; j < k; ++j) {
-            const Vec<T, VEC> vv = vload<T, VEC>(V + j * ld + i * VEC);
+            const Vec<T, VEC> vv = vload<T, VEC>(V + (size_t)j * ld + i * VEC);
             const double hj = sh[j];
 #pragma unroll
             for (int q = 0; q < VEC; ++q) acc[q] += hj * (double)vv.v[q];
@@ -367,7 +369,7 @@ hipError_t blas_mdot(const void* V, size_t ld, int k, const void* w, size_t n, i
 // a new basis vector.  part: blas_grid(n) doubles.
 hipError_t blas_gs_update_normalize(const void* V, size_t ld, int k, const double* h, void* u, size_t n, int f32,
                                     double* part, double* nrm2, hipStream_t st) {
-    if (k > 64) return hipErrorInvalidValue;
+    if (k > GS_MAXK) return hipErrorInvalidValue;
     const int vec = vec_of(n, ld, f32, V, u);
     int g = blas_grid(n / vec);
     if (f32 && vec == 4)
@@ -397,7 +399,7 @@ hipError_t blas_gs_update_normalize(const void* V, size_t ld, int k, const doubl
 hipError_t blas_gs_gram(const void* V, size_t ld, int k, const void* w1, const void* w2, size_t n, int f32,
                         double* part, double* h1, double* g, double* G, int ldg, double* h, unsigned* counter,
                         hipStream_t st) {
-    if (k > 64 || k > ldg || g != h1 + k) return hipErrorInvalidValue;
+    if (k > GS_MAXK || k > ldg || g != h1 + k) return hipErrorInvalidValue;
     const int vec = (vec_of(n, ld, f32, V, w1) == vec_of(n, ld, f32, V, w2)) ? vec_of(n, ld, f32, V, w1) : 1;
     int gr = blas_grid(n / vec, MDOT_GRID);
     for (int j0 = 0; j0 < k; j0 += MDOT2_CHUNK) {

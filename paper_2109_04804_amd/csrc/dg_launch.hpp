@@ -134,6 +134,15 @@ template <int D, class EQ> hipError_t launch_family(const GeomHost& g, const Lau
         HBPC_NP_CASE(4)
         HBPC_NP_CASE(5)
         HBPC_NP_CASE(6)
+    case 7:
+    case 8:
+        // N = 6, 7 (the paper's convergence studies use N = 7 in 2-D); a 3-D element of 343 or
+        // 512 nodes exceeds one 256-thread block with one thread per node
+        if constexpr (D < 3) {
+            if (g.NP == 7) return f32 ? launch_family_np<D, 7, EQ, float>(g, r) : launch_family_np<D, 7, EQ, double>(g, r);
+            return f32 ? launch_family_np<D, 8, EQ, float>(g, r) : launch_family_np<D, 8, EQ, double>(g, r);
+        }
+        return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 #undef HBPC_NP_CASE

@@ -320,19 +320,20 @@ __global__ void __launch_bounds__(256) lift_trace_kernel(const T* __restrict__ u
 }
 
 // ----------------------------------------------------------------- operator kernel
-// numerical flux at one face point; face = 2m + side is a compile-time constant
-// so that the state components indexed by m stay in registers
-template <int D, int NP, int FACE, class EQ, class OP, typename T, int EPB, int NN, int NFP>
+// numerical flux at one face point of direction M (a compile-time constant, so that the state
+// components indexed by M stay in registers); the side (0: the element's -e_M face, 1: its +e_M
+// face) is a run-time value, so that every wave of the face phase runs one flux body whatever
+// mix of sides it holds
+template <int D, int NP, int M, class EQ, class OP, typename T, int EPB, int NN, int NFP>
 __device__ __forceinline__ void face_point(const OpArgs<T>& a, const EqParams<T>& ep, const T* s_b,
                                            T (*s_fld)[EPB][EQ::NV][NN], T (*s_fs)[EPB][2 * D][EQ::NV][NFP],
-                                           const T* s_q, int fel, int fe, int fp) {
+                                           const T* s_q, int fel, int fe, int fp, int side) {
     constexpr int NV = EQ::NV, NJ = OP::NJ, NC = OP::NC;
-    constexpr int M = FACE >> 1, SIDE = FACE & 1;
     using S = typename OP::S;
-    const T* l = s_b + (SIDE ? BOff<NP>::LP : BOff<NP>::LM);
+    const T* l = s_b + (side ? BOff<NP>::LP : BOff<NP>::LM);
     S own[NV], nb[NV];
-    const int enb = nbr_elem<D>(fe, M, SIDE ? 1 : -1, a.nel);
-    const size_t nbase = ((size_t)enb * 2 * D + (2 * M + 1 - SIDE)) * NV * NFP + fp;
+    const int enb = nbr_elem<D>(fe, M, side ? 1 : -1, a.nel);
+    const size_t nbase = ((size_t)enb * 2 * D + (2 * M + 1 - side)) * NV * NFP + fp;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         T x[NJ], y[NJ];
@@ -348,9 +349,15 @@ __device__ __forceinline__ void face_point(const OpArgs<T>& a, const EqParams<T>
         own[v] = OP::make(x, a);
         nb[v] = OP::make(y, a);
     }
+    // the element is the left state on its +e_M face and the right state on its -e_M face
+    S wl[NV], wr[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        wl[v] = side ? own[v] : nb[v];
+        wr[v] = side ? nb[v] : own[v];
+    }
     S f[NV];
-    if (SIDE) numerical_flux<EQ>(own, nb, M, f, ep);
-    else numerical_flux<EQ>(nb, own, M, f, ep);
+    numerical_flux<EQ>(wl, wr, M, f, ep);
     if constexpr (EQ::VISC) {
         // BR1 viscous surface flux -nu (q_L + q_R)/2 of the lifted gradient q_M
         // (s_q[j][m][el][node], NV = 1); neighbour traces of q from a.qtr
@@ -363,7 +370,7 @@ __device__ __forceinline__ void face_point(const OpArgs<T>& a, const EqParams<T>
             for (int q = 0; q < NP; ++q) acc += l[q] * qj[node_on_line<D, NP>(fp, M, q)];
             x[j] = acc;
             const T* t = j >= OP::NGLOB ? nullptr : a.qtr[j];
-            y[j] = t ? t[((size_t)enb * 2 * D + (2 * M + 1 - SIDE)) * NFP + fp] : T(0);
+            y[j] = t ? t[((size_t)enb * 2 * D + (2 * M + 1 - side)) * NFP + fp] : T(0);
         }
         S qo = OP::make(x, a), qn = OP::make(y, a);
         f[0] = f[0] - (qo + qn) * (T(0.5) * ep.nu);
@@ -373,7 +380,7 @@ __device__ __forceinline__ void face_point(const OpArgs<T>& a, const EqParams<T>
         T c[NC];
         OP::combo(f[v], c, a);
 #pragma unroll
-        for (int k = 0; k < NC; ++k) s_fs[k][fel][FACE][v][fp] = c[k];
+        for (int k = 0; k < NC; ++k) s_fs[k][fel][2 * M + side][v][fp] = c[k];
     }
 }
 
@@ -482,26 +489,24 @@ __global__ void __launch_bounds__(256) dg_op_kernel(OpArgs<T> a, EqParams<T> ep)
             }
     }
 
-    // 3) numerical fluxes at the face points (own trace from LDS, neighbour trace from HBM)
-    for (int i = tid; i < nloc * 2 * D * NFP; i += NT) {
-        const int fel = i / (2 * D * NFP), r = i % (2 * D * NFP);
-        const int face = r / NFP, fp = r % NFP;
+    // 3) numerical fluxes at the face points (own trace from LDS, neighbour trace from HBM); items
+    //    ordered (direction, element, side, face point), so that a wave holds one direction (two
+    //    where it straddles a direction boundary) and evaluates one flux body per direction
+    constexpr int PER_M = 2 * NFP;
+    const int per_dir = nloc * PER_M;
+    for (int i = tid; i < D * per_dir; i += NT) {
+        const int m = i / per_dir, r = i % per_dir;
+        const int fel = r / PER_M, r2 = r % PER_M;
+        const int side = r2 / NFP, fp = r2 % NFP;
         const int fe = e0 + fel;
-        switch (face) {
-        case 0: face_point<D, NP, 0, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, fel, fe, fp); break;
-        case 1: face_point<D, NP, 1, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, fel, fe, fp); break;
-        case 2:
-            if (D > 1) face_point<D, NP, 2 % (2 * D), EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, fel, fe, fp);
-            break;
-        case 3:
-            if (D > 1) face_point<D, NP, 3 % (2 * D), EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, fel, fe, fp);
-            break;
-        case 4:
-            if (D > 2) face_point<D, NP, 4 % (2 * D), EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, fel, fe, fp);
-            break;
-        default:
-            if (D > 2) face_point<D, NP, 5 % (2 * D), EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, fel, fe, fp);
-            break;
+        if (m == 0) {
+            face_point<D, NP, 0, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, fel, fe, fp, side);
+        } else if (m == 1) {
+            if constexpr (D > 1)
+                face_point<D, NP, 1, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, fel, fe, fp, side);
+        } else {
+            if constexpr (D > 2)
+                face_point<D, NP, 2, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, fel, fe, fp, side);
         }
     }
     __syncthreads();

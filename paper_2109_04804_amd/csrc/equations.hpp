@@ -4,12 +4,15 @@
 //   f*(wL, wR; +e_m) = (F_m(wL) + F_m(wR))/2 + lambda (wL - wR)/2
 // lambda: central 0, upwind |a_m|, lf a global constant, rusanov
 // max(|v_m,L| + c_L/eps, |v_m,R| + c_R/eps) with c = sqrt(gamma p / rho).
+// lf_literal (Euler): Eq. Riemann as printed, f* = (F_m(wL) + F_m(wR))/2 + lambda_v (wL - wR)
+// with no 1/2 and the diagonal lambda of the Euler set-up (Sec. 4.1.2), 1/eps on density and
+// energy, 1 on the momenta.
 // Euler is the eps-scaled system of Eq. Euler: momentum flux carries p/eps^2,
 // p = (gamma - 1)(E - eps^2/2 |rho v|^2 / rho).
 #pragma once
 #include "jets.hpp"
 
-enum { FLUX_CENTRAL = 0, FLUX_UPWIND = 1, FLUX_LF = 2, FLUX_RUSANOV = 3 };
+enum { FLUX_CENTRAL = 0, FLUX_UPWIND = 1, FLUX_LF = 2, FLUX_RUSANOV = 3, FLUX_LF_LITERAL = 4 };
 
 template <typename T> struct EqParams {
     T adv[3];
@@ -106,6 +109,10 @@ HD void numerical_flux(const S* wL, const S* wR, int m, S* f, const EqParams<T>&
         S lam = jmax(EQ::wave_speed(wL, m, p), EQ::wave_speed(wR, m, p)) * T(0.5);
 #pragma unroll
         for (int v = 0; v < NV; ++v) f[v] = (FL[v] + FR[v]) * T(0.5) + lam * (wL[v] - wR[v]);
+    } else if (p.flux == FLUX_LF_LITERAL) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            f[v] = (FL[v] + FR[v]) * T(0.5) + (wL[v] - wR[v]) * ((v == 0 || v == NV - 1) ? p.inv_eps : T(1));
     } else {
         T lam = p.flux == FLUX_UPWIND ? jabs(p.adv[m]) : (p.flux == FLUX_LF ? p.lam : T(0));
         lam *= T(0.5);

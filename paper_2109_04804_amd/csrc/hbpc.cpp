@@ -289,11 +289,13 @@ static int status_read(hbpc_ctx* c) {
 
 // ||x||_2 (FP64 or FP32 vector of length n), synchronising
 static double dnorm(hbpc_ctx* c, const void* x, size_t n, int f32) {
-    // own result slots: the Arnoldi copies of an iteration in flight use hres[0..386]
-    hipchk(c, blas_mdot(x, 0, 1, x, n, f32, c->part, c->dres + 250, c->stream), "norm");
-    hipchk(c, hipMemcpyAsync(c->hres + 500, c->dres + 250, sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy");
+    // own result slots after the two Arnoldi slots (an iteration in flight may be writing those)
+    hipchk(c, blas_mdot(x, 0, 1, x, n, f32, c->part, c->dres + c->arn_len, c->stream), "norm");
+    hipchk(c, hipMemcpyAsync(c->hres + 2 * c->arn_len, c->dres + c->arn_len, sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream),
+           "copy");
     hipchk(c, hipStreamSynchronize(c->stream), "sync");
-    return std::sqrt(c->hres[500]);
+    return std::sqrt(c->hres[2 * c->arn_len]);
 }
 
 // ------------------------------------------------------------------ BJ_ext
@@ -837,9 +839,10 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
                 lpc_collect_krylov(c, w, trw, Vj(j), zj, a1dt, bc, f32);
             void* u = Vj(j + 1);
             jvp(zj, u);
-            double* h1 = c->dres;            // V^T u, then (adjacent) g = V^T v_j
-            double* hn = c->dres + 128;      // ||u - V h||^2
-            double* h = c->dres + 132;       // two-pass coefficients
+            const size_t R = (size_t)c->m_alloc + 1;
+            double* h1 = c->dres;              // V^T u, then (adjacent) g = V^T v_j: 2 (j + 1) <= 2 R
+            double* hn = c->dres + 2 * R;      // ||u - V h||^2
+            double* h = c->dres + 2 * R + 4;   // two-pass coefficients, j + 1 <= R
             const double vb = (double)n2 * esz;
             long pi = prof_begin(c, KC_GSDOT);
             hipchk(c, blas_gs_gram(V, n2, j + 1, u, Vj(j), n2, f32, c->part, h1, h1 + (j + 1), c->dgram, m + 1, h,
@@ -849,8 +852,8 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
             pi = prof_begin(c, KC_GSUPD);
             hipchk(c, blas_gs_update_normalize(V, n2, j + 1, h, u, n2, f32, c->part, hn, c->stream), "gs update");
             prof_end(c, pi, KC_GSUPD, (j + 5) * vb);
-            hipchk(c, hipMemcpyAsync(c->hres + 256 * (j & 1), c->dres, 196 * sizeof(double), hipMemcpyDeviceToHost,
-                                     c->stream),
+            hipchk(c, hipMemcpyAsync(c->hres + c->arn_len * (j & 1), c->dres, (3 * R + 4) * sizeof(double),
+                                     hipMemcpyDeviceToHost, c->stream),
                    "copy");
             hipchk(c, hipEventRecord(c->arn_ev[j & 1], c->stream), "event");
         };
@@ -860,9 +863,10 @@ static int fgmres(hbpc_ctx* c, const double* rhs, double* dX, double a1dt, doubl
             // discarded if this one ends the cycle)
             if (j + 1 < mc && total + 1 < maxit) enqueue(j + 1);
             hipchk(c, hipEventSynchronize(c->arn_ev[j & 1]), "sync");
-            const double* hr = c->hres + 256 * (j & 1);
-            for (int i = 0; i <= j; ++i) Hc(i, j) = hr[132 + i];
-            double hnrm = std::sqrt(hr[128]);
+            const double* hr = c->hres + c->arn_len * (j & 1);
+            const size_t R = (size_t)c->m_alloc + 1;
+            for (int i = 0; i <= j; ++i) Hc(i, j) = hr[2 * R + 4 + i];
+            double hnrm = std::sqrt(hr[2 * R]);
             Hc(j + 1, j) = hnrm;
             if (!std::isfinite(hnrm)) {
                 // a non-finite learned-preconditioner output: drop column j and fall back
@@ -1103,6 +1107,77 @@ static void ctx_free(hbpc_ctx* c) {
     c->ev.clear();
 }
 
+// Mesh, degree, equation and flux checks and the geometry of the operator kernels (device
+// pointers of the 1-D operators left null); shared by hbpc_create and the context-free R1 entry.
+int geom_configure(const hbpc_mesh* mesh, int N, int equation, const hbpc_params* prm, Basis1DHost& basis,
+                   GeomHost& g, FamilyLauncher& launch, int& visc, std::string& msg) {
+    const int D = mesh->dim;
+    visc = 0;
+    if (D < 1 || D > 3) { msg = "dim must be 1, 2 or 3"; return HBPC_ERR_ARG; }
+    if (N < 2 || N > 7) { msg = "N must be in 2..7"; return HBPC_ERR_UNSUPPORTED; }
+    if (D == 3 && N > 5) { msg = "N must be in 2..5 in 3-D"; return HBPC_ERR_UNSUPPORTED; }
+    for (int m = 0; m < D; ++m)
+        if (mesh->nelem[m] < 1 || !(mesh->length[m] > 0)) { msg = "bad mesh extent"; return HBPC_ERR_ARG; }
+    int NV = 1;
+    if (equation == HBPC_EQ_ADVECTION) {
+        launch = dg_launch_advection;
+    } else if (equation == HBPC_EQ_EULER) {
+        if (D < 2) { msg = "Euler needs dim 2 or 3"; return HBPC_ERR_UNSUPPORTED; }
+        NV = D + 2;
+        launch = dg_launch_euler;
+    } else if (equation == HBPC_EQ_BURGERS_BR1) {
+        if (D > 2) { msg = "viscous Burgers is compiled for dim 1 and 2"; return HBPC_ERR_UNSUPPORTED; }
+        visc = 1;
+        launch = dg_launch_burgers;
+    } else {
+        msg = "unknown equation";
+        return HBPC_ERR_ARG;
+    }
+    if (prm->flux < 0 || prm->flux > 4) { msg = "unknown flux"; return HBPC_ERR_ARG; }
+    if ((prm->flux == HBPC_FLUX_RUSANOV || prm->flux == HBPC_FLUX_LF_LITERAL) && equation != HBPC_EQ_EULER) {
+        msg = "Rusanov and lf_literal fluxes need the Euler equations";
+        return HBPC_ERR_ARG;
+    }
+    if (prm->flux == HBPC_FLUX_UPWIND && equation != HBPC_EQ_ADVECTION) {
+        msg = "upwind flux needs advection";
+        return HBPC_ERR_ARG;
+    }
+    if (equation == HBPC_EQ_BURGERS_BR1 && !(prm->nu >= 0)) { msg = "nu must be >= 0"; return HBPC_ERR_ARG; }
+    if (equation == HBPC_EQ_EULER && !(prm->eps_ref > 0 && prm->gamma > 1)) {
+        msg = "Euler needs gamma > 1 and eps_ref > 0";
+        return HBPC_ERR_ARG;
+    }
+    if (!basis1d_build(N, prm->nodes, basis)) { msg = "bad node set"; return HBPC_ERR_ARG; }
+    std::memset(&g, 0, sizeof(g));
+    g.D = D;
+    g.NP = N + 1;
+    g.NV = NV;
+    g.nE = 1;
+    for (int m = 0; m < D; ++m) g.nE *= mesh->nelem[m];
+    for (int m = 0; m < 3; ++m) {
+        g.nel[m] = m < D ? mesh->nelem[m] : 1;
+        g.two_h[m] = m < D ? 2.0 * mesh->nelem[m] / mesh->length[m] : 0.0;
+        g.adv[m] = prm->adv[m];
+    }
+    g.lam = prm->lambda;
+    g.nu = prm->nu;
+    g.gamma = equation == HBPC_EQ_EULER ? prm->gamma : 1.4;
+    g.eps = equation == HBPC_EQ_EULER ? prm->eps_ref : 1.0;
+    g.flux = prm->flux;
+    return HBPC_OK;
+}
+
+// 1-D operators in the kernels' layout: Dhat, l(+1), l(-1), lhat(+1), lhat(-1)
+std::vector<double> basis_table(const Basis1DHost& b) {
+    std::vector<double> hb;
+    hb.insert(hb.end(), b.Dhat.begin(), b.Dhat.end());
+    hb.insert(hb.end(), b.lp.begin(), b.lp.end());
+    hb.insert(hb.end(), b.lm.begin(), b.lm.end());
+    hb.insert(hb.end(), b.lhp.begin(), b.lhp.end());
+    hb.insert(hb.end(), b.lhm.begin(), b.lhm.end());
+    return hb;
+}
+
 static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, const hbpc_params* prm) {
     const char* vb = std::getenv("HBPC_VERBOSE");
     c->verbose = vb && vb[0] && vb[0] != '0';
@@ -1113,32 +1188,14 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
     c->NP = N + 1;
     c->D = mesh->dim;
     c->equation = equation;
-    if (c->D < 1 || c->D > 3) set_err(c, HBPC_ERR_ARG, "dim must be 1, 2 or 3");
-    if (N < 2 || N > 5) set_err(c, HBPC_ERR_UNSUPPORTED, "N must be in 2..5");
-    for (int m = 0; m < c->D; ++m)
-        if (mesh->nelem[m] < 1 || !(mesh->length[m] > 0)) set_err(c, HBPC_ERR_ARG, "bad mesh extent");
-    if (equation == HBPC_EQ_ADVECTION) {
-        c->NV = 1;
-        c->launch = dg_launch_advection;
-    } else if (equation == HBPC_EQ_EULER) {
-        if (c->D < 2) set_err(c, HBPC_ERR_UNSUPPORTED, "Euler needs dim 2 or 3");
-        c->NV = c->D + 2;
-        c->launch = dg_launch_euler;
-    } else if (equation == HBPC_EQ_BURGERS_BR1) {
-        if (c->D > 2) set_err(c, HBPC_ERR_UNSUPPORTED, "viscous Burgers is compiled for dim 1 and 2");
-        c->NV = 1;
-        c->visc = 1;
-        c->launch = dg_launch_burgers;
-    } else {
-        set_err(c, HBPC_ERR_ARG, "unknown equation");
+    {
+        std::string msg;
+        const int rc = geom_configure(mesh, N, equation, prm, c->basis, c->geom, c->launch, c->visc, msg);
+        if (rc != HBPC_OK) set_err(c, rc, msg);
     }
-    if (prm->flux < 0 || prm->flux > 3) set_err(c, HBPC_ERR_ARG, "unknown flux");
-    if (prm->flux == HBPC_FLUX_RUSANOV && equation != HBPC_EQ_EULER)
-        set_err(c, HBPC_ERR_ARG, "Rusanov flux needs the Euler equations");
-    if (prm->flux == HBPC_FLUX_UPWIND && equation != HBPC_EQ_ADVECTION)
-        set_err(c, HBPC_ERR_ARG, "upwind flux needs advection");
-    if (equation == HBPC_EQ_BURGERS_BR1 && !(prm->nu >= 0)) set_err(c, HBPC_ERR_ARG, "nu must be >= 0");
-    if (prm->gmres_restart < 1 || prm->gmres_restart > 64) set_err(c, HBPC_ERR_ARG, "gmres_restart must be 1..64");
+    c->NV = c->geom.NV;
+    if (prm->gmres_restart < 1 || prm->gmres_restart > HBPC_MAX_RESTART)
+        set_err(c, HBPC_ERR_ARG, "gmres_restart must be 1.." + std::to_string(HBPC_MAX_RESTART));
     if (prm->precond < HBPC_PC_NONE || prm->precond > HBPC_PC_BJEXT_H)
         set_err(c, HBPC_ERR_ARG, "unknown precond");
     if (prm->pc_rebuild < HBPC_PC_PER_SOLVE || prm->pc_rebuild > HBPC_PC_ACROSS_STEPS)
@@ -1152,46 +1209,21 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
         set_err(c, HBPC_ERR_ARG, "unknown mlp_precision");
     if (prm->q != 4 && prm->q != 6 && prm->q != 8) set_err(c, HBPC_ERR_ARG, "q must be 4, 6 or 8");
     if (prm->kmax < 0) set_err(c, HBPC_ERR_ARG, "kmax must be >= 0");
-    if (equation == HBPC_EQ_EULER && !(prm->eps_ref > 0 && prm->gamma > 1))
-        set_err(c, HBPC_ERR_ARG, "Euler needs gamma > 1 and eps_ref > 0");
-    if (!basis1d_build(N, prm->nodes, c->basis)) set_err(c, HBPC_ERR_ARG, "bad node set");
     c->stream = (hipStream_t)prm->stream;
     c->NN = 1;
     c->NFP = 1;
     for (int m = 0; m < c->D; ++m) c->NN *= c->NP;
     for (int m = 0; m + 1 < c->D; ++m) c->NFP *= c->NP;
     c->NE = c->NV * c->NN;
-    c->nE = 1;
-    for (int m = 0; m < c->D; ++m) c->nE *= mesh->nelem[m];
+    c->nE = c->geom.nE;
     c->ndof = (size_t)c->nE * c->NE;
     c->n2 = 2 * c->ndof;
     c->tsz = (size_t)c->nE * 2 * c->D * c->NV * c->NFP;
     GeomHost& g = c->geom;
-    std::memset(&g, 0, sizeof(g));
-    g.D = c->D;
-    g.NP = c->NP;
-    g.NV = c->NV;
-    g.nE = c->nE;
-    for (int m = 0; m < 3; ++m) {
-        g.nel[m] = m < c->D ? mesh->nelem[m] : 1;
-        g.two_h[m] = m < c->D ? 2.0 * mesh->nelem[m] / mesh->length[m] : 0.0;
-        g.adv[m] = prm->adv[m];
-    }
-    g.lam = prm->lambda;
-    g.nu = prm->nu;
-    g.gamma = equation == HBPC_EQ_EULER ? prm->gamma : 1.4;
-    g.eps = equation == HBPC_EQ_EULER ? prm->eps_ref : 1.0;
-    g.flux = prm->flux;
 
     const size_t n = c->ndof;
-    {   // 1-D operators: Dhat, l(+1), l(-1), lhat(+1), lhat(-1)
-        const int NP = c->NP;
-        std::vector<double> hb;
-        hb.insert(hb.end(), c->basis.Dhat.begin(), c->basis.Dhat.end());
-        hb.insert(hb.end(), c->basis.lp.begin(), c->basis.lp.end());
-        hb.insert(hb.end(), c->basis.lm.begin(), c->basis.lm.end());
-        hb.insert(hb.end(), c->basis.lhp.begin(), c->basis.lhp.end());
-        hb.insert(hb.end(), c->basis.lhm.begin(), c->basis.lhm.end());
+    {   // 1-D operators
+        std::vector<double> hb = basis_table(c->basis);
         std::vector<float> hf(hb.begin(), hb.end());
         c->basis64 = dalloc<double>(c, hb.size());
         c->basis32 = dalloc<float>(c, hf.size());
@@ -1199,7 +1231,6 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
         hipchk(c, hipMemcpy(c->basis32, hf.data(), hf.size() * 4, hipMemcpyHostToDevice), "copy basis");
         g.basis64 = c->basis64;
         g.basis32 = c->basis32;
-        (void)NP;
     }
     for (int i = 0; i < 4; ++i) {
         c->W[i] = dalloc<double>(c, n);
@@ -1250,14 +1281,17 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
     // inversion kernel runs tens of workgroup rounds instead of three with a 16 % tail)
     size_t per = (size_t)c->NE * c->NE * 8;
     c->kt_chunk = std::max<size_t>(1, std::min<size_t>(c->nE, ((size_t)4 << 30) / per));
-    c->part = dalloc<double>(c, (size_t)blas_mdot_grid(c->n2) * 130 + 64);
-    c->dres = dalloc<double>(c, 256);
+    // block partials of up to 2 (m + 1) columns; device results: one Arnoldi slot (h1 | g of
+    // 2 (m + 1), ||u||^2 in 4, h of m + 1), then the norm and loss words
+    c->part = dalloc<double>(c, (size_t)blas_mdot_grid(c->n2) * (2 * (c->m_alloc + 1) + 2) + 64);
+    c->arn_len = 3 * ((size_t)c->m_alloc + 1) + 8;
+    c->dres = dalloc<double>(c, c->arn_len + 64);
     c->dgram = dalloc<double>(c, (size_t)(c->m_alloc + 1) * (c->m_alloc + 1));
     c->dcount = dalloc<unsigned>(c, 4);
     hipchk(c, hipMemset(c->dcount, 0, 4 * sizeof(unsigned)), "memset");
     c->dstatus = dalloc<int>(c, 1);
     void* h = nullptr;
-    hipchk(c, hipHostMalloc(&h, 512 * sizeof(double)), "hipHostMalloc");
+    hipchk(c, hipHostMalloc(&h, (2 * c->arn_len + 64) * sizeof(double)), "hipHostMalloc");
     c->hres = (double*)h;
     for (int i = 0; i < 2; ++i) hipchk(c, hipEventCreateWithFlags(&c->arn_ev[i], hipEventDisableTiming), "event");
 }
@@ -1281,7 +1315,7 @@ static void train_impl(hbpc_ctx* c, const float* X, const float* T, size_t count
     float* Tb = Xb + (size_t)B * ni;
     std::vector<int> perm(count);
     unsigned long long state = cfg->seed;
-    double* sse = c->dres + 200;
+    double* sse = c->dres + c->arn_len + 8;
     int steps = 0;
     double first = 0.0, last = 0.0;
     for (int ep = 0; ep < cfg->epochs; ++ep) {
@@ -1616,7 +1650,7 @@ int hbpc_mlp_loss_grad(hbpc_ctx* c, const float* X, const float* T, int rows, fl
     if (!c || !X || !T || !grad || rows <= 0) return HBPC_ERR_ARG;
     if (precision != HBPC_MLP_BF16 && precision != HBPC_MLP_FP32) return HBPC_ERR_ARG;
     HBPC_TRY(c, {
-        double* sse = c->dres + 200;
+        double* sse = c->dres + c->arn_len + 8;
         hipchk(c, hipMemsetAsync(sse, 0, sizeof(double), c->stream), "memset");
         mlp_loss_grad_dev(c, X, T, rows, grad, sse, precision == HBPC_MLP_BF16);
         double h = 0.0;

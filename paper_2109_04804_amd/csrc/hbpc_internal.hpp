@@ -55,14 +55,20 @@ struct Basis1DHost {
     std::vector<double> xi, w, Dhat /*NP*NP, Dhat[i*NP+lam]*/, lp, lm, lhp, lhm;
 };
 bool basis1d_build(int N, int kind, Basis1DHost& out);
+std::vector<double> basis_table(const Basis1DHost& b);
+
+typedef hipError_t (*FamilyLauncher)(const GeomHost&, const LaunchReq&, int);
+
+// mesh / degree / equation / flux checks and the kernels' geometry (basis pointers left null);
+// returns HBPC_OK or an error code with its message
+int geom_configure(const hbpc_mesh* mesh, int N, int equation, const hbpc_params* prm, Basis1DHost& basis,
+                   GeomHost& g, FamilyLauncher& launch, int& visc, std::string& msg);
 
 // ---- error carrier
 struct HbpcError {
     int code;
     std::string msg;
 };
-
-typedef hipError_t (*FamilyLauncher)(const GeomHost&, const LaunchReq&, int);
 
 struct DevBuf {
     void* p = nullptr;
@@ -124,10 +130,11 @@ struct hbpc_ctx {
     int pc_steps;             // HBPC_PC_ACROSS_STEPS: steps since the kept blocks were invalidated
     // reductions
     double* part;             // blas partials
-    double* dres;             // device results (256)
+    double* dres;             // device results: one Arnoldi slot (arn_len), then 64 words (norm, loss)
+    size_t arn_len;           // 3 (m + 1) + 8: h1 | g, ||u||^2, h of one Arnoldi iteration
     double* dgram;            // Gram matrix V^T V of the current FGMRES cycle, (m+1) x (m+1)
     unsigned* dcount;         // grid-wide hand-over counters of the fused reductions (0 between launches)
-    double* hres;             // pinned host copies (512: two Arnoldi result slots of 256)
+    double* hres;             // pinned host copies: two Arnoldi slots of arn_len, then 64 words
     hipEvent_t arn_ev[2];     // Arnoldi results of iteration j copied to slot j % 2
     int* dstatus;
     // FD scratch (allocated on demand)

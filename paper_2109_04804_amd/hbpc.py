@@ -18,7 +18,7 @@ ERRORS = {-1: "HBPC_ERR_ARG", -2: "HBPC_ERR_OOM", -3: "HBPC_ERR_HIP", -4: "HBPC_
           -5: "HBPC_ERR_NEWTON", -6: "HBPC_ERR_GMRES", -7: "HBPC_ERR_UNSUPPORTED"}
 EQ = {"advection": 1, "burgers": 2, "euler": 3}
 NODES = {"gauss": 0, "lobatto": 1}
-FLUX = {"central": 0, "upwind": 1, "lf": 2, "rusanov": 3}
+FLUX = {"central": 0, "upwind": 1, "lf": 2, "rusanov": 3, "lf_literal": 4}
 PRECISION = {"fp64": 0, "mixed": 1}
 PRECOND = {"none": 0, "bjext": 1, "learned": 2, "learned_first": 3, "learned_guess": 4, "bjext_h": 5}
 MLP_PRECISION = {"bf16": 0, "fp32": 1}

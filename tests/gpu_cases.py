@@ -24,6 +24,9 @@ CASES = {
                       flux="rusanov"),
     "euler2_n3_lobatto": dict(dim=2, nelem=[4, 5], length=[10.0, 10.0], N=3, equation="euler",
                               nodes="lobatto", flux="rusanov"),
+    # Eq. Riemann as printed with the Euler set-up's lambda = diag(1/eps, 1, 1, 1/eps) (Sec. 4.1.2)
+    "euler2_lfl": dict(dim=2, nelem=[5, 4], length=[10.0, 10.0], N=4, equation="euler", nodes="gauss",
+                       flux="lf_literal", eps_ref=0.5),
     "euler2_lf": dict(dim=2, nelem=[3, 3], length=[10.0, 10.0], N=4, equation="euler", nodes="gauss",
                       flux="lf", **{"lambda": 3.0}),
     # 3-D eps-scaled Euler (eps = 0.1), N = 3 as in the Taylor-Green workload
@@ -40,6 +43,13 @@ CASES = {
                      flux="lf", nu=0.01, **{"lambda": 1.0}),
     "burgers1_lobatto": dict(dim=1, nelem=[7], length=[TWO_PI], N=3, equation="burgers", nodes="lobatto",
                              flux="lf", nu=0.05, **{"lambda": 1.0}),
+    # N = 6 and 7, the degrees of the paper's convergence studies (blocks of 64 and 256 unknowns)
+    "adv2_n7": dict(dim=2, nelem=[4, 3], length=[2.0, 2.0], N=7, equation="advection", nodes="gauss",
+                    flux="upwind", adv=[0.3, 0.3]),
+    "euler2_n7_lfl": dict(dim=2, nelem=[3, 2], length=[2.0, 2.0], N=7, equation="euler", nodes="gauss",
+                          flux="lf_literal"),
+    "burgers2_n6": dict(dim=2, nelem=[3, 4], length=[TWO_PI, TWO_PI], N=6, equation="burgers", nodes="lobatto",
+                        flux="lf", nu=0.02, **{"lambda": 1.0}),
     # degenerate: one element per direction (every neighbour is the element itself)
     "euler2_single": dict(dim=2, nelem=[1, 1], length=[10.0, 10.0], N=5, equation="euler", nodes="gauss",
                           flux="rusanov"),

@@ -52,6 +52,14 @@ def test_host_only_calls():
     assert lib.hbpc_create(None, 3, 3, ctypes.byref(p), ctypes.byref(h)) == -1
     assert lib.hbpc_destroy(None) == -1
     assert lib.hbpc_ndof(None) == 0
+    # degrees outside the instantiated range are rejected before any device work
+    for dim, N in ((2, 8), (1, 1), (3, 6)):
+        m = hbpc.make_mesh(dim, [2] * dim, [1.0] * dim)
+        pa = hbpc.make_params(flux="upwind", adv=[1.0, 0.5, 0.25])
+        assert lib.hbpc_create(ctypes.byref(m), N, 1, ctypes.byref(pa), ctypes.byref(h)) == -7, (dim, N)
+    m = hbpc.make_mesh(2, [2, 2], [1.0, 1.0])
+    pa = hbpc.make_params(flux="upwind", adv=[1.0, 0.5], gmres_restart=1025)
+    assert lib.hbpc_create(ctypes.byref(m), 3, 1, ctypes.byref(pa), ctypes.byref(h)) == -1
 
 
 def test_struct_layouts_match_header():
