@@ -293,3 +293,21 @@ def test_pc_kept_across_steps(precond):
     with pytest.raises(HbpcError) as ei:
         ctx_for(case, q=8, kmax=1, pc_rebuild="across_steps")
     assert ei.value.code == -1
+
+
+@pytest.mark.parametrize("name", ["adv2_n7", "euler2_n7_lfl"])
+def test_degree7_step(name):
+    """N = 7, the degree of the paper's convergence studies (Sec. 4.3): one HBPC(6,2) step at
+    dt = 0.1, FP64 with eps_N = 1e-12 and BJ_ext (blocks of 64 and 256 unknowns), against the
+    oracle (relative L2 <= 1e-10).  Euler with Eq. Riemann as printed (diagonal lambda) on the
+    density wave."""
+    case = CASES[name]
+    dg = oracle_for(case)
+    X = dg.node_coords()
+    w0 = state(dg, seed=2) if case["equation"] == "advection" else inputs.density_wave(X, a=0.3)
+    ctx = ctx_for(case, q=6, kmax=2, newton_rtol=1e-12, gmres_rtol=1e-5, precision="fp64")
+    wg = dev(w0)
+    stats = ctx.step(wg, 0.1)
+    print(name, stats["newton_its"], stats["gmres_its"], flush=True)
+    ref = dg_hbpc_step(dg, w0, 0.1, 6, 2, StageSolver(dg, newton_rtol=1e-12, gmres_rtol=1e-5))
+    assert rel(host(wg), ref) < 1e-10
