@@ -59,6 +59,12 @@ WORKLOADS = {
     # corrector stages need more than 7000 FGMRES(30) iterations per Newton step with BJ_ext on 48^3)
     "euler_tgv_48x48x48_N3": dict(dim=3, nelem=[48, 48, 48], length=[2 * 3.141592653589793] * 3, N=3,
                                   dt=0.027, equation="euler", field="tgv", eps_ref=0.1),
+    # the same workload at its configured acoustic CFL of about 20 (dt = 0.06), with the longer restart
+    # that the paper's Euler runs use (Sec. 4.1.2 restarts after 700): FGMRES(200) in FP32, FGMRES(100) in
+    # FP64 (101 + 100 basis vectors of 70.8M FP64 values = 114 GB beside 91 GB of FP64 S^-1 blocks)
+    "euler_tgv_48x48x48_N3_cfl20": dict(dim=3, nelem=[48, 48, 48], length=[2 * 3.141592653589793] * 3, N=3,
+                                        dt=0.06, equation="euler", field="tgv", eps_ref=0.1,
+                                        restart={"fp64": 100, "mixed": 200}),
     # the same CFL on a 16^3 mesh
     "euler_tgv_16x16x16_N3": dict(dim=3, nelem=[16, 16, 16], length=[2 * 3.141592653589793] * 3, N=3,
                                   dt=0.18, equation="euler", field="tgv", eps_ref=0.1),
@@ -108,7 +114,8 @@ def train_learned(wl, samples=20480, per_correction=512, seeds=(1, 2), epochs=20
     from paper_2109_04804_amd.hbpc import Context
     t0 = time.perf_counter()
     col = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], "euler", q=6, kmax=4, newton_rtol=1e-8,
-                  gmres_rtol=1e-6, gmres_restart=30, gmres_maxit=7000, precond="bjext", precision="fp64",
+                  gmres_rtol=1e-6, gmres_restart=restart_of(wl, "fp64"), gmres_maxit=7000, precond="bjext",
+                  precision="fp64",
                   **_eqkw(wl))
     n_in, H, n_out, n_p = col.mlp_shape()
     X = torch.zeros(samples * n_in, dtype=torch.float32, device="cuda")
@@ -159,13 +166,20 @@ def form_settings(form):
     return precision, pc, 1 if form == "mixed16" else 0
 
 
+def restart_of(wl, precision):
+    """FGMRES restart length of a workload in a precision (30 unless the workload names one)."""
+    r = wl.get("restart", 30)
+    return r[precision] if isinstance(r, dict) else r
+
+
 def run_form(wl, form, steps, warmup, theta=None, pc_rebuild="per_solve", pc_reuse_steps=4, pc_probe_its=0):
     import numpy as np
     import torch
     from paper_2109_04804_amd.hbpc import Context
     precision, pc, half = form_settings(form)
     ctx = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], wl.get("equation", "euler"), q=6, kmax=4,
-                  newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=30, gmres_maxit=7000, precond=pc,
+                  newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=restart_of(wl, precision), gmres_maxit=7000,
+                  precond=pc,
                   precision=precision, pc_fallback=0.5, pc_rebuild=pc_rebuild, pc_half=half,
                   pc_reuse_steps=pc_reuse_steps, pc_probe_its=pc_probe_its, **_eqkw(wl))
     if pc.startswith("learned"):
@@ -265,29 +279,81 @@ def measured_traffic(kernel, workload):
     return None
 
 
-def cpu_baseline(seconds_hint=30.0):
-    """FP64 NumPy oracle, one thread, one HBPC(6,4) step of the vortex workload
-    on a reduced 8 x 8-element mesh of the same domain (N = 5, dt = 0.1,
-    eps_N 1e-8, GMRES(30) + BJ_ext)."""
-    import numpy as np
-    from threadpoolctl import threadpool_limits
+PARITY_N = 8   # elements per direction of the parity and CPU-baseline sample
+
+
+def parity_sample():
+    """The vortex workload on a reduced 8 x 8-element mesh of the same domain (N = 5):
+    (oracle DGSEM, initial state)."""
     from oracle.dgsem import DGSEM, Mesh
     from oracle.equations import Euler
-    from oracle.solvers import StageSolver, dg_hbpc_step
     from paper_2109_04804_amd import inputs
-    n = 8
-    dg = DGSEM(Mesh(2, [n, n], [10.0, 10.0]), 5, Euler(2), flux="rusanov")
+    dg = DGSEM(Mesh(2, [PARITY_N, PARITY_N], [10.0, 10.0]), 5, Euler(2), flux="rusanov")
     X = dg.node_coords()
     xc, yc, beta = inputs.vortex_params(inputs.DEFAULT_SEED, beta=5.0)
-    w = inputs.isentropic_vortex(X[0], X[1], xc, yc, beta)
-    sol = StageSolver(dg, newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=30)
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        dg_hbpc_step(dg, w, 0.1, 6, 4, sol)
-        dt = time.perf_counter() - t0
-    return {"value": dg.ndof / dt, "unit": "DOF-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "one HBPC(6,4) step, vortex on 8x8 elements of [0,10]^2 (%d DOF), N=5, dt=0.1, "
-                      "eps_N 1e-8, GMRES(30)+BJ_ext, NumPy FP64, 1 thread, %.1f s" % (dg.ndof, dt)}
+    return dg, inputs.isentropic_vortex(X[0], X[1], xc, yc, beta)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline():
+    """FP64 NumPy oracle: one HBPC(6,4) step of the parity sample (dt = 0.1, eps_N 1e-8,
+    GMRES(30) + BJ_ext), timed on one thread and on all the host threads the process may
+    use (OMP_NUM_THREADS, else the CPU count).  Returns (report, the oracle's new state)."""
+    from threadpoolctl import threadpool_limits
+    from oracle.solvers import StageSolver, dg_hbpc_step
+    dg, w = parity_sample()
+    runs = {}
+    out = None
+    threads_all = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    for threads in sorted({1, threads_all}):
+        sol = StageSolver(dg, newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=30)
+        with threadpool_limits(limits=threads):
+            t0 = time.perf_counter()
+            out = dg_hbpc_step(dg, w, 0.1, 6, 4, sol)
+            runs[threads] = time.perf_counter() - t0
+        print("[bench] oracle step on %d thread(s): %.1f s" % (threads, runs[threads]), file=sys.stderr, flush=True)
+    rep = {"value": dg.ndof / runs[1], "unit": "DOF-steps/s", "cores": 1, "kind": "oracle",
+           "sample": "one HBPC(6,4) step, vortex on %dx%d elements of [0,10]^2 (%d DOF), N=5, dt=0.1, "
+                     "eps_N 1e-8, GMRES(30)+BJ_ext, NumPy FP64, 1 thread, %.1f s"
+                     % (PARITY_N, PARITY_N, dg.ndof, runs[1]),
+           "all_cores": {"value": dg.ndof / runs[threads_all], "cores": threads_all, "seconds": runs[threads_all]},
+           "cpu_model": cpu_model()}
+    return rep, out
+
+
+def form_parity(wl, forms, ref, theta, pc_rebuild, pc_reuse_steps, pc_probe_its):
+    """Relative L2 difference between one GPU step of each form on the parity sample and the
+    oracle's step (both at eps_N 1e-8): the error against the FP64 oracle of every timed form."""
+    import numpy as np
+    import torch
+    from paper_2109_04804_amd.hbpc import Context
+    _, w0 = parity_sample()
+    out = {}
+    for f in forms:
+        precision, pc, half = form_settings(f)
+        ctx = Context(2, [PARITY_N, PARITY_N], [10.0, 10.0], 5, "euler", q=6, kmax=4, newton_rtol=1e-8,
+                      gmres_rtol=1e-3, gmres_restart=30, gmres_maxit=7000, precond=pc, precision=precision,
+                      pc_fallback=0.5, pc_rebuild=pc_rebuild, pc_half=half, pc_reuse_steps=pc_reuse_steps,
+                      pc_probe_its=pc_probe_its, flux="rusanov", gamma=1.4, eps_ref=1.0)
+        if pc.startswith("learned"):
+            ctx.mlp_set_params(theta)
+        w = torch.tensor(np.ascontiguousarray(w0).reshape(-1), dtype=torch.float64, device="cuda")
+        st = ctx.step(w, 0.1)
+        got = w.cpu().numpy()
+        ctx.close()
+        out[f] = float(np.linalg.norm(got - ref.ravel()) / np.linalg.norm(ref.ravel()))
+        print("[bench] parity %s: rel L2 %.3e (fallbacks %d)" % (f, out[f], st["pc_fallbacks"]), file=sys.stderr,
+              flush=True)
+    return out
 
 
 # Preconditioner study of Sec. 4.1.2 (Figs. 4 and 5): the eps-scaled density wave of
@@ -424,7 +490,9 @@ def main():
                   "mixed16": "f64+f32+f16", "fp64": "f64", "fp64_h": "f64", "mixed_h": "f64+f32"}[head],
         "data": "synthetic",
         "config": {"workload": a.workload, "dof": dof, "scheme": "HBPC(6,4)", "dt": wl["dt"],
-                   "newton_rtol": 1e-8, "krylov": "FGMRES(30), eps_G 1e-3", "pc_rebuild": a.pc_rebuild,
+                   "newton_rtol": 1e-8,
+                   "krylov": "FGMRES(%d), eps_G 1e-3" % restart_of(wl, form_settings(head)[0]),
+                   "pc_rebuild": a.pc_rebuild,
                    "pc_reuse_steps": a.pc_reuse_steps if a.pc_rebuild == "across_steps" else None,
                    "pc_probe_its": a.pc_probe_its,
                    "precond": {"learned": "learned (BJ_ext fallback 0.5)",
@@ -447,8 +515,15 @@ def main():
     if train_report:
         out["learned_training"] = train_report
     if not a.no_cpu_baseline:
-        cb = cpu_baseline()
+        cb, ref = cpu_baseline()
         out["cpu_baseline"] = cb
+        if wl["dim"] == 2 and wl.get("equation", "euler") == "euler":
+            out["parity"] = {"sample": "vortex %dx%d elements, N=5, one HBPC(6,4) step at dt=0.1 in each timed "
+                                       "form's composition" % (PARITY_N, PARITY_N),
+                             "reference": "FP64 oracle step, eps_N 1e-8, GMRES(30)+BJ_ext",
+                             "bound": 1e-8,
+                             "rel_l2": form_parity(wl, forms, ref, theta, a.pc_rebuild, a.pc_reuse_steps,
+                                                   a.pc_probe_its)}
     print(json.dumps(out))
 
 
