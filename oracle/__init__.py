@@ -17,11 +17,13 @@ basis      1-D Gauss / Gauss-Lobatto nodes, Lagrange basis, weak-form D-hat
            (Sec. 3.1.1, Eqs. Interpolation and DGSEM_wt).
 jets       hyper-dual numbers: exact first and second directional
            derivatives, used to define R2 = R1'(w) sigma and the Hessian term.
-equations  physical fluxes (advection, Burgers, eps-scaled Euler of Eq. Euler)
-           and the Lax-Friedrichs / Rusanov numerical flux (Eq. Riemann).
+equations  physical fluxes (advection, Burgers, eps-scaled Euler of Eq. Euler,
+           Navier-Stokes of Eq. NavierStokes with its viscous flux) and the
+           Lax-Friedrichs / Rusanov numerical flux (Eq. Riemann).
 dgsem      the DGSEM operators R1_h (Eq. DGSEM_wt), R2_h (Eq. DGSEM_wtt),
-           BR1 lifting, the extended residual G(X) and Jacobian-vector
-           product (Eq. nonlinear_eqsys), the element-local Jacobian.
+           BR1 lifting (viscous Burgers), BR2 lifting (Navier-Stokes, Sec. 5.1),
+           the extended residual G(X) and Jacobian-vector product (Eq.
+           nonlinear_eqsys), the element-local Jacobian.
 tableaux   the Hermite-Birkhoff Butcher tableaux of the appendix.
 hbpc       Algorithm 1 (predictor, corrector, update) over abstract R1/R2/solve.
 solvers    Newton on G(X), restarted right-preconditioned GMRES (MGS), the

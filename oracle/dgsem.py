@@ -24,6 +24,21 @@ BR1 for viscous Burgers: q_m = (2/h_m)[Dhat u + u*_+ lhat(+1) - u*_- lhat(-1)]
 with u* = (uL + uR)/2; viscous flux -nu q_m in the volume, -nu (qL + qR)/2 on
 faces.
 
+BR2 for Navier-Stokes (Sec. 5.1, Eqs. NS_System, Lifting, Riemann_visc), with
+g = w_grad(w) = (v, T) at the nodes, g^+- = w_grad(w^+-) at a face from the
+traces of w, and g* = (g^L + g^R)/2:
+  * volume gradients (global lifting, strong form):
+        d_{k,j} = (2/h_j)[D g_k + lhat(+1)(g*_{k,+j} - g^+_k) - lhat(-1)(g*_{k,-j} - g^-_k)]
+    with D_{i lam} = l_lam'(xi_i);
+  * face gradients (BR2 local lifting of the face's own jump): on the +e_m
+    face d^L_{k,j} = [(2/h_j) D_j g_k](+1 along m) + eta delta_jm (2/h_m) c_+ (g*_k - g^+_k),
+    on the -e_m face the same with l(-1), c_- and a minus sign;
+    c_+- = sum_i l_i(+-1)^2 / omega_i (the local lifting evaluated on its face);
+  * volume flux F - F^v(w, d); face flux f*(wL, wR) - (F^v(wL, d^L) + F^v(wR, d^R))/2.
+eta (eta_br2) is the BR2 stabilisation parameter, 2 by default.  R2 is again
+the exact directional derivative, so that the linearised lifting (the eta
+auxiliary variable of Eq. Lifting_eta) is carried by the jets.
+
 Layout of flat arrays: w[e][v][node], node = i + (N+1)(j + (N+1)k), elements
 lexicographic with x fastest.  Internally each variable is an array of shape
 (n_{d-1}, .., n_0, N+1, .., N+1) whose last axis is the x node index.
@@ -31,7 +46,7 @@ lexicographic with x fastest.  Internally each variable is an array of shape
 import numpy as np
 from . import jets
 from .basis import Basis1D
-from .equations import numerical_flux, Burgers
+from .equations import numerical_flux, Burgers, NavierStokes
 
 
 class Mesh:
@@ -68,7 +83,7 @@ def _const_but_b(x):
 
 
 class DGSEM:
-    def __init__(self, mesh, N, eq, nodes="gauss", flux="rusanov", lam=0.0):
+    def __init__(self, mesh, N, eq, nodes="gauss", flux="rusanov", lam=0.0, eta_br2=2.0):
         self.mesh = mesh
         self.d = mesh.dim
         self.N = N
@@ -82,6 +97,8 @@ class DGSEM:
         self.ndof = mesh.n_elem * self.nvar * self.nnode
         self.viscous = isinstance(eq, Burgers) and eq.nu != 0.0
         self.is_burgers = isinstance(eq, Burgers)
+        self.ns = isinstance(eq, NavierStokes)
+        self.eta_br2 = float(eta_br2)
 
     # ---------------------------------------------------------------- layout
     def _egrid(self):
@@ -158,8 +175,67 @@ class DGSEM:
             q.append(s * (2.0 / self.mesh.h[m]))
         return q
 
+    def _r1_ns(self, u, local=False):
+        """R1_h of the Navier-Stokes equations with BR2 lifting (module docstring)."""
+        b = self.basis
+        eq = self.eq
+        d = self.d
+        nv = self.nvar
+        ng = eq.ngrad
+        h = self.mesh.h
+        keep = (_const_but_b if local == "b" else _const) if local else (lambda x: x)
+        g = eq.grad_vars(u)
+        # strong (broken) gradient at the nodes: dvol[k][j] = (2/h_j) D_j g_k
+        dvol = [[self._contract(b.Dstd, g[k], j) * (2.0 / h[j]) for j in range(d)] for k in range(ng)]
+        faces = []
+        for m in range(d):
+            up, um, nl, nr = self._neighbour_traces(u, m, local)
+            gp, gm = eq.grad_vars(up), eq.grad_vars(um)
+            gnl, gnr = eq.grad_vars(nl), eq.grad_vars(nr)
+            jp = [0.5 * (gp[k] + gnr[k]) - gp[k] for k in range(ng)]   # g* - g^+ on the +e_m face
+            jm = [0.5 * (gnl[k] + gm[k]) - gm[k] for k in range(ng)]   # g* - g^- on the -e_m face
+            faces.append((up, um, nl, nr, jp, jm))
+        # global lifting: the volume gradients
+        dglob = [[None] * d for _ in range(ng)]
+        for j in range(d):
+            jp, jm = faces[j][4], faces[j][5]
+            for k in range(ng):
+                s = self._spread(jp[k], b.lhat_plus, j) - self._spread(jm[k], b.lhat_minus, j)
+                dglob[k][j] = dvol[k][j] + s * (2.0 / h[j])
+        c_p = float(np.sum(b.l_plus ** 2 / b.w))
+        c_m = float(np.sum(b.l_minus ** 2 / b.w))
+        R = [None] * nv
+        for m in range(d):
+            up, um, nl, nr, jp, jm = faces[m]
+            # own BR2 face gradients on the +-e_m faces
+            dfp = [[self._trace(dvol[k][j], b.l_plus, m) for j in range(d)] for k in range(ng)]
+            dfm = [[self._trace(dvol[k][j], b.l_minus, m) for j in range(d)] for k in range(ng)]
+            for k in range(ng):
+                dfp[k][m] = dfp[k][m] + jp[k] * (self.eta_br2 * 2.0 / h[m] * c_p)
+                dfm[k][m] = dfm[k][m] - jm[k] * (self.eta_br2 * 2.0 / h[m] * c_m)
+            # the neighbours' face gradients on the shared faces (computed by the neighbours)
+            dfnr = [[keep(self._roll(dfm[k][j], -1, m)) for j in range(d)] for k in range(ng)]
+            dfnl = [[keep(self._roll(dfp[k][j], +1, m)) for j in range(d)] for k in range(ng)]
+            F = eq.flux(u, m)
+            Fv = eq.viscous_flux(u, dglob, m)
+            F = [F[v] - Fv[v] for v in range(nv)]
+            fp = numerical_flux(eq, self.flux_kind, self.lam, up, nr, m)    # element on L side
+            fm = numerical_flux(eq, self.flux_kind, self.lam, nl, um, m)    # element on R side
+            vp_own, vp_nb = eq.viscous_flux(up, dfp, m), eq.viscous_flux(nr, dfnr, m)
+            vm_nb, vm_own = eq.viscous_flux(nl, dfnl, m), eq.viscous_flux(um, dfm, m)
+            fp = [fp[v] - 0.5 * (vp_own[v] + vp_nb[v]) for v in range(nv)]
+            fm = [fm[v] - 0.5 * (vm_nb[v] + vm_own[v]) for v in range(nv)]
+            for v in range(nv):
+                vol = self._contract(b.Dhat, F[v], m)
+                s = vol + self._spread(fp[v], b.lhat_plus, m) - self._spread(fm[v], b.lhat_minus, m)
+                s = s * (2.0 / h[m])
+                R[v] = s if R[v] is None else R[v] + s
+        return [-x for x in R]
+
     def _r1_vars(self, u, local=False):
         """R1_h on a list of per-variable arrays (values, complex or jets)."""
+        if self.ns:
+            return self._r1_ns(u, local)
         b = self.basis
         eq = self.eq
         nv = self.nvar

@@ -101,6 +101,54 @@ class Euler:
         return False
 
 
+class NavierStokes(Euler):
+    """Compressible Navier-Stokes (Sec. 5.1, Eq. NavierStokes) on the eps-scaled Euler
+    system: w_t + div(F(w) - F^v(w, grad w)) = 0 with the viscous flux as printed,
+
+        F^v = (0, tau, tau.v + q),
+        tau = mu (grad v + grad v^T - 2/3 (div v) I),   q = kappa grad T,
+        kappa = c_p mu / Pr,  c_p = R gamma / (gamma - 1),  R = 1 / (gamma eps^2),
+        p = rho R T,  Pr = 0.72 by default.
+
+    The viscous flux depends on w and on the gradients d = grad w_grad of
+    w_grad = (v_1, .., v_d, T) (Eq. LiftingEq), which the DGSEM operator lifts."""
+
+    def __init__(self, dim, gamma=1.4, eps=1.0, mu=1e-3, Pr=0.72):
+        super().__init__(dim, gamma, eps)
+        self.mu = float(mu)
+        self.Pr = float(Pr)
+        self.R = 1.0 / (self.gamma * self.eps ** 2)
+        self.cp = self.R * self.gamma / (self.gamma - 1.0)
+        self.kappa = self.cp * self.mu / self.Pr
+        self.ngrad = dim + 1
+
+    def grad_vars(self, w):
+        """w_grad = (v_1, .., v_d, T) with T = p / (rho R)."""
+        rho = w[0]
+        out = [w[1 + k] / rho for k in range(self.dim)]
+        out.append(self.pressure(w) / (rho * self.R))
+        return out
+
+    def viscous_flux(self, w, g, m):
+        """F^v_m(w, d), g[k][j] = d w_grad_k / d x_j."""
+        d = self.dim
+        rho = w[0]
+        vel = [w[1 + k] / rho for k in range(d)]
+        div = g[0][0]
+        for k in range(1, d):
+            div = div + g[k][k]
+        tau = []
+        for i in range(d):     # tau_{i m}
+            t = (g[i][m] + g[m][i]) * self.mu
+            if i == m:
+                t = t - div * (2.0 / 3.0 * self.mu)
+            tau.append(t)
+        energy = g[d][m] * self.kappa
+        for i in range(d):
+            energy = energy + tau[i] * vel[i]
+        return [rho * 0.0] + tau + [energy]
+
+
 def numerical_flux(eq, kind, lam_const, wL, wR, m):
     """f* in direction +e_m from the two traces (lists of per-variable arrays)."""
     FL = eq.flux(wL, m)
