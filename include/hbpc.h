@@ -200,6 +200,21 @@ int hbpc_nodes(const hbpc_ctx* ctx, double* xi_host, double* w_host);
 
 /* R1_h(w) -> r1 (Eq. DGSEM_wt). */
 int hbpc_residual1(hbpc_ctx* ctx, const double* w, double* r1);
+/* For callers that cannot allocate device memory (code under stream capture, tight serving
+ * loops, hosts that forbid hipMalloc): R1_h(w) -> r1 as hbpc_residual1 computes it, with no
+ * context and no allocation of any kind.  mesh, params: host structs as for hbpc_create
+ * (only the mesh, nodes, flux and equation parameters and params->stream are used); w, r1:
+ * caller-owned device arrays of ndof doubles in the layout of hbpc_residual1, enqueued on
+ * params->stream (0: the null stream) and not waited for.  The 1-D operators and the face
+ * traces are kept in a static device array of 64 MiB per GPU, held from the library's load
+ * until the process ends; the traces need nE * 2d * nvar * (N+1)^(d-1) * 8 bytes (twice
+ * that with BR1) of it after 4 KiB for the operators, and larger meshes are refused with
+ * HBPC_ERR_ARG before any device work.  Every call on a GPU shares that GPU's array: calls
+ * that overlap on one GPU (other streams, other host threads) race and must be serialised
+ * by the caller.  Errors (returned only, there is no context for hbpc_last_error):
+ * HBPC_ERR_ARG, HBPC_ERR_UNSUPPORTED as for hbpc_create, HBPC_ERR_HIP. */
+int hbpc_residual1_noalloc(const hbpc_mesh* mesh, int N, int equation, const hbpc_params* params,
+                           const double* w, double* r1);
 /* R2_h(w, sigma) = R1_h'(w) sigma -> r2 (Eq. DGSEM_wtt, exact directional
  * derivative).  sigma == NULL: sigma = R1_h(w) is computed first. */
 int hbpc_residual2(hbpc_ctx* ctx, const double* w, const double* sigma, double* r2);

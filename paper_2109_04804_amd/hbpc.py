@@ -93,6 +93,7 @@ SIGNATURES = {
     "hbpc_block_size": (_I, [_P]),
     "hbpc_nodes": (_I, [_P, _P, _P]),
     "hbpc_residual1": (_I, [_P, _P, _P]),
+    "hbpc_residual1_noalloc": (_I, [ctypes.POINTER(HbpcMesh), _I, _I, ctypes.POINTER(HbpcParams), _P, _P]),
     "hbpc_residual2": (_I, [_P, _P, _P, _P]),
     "hbpc_newton_residual": (_I, [_P, _P, _P, _P, _D, _D, _P]),
     "hbpc_jvp": (_I, [_P, _P, _P, _D, _D, _P, _P, _I]),
@@ -197,6 +198,25 @@ def _ptr(t, n, dtype):
     if t.numel() != n:
         raise ValueError("expected %d values, got %d" % (n, t.numel()))
     return ctypes.c_void_p(t.data_ptr())
+
+
+def residual1_noalloc(dim, nelem, length, N, equation, w, out, origin=(0.0, 0.0, 0.0), stream=None, **params):
+    """hbpc_residual1_noalloc: R1(w) -> out without a context or any device allocation
+    (w, out: float64 GPU tensors of the mesh's ndof values)."""
+    import torch
+    lib = load_library()
+    p = make_params(**params)
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    p.stream = ctypes.c_void_p(stream)
+    m = make_mesh(dim, nelem, length, origin)
+    eq = EQ[equation] if isinstance(equation, str) else int(equation)
+    n = w.numel()
+    rc = lib.hbpc_residual1_noalloc(ctypes.byref(m), int(N), eq, ctypes.byref(p), _ptr(w, n, torch.float64),
+                                    _ptr(out, n, torch.float64))
+    if rc != HBPC_OK:
+        raise HbpcError(rc, "hbpc_residual1_noalloc failed (%s)" % lib.hbpc_strerror(rc).decode())
+    return out
 
 
 class Context:
