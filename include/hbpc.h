@@ -46,6 +46,8 @@ typedef struct hbpc_ctx hbpc_ctx;
 #define HBPC_EQ_ADVECTION 1
 #define HBPC_EQ_BURGERS_BR1 2
 #define HBPC_EQ_EULER 3
+#define HBPC_EQ_NAVIER_STOKES 4    /* Sec. 5.1: eps-scaled Euler flux minus the viscous flux, BR2 lifting
+                                      (d = 2 with N <= 7, d = 3 with N <= 4) */
 
 /* interpolation/quadrature nodes (Sec. 3.1.1 uses Gauss-Legendre) */
 #define HBPC_NODES_GAUSS 0
@@ -120,6 +122,11 @@ typedef struct {
     double nu;            /* viscosity (HBPC_EQ_BURGERS_BR1) */
     double gamma;         /* ratio of specific heats (Euler) */
     double eps_ref;       /* reference Mach number eps (Euler, Eq. Euler) */
+    double mu;            /* dynamic viscosity (HBPC_EQ_NAVIER_STOKES, Eq. NavierStokes; default 0) */
+    double prandtl;       /* Prandtl number (Navier-Stokes; default 0.72): heat conductivity
+                             c_p mu / Pr with c_p = R gamma / (gamma - 1), R = 1 / (gamma eps^2) */
+    double eta_br2;       /* BR2 stabilisation of the face gradients (Navier-Stokes; default 2):
+                             face gradient = broken gradient + eta_br2 x the face's local lifting */
     int q;                /* quadrature order of the tableau: 4, 6 or 8 (appendix) */
     int kmax;             /* corrector sweeps k_max */
     double newton_rtol;   /* eps_N: stop when ||G(X^r)|| <= eps_N ||G(X^0)|| */
@@ -212,7 +219,8 @@ int hbpc_residual1(hbpc_ctx* ctx, const double* w, double* r1);
  * HBPC_ERR_ARG before any device work.  Every call on a GPU shares that GPU's array: calls
  * that overlap on one GPU (other streams, other host threads) race and must be serialised
  * by the caller.  Errors (returned only, there is no context for hbpc_last_error):
- * HBPC_ERR_ARG, HBPC_ERR_UNSUPPORTED as for hbpc_create, HBPC_ERR_HIP. */
+ * HBPC_ERR_ARG, HBPC_ERR_UNSUPPORTED as for hbpc_create and for HBPC_EQ_NAVIER_STOKES (whose
+ * BR2 face gradients are not kept in the scratch), HBPC_ERR_HIP. */
 int hbpc_residual1_noalloc(const hbpc_mesh* mesh, int N, int equation, const hbpc_params* params,
                            const double* w, double* r1);
 /* R2_h(w, sigma) = R1_h'(w) sigma -> r2 (Eq. DGSEM_wtt, exact directional

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhbpc.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["dg_euler.hip", "dg_advection.hip", "dg_burgers.hip", "bjext.hip", "bj_apply.hip", "blas.hip", "mlp.hip", "noalloc.hip", "basis1d.cpp",
+SOURCES = ["dg_euler.hip", "dg_advection.hip", "dg_burgers.hip", "dg_ns.hip", "bjext.hip", "bj_apply.hip", "blas.hip", "mlp.hip", "noalloc.hip", "basis1d.cpp",
            "hbpc.cpp"]
 
 # -packed-fp32-ops: never emit packed FP32 VALU instructions

@@ -8,7 +8,9 @@
 // derivative matrix of the collocated DGSEM is
 //   Dhat[i][lam] = -(omega_lam / omega_i) l_i'(xi_lam),
 // (the weight ratio the weak form produces; free-stream and polynomial
-// exactness hold with it), and lhat_i(+-1) = l_i(+-1) / omega_i.
+// exactness hold with it), and lhat_i(+-1) = l_i(+-1) / omega_i.  For the BR2
+// lifting of the Navier-Stokes equations also the strong-form derivative
+// Dstr[i][lam] = l_lam'(xi_i) and the face values built from it.
 #include <cmath>
 #include "hbpc_internal.hpp"
 
@@ -111,6 +113,22 @@ bool basis1d_build(int N, int kind, Basis1DHost& B) {
     for (int i = 0; i < NP; ++i) {
         B.lhp[i] = B.lp[i] / B.w[i];
         B.lhm[i] = B.lm[i] / B.w[i];
+    }
+    // strong-form derivative (BR2 lifting): Dstr[i][lam] = l_lam'(xi_i); its interpolant's value at
+    // +-1, lDp[lam] = sum_i l_i(+1) Dstr[i][lam] (lDm likewise); the local lifting of one face
+    // evaluated on that face, c_+- = sum_i l_i(+-1)^2 / omega_i
+    B.Dstr = Dstd;
+    B.lDp.assign(NP, 0.0);
+    B.lDm.assign(NP, 0.0);
+    B.cp = 0.0;
+    B.cm = 0.0;
+    for (int i = 0; i < NP; ++i) {
+        for (int lam = 0; lam < NP; ++lam) {
+            B.lDp[lam] += B.lp[i] * Dstd[i * NP + lam];
+            B.lDm[lam] += B.lm[i] * Dstd[i * NP + lam];
+        }
+        B.cp += B.lp[i] * B.lhp[i];
+        B.cm += B.lm[i] * B.lhm[i];
     }
     return true;
 }

@@ -17,6 +17,7 @@ struct GeomHost {
     const double* basis64;   // device copies of the 1-D operators (dg_ops.hpp layout)
     const float* basis32;
     double adv[3], lam, nu, gamma, eps;
+    double mu, kappa, gam_eps2, eta;   // Navier-Stokes: viscosity, heat conductivity, 1/R, BR2 eta
     int flux;
 };
 
@@ -27,6 +28,8 @@ struct LaunchReq {
     const void* q[4][3];
     const void* qtr[4];
     void* out[4];
+    void* nsg[4];         // BR2 face gradients per jet component (Navier-Stokes)
+    int aux;              // 1: run the BR2 face-gradient kernel of this op instead of the op
     double c0, c1;
     int col;
     int e_begin, e_end;   // element range (e_end <= 0: whole mesh)
@@ -47,6 +50,10 @@ template <typename T> EqParams<T> make_eq(const GeomHost& g) {
     p.half_eps2 = (T)(0.5 * g.eps * g.eps);
     p.inv_eps = (T)(1.0 / g.eps);
     p.inv_eps2 = (T)(1.0 / (g.eps * g.eps));
+    p.mu = (T)g.mu;
+    p.kappa = (T)g.kappa;
+    p.gam_eps2 = (T)g.gam_eps2;
+    p.eta = (T)g.eta;
     p.flux = g.flux;
     return p;
 }
@@ -57,6 +64,7 @@ template <typename T> OpArgs<T> make_args(const GeomHost& g, const LaunchReq& r)
         a.fld[j] = (const T*)r.fld[j];
         a.trc[j] = (const T*)r.trc[j];
         a.qtr[j] = (const T*)r.qtr[j];
+        a.nsg[j] = (T*)r.nsg[j];
         for (int m = 0; m < 3; ++m) a.q[j][m] = (const T*)r.q[j][m];
     }
     a.out[0] = (T*)r.out[0];
@@ -75,10 +83,28 @@ template <typename T> OpArgs<T> make_args(const GeomHost& g, const LaunchReq& r)
     return a;
 }
 
+// BR2 face gradients of the jet of OP over the whole mesh (Navier-Stokes only)
+template <int D, int NP, class EQ, class OP, typename T>
+hipError_t launch_nsaux(const GeomHost& g, const LaunchReq& r) {
+    if constexpr (!EQ::NS) {
+        return hipErrorInvalidValue;
+    } else {
+        constexpr int NN = ipow(NP, D);
+        constexpr int EPB = aux_epb<D, NP, EQ, OP, T>();
+        OpArgs<T> a = make_args<T>(g, r);
+        int grid = (g.nE + EPB - 1) / EPB;
+        if (grid <= 0) return hipSuccess;
+        hipLaunchKernelGGL((ns_facegrad_kernel<D, NP, EQ, OP, T>), dim3(grid), dim3(EPB * NN), 0, r.stream, a,
+                           make_eq<T>(g));
+        return hipGetLastError();
+    }
+}
+
 template <int D, int NP, class EQ, class OP, typename T>
 hipError_t launch_op(const GeomHost& g, const LaunchReq& r) {
+    if (r.aux) return launch_nsaux<D, NP, EQ, OP, T>(g, r);
     constexpr int NN = ipow(NP, D);
-    constexpr int EPB = op_epb<D, NP, EQ::NV, OP::NJ, OP::NC, T>();
+    constexpr int EPB = kernel_epb<D, NP, EQ, OP, T>();
     OpArgs<T> a = make_args<T>(g, r);
     int grid = (a.e_end - a.e_begin + EPB - 1) / EPB;
     if (grid <= 0) return hipSuccess;
@@ -124,25 +150,29 @@ template <int D, int NP, class EQ, typename T> hipError_t launch_family_np(const
     }
 }
 
+// largest N + 1 instantiated: 8 (N = 7) in 1-D and 2-D, 6 in 3-D (a 3-D element of 343 nodes exceeds
+// one 256-thread block with one thread per node); with the BR2 lifting in 3-D 5, where the LDS of
+// the lifted gradients in hyper-dual FP64 still fits gfx950's 160 KB per workgroup
+template <int D, class EQ> constexpr int max_np() {
+    if constexpr (D == 3 && EQ::NS) return 5;
+    else if constexpr (D == 3) return 6;
+    else return 8;
+}
+
 template <int D, class EQ> hipError_t launch_family(const GeomHost& g, const LaunchReq& r, int f32) {
-#define HBPC_NP_CASE(NPV)                                                          \
-    case NPV:                                                                      \
-        return f32 ? launch_family_np<D, NPV, EQ, float>(g, r)                     \
-                   : launch_family_np<D, NPV, EQ, double>(g, r);
+#define HBPC_NP_CASE(NPV)                                                                  \
+    case NPV:                                                                              \
+        if constexpr (NPV <= max_np<D, EQ>())                                              \
+            return f32 ? launch_family_np<D, NPV, EQ, float>(g, r)                         \
+                       : launch_family_np<D, NPV, EQ, double>(g, r);                       \
+        return hipErrorInvalidValue;
     switch (g.NP) {
         HBPC_NP_CASE(3)
         HBPC_NP_CASE(4)
         HBPC_NP_CASE(5)
         HBPC_NP_CASE(6)
-    case 7:
-    case 8:
-        // N = 6, 7 (the paper's convergence studies use N = 7 in 2-D); a 3-D element of 343 or
-        // 512 nodes exceeds one 256-thread block with one thread per node
-        if constexpr (D < 3) {
-            if (g.NP == 7) return f32 ? launch_family_np<D, 7, EQ, float>(g, r) : launch_family_np<D, 7, EQ, double>(g, r);
-            return f32 ? launch_family_np<D, 8, EQ, float>(g, r) : launch_family_np<D, 8, EQ, double>(g, r);
-        }
-        return hipErrorInvalidValue;
+        HBPC_NP_CASE(7)
+        HBPC_NP_CASE(8)
     default: return hipErrorInvalidValue;
     }
 #undef HBPC_NP_CASE

@@ -32,10 +32,13 @@ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
 // 1-D operators in device memory, copied to LDS by every block:
 //   Dhat[NP*NP] (Dhat[i*NP+lam]), lp[NP] = l_i(+1), lm[NP] = l_i(-1),
-//   lhp[NP] = l_i(+1)/omega_i, lhm[NP] = l_i(-1)/omega_i
-template <int NP> constexpr int basis_len() { return NP * NP + 4 * NP; }
+//   lhp[NP] = l_i(+1)/omega_i, lhm[NP] = l_i(-1)/omega_i,
+//   for the BR2 lifting: Dstr[NP*NP] (Dstr[i*NP+lam] = l_lam'(xi_i)), lDp[NP], lDm[NP]
+//   (lDp[lam] = sum_i l_i(+1) Dstr[i][lam]), c[2] = sum_i l_i(+-1)^2 / omega_i
+template <int NP> constexpr int basis_len() { return 2 * NP * NP + 6 * NP + 2; }
 template <int NP> struct BOff {
     static constexpr int D = 0, LP = NP * NP, LM = LP + NP, LHP = LM + NP, LHM = LHP + NP;
+    static constexpr int DS = LHM + NP, LDP = DS + NP * NP, LDM = LDP + NP, CP = LDM + NP, CM = CP + 1;
 };
 
 template <typename T> struct OpArgs {
@@ -43,6 +46,8 @@ template <typename T> struct OpArgs {
     const T* trc[4];      // neighbour traces of the jet fields (nullptr = zero)
     const T* q[4][3];     // BR1: lifted gradient of jet field j, direction m
     const T* qtr[4];      // BR1: traces of q (face 2m+s holds q_m)
+    T* nsg[4];            // BR2 face gradients of jet component j (written by the face-gradient
+                          // kernel, read as neighbour data by the operator kernel)
     T* out[2];
     const T* basis;       // 1-D operators (layout above)
     T c0, c1;             // a1dt, bcoef
@@ -89,6 +94,7 @@ template <typename T> struct OpR1 {
     static constexpr int NGLOB = NJ;
     HD static T load(const OpArgs<T>& a, int j, size_t g, int loc) { return a.fld[0][g]; }
     HD static S make(const T* x, const OpArgs<T>& a) { return x[0]; }
+    HD static void split(const S& v, T* x) { jet_split(v, x); }
     HD static void combo(const S& f, T* c, const OpArgs<T>& a) { c[0] = f; }
     HD static void output(const OpArgs<T>& a, size_t g, int e, int loc, const T* gv) { a.out[0][g] = gv[0]; }
 };
@@ -99,6 +105,7 @@ template <typename T> struct OpR2 {
     static constexpr int NGLOB = NJ;
     HD static T load(const OpArgs<T>& a, int j, size_t g, int loc) { return a.fld[j][g]; }
     HD static S make(const T* x, const OpArgs<T>& a) { return {x[0], x[1]}; }
+    HD static void split(const S& v, T* x) { jet_split(v, x); }
     HD static void combo(const S& f, T* c, const OpArgs<T>& a) { c[0] = f.b; }
     HD static void output(const OpArgs<T>& a, size_t g, int e, int loc, const T* gv) { a.out[0][g] = gv[0]; }
 };
@@ -109,6 +116,7 @@ template <typename T> struct OpRes {   // fld: w, sigma, b
     static constexpr int NGLOB = NJ;
     HD static T load(const OpArgs<T>& a, int j, size_t g, int loc) { return a.fld[j][g]; }
     HD static S make(const T* x, const OpArgs<T>& a) { return {x[0], x[1]}; }
+    HD static void split(const S& v, T* x) { jet_split(v, x); }
     HD static void combo(const S& f, T* c, const OpArgs<T>& a) {
         c[0] = -a.c0 * f.a + a.c1 * f.b;
         c[1] = f.a;
@@ -123,12 +131,14 @@ template <typename T, bool HESS> struct JvpJet;
 template <typename T> struct JvpJet<T, true> {   // w + e_s sigma + e_d dw + e_s e_d dsigma
     using S = HDual<T>;
     HD static S make(const T* x) { return {x[0], x[1], x[2], x[3]}; }
+    HD static void split(const S& v, T* x) { jet_split(v, x); }
     HD static T first(const S& f) { return f.d; }
     HD static T second(const S& f) { return f.m; }
 };
 template <typename T> struct JvpJet<T, false> {   // w + e1 dw + e2 dsigma
     using S = Dual2<T>;
     HD static S make(const T* x) { return {x[0], x[2], x[3]}; }
+    HD static void split(const S& v, T* x) { x[0] = v.a; x[1] = T(0); x[2] = v.b; x[3] = v.c; }
     HD static T first(const S& f) { return f.b; }
     HD static T second(const S& f) { return f.c; }
 };
@@ -140,6 +150,7 @@ template <typename T, bool HESS> struct OpJvp {   // fld: w, sigma, dw, dsigma
     static constexpr int NGLOB = NJ;
     HD static T load(const OpArgs<T>& a, int j, size_t g, int loc) { return a.fld[j][g]; }
     HD static S make(const T* x, const OpArgs<T>& a) { return J::make(x); }
+    HD static void split(const S& v, T* x) { J::split(v, x); }
     HD static void combo(const S& f, T* c, const OpArgs<T>& a) {
         c[0] = -a.c0 * J::first(f) + a.c1 * J::second(f);
         c[1] = J::first(f);
@@ -158,6 +169,7 @@ template <typename T, int NE> struct OpKcol {   // fld: w; column = blockIdx.y; 
         return j == 0 ? a.fld[0][g] : (loc == (int)blockIdx.y ? T(1) : T(0));
     }
     HD static S make(const T* x, const OpArgs<T>& a) { return {x[0], x[1]}; }
+    HD static void split(const S& v, T* x) { jet_split(v, x); }
     HD static void combo(const S& f, T* c, const OpArgs<T>& a) { c[0] = f.b; }
     HD static void output(const OpArgs<T>& a, size_t g, int e, int loc, const T* gv) {
         a.out[0][((size_t)(e - a.e_begin) * NE + blockIdx.y) * NE + loc] = gv[0];
@@ -176,6 +188,7 @@ template <typename T, int NE> struct OpKHcol {
         return (j == 2 && loc == (int)blockIdx.y) ? T(1) : T(0);
     }
     HD static S make(const T* x, const OpArgs<T>& a) { return {x[0], x[1], x[2], x[3]}; }
+    HD static void split(const S& v, T* x) { jet_split(v, x); }
     HD static void combo(const S& f, T* c, const OpArgs<T>& a) { c[0] = f.d; c[1] = f.m; }
     HD static void output(const OpArgs<T>& a, size_t g, int e, int loc, const T* gv) {
         const size_t i = ((size_t)(e - a.e_begin) * NE + blockIdx.y) * NE + loc;
@@ -194,6 +207,7 @@ template <typename T> struct OpPcPre {   // fld: w, vw, vs
         return a.fld[1][g] - a.c0 * a.fld[2][g];
     }
     HD static S make(const T* x, const OpArgs<T>& a) { return {x[0], x[1], x[2]}; }
+    HD static void split(const S& v, T* x) { jet_split(v, x); }
     HD static void combo(const S& f, T* c, const OpArgs<T>& a) { c[0] = f.b; c[1] = f.c; }
     HD static void output(const OpArgs<T>& a, size_t g, int e, int loc, const T* gv) {
         a.out[0][g] = a.fld[1][g] - a.c1 * gv[0];
@@ -209,17 +223,44 @@ template <typename T, bool LOC> struct OpLin {
     static constexpr int NGLOB = LOC ? 1 : NJ;
     HD static T load(const OpArgs<T>& a, int j, size_t g, int loc) { return a.fld[j][g]; }
     HD static S make(const T* x, const OpArgs<T>& a) { return {x[0], x[1]}; }
+    HD static void split(const S& v, T* x) { jet_split(v, x); }
     HD static void combo(const S& f, T* c, const OpArgs<T>& a) { c[0] = f.b; }
     HD static void output(const OpArgs<T>& a, size_t g, int e, int loc, const T* gv) {
         a.out[0][g] = a.fld[2][g] + a.c0 * gv[0];
     }
 };
 
-// elements per block: as many as fit 256 threads and ~64 KB of LDS
-template <int D, int NP, int NV, int NJ, int NC, typename T> constexpr int op_epb() {
+// elements per block: as many as fit 256 threads and ~64 KB of LDS (EXTRA: bytes per element of
+// LDS beyond the jet fields, fluxes and face fluxes; with it the budget is gfx950's 160 KB)
+template <int D, int NP, int NV, int NJ, int NC, typename T, int EXTRA = 0> constexpr int op_epb() {
     constexpr int NN = ipow(NP, D), NFP = ipow(NP, D - 1);
-    constexpr int bytes = (NJ * NV * NN + NC * D * NV * NN + NC * 2 * D * NV * NFP) * (int)sizeof(T) + 64;
-    constexpr int by_lds = 65536 / bytes;
+    constexpr int bytes = (NJ * NV * NN + NC * D * NV * NN + NC * 2 * D * NV * NFP) * (int)sizeof(T) + EXTRA + 64;
+    constexpr int budget = EXTRA > 0 ? 159 * 1024 : 65536;
+    constexpr int by_lds = budget / bytes;
+    constexpr int by_thr = 256 / NN;
+    constexpr int e = by_lds < by_thr ? by_lds : by_thr;
+    return e < 1 ? 1 : e;
+}
+
+// Navier-Stokes: number of lifted variables g = (v, T) (0 for the other equations)
+template <class EQ> constexpr int eq_ng() {
+    if constexpr (EQ::NS) return EQ::NG;
+    else return 0;
+}
+// LDS bytes per element of the BR2 lifting: g at the nodes, the jumps at the face points, the
+// strong gradients at the nodes, in the jet type S
+template <int D, int NP, class EQ, class S> constexpr int ns_lds_bytes() {
+    constexpr int NN = ipow(NP, D), NFP = ipow(NP, D - 1), NG = eq_ng<EQ>();
+    return (NG * NN + NG * 2 * D * NFP + NG * D * NN) * (int)sizeof(S);
+}
+template <int D, int NP, class EQ, class OP, typename T> constexpr int kernel_epb() {
+    return op_epb<D, NP, EQ::NV, OP::NJ, OP::NC, T, ns_lds_bytes<D, NP, EQ, typename OP::S>()>();
+}
+// elements per block of the BR2 face-gradient kernel (jet fields and the lifting in LDS)
+template <int D, int NP, class EQ, class OP, typename T> constexpr int aux_epb() {
+    constexpr int NN = ipow(NP, D);
+    constexpr int bytes = OP::NJ * EQ::NV * NN * (int)sizeof(T) + ns_lds_bytes<D, NP, EQ, typename OP::S>() + 64;
+    constexpr int by_lds = 159 * 1024 / bytes;
     constexpr int by_thr = 256 / NN;
     constexpr int e = by_lds < by_thr ? by_lds : by_thr;
     return e < 1 ? 1 : e;
@@ -319,6 +360,209 @@ __global__ void __launch_bounds__(256) lift_trace_kernel(const T* __restrict__ u
     }
 }
 
+// ----------------------------------------------------------------- BR2 lifting (Navier-Stokes)
+// Sec. 5.1 with the lifting in strong form: g = (v_1..v_D, T) at the nodes, g at a face point
+// from the trace of w there, the jump J = g* - g_own = (g(w_nbr) - g(w_own))/2 at every face
+// point, the strong (broken) gradient (2/h_j) Dstr g_k at the nodes, and
+//   volume gradient   d_kj = (2/h_j)[Dstr g_k + lhat(+1) J_k(+e_j) - lhat(-1) J_k(-e_j)]
+//   face gradient     d_kj(face +-e_m) = [(2/h_j) Dstr_j g_k](+-1 along m) +- delta_jm eta (2/h_m) c_+- J_k
+// (BR2: the broken gradient plus eta times the face's own local lifting, c_+- = sum l(+-1)^2/omega).
+// Layouts in LDS (jet type S): s_g[k][el][node], s_jmp[k][el][face][fp], s_dv[k][j][el][node].
+// AUX: components j >= NGLOB of the jet are zero (the face-gradient kernel produces only the
+// parts that neighbours read).
+template <class OP, bool AUX, typename T, int EPB, int NV, int NN>
+__device__ __forceinline__ typename OP::S ns_jet(const OpArgs<T>& a, const T (*s_fld)[EPB][NV][NN], int el, int v,
+                                                 int node) {
+    T x[OP::NJ];
+#pragma unroll
+    for (int j = 0; j < OP::NJ; ++j) x[j] = (AUX && j >= OP::NGLOB) ? T(0) : s_fld[j][el][v][node];
+    return OP::make(x, a);
+}
+
+// phase A (every node): g into s_g
+template <int D, int NP, class EQ, class OP, bool AUX, typename T, int EPB, int NN>
+__device__ __forceinline__ void ns_stage_g(const OpArgs<T>& a, const EqParams<T>& ep,
+                                           const T (*s_fld)[EPB][EQ::NV][NN], typename OP::S* s_g, int el,
+                                           int node) {
+    using S = typename OP::S;
+    constexpr int NV = EQ::NV, NG = EQ::NG;
+    S wn[NV], g[NG];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) wn[v] = ns_jet<OP, AUX, T, EPB, NV, NN>(a, s_fld, el, v, node);
+    EQ::grad_vars(wn, g, ep);
+#pragma unroll
+    for (int k = 0; k < NG; ++k) s_g[(k * EPB + el) * NN + node] = g[k];
+}
+
+// phase A (every face point): the jump J into s_jmp
+template <int D, int NP, class EQ, class OP, bool AUX, typename T, int EPB, int NN, int NFP>
+__device__ __forceinline__ void ns_face_jump(const OpArgs<T>& a, const EqParams<T>& ep, const T* s_b,
+                                             const T (*s_fld)[EPB][EQ::NV][NN], typename OP::S* s_jmp, int fel,
+                                             int fe, int face, int fp) {
+    using S = typename OP::S;
+    constexpr int NV = EQ::NV, NG = EQ::NG, NJ = OP::NJ;
+    const int m = face >> 1, side = face & 1;
+    const T* l = s_b + (side ? BOff<NP>::LP : BOff<NP>::LM);
+    const int enb = nbr_elem<D>(fe, m, side ? 1 : -1, a.nel);
+    const size_t nbase = ((size_t)enb * 2 * D + (2 * m + 1 - side)) * NV * NFP + fp;
+    S own[NV], nb[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        T x[NJ], y[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            T acc = T(0);
+            if (!(AUX && j >= OP::NGLOB)) {
+#pragma unroll
+                for (int q = 0; q < NP; ++q) acc += l[q] * s_fld[j][fel][v][node_on_line<D, NP>(fp, m, q)];
+            }
+            x[j] = acc;
+            const T* t = j >= OP::NGLOB ? nullptr : a.trc[j];
+            y[j] = t ? t[nbase + (size_t)v * NFP] : T(0);
+        }
+        own[v] = OP::make(x, a);
+        nb[v] = OP::make(y, a);
+    }
+    S go[NG], gn[NG];
+    EQ::grad_vars(own, go, ep);
+    EQ::grad_vars(nb, gn, ep);
+#pragma unroll
+    for (int k = 0; k < NG; ++k) s_jmp[((k * EPB + fel) * 2 * D + face) * NFP + fp] = (gn[k] - go[k]) * T(0.5);
+}
+
+// phase B (every node): strong gradients into s_dv
+template <int D, int NP, class EQ, class OP, typename T, int EPB, int NN>
+__device__ __forceinline__ void ns_strong_grad(const OpArgs<T>& a, const T* s_b, const typename OP::S* s_g,
+                                               typename OP::S* s_dv, int el, int node) {
+    using S = typename OP::S;
+    constexpr int NG = EQ::NG;
+    const int idx[3] = {node % NP, (node / NP) % NP, node / (NP * NP)};
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const int ij = idx[j];
+        const int stride = j == 0 ? 1 : (j == 1 ? NP : NP * NP);
+        const int b0 = node - ij * stride;
+        const T* Drow = s_b + BOff<NP>::DS + ij * NP;
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+            const S* gk = s_g + (k * EPB + el) * NN;
+            S acc = gk[b0] * Drow[0];
+#pragma unroll
+            for (int q = 1; q < NP; ++q) acc = acc + gk[b0 + q * stride] * Drow[q];
+            s_dv[((k * D + j) * EPB + el) * NN + node] = acc * a.two_h[j];
+        }
+    }
+}
+
+// volume gradient d at one node (global lifting)
+template <int D, int NP, class EQ, class OP, typename T, int EPB, int NN, int NFP>
+__device__ __forceinline__ void ns_volume_grad(const OpArgs<T>& a, const T* s_b, const typename OP::S* s_dv,
+                                               const typename OP::S* s_jmp, int el, int node,
+                                               typename OP::S (*d)[D]) {
+    constexpr int NG = EQ::NG;
+    const int idx[3] = {node % NP, (node / NP) % NP, node / (NP * NP)};
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const int ij = idx[j];
+        const int fpj = fp_of_node<D, NP>(node, j);
+        const T lp = s_b[BOff<NP>::LHP + ij], lm = s_b[BOff<NP>::LHM + ij];
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+            const auto jp = s_jmp[((k * EPB + el) * 2 * D + 2 * j + 1) * NFP + fpj];
+            const auto jm = s_jmp[((k * EPB + el) * 2 * D + 2 * j) * NFP + fpj];
+            d[k][j] = s_dv[((k * D + j) * EPB + el) * NN + node] + (jp * lp - jm * lm) * a.two_h[j];
+        }
+    }
+}
+
+// the element's own BR2 gradient at a face point of its face 2M + side
+template <int D, int NP, int M, class EQ, class OP, typename T, int EPB, int NN, int NFP>
+__device__ __forceinline__ void ns_face_grad(const OpArgs<T>& a, const EqParams<T>& ep, const T* s_b,
+                                             const typename OP::S* s_dv, const typename OP::S* s_jmp, int fel,
+                                             int side, int fp, typename OP::S (*d)[D]) {
+    using S = typename OP::S;
+    constexpr int NG = EQ::NG, m = M;
+    const T* l = s_b + (side ? BOff<NP>::LP : BOff<NP>::LM);
+    const T pen = (side ? ep.eta : -ep.eta) * a.two_h[m] * s_b[side ? BOff<NP>::CP : BOff<NP>::CM];
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const S* dv = s_dv + ((k * D + j) * EPB + fel) * NN;
+            S acc = dv[node_on_line<D, NP>(fp, m, 0)] * l[0];
+#pragma unroll
+            for (int q = 1; q < NP; ++q) acc = acc + dv[node_on_line<D, NP>(fp, m, q)] * l[q];
+            d[k][j] = acc;
+        }
+        d[k][m] = d[k][m] + s_jmp[((k * EPB + fel) * 2 * D + 2 * m + side) * NFP + fp] * pen;
+    }
+}
+
+// BR2 face-gradient kernel: for every element and face point the element's own face gradient
+// d (jet components j < NGLOB) into a.nsg[j][((e * 2D + face) * NG * D + k * D + jdir) * NFP + fp];
+// the operator kernel reads the neighbours' values from there
+template <int D, int NP, class EQ, class OP, typename T>
+__global__ void __launch_bounds__(256) ns_facegrad_kernel(OpArgs<T> a, EqParams<T> ep) {
+    if constexpr (EQ::NS) {
+        constexpr int NN = ipow(NP, D), NFP = ipow(NP, D - 1);
+        constexpr int NV = EQ::NV, NJ = OP::NJ, NG = EQ::NG;
+        constexpr int EPB = aux_epb<D, NP, EQ, OP, T>();
+        constexpr int NT = EPB * NN;
+        using S = typename OP::S;
+        __shared__ T s_fld[NJ][EPB][NV][NN];
+        __shared__ T s_b[basis_len<NP>()];
+        __shared__ S s_g[NG * EPB * NN];
+        __shared__ S s_jmp[NG * EPB * 2 * D * NFP];
+        __shared__ S s_dv[NG * D * EPB * NN];
+        const int tid = threadIdx.x;
+        const int e0 = blockIdx.x * EPB;
+        const int nloc = min(EPB, a.nE - e0);
+        for (int i = tid; i < basis_len<NP>(); i += NT) s_b[i] = a.basis[i];
+        for (int i = tid; i < nloc * NV * NN; i += NT) {
+            const int loc = i % (NV * NN);
+            const size_t g = (size_t)e0 * NV * NN + i;
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) (&s_fld[j][0][0][0])[i] = j < OP::NGLOB ? OP::load(a, j, g, loc) : T(0);
+        }
+        __syncthreads();
+        const int el = tid / NN, node = tid % NN;
+        if (el < nloc) ns_stage_g<D, NP, EQ, OP, true, T, EPB, NN>(a, ep, s_fld, s_g, el, node);
+        for (int i = tid; i < nloc * 2 * D * NFP; i += NT) {
+            const int fel = i / (2 * D * NFP), r = i % (2 * D * NFP);
+            ns_face_jump<D, NP, EQ, OP, true, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_jmp, fel, e0 + fel, r / NFP,
+                                                                r % NFP);
+        }
+        __syncthreads();
+        if (el < nloc) ns_strong_grad<D, NP, EQ, OP, T, EPB, NN>(a, s_b, s_g, s_dv, el, node);
+        __syncthreads();
+        for (int i = tid; i < nloc * 2 * D * NFP; i += NT) {
+            const int fel = i / (2 * D * NFP), r = i % (2 * D * NFP);
+            const int face = r / NFP, fp = r % NFP;
+            S d[NG][D];
+            const int m = face >> 1, side = face & 1;
+            if (m == 0) {
+                ns_face_grad<D, NP, 0, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_dv, s_jmp, fel, side, fp, d);
+            } else if (m == 1) {
+                if constexpr (D > 1)
+                    ns_face_grad<D, NP, 1, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_dv, s_jmp, fel, side, fp, d);
+            } else {
+                if constexpr (D > 2)
+                    ns_face_grad<D, NP, 2, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_dv, s_jmp, fel, side, fp, d);
+            }
+            const size_t base = ((size_t)(e0 + fel) * 2 * D + face) * NG * D;
+#pragma unroll
+            for (int k = 0; k < NG; ++k)
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    T x[NJ];
+                    OP::split(d[k][j], x);
+#pragma unroll
+                    for (int c = 0; c < OP::NGLOB; ++c) a.nsg[c][(base + k * D + j) * NFP + fp] = x[c];
+                }
+        }
+    }
+}
+
 // ----------------------------------------------------------------- operator kernel
 // numerical flux at one face point of direction M (a compile-time constant, so that the state
 // components indexed by M stay in registers); the side (0: the element's -e_M face, 1: its +e_M
@@ -327,7 +571,8 @@ __global__ void __launch_bounds__(256) lift_trace_kernel(const T* __restrict__ u
 template <int D, int NP, int M, class EQ, class OP, typename T, int EPB, int NN, int NFP>
 __device__ __forceinline__ void face_point(const OpArgs<T>& a, const EqParams<T>& ep, const T* s_b,
                                            T (*s_fld)[EPB][EQ::NV][NN], T (*s_fs)[EPB][2 * D][EQ::NV][NFP],
-                                           const T* s_q, int fel, int fe, int fp, int side) {
+                                           const T* s_q, const typename OP::S* s_dv, const typename OP::S* s_jmp,
+                                           int fel, int fe, int fp, int side) {
     constexpr int NV = EQ::NV, NJ = OP::NJ, NC = OP::NC;
     using S = typename OP::S;
     const T* l = s_b + (side ? BOff<NP>::LP : BOff<NP>::LM);
@@ -375,6 +620,29 @@ __device__ __forceinline__ void face_point(const OpArgs<T>& a, const EqParams<T>
         S qo = OP::make(x, a), qn = OP::make(y, a);
         f[0] = f[0] - (qo + qn) * (T(0.5) * ep.nu);
     }
+    if constexpr (EQ::NS) {
+        // BR2 viscous surface flux (F^v(w_own, d_own) + F^v(w_nbr, d_nbr))/2 (Eq. Riemann_visc), the
+        // neighbour's face gradient from the face-gradient kernel
+        constexpr int NG = EQ::NG;
+        S dn[NG][D], dnb[NG][D];
+        ns_face_grad<D, NP, M, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_dv, s_jmp, fel, side, fp, dn);
+        const size_t gb = ((size_t)enb * 2 * D + (2 * M + 1 - side)) * NG * D;
+#pragma unroll
+        for (int k = 0; k < NG; ++k)
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                T y[NJ];
+#pragma unroll
+                for (int c = 0; c < NJ; ++c)
+                    y[c] = c < OP::NGLOB ? a.nsg[c][(gb + k * D + j) * NFP + fp] : T(0);
+                dnb[k][j] = OP::make(y, a);
+            }
+        S fo[NV], fn[NV];
+        EQ::viscous_flux(own, dn, M, fo, ep);
+        EQ::viscous_flux(nb, dnb, M, fn, ep);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) f[v] = f[v] - (fo[v] + fn[v]) * T(0.5);
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         T c[NC];
@@ -388,11 +656,15 @@ template <int D, int NP, class EQ, class OP, typename T>
 __global__ void __launch_bounds__(256) dg_op_kernel(OpArgs<T> a, EqParams<T> ep) {
     constexpr int NN = ipow(NP, D), NFP = ipow(NP, D - 1);
     constexpr int NV = EQ::NV, NJ = OP::NJ, NC = OP::NC;
-    constexpr int EPB = op_epb<D, NP, NV, NJ, NC, T>();
+    constexpr int EPB = kernel_epb<D, NP, EQ, OP, T>();
     constexpr int NT = EPB * NN;
     using S = typename OP::S;
 
     __shared__ T s_fld[NJ][EPB][NV][NN];
+    constexpr int NG = eq_ng<EQ>();                      // BR2 (Navier-Stokes) lifting in LDS
+    __shared__ S s_g[NG > 0 ? NG * EPB * NN : 1];
+    __shared__ S s_jmp[NG > 0 ? NG * EPB * 2 * D * NFP : 1];
+    __shared__ S s_dv[NG > 0 ? NG * D * EPB * NN : 1];
     __shared__ T s_flx[NC][D][EPB][NV][NN];
     __shared__ T s_fs[NC][EPB][2 * D][NV][NFP];
     __shared__ T s_b[basis_len<NP>()];
@@ -416,6 +688,19 @@ __global__ void __launch_bounds__(256) dg_op_kernel(OpArgs<T> a, EqParams<T> ep)
 
     const int el = tid / NN, node = tid % NN;
     const bool valid = el < nloc;
+
+    if constexpr (EQ::NS) {
+        // 1b) BR2: g at the nodes, jumps at the face points, then the strong gradients
+        if (valid) ns_stage_g<D, NP, EQ, OP, false, T, EPB, NN>(a, ep, s_fld, s_g, el, node);
+        for (int i = tid; i < nloc * 2 * D * NFP; i += NT) {
+            const int fel = i / (2 * D * NFP), r = i % (2 * D * NFP);
+            ns_face_jump<D, NP, EQ, OP, false, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_jmp, fel, e0 + fel, r / NFP,
+                                                                 r % NFP);
+        }
+        __syncthreads();
+        if (valid) ns_strong_grad<D, NP, EQ, OP, T, EPB, NN>(a, s_b, s_g, s_dv, el, node);
+        __syncthreads();
+    }
 
     if constexpr (EQ::VISC) {
         // 1b) BR1 lifting q_m = (2/h_m)[Dhat u + lhat(+1) u*_+ - lhat(-1) u*_-], u* central
@@ -469,6 +754,18 @@ __global__ void __launch_bounds__(256) dg_op_kernel(OpArgs<T> a, EqParams<T> ep)
         }
         S F[D][NV];
         EQ::flux_all(wn, F, ep);
+        if constexpr (EQ::NS) {
+            // minus the viscous flux of the volume gradient (global lifting)
+            S d[eq_ng<EQ>()][D];
+            ns_volume_grad<D, NP, EQ, OP, T, EPB, NN, NFP>(a, s_b, s_dv, s_jmp, el, node, d);
+#pragma unroll
+            for (int m = 0; m < D; ++m) {
+                S Fv[NV];
+                EQ::viscous_flux(wn, d, m, Fv, ep);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) F[m][v] = F[m][v] - Fv[v];
+            }
+        }
         if constexpr (EQ::VISC) {
 #pragma unroll
             for (int m = 0; m < D; ++m) {
@@ -500,13 +797,16 @@ __global__ void __launch_bounds__(256) dg_op_kernel(OpArgs<T> a, EqParams<T> ep)
         const int side = r2 / NFP, fp = r2 % NFP;
         const int fe = e0 + fel;
         if (m == 0) {
-            face_point<D, NP, 0, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, fel, fe, fp, side);
+            face_point<D, NP, 0, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, s_dv, s_jmp, fel, fe, fp,
+                                                               side);
         } else if (m == 1) {
             if constexpr (D > 1)
-                face_point<D, NP, 1, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, fel, fe, fp, side);
+                face_point<D, NP, 1, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, s_dv, s_jmp, fel, fe, fp,
+                                                               side);
         } else {
             if constexpr (D > 2)
-                face_point<D, NP, 2, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, fel, fe, fp, side);
+                face_point<D, NP, 2, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_fs, s_q, s_dv, s_jmp, fel, fe, fp,
+                                                               side);
         }
     }
     __syncthreads();

@@ -23,12 +23,17 @@ template <typename T> struct EqParams {
     T half_eps2;
     T inv_eps;
     T inv_eps2;
+    T mu;        // Navier-Stokes: dynamic viscosity
+    T kappa;     // heat conductivity c_p mu / Pr
+    T gam_eps2;  // 1 / R = gamma eps^2 (T = p / (rho R))
+    T eta;       // BR2 stabilisation
     int flux;
 };
 
 template <int D> struct AdvectionEq {
     static constexpr int NV = 1;
     static constexpr bool VISC = false;
+    static constexpr bool NS = false;
     template <class S, class T> HD static void flux_dir(const S* w, int m, S* F, const EqParams<T>& p) {
         F[0] = w[0] * p.adv[m];
     }
@@ -44,6 +49,7 @@ template <int D> struct AdvectionEq {
 template <int D> struct BurgersEq {   // inviscid part u^2/2 per direction; the operator adds -nu q (BR1)
     static constexpr int NV = 1;
     static constexpr bool VISC = true;
+    static constexpr bool NS = false;
     template <class S, class T> HD static void flux_dir(const S* w, int m, S* F, const EqParams<T>& p) {
         F[0] = w[0] * w[0] * T(0.5);
     }
@@ -60,6 +66,7 @@ template <int D> struct BurgersEq {   // inviscid part u^2/2 per direction; the 
 template <int D> struct EulerEq {
     static constexpr int NV = D + 2;
     static constexpr bool VISC = false;
+    static constexpr bool NS = false;
     template <class S, class T> HD static S pressure(const S* w, S irho, const EqParams<T>& p) {
         S m2 = w[1] * w[1];
 #pragma unroll
@@ -96,6 +103,38 @@ template <int D> struct EulerEq {
         S pr = pressure(w, irho, p);
         S c = jsqrt(pr * irho * p.gamma);
         return jabs(w[1 + m] * irho) + c * p.inv_eps;
+    }
+};
+
+// Navier-Stokes (Sec. 5.1, Eq. NavierStokes): the Euler flux minus the viscous flux
+// F^v_m = (0, tau_{.m}, tau_{.m}.v + kappa dT/dx_m), tau = mu (grad v + grad v^T - 2/3 div v I),
+// which depends on the gradients d[k][j] = d g_k / dx_j of g = (v_1..v_D, T), T = p / (rho R);
+// the operator kernel owns the BR2 lifting that provides d.
+template <int D> struct NavierStokesEq : EulerEq<D> {
+    static constexpr bool NS = true;
+    static constexpr int NG = D + 1;
+    template <class S, class T> HD static void grad_vars(const S* w, S* g, const EqParams<T>& p) {
+        S irho = jrecip(w[0]);
+#pragma unroll
+        for (int k = 0; k < D; ++k) g[k] = w[1 + k] * irho;
+        g[D] = EulerEq<D>::pressure(w, irho, p) * irho * p.gam_eps2;
+    }
+    template <class S, class T>
+    HD static void viscous_flux(const S* w, const S (*d)[D], int m, S* F, const EqParams<T>& p) {
+        S irho = jrecip(w[0]);
+        S div = d[0][0];
+#pragma unroll
+        for (int k = 1; k < D; ++k) div = div + d[k][k];
+        S energy = d[D][m] * p.kappa;
+        F[0] = jconst<S, T>(T(0));
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            S t = (d[i][m] + d[m][i]) * p.mu;
+            if (i == m) t = t - div * (T(2) / T(3) * p.mu);
+            F[1 + i] = t;
+            energy = energy + t * (w[1 + i] * irho);
+        }
+        F[D + 1] = energy;
     }
 };
 

@@ -105,7 +105,7 @@ double now_ms() {
 // ------------------------------------------------------------------ kernel timing
 static const char* KC_NAMES[KC_COUNT] = {"trace",    "r1",        "r2",   "res",  "jvp", "kcol",   "pcpre",
                                          "bj_apply", "bj_invert", "mdot", "gemv", "vec", "gs_dot", "gs_update",
-                                         "lin",      "mlp_feat",  "mlp_gemm", "mlp_vec"};
+                                         "lin",      "mlp_feat",  "mlp_gemm", "mlp_vec", "ns_grad"};
 
 // record a launch of class cls (all classes, or only c->prof_only when that is >= 0)
 static long prof_begin(hbpc_ctx* c, int cls) {
@@ -172,6 +172,26 @@ int op_launch(hbpc_ctx* c, const LaunchReq& r, int f32) {
     case OPK_KHCOL: cls = KC_KCOL; bytes = (double)(r.e_end - r.e_begin) * c->NE * (16.0 + c->NE * 16.0); break;
     case OPK_PCPRE: cls = KC_PCPRE; bytes = 5 * n * esz; break;
     case OPK_LINLOC: cls = KC_LIN; bytes = 4 * n * esz; break;
+    }
+    if (c->ns && r.op != OPK_TRACE) {
+        // BR2: the face gradients of this op's jet over the whole mesh first (neighbour data of
+        // the operator kernel), then the operator with them
+        LaunchReq ra = r;
+        ra.aux = 1;
+        ra.e_begin = 0;
+        ra.e_end = 0;
+        for (int j = 0; j < 4; ++j) ra.nsg[j] = c->nsg[f32][j];
+        long pa = prof_begin(c, KC_NSGRAD);
+        hipError_t ea = c->launch(c->geom, ra, f32);
+        prof_end(c, pa, KC_NSGRAD, bytes);
+        if (ea != hipSuccess) set_err(c, HBPC_ERR_HIP, std::string("face-gradient kernel launch: ") + hipGetErrorString(ea));
+        LaunchReq rm = r;
+        for (int j = 0; j < 4; ++j) rm.nsg[j] = c->nsg[f32][j];
+        long pi = prof_begin(c, cls);
+        hipError_t e = c->launch(c->geom, rm, f32);
+        prof_end(c, pi, cls, bytes);
+        if (e != hipSuccess) set_err(c, HBPC_ERR_HIP, std::string("operator kernel launch: ") + hipGetErrorString(e));
+        return 0;
     }
     long pi = prof_begin(c, cls);
     hipError_t e = c->launch(c->geom, r, f32);
@@ -1099,6 +1119,8 @@ static void ctx_free(hbpc_ctx* c) {
     for (int j = 0; j < 4; ++j) {
         dfree(c->qtr[0][j]);
         dfree(c->qtr[1][j]);
+        dfree(c->nsg[0][j]);
+        dfree(c->nsg[1][j]);
     }
     if (c->hres) (void)hipHostFree(c->hres);
     for (int i = 0; i < 2; ++i)
@@ -1110,9 +1132,10 @@ static void ctx_free(hbpc_ctx* c) {
 // Mesh, degree, equation and flux checks and the geometry of the operator kernels (device
 // pointers of the 1-D operators left null); shared by hbpc_create and the context-free R1 entry.
 int geom_configure(const hbpc_mesh* mesh, int N, int equation, const hbpc_params* prm, Basis1DHost& basis,
-                   GeomHost& g, FamilyLauncher& launch, int& visc, std::string& msg) {
+                   GeomHost& g, FamilyLauncher& launch, int& visc, int& ns, std::string& msg) {
     const int D = mesh->dim;
     visc = 0;
+    ns = 0;
     if (D < 1 || D > 3) { msg = "dim must be 1, 2 or 3"; return HBPC_ERR_ARG; }
     if (N < 2 || N > 7) { msg = "N must be in 2..7"; return HBPC_ERR_UNSUPPORTED; }
     if (D == 3 && N > 5) { msg = "N must be in 2..5 in 3-D"; return HBPC_ERR_UNSUPPORTED; }
@@ -1125,6 +1148,12 @@ int geom_configure(const hbpc_mesh* mesh, int N, int equation, const hbpc_params
         if (D < 2) { msg = "Euler needs dim 2 or 3"; return HBPC_ERR_UNSUPPORTED; }
         NV = D + 2;
         launch = dg_launch_euler;
+    } else if (equation == HBPC_EQ_NAVIER_STOKES) {
+        if (D < 2) { msg = "Navier-Stokes needs dim 2 or 3"; return HBPC_ERR_UNSUPPORTED; }
+        if (D == 3 && N > 4) { msg = "Navier-Stokes in 3-D is compiled for N <= 4"; return HBPC_ERR_UNSUPPORTED; }
+        NV = D + 2;
+        ns = 1;
+        launch = dg_launch_ns;
     } else if (equation == HBPC_EQ_BURGERS_BR1) {
         if (D > 2) { msg = "viscous Burgers is compiled for dim 1 and 2"; return HBPC_ERR_UNSUPPORTED; }
         visc = 1;
@@ -1134,8 +1163,9 @@ int geom_configure(const hbpc_mesh* mesh, int N, int equation, const hbpc_params
         return HBPC_ERR_ARG;
     }
     if (prm->flux < 0 || prm->flux > 4) { msg = "unknown flux"; return HBPC_ERR_ARG; }
-    if ((prm->flux == HBPC_FLUX_RUSANOV || prm->flux == HBPC_FLUX_LF_LITERAL) && equation != HBPC_EQ_EULER) {
-        msg = "Rusanov and lf_literal fluxes need the Euler equations";
+    const bool euler_like = equation == HBPC_EQ_EULER || equation == HBPC_EQ_NAVIER_STOKES;
+    if ((prm->flux == HBPC_FLUX_RUSANOV || prm->flux == HBPC_FLUX_LF_LITERAL) && !euler_like) {
+        msg = "Rusanov and lf_literal fluxes need the Euler or Navier-Stokes equations";
         return HBPC_ERR_ARG;
     }
     if (prm->flux == HBPC_FLUX_UPWIND && equation != HBPC_EQ_ADVECTION) {
@@ -1143,8 +1173,12 @@ int geom_configure(const hbpc_mesh* mesh, int N, int equation, const hbpc_params
         return HBPC_ERR_ARG;
     }
     if (equation == HBPC_EQ_BURGERS_BR1 && !(prm->nu >= 0)) { msg = "nu must be >= 0"; return HBPC_ERR_ARG; }
-    if (equation == HBPC_EQ_EULER && !(prm->eps_ref > 0 && prm->gamma > 1)) {
+    if (euler_like && !(prm->eps_ref > 0 && prm->gamma > 1)) {
         msg = "Euler needs gamma > 1 and eps_ref > 0";
+        return HBPC_ERR_ARG;
+    }
+    if (ns && !(prm->mu >= 0 && prm->prandtl > 0 && prm->eta_br2 >= 0)) {
+        msg = "Navier-Stokes needs mu >= 0, prandtl > 0 and eta_br2 >= 0";
         return HBPC_ERR_ARG;
     }
     if (!basis1d_build(N, prm->nodes, basis)) { msg = "bad node set"; return HBPC_ERR_ARG; }
@@ -1161,13 +1195,21 @@ int geom_configure(const hbpc_mesh* mesh, int N, int equation, const hbpc_params
     }
     g.lam = prm->lambda;
     g.nu = prm->nu;
-    g.gamma = equation == HBPC_EQ_EULER ? prm->gamma : 1.4;
-    g.eps = equation == HBPC_EQ_EULER ? prm->eps_ref : 1.0;
+    g.gamma = euler_like ? prm->gamma : 1.4;
+    g.eps = euler_like ? prm->eps_ref : 1.0;
+    if (ns) {
+        const double R = 1.0 / (g.gamma * g.eps * g.eps);
+        g.mu = prm->mu;
+        g.kappa = R * g.gamma / (g.gamma - 1.0) * prm->mu / prm->prandtl;
+        g.gam_eps2 = 1.0 / R;
+        g.eta = prm->eta_br2;
+    }
     g.flux = prm->flux;
     return HBPC_OK;
 }
 
-// 1-D operators in the kernels' layout: Dhat, l(+1), l(-1), lhat(+1), lhat(-1)
+// 1-D operators in the kernels' layout: Dhat, l(+1), l(-1), lhat(+1), lhat(-1), and for BR2 the
+// strong derivative, its interpolant's values at +-1 and c_+-
 std::vector<double> basis_table(const Basis1DHost& b) {
     std::vector<double> hb;
     hb.insert(hb.end(), b.Dhat.begin(), b.Dhat.end());
@@ -1175,6 +1217,11 @@ std::vector<double> basis_table(const Basis1DHost& b) {
     hb.insert(hb.end(), b.lm.begin(), b.lm.end());
     hb.insert(hb.end(), b.lhp.begin(), b.lhp.end());
     hb.insert(hb.end(), b.lhm.begin(), b.lhm.end());
+    hb.insert(hb.end(), b.Dstr.begin(), b.Dstr.end());
+    hb.insert(hb.end(), b.lDp.begin(), b.lDp.end());
+    hb.insert(hb.end(), b.lDm.begin(), b.lDm.end());
+    hb.push_back(b.cp);
+    hb.push_back(b.cm);
     return hb;
 }
 
@@ -1190,7 +1237,7 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
     c->equation = equation;
     {
         std::string msg;
-        const int rc = geom_configure(mesh, N, equation, prm, c->basis, c->geom, c->launch, c->visc, msg);
+        const int rc = geom_configure(mesh, N, equation, prm, c->basis, c->geom, c->launch, c->visc, c->ns, msg);
         if (rc != HBPC_OK) set_err(c, rc, msg);
     }
     c->NV = c->geom.NV;
@@ -1258,6 +1305,13 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
             c->qtr[0][j] = dalloc<double>(c, c->tsz);
             c->qtr[1][j] = dalloc<float>(c, c->tsz);
         }
+    if (c->ns) {   // per element and face: NG = d + 1 lifted variables x d gradient directions
+        const size_t gsz = (size_t)c->nE * 2 * c->D * (c->D + 1) * c->D * c->NFP;
+        for (int j = 0; j < 4; ++j) {
+            c->nsg[0][j] = dalloc<double>(c, gsz);
+            c->nsg[1][j] = dalloc<float>(c, gsz);
+        }
+    }
     c->m_alloc = prm->gmres_restart;
     c->kr_f32 = prm->precision == HBPC_MIXED;
     size_t ksz = c->kr_f32 ? 4 : 8;
@@ -1398,6 +1452,9 @@ void hbpc_default_params(hbpc_params* p) {
     p->nu = 0.0;
     p->gamma = 1.4;
     p->eps_ref = 1.0;
+    p->mu = 0.0;
+    p->prandtl = 0.72;
+    p->eta_br2 = 2.0;
     p->q = 6;
     p->kmax = 4;
     p->newton_rtol = 1e-8;

@@ -11,6 +11,7 @@
 hipError_t dg_launch_euler(const GeomHost& g, const LaunchReq& r, int f32);
 hipError_t dg_launch_advection(const GeomHost& g, const LaunchReq& r, int f32);
 hipError_t dg_launch_burgers(const GeomHost& g, const LaunchReq& r, int f32);
+hipError_t dg_launch_ns(const GeomHost& g, const LaunchReq& r, int f32);
 hipError_t bj_invert(double* KT, const double* HT, void* SinvT, int type, int NE, int nE, double a1dt, double bc, int* status,
                      hipStream_t st);
 hipError_t bj_apply(const void* SinvT, int m_type, const void* xa, const void* xc, void* yw, void* ys, int v_f32,
@@ -53,6 +54,8 @@ hipError_t mlp_uniform(float* out, long long n, float lim, unsigned long long se
 struct Basis1DHost {
     int N, NP;
     std::vector<double> xi, w, Dhat /*NP*NP, Dhat[i*NP+lam]*/, lp, lm, lhp, lhm;
+    std::vector<double> Dstr /*NP*NP, Dstr[i*NP+lam] = l_lam'(xi_i)*/, lDp, lDm;
+    double cp = 0.0, cm = 0.0;
 };
 bool basis1d_build(int N, int kind, Basis1DHost& out);
 std::vector<double> basis_table(const Basis1DHost& b);
@@ -62,7 +65,7 @@ typedef hipError_t (*FamilyLauncher)(const GeomHost&, const LaunchReq&, int);
 // mesh / degree / equation / flux checks and the kernels' geometry (basis pointers left null);
 // returns HBPC_OK or an error code with its message
 int geom_configure(const hbpc_mesh* mesh, int N, int equation, const hbpc_params* prm, Basis1DHost& basis,
-                   GeomHost& g, FamilyLauncher& launch, int& visc, std::string& msg);
+                   GeomHost& g, FamilyLauncher& launch, int& visc, int& ns, std::string& msg);
 
 // ---- error carrier
 struct HbpcError {
@@ -102,6 +105,8 @@ struct hbpc_ctx {
     double* trw; double* trs; double* trd1; double* trd2;   // FP64 traces
     double* basis64; float* basis32;                         // 1-D operators on the device
     int visc;                                                // BR1 viscous terms (Burgers)
+    int ns;                                                  // BR2 viscous terms (Navier-Stokes)
+    void* nsg[2][4];          // BR2 face gradients per jet component, [FP64|FP32][component]
     void* qtr[2][4];                                         // BR1 lifted-gradient traces [f32][field]
     // FP32 snapshots
     float* X32;               // 2 ndof
@@ -168,7 +173,7 @@ struct hbpc_ctx {
 };
 
 enum { KC_TRACE = 0, KC_R1, KC_R2, KC_RES, KC_JVP, KC_KCOL, KC_PCPRE, KC_BJAPPLY, KC_BJINV, KC_MDOT, KC_GEMV,
-       KC_VEC, KC_GSDOT, KC_GSUPD, KC_LIN, KC_FEAT, KC_GEMM, KC_MLPV, KC_COUNT };
+       KC_VEC, KC_GSDOT, KC_GSUPD, KC_LIN, KC_FEAT, KC_GEMM, KC_MLPV, KC_NSGRAD, KC_COUNT };
 
 // helpers implemented in ops.cpp
 int op_launch(hbpc_ctx* c, const LaunchReq& r, int f32);

@@ -90,6 +90,12 @@ template <typename T> HD HDual<T> jabs(HDual<T> x) { return x.a >= T(0) ? x : -x
 template <typename T> HD HDual<T> jmax(HDual<T> x, HDual<T> y) { return x.a >= y.a ? x : y; }
 template <typename T> HD T jval(HDual<T> x) { return x.a; }
 
+// components of a jet in member order (the inverse of building it from x[0..])
+template <typename T> HD void jet_split(T v, T* x) { x[0] = v; }
+template <typename T> HD void jet_split(Dual<T> v, T* x) { x[0] = v.a; x[1] = v.b; }
+template <typename T> HD void jet_split(Dual2<T> v, T* x) { x[0] = v.a; x[1] = v.b; x[2] = v.c; }
+template <typename T> HD void jet_split(HDual<T> v, T* x) { x[0] = v.a; x[1] = v.s; x[2] = v.d; x[3] = v.m; }
+
 // constant of the jet type
 template <typename S, typename T> HD S jconst(T k);
 template <> HD double jconst<double, double>(double k) { return k; }

@@ -17,9 +17,9 @@ static __device__ __align__(256) char scratch[size_t(64) << 20];   // SCRATCH_BY
 namespace {
 
 constexpr size_t SCRATCH_BYTES = sizeof(scratch);     // 64 MiB per GPU
-constexpr size_t BASIS_SLOT = 4096;                  // bytes before the traces (operators: <= 96 doubles)
+constexpr size_t BASIS_SLOT = 4096;                  // bytes before the traces (operators: <= 178 doubles)
 constexpr int MAX_DEVICES = 64;
-constexpr int BASIS_MAX = 96;                         // basis_len for N = 7: 8*8 + 4*8
+constexpr int BASIS_MAX = 184;                        // basis_len for N = 7: 2*8*8 + 6*8 + 2 = 178
 
 std::mutex g_mu;
 char* g_scratch[MAX_DEVICES];   // device address of `scratch` on each GPU (null until looked up)
@@ -61,10 +61,11 @@ extern "C" int hbpc_residual1_noalloc(const hbpc_mesh* mesh, int N, int equation
     Basis1DHost basis;
     GeomHost g;
     FamilyLauncher launch = nullptr;
-    int visc = 0;
+    int visc = 0, ns = 0;
     std::string msg;
-    const int rc = geom_configure(mesh, N, equation, params, basis, g, launch, visc, msg);
+    const int rc = geom_configure(mesh, N, equation, params, basis, g, launch, visc, ns, msg);
     if (rc != HBPC_OK) return rc;
+    if (ns) return HBPC_ERR_UNSUPPORTED;   // the BR2 face gradients need a buffer of their own
     const size_t tsz = trace_len(g);
     if (BASIS_SLOT + tsz * sizeof(double) * (visc ? 2 : 1) > SCRATCH_BYTES) return HBPC_ERR_ARG;
     const std::vector<double> table = basis_table(basis);
@@ -82,7 +83,7 @@ extern "C" int hbpc_residual1_noalloc(const hbpc_mesh* mesh, int N, int equation
     BasisArg b;
     b.n = (int)table.size();
     for (int i = 0; i < BASIS_MAX; ++i) b.v[i] = i < b.n ? table[i] : 0.0;
-    hipLaunchKernelGGL(basis_fill_kernel, dim3(1), dim3(BASIS_MAX), 0, st, dbasis, b);
+    hipLaunchKernelGGL(basis_fill_kernel, dim3(1), dim3(256), 0, st, dbasis, b);
     if (hipGetLastError() != hipSuccess) return HBPC_ERR_HIP;
     g.basis64 = dbasis;
     g.basis32 = nullptr;

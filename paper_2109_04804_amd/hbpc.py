@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libhbpc.so")
 HBPC_OK = 0
 ERRORS = {-1: "HBPC_ERR_ARG", -2: "HBPC_ERR_OOM", -3: "HBPC_ERR_HIP", -4: "HBPC_ERR_NONFINITE",
           -5: "HBPC_ERR_NEWTON", -6: "HBPC_ERR_GMRES", -7: "HBPC_ERR_UNSUPPORTED"}
-EQ = {"advection": 1, "burgers": 2, "euler": 3}
+EQ = {"advection": 1, "burgers": 2, "euler": 3, "navier_stokes": 4}
 NODES = {"gauss": 0, "lobatto": 1}
 FLUX = {"central": 0, "upwind": 1, "lf": 2, "rusanov": 3, "lf_literal": 4}
 PRECISION = {"fp64": 0, "mixed": 1}
@@ -36,7 +36,8 @@ class HbpcMesh(ctypes.Structure):
 class HbpcParams(ctypes.Structure):
     _fields_ = [("nodes", ctypes.c_int), ("flux", ctypes.c_int), ("lambda_", ctypes.c_double),
                 ("adv", ctypes.c_double * 3), ("nu", ctypes.c_double), ("gamma", ctypes.c_double),
-                ("eps_ref", ctypes.c_double), ("q", ctypes.c_int), ("kmax", ctypes.c_int),
+                ("eps_ref", ctypes.c_double), ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
+                ("eta_br2", ctypes.c_double), ("q", ctypes.c_int), ("kmax", ctypes.c_int),
                 ("newton_rtol", ctypes.c_double), ("newton_atol_dw", ctypes.c_double),
                 ("newton_maxit", ctypes.c_int), ("gmres_rtol", ctypes.c_double),
                 ("gmres_restart", ctypes.c_int), ("gmres_maxit", ctypes.c_int),

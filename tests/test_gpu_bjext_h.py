@@ -40,7 +40,7 @@ def sigma_of(dg, w, seed):
     return r1 + 0.05 * np.abs(r1).max() * p / np.abs(p).max()
 
 
-@pytest.mark.parametrize("name", ["euler2_n3_lobatto", "euler2_n5", "burgers2", "adv2_ragged", "euler3_n3"])
+@pytest.mark.parametrize("name", ["euler2_n3_lobatto", "euler2_n5", "burgers2", "adv2_ragged", "euler3_n3", "ns2"])
 def test_pc_apply_hess(name):
     """Blocks of 64, 144 (register inversion), 320 (blocked); viscous Burgers (BR1); the
     linear flux, where H = 0 and the result is BJ_ext's."""

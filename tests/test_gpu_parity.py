@@ -121,7 +121,7 @@ def test_jvp_fp64(name, hessian):
     assert rel(host(out), np.concatenate([Jw.ravel(), Js.ravel()])) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["euler2_n5", "euler3_n3", "adv2_ragged", "euler2_single", "burgers2"])
+@pytest.mark.parametrize("name", ["euler2_n5", "euler3_n3", "adv2_ragged", "euler2_single", "burgers2", "ns2", "ns3"])
 def test_jvp_fp32(name):
     case, dg, ctx = setup(name)
     f32 = lambda x: np.asarray(x, dtype=np.float32).astype(np.float64)
@@ -136,7 +136,7 @@ def test_jvp_fp32(name):
     assert rel(host(out), np.concatenate([Jw.ravel(), Js.ravel()])) < 5e-5
 
 
-@pytest.mark.parametrize("name", ["euler2_n5", "euler3_n3", "adv1_upwind", "burgers2"])
+@pytest.mark.parametrize("name", ["euler2_n5", "euler3_n3", "adv1_upwind", "burgers2", "ns2"])
 def test_jvp_finite_difference(name):
     """Eq. MatrixFree_nonlinear on the GPU against the exact (oracle) JVP."""
     case, dg, ctx = setup(name)
@@ -188,7 +188,8 @@ def test_pc_build_rejects_blocks_above_1024():
 
 
 @pytest.mark.parametrize("name", ["euler2_n3_lobatto", "euler2_n5", "adv2_ragged", "adv1_upwind", "euler3_n3",
-                                  "adv3_n5", "euler3_n4", "burgers2", "burgers1_lobatto"])
+                                  "adv3_n5", "euler3_n4", "burgers2", "burgers1_lobatto", "ns2", "ns3",
+                                  "ns2_lobatto_lfl"])
 def test_pc_apply(name):
     """BJ_ext: GPU (explicit S^-1, commuted form) vs oracle (LU, D/E/F/G blocks); element
     blocks of 16..144 unknowns take the register kernel, 216, 320 and 625 the blocked one."""

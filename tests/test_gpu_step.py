@@ -311,3 +311,40 @@ def test_degree7_step(name):
     print(name, stats["newton_its"], stats["gmres_its"], flush=True)
     ref = dg_hbpc_step(dg, w0, 0.1, 6, 2, StageSolver(dg, newton_rtol=1e-12, gmres_rtol=1e-5))
     assert rel(host(wg), ref) < 1e-10
+
+
+@pytest.mark.parametrize("name,precision,rtol,tol", [("ns2", "fp64", 1e-12, 1e-10), ("ns2", "mixed", 1e-8, 1e-8),
+                                                     ("ns3", "fp64", 1e-12, 1e-10), ("ns3", "mixed", 1e-8, 1e-8)])
+def test_navier_stokes_step(name, precision, rtol, tol):
+    """Navier-Stokes with BR2 lifting (Sec. 5.1): one HBPC(6,2) step (2-D, 4 x 4 elements, N = 4,
+    dt = 0.2, mu = 0.05) or HBPC(6,1) (3-D eps-scaled, 2 x 2 x 2 elements, N = 3, dt = 0.1,
+    mu = 0.02) with BJ_ext and the linearised JVP through the lifting, against the oracle."""
+    case = dict(CASES[name])
+    case.update(nelem=[4, 4] if case["dim"] == 2 else [2, 2, 2])
+    kmax, dt = (2, 0.2) if case["dim"] == 2 else (1, 0.1)
+    dg = oracle_for(case)
+    w0 = state(dg, seed=4)
+    ctx = ctx_for(case, q=6, kmax=kmax, newton_rtol=rtol, gmres_rtol=1e-5, precision=precision)
+    wg = dev(w0)
+    stats = ctx.step(wg, dt)
+    print(name, precision, stats["newton_its"], stats["gmres_its"], flush=True)
+    ref = _ns_reference(name)
+    err = rel(host(wg), ref)
+    print("rel err", err, flush=True)
+    assert err < tol
+    assert np.abs(dg.integral(host(wg).reshape(w0.shape)) - dg.integral(w0)).max() < 1e-10 * np.abs(dg.integral(w0)).max()
+
+
+_NS_REF = {}
+
+
+def _ns_reference(name):
+    """The oracle's step of test_navier_stokes_step at eps_N = 1e-12 (shared by both precisions)."""
+    if name not in _NS_REF:
+        case = dict(CASES[name])
+        case.update(nelem=[4, 4] if case["dim"] == 2 else [2, 2, 2])
+        kmax, dt = (2, 0.2) if case["dim"] == 2 else (1, 0.1)
+        dg = oracle_for(case)
+        _NS_REF[name] = dg_hbpc_step(dg, state(dg, seed=4), dt, 6, kmax,
+                                     StageSolver(dg, newton_rtol=1e-12, gmres_rtol=1e-5))
+    return _NS_REF[name]
