@@ -65,6 +65,15 @@ WORKLOADS = {
     "euler_tgv_48x48x48_N3_cfl20": dict(dim=3, nelem=[48, 48, 48], length=[2 * 3.141592653589793] * 3, N=3,
                                         dt=0.06, equation="euler", field="tgv", eps_ref=0.1,
                                         restart={"fp64": 100, "mixed": 200}),
+    # the paper's viscous Taylor-Green vortex (Sec. 5.3.3): Navier-Stokes with BR2 lifting, mu = 1.25e-3
+    # (Re = 800), eps = 0.1, N = 3 on 32^3 elements of [0, 2 pi]^3, HBPC(4,0) at dt = 0.25 (acoustic CFL
+    # about 56), FGMRES(200) in FP32 / FGMRES(100) in FP64
+    "ns_tgv_32x32x32_N3": dict(dim=3, nelem=[32, 32, 32], length=[2 * 3.141592653589793] * 3, N=3, dt=0.25,
+                               equation="navier_stokes", field="tgv", eps_ref=0.1, mu=1.25e-3, q=4, kmax=0,
+                               restart={"fp64": 100, "mixed": 200}),
+    # the same at a tenth of the step (acoustic CFL about 5.6) with the bench's HBPC(6,4)
+    "ns_tgv_32x32x32_N3_dt0025": dict(dim=3, nelem=[32, 32, 32], length=[2 * 3.141592653589793] * 3, N=3,
+                                      dt=0.025, equation="navier_stokes", field="tgv", eps_ref=0.1, mu=1.25e-3),
     # the same CFL on a 16^3 mesh
     "euler_tgv_16x16x16_N3": dict(dim=3, nelem=[16, 16, 16], length=[2 * 3.141592653589793] * 3, N=3,
                                   dt=0.18, equation="euler", field="tgv", eps_ref=0.1),
@@ -87,7 +96,15 @@ def initial_state(ctx, wl):
 def _eqkw(wl):
     if wl.get("equation") == "burgers":
         return dict(flux="lf", nu=0.01, **{"lambda": 1.0})
-    return dict(flux="rusanov", gamma=1.4, eps_ref=wl.get("eps_ref", 1.0))
+    kw = dict(flux="rusanov", gamma=1.4, eps_ref=wl.get("eps_ref", 1.0))
+    if wl.get("equation") == "navier_stokes":
+        kw["mu"] = wl["mu"]
+    return kw
+
+
+def scheme_of(wl):
+    """(q, k_max) of a workload: HBPC(6,4) unless it names another."""
+    return wl.get("q", 6), wl.get("kmax", 4)
 
 
 def training_state(wl, X, seed):
@@ -113,7 +130,9 @@ def train_learned(wl, samples=20480, per_correction=512, seeds=(1, 2), epochs=20
     from paper_2109_04804_amd import inputs
     from paper_2109_04804_amd.hbpc import Context
     t0 = time.perf_counter()
-    col = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], "euler", q=6, kmax=4, newton_rtol=1e-8,
+    q, kmax = scheme_of(wl)
+    col = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], wl.get("equation", "euler"), q=q, kmax=kmax,
+                  newton_rtol=1e-8,
                   gmres_rtol=1e-6, gmres_restart=restart_of(wl, "fp64"), gmres_maxit=7000, precond="bjext",
                   precision="fp64",
                   **_eqkw(wl))
@@ -134,7 +153,8 @@ def train_learned(wl, samples=20480, per_correction=512, seeds=(1, 2), epochs=20
     count = col.mlp_collected()
     col.close()
     t_collect = time.perf_counter() - t0
-    tr = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], "euler", precond="learned", precision="mixed",
+    tr = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], wl.get("equation", "euler"), precond="learned",
+                 precision="mixed",
                  **_eqkw(wl))
     tr.mlp_init(7)
     log = tr.train_mlp(X, T, count, epochs=epochs, batch=256, lr=1e-3, seed=5, precision="bf16")
@@ -177,7 +197,8 @@ def run_form(wl, form, steps, warmup, theta=None, pc_rebuild="per_solve", pc_reu
     import torch
     from paper_2109_04804_amd.hbpc import Context
     precision, pc, half = form_settings(form)
-    ctx = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], wl.get("equation", "euler"), q=6, kmax=4,
+    q, kmax = scheme_of(wl)
+    ctx = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], wl.get("equation", "euler"), q=q, kmax=kmax,
                   newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=restart_of(wl, precision), gmres_maxit=7000,
                   precond=pc,
                   precision=precision, pc_fallback=0.5, pc_rebuild=pc_rebuild, pc_half=half,
@@ -357,15 +378,17 @@ def form_parity(wl, forms, ref, theta, pc_rebuild, pc_reuse_steps, pc_probe_its)
 
 
 # Preconditioner study of Sec. 4.1.2 (Figs. 4 and 5): the eps-scaled density wave of
-# Eq. euler_convtest on [-1,1]^2, 16^2 elements, N = 5, eps_G 1e-3, eps_N 1e-8, at most 7000 Krylov
-# iterations per Newton step, preconditioners rebuilt at every Newton iterate; one time step of the
-# HBPC(4,0) predictor per point.  Time steps within the ranges the paper plots for each eps.
+# Eq. euler_convtest on [-1,1]^2, 16^2 elements, N = 5, Eq. Riemann as printed with the Euler
+# set-up's lambda = diag(1/eps, 1, 1, 1/eps) (lf_literal; the Rusanov flux on request), eps_G 1e-3,
+# eps_N 1e-8, FGMRES restarted after 700 iterations and at most 7000 Krylov iterations per Newton
+# step, preconditioners rebuilt at every Newton iterate; one time step of the HBPC(4,0) predictor
+# per point.  Time steps within the ranges the paper plots for each eps.
 STUDY_DT = {1.0: [0.0125, 0.05, 0.2, 0.8], 0.1: [0.003125, 0.0125, 0.05, 0.2],
             0.01: [0.00078125, 0.003125, 0.0125, 0.025]}
 STUDY_PC = ("none", "bjext", "bjext_h")
 
 
-def precond_study(precision):
+def precond_study(precision, flux="lf_literal", restart=700):
     """Rows (eps, dt, preconditioner, Krylov and Newton iterations, ms per step); a point
     without convergence within the iteration cap is reported with its error code."""
     import numpy as np
@@ -377,8 +400,8 @@ def precond_study(precision):
         for dt in dts:
             for pc in STUDY_PC:
                 ctx = Context(2, [16, 16], [2.0, 2.0], 5, "euler", origin=(-1.0, -1.0, 0.0), q=4, kmax=0,
-                              newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=30, gmres_maxit=7000,
-                              precision=precision, precond=pc, pc_rebuild="per_newton_it", flux="rusanov",
+                              newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=restart, gmres_maxit=7000,
+                              precision=precision, precond=pc, pc_rebuild="per_newton_it", flux=flux,
                               gamma=1.4, eps_ref=eps)
                 xi, _ = ctx.nodes()
                 X = inputs.node_coords(2, [16, 16], [2.0, 2.0], [-1.0, -1.0], xi)
@@ -428,6 +451,8 @@ def main():
                     help="instead of the benchmark: the preconditioner study over eps and dt (none, BJ_ext, "
                          "BJ^H_ext; one JSON line)")
     ap.add_argument("--study-precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--study-flux", choices=["lf_literal", "rusanov"], default="lf_literal")
+    ap.add_argument("--study-restart", type=int, default=700)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run a plain device copy of this many bytes three times (reference dispatch "
                          "for scaling hardware byte counters)")
@@ -443,11 +468,12 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
     if a.study == "precond_eps":
-        rows = precond_study(a.study_precision)
-        print(json.dumps({"study": "precond_eps", "precision": a.study_precision,
-                          "setup": "density wave, [-1,1]^2, 16^2 elements, N = 5, Rusanov, HBPC(4,0) "
-                                   "predictor, eps_G 1e-3, eps_N 1e-8, FGMRES(30), cap 7000 per Newton step, "
-                                   "preconditioner rebuilt at every Newton iterate", "rows": rows}))
+        rows = precond_study(a.study_precision, a.study_flux, a.study_restart)
+        print(json.dumps({"study": "precond_eps", "precision": a.study_precision, "flux": a.study_flux,
+                          "setup": "density wave, [-1,1]^2, 16^2 elements, N = 5, HBPC(4,0) predictor, "
+                                   "eps_G 1e-3, eps_N 1e-8, FGMRES(%d), cap 7000 per Newton step, "
+                                   "preconditioner rebuilt at every Newton iterate" % a.study_restart,
+                          "rows": rows}))
         return
     if a.copy_bytes > 0:
         src = torch.ones(a.copy_bytes // 4, dtype=torch.float32, device="cuda")
@@ -489,7 +515,7 @@ def main():
                   "mixed": "f64+f32",
                   "mixed16": "f64+f32+f16", "fp64": "f64", "fp64_h": "f64", "mixed_h": "f64+f32"}[head],
         "data": "synthetic",
-        "config": {"workload": a.workload, "dof": dof, "scheme": "HBPC(6,4)", "dt": wl["dt"],
+        "config": {"workload": a.workload, "dof": dof, "scheme": "HBPC(%d,%d)" % scheme_of(wl), "dt": wl["dt"],
                    "newton_rtol": 1e-8,
                    "krylov": "FGMRES(%d), eps_G 1e-3" % restart_of(wl, form_settings(head)[0]),
                    "pc_rebuild": a.pc_rebuild,
