@@ -197,6 +197,8 @@ def run_form(wl, form, steps, warmup, theta=None, pc_rebuild="per_solve", pc_reu
     import torch
     from paper_2109_04804_amd.hbpc import Context
     precision, pc, half = form_settings(form)
+    if pc_rebuild == "paired" and pc != "bjext":
+        pc_rebuild = "per_stage"   # the paired corrector solves run BJ_ext only
     q, kmax = scheme_of(wl)
     ctx = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], wl.get("equation", "euler"), q=q, kmax=kmax,
                   newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=restart_of(wl, precision), gmres_maxit=7000,
@@ -361,9 +363,10 @@ def form_parity(wl, forms, ref, theta, pc_rebuild, pc_reuse_steps, pc_probe_its)
     out = {}
     for f in forms:
         precision, pc, half = form_settings(f)
+        rebuild = "per_stage" if (pc_rebuild == "paired" and pc != "bjext") else pc_rebuild
         ctx = Context(2, [PARITY_N, PARITY_N], [10.0, 10.0], 5, "euler", q=6, kmax=4, newton_rtol=1e-8,
                       gmres_rtol=1e-3, gmres_restart=30, gmres_maxit=7000, precond=pc, precision=precision,
-                      pc_fallback=0.5, pc_rebuild=pc_rebuild, pc_half=half, pc_reuse_steps=pc_reuse_steps,
+                      pc_fallback=0.5, pc_rebuild=rebuild, pc_half=half, pc_reuse_steps=pc_reuse_steps,
                       pc_probe_its=pc_probe_its, flux="rusanov", gamma=1.4, eps_ref=1.0)
         if pc.startswith("learned"):
             ctx.mlp_set_params(theta)
@@ -440,7 +443,8 @@ def main():
                          "(as mixed with the BJ_ext blocks stored in FP16), fp64_h / mixed_h (as fp64 / mixed "
                          "with BJ^H_ext)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--pc-rebuild", default="per_stage", choices=["per_solve", "per_stage", "across_steps"],
+    ap.add_argument("--pc-rebuild", default="per_stage",
+                    choices=["per_solve", "per_stage", "across_steps", "paired"],
                     help="BJ_ext builds: kept per corrector stage across sweeps (default), once per stage "
                          "solve, or every stage's blocks kept across --pc-reuse-steps time steps")
     ap.add_argument("--pc-reuse-steps", type=int, default=4)

@@ -102,6 +102,13 @@ typedef struct hbpc_ctx hbpc_ctx;
                                       built on first use, rebuilt after pc_reuse_steps steps or
                                       when the solve's coefficients (dt) change.  Keeps 2 (s - 1)
                                       sets of S^-1 blocks, so q <= 6. */
+#define HBPC_PC_PAIRED 4           /* corrector stages solved in pairs (their equations are
+                                      independent, Alg. 1): the Newton and FGMRES iterations of two
+                                      stages advance in lock step, the S^-1 blocks built at the first
+                                      stage's state in the first sweep serve both stages and every
+                                      later sweep, and one pass over the blocks applies them to the
+                                      four right-hand sides of an iteration; the predictor as
+                                      HBPC_PC_PER_SOLVE.  BJ_ext with the linearised JVP only. */
 
 /* Jacobian-vector product */
 #define HBPC_JVP_LINEARISED 0      /* exact directional derivatives (hyper-dual flux) */
@@ -146,7 +153,7 @@ typedef struct {
     int precision;        /* HBPC_FP64 | HBPC_MIXED */
     int precond;          /* HBPC_PC_* */
     int pc_rebuild;       /* HBPC_PC_PER_SOLVE | HBPC_PC_PER_NEWTON_IT | HBPC_PC_PER_STAGE |
-                             HBPC_PC_ACROSS_STEPS */
+                             HBPC_PC_ACROSS_STEPS | HBPC_PC_PAIRED */
     int jvp_mode;         /* HBPC_JVP_* */
     int hessian;          /* 1: include dR2/dw in the JVP (exact Newton), 0: drop it */
     int mlp_precision;    /* HBPC_MLP_BF16 | HBPC_MLP_FP32: network arithmetic of HBPC_PC_LEARNED */

@@ -8,15 +8,20 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
-// y = S^-1 x for the two right-hand sides (w block, sigma block).
-// yw = S^-1 xa, ys = S^-1 xc per element; S^-1 stored transposed (column-major blocks, SinvT[e][c][r]),
-// each thread owns groups of VR consecutive rows (one 16-byte load per column when VR * sizeof(TM)
-// == 16): min(NE / VR, 256) threads per element, a thread taking every tpe-th group when there are
-// more groups than threads; several elements per block; the two right-hand sides staged in LDS
-template <typename TM, typename T, int VR>
-__global__ void __launch_bounds__(256) bj_apply_kernel(const TM* __restrict__ SinvT, const T* __restrict__ xa,
-                                                      const T* __restrict__ xc, T* __restrict__ yw,
-                                                      T* __restrict__ ys, int NE, int nE) {
+// y_k = S^-1 x_k for NR right-hand sides: the w and sigma blocks of one Krylov vector (NR = 2), or
+// of two systems that share the blocks (NR = 4: the corrector stages of a sweep solved together).
+// S^-1 stored transposed (column-major blocks, SinvT[e][c][r]), each thread owns groups of VR
+// consecutive rows (one 16-byte load per column when VR * sizeof(TM) == 16): min(NE / VR, 256)
+// threads per element, a thread taking every tpe-th group when there are more groups than threads;
+// several elements per block; the right-hand sides staged in LDS.  One pass over S^-1 serves all NR.
+template <typename T, int NR> struct ApplyVecs {
+    const T* x[NR];
+    T* y[NR];
+};
+
+template <typename TM, typename T, int VR, int NR>
+__global__ void __launch_bounds__(256) bj_apply_kernel(const TM* __restrict__ SinvT, ApplyVecs<T, NR> v, int NE,
+                                                      int nE) {
     extern __shared__ unsigned char smem_raw[];
     T* sx = reinterpret_cast<T*>(smem_raw);
     const int ng = NE / VR;
@@ -28,76 +33,96 @@ __global__ void __launch_bounds__(256) bj_apply_kernel(const TM* __restrict__ Si
         int le = i / NE;
         size_t g = (size_t)(e0 + le) * NE + (i % NE);
         bool ok = e0 + le < nE;
-        sx[2 * i] = ok ? xa[g] : T(0);
-        sx[2 * i + 1] = ok ? xc[g] : T(0);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) sx[NR * i + k] = ok ? v.x[k][g] : T(0);
     }
     __syncthreads();
     const int e = e0 + el;
     if (el >= epb || e >= nE) return;
     typedef TM VT __attribute__((ext_vector_type(VR)));
-    const T* x = sx + 2 * el * NE;
+    const T* x = sx + NR * el * NE;
     for (int gr = threadIdx.x % tpe; gr < ng; gr += tpe) {
         const int r0 = gr * VR;
         const TM* M = SinvT + (size_t)e * NE * NE + r0;
-        T s0[VR], s1[VR];
+        T s[NR][VR];
 #pragma unroll
-        for (int q = 0; q < VR; ++q) s0[q] = s1[q] = T(0);
+        for (int k = 0; k < NR; ++k)
+#pragma unroll
+            for (int q = 0; q < VR; ++q) s[k][q] = T(0);
 #pragma unroll 4
         for (int c = 0; c < NE; ++c) {
             const VT m = *reinterpret_cast<const VT*>(M + (size_t)c * NE);
-            const T xa_c = x[2 * c], xc_c = x[2 * c + 1];
 #pragma unroll
-            for (int q = 0; q < VR; ++q) {
-                s0[q] += (T)m[q] * xa_c;
-                s1[q] += (T)m[q] * xc_c;
+            for (int k = 0; k < NR; ++k) {
+                const T xc = x[NR * c + k];
+#pragma unroll
+                for (int q = 0; q < VR; ++q) s[k][q] += (T)m[q] * xc;
             }
         }
 #pragma unroll
-        for (int q = 0; q < VR; ++q) {
-            yw[(size_t)e * NE + r0 + q] = s0[q];
-            ys[(size_t)e * NE + r0 + q] = s1[q];
-        }
+        for (int k = 0; k < NR; ++k)
+#pragma unroll
+            for (int q = 0; q < VR; ++q) v.y[k][(size_t)e * NE + r0 + q] = s[k][q];
     }
 }
 
-template <typename TM, typename T, int VR>
-static void launch_apply(const TM* SinvT, const T* xa, const T* xc, T* yw, T* ys, int NE, int nE, hipStream_t st) {
+template <typename TM, typename T, int VR, int NR>
+static void launch_apply(const TM* SinvT, const ApplyVecs<T, NR>& v, int NE, int nE, hipStream_t st) {
     const int ng = NE / VR;
     const int tpe = ng < 256 ? ng : 256;
     const int epb = 256 / tpe;
     const int threads = epb * tpe;
     const int grid = (nE + epb - 1) / epb;
-    const size_t sh = (size_t)2 * epb * NE * sizeof(T);
-    hipLaunchKernelGGL((bj_apply_kernel<TM, T, VR>), dim3(grid), dim3(threads), sh, st, SinvT, xa, xc, yw, ys, NE, nE);
+    const size_t sh = (size_t)NR * epb * NE * sizeof(T);
+    hipLaunchKernelGGL((bj_apply_kernel<TM, T, VR, NR>), dim3(grid), dim3(threads), sh, st, SinvT, v, NE, nE);
 }
 
 // rows per thread: a 16-byte load of S^-1 when NE allows it
-template <typename TM, typename T>
-static void apply_vr(const void* SinvT, const void* xa, const void* xc, void* yw, void* ys, int NE, int nE,
-                     hipStream_t st) {
+template <typename TM, typename T, int NR>
+static void apply_vr(const void* SinvT, const void* const* xs, void* const* ys, int NE, int nE, hipStream_t st) {
     constexpr int V = 16 / sizeof(TM);
     const TM* M = (const TM*)SinvT;
+    ApplyVecs<T, NR> v;
+    for (int k = 0; k < NR; ++k) {
+        v.x[k] = (const T*)xs[k];
+        v.y[k] = (T*)ys[k];
+    }
     if (NE % V == 0)
-        launch_apply<TM, T, V>(M, (const T*)xa, (const T*)xc, (T*)yw, (T*)ys, NE, nE, st);
+        launch_apply<TM, T, V, NR>(M, v, NE, nE, st);
     else if (NE % 2 == 0)
-        launch_apply<TM, T, 2>(M, (const T*)xa, (const T*)xc, (T*)yw, (T*)ys, NE, nE, st);
+        launch_apply<TM, T, 2, NR>(M, v, NE, nE, st);
     else
-        launch_apply<TM, T, 1>(M, (const T*)xa, (const T*)xc, (T*)yw, (T*)ys, NE, nE, st);
+        launch_apply<TM, T, 1, NR>(M, v, NE, nE, st);
 }
 
-// m_type: storage of S^-1, 0 FP64, 1 FP32, 2 FP16 (FP32 vectors only); the sums run in the vector type
-hipError_t bj_apply(const void* SinvT, int m_type, const void* xa, const void* xc, void* yw, void* ys, int v_f32,
-                    int NE, int nE, hipStream_t st) {
+template <typename TM, typename T>
+static void apply_nr(const void* SinvT, const void* const* xs, void* const* ys, int nr, int NE, int nE,
+                     hipStream_t st) {
+    if (nr == 4) apply_vr<TM, T, 4>(SinvT, xs, ys, NE, nE, st);
+    else apply_vr<TM, T, 2>(SinvT, xs, ys, NE, nE, st);
+}
+
+// y_k = S^-1 x_k, k < nr (2 or 4); m_type: storage of S^-1, 0 FP64, 1 FP32, 2 FP16 (FP32 vectors only)
+hipError_t bj_apply_n(const void* SinvT, int m_type, const void* const* xs, void* const* ys, int nr, int v_f32,
+                      int NE, int nE, hipStream_t st) {
     if (nE == 0) return hipSuccess;
-    if (NE > 1024) return hipErrorInvalidValue;
+    if (NE > 1024 || (nr != 2 && nr != 4)) return hipErrorInvalidValue;
     if (m_type == 2 && !v_f32) return hipErrorInvalidValue;
     if (v_f32) {
-        if (m_type == 2) apply_vr<_Float16, float>(SinvT, xa, xc, yw, ys, NE, nE, st);
-        else if (m_type == 1) apply_vr<float, float>(SinvT, xa, xc, yw, ys, NE, nE, st);
-        else apply_vr<double, float>(SinvT, xa, xc, yw, ys, NE, nE, st);
+        if (m_type == 2) apply_nr<_Float16, float>(SinvT, xs, ys, nr, NE, nE, st);
+        else if (m_type == 1) apply_nr<float, float>(SinvT, xs, ys, nr, NE, nE, st);
+        else apply_nr<double, float>(SinvT, xs, ys, nr, NE, nE, st);
     } else {
-        if (m_type == 1) apply_vr<float, double>(SinvT, xa, xc, yw, ys, NE, nE, st);
-        else apply_vr<double, double>(SinvT, xa, xc, yw, ys, NE, nE, st);
+        if (m_type == 1) apply_nr<float, double>(SinvT, xs, ys, nr, NE, nE, st);
+        else apply_nr<double, double>(SinvT, xs, ys, nr, NE, nE, st);
     }
     return hipGetLastError();
+}
+
+// the two right-hand sides of one Krylov vector; the sums run in the vector type
+hipError_t bj_apply(const void* SinvT, int m_type, const void* xa, const void* xc, void* yw, void* ys, int v_f32,
+                    int NE, int nE, hipStream_t st) {
+    const void* xs[2] = {xa, xc};
+    void* ys2[2] = {yw, ys};
+    return bj_apply_n(SinvT, m_type, xs, ys2, 2, v_f32, NE, nE, st);
 }

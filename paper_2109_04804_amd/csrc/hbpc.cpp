@@ -253,15 +253,21 @@ static void op_r1r2(hbpc_ctx* c, const double* w, double* r1, double* r2) {
 }
 
 // G(X) with the traces of X in trw/trs (FP64)
+static void op_res(hbpc_ctx* c, const double* X, const double* b, double a1dt, double bc, double* G,
+                   const double* trw, const double* trs);
 static void op_res(hbpc_ctx* c, const double* X, const double* b, double a1dt, double bc, double* G) {
+    op_res(c, X, b, a1dt, bc, G, c->trw, c->trs);
+}
+static void op_res(hbpc_ctx* c, const double* X, const double* b, double a1dt, double bc, double* G,
+                   const double* trw, const double* trs) {
     LaunchReq r = op_req(c, OPK_RES);
     r.fld[0] = X;
     r.fld[1] = X + c->ndof;
     r.fld[2] = b;
-    r.trc[0] = c->trw;
-    r.trc[1] = c->trs;
-    r.qtr[0] = op_lift(c, X, c->trw, 0, 0);
-    r.qtr[1] = op_lift(c, X + c->ndof, c->trs, 1, 0);
+    r.trc[0] = trw;
+    r.trc[1] = trs;
+    r.qtr[0] = op_lift(c, X, trw, 0, 0);
+    r.qtr[1] = op_lift(c, X + c->ndof, trs, 1, 0);
     r.out[0] = G;
     r.out[1] = G + c->ndof;
     r.c0 = a1dt;
@@ -1040,6 +1046,319 @@ static void newton_solve(hbpc_ctx* c, const double* b, double a1dt, double bc, c
     c->st.n_solves = c->cur_solve;
 }
 
+// ------------------------------------------------------------------ paired corrector stage solves
+// HBPC_PC_PAIRED: two corrector stage equations of a sweep (independent, Alg. 1) solved side by
+// side.  Newton and FGMRES iterations advance in lock step; per iteration the PCPRE products of
+// both systems, one pass of bj_apply over the shared S^-1 for the four right-hand sides, then per
+// system the JVP at its own state and the Gram-Schmidt passes.  A system that converges drops out
+// while the other goes on.  Stopping rules as in fgmres() and newton_solve().
+static StageSys sys_ctx(hbpc_ctx* c) {
+    StageSys S;
+    S.X = c->X;
+    S.G = c->G;
+    S.dX = c->dX;
+    S.rhs = c->rhs;
+    S.b = c->b;
+    S.trw = c->trw;
+    S.trs = c->trs;
+    S.X32 = c->X32;
+    S.trw32 = c->trw32;
+    S.trs32 = c->trs32;
+    S.V = (char*)c->V;
+    S.Z = (char*)c->Z;
+    S.kv = c->kv;
+    S.part = c->part;
+    S.dres = c->dres;
+    S.dgram = c->dgram;
+    S.hres = c->hres;
+    S.dcount = c->dcount;
+    return S;
+}
+
+static void pair_alloc(hbpc_ctx* c) {
+    StageSys& P = c->pair;
+    if (P.X) return;
+    const size_t n = c->ndof, n2 = c->n2, esz = c->kr_f32 ? 4 : 8;
+    P.X = dalloc<double>(c, n2);
+    P.G = dalloc<double>(c, n2);
+    P.dX = dalloc<double>(c, n2);
+    P.rhs = dalloc<double>(c, n2);
+    P.b = dalloc<double>(c, n);
+    P.trw = dalloc<double>(c, c->tsz);
+    P.trs = dalloc<double>(c, c->tsz);
+    P.X32 = dalloc<float>(c, n2);
+    P.trw32 = dalloc<float>(c, c->tsz);
+    P.trs32 = dalloc<float>(c, c->tsz);
+    P.V = dalloc<char>(c, (size_t)(c->m_alloc + 1) * n2 * esz);
+    P.Z = dalloc<char>(c, (size_t)c->m_alloc * n2 * esz);
+    P.kv = dalloc<char>(c, n2 * esz);
+    P.part = dalloc<double>(c, (size_t)blas_mdot_grid(n2) * (2 * (c->m_alloc + 1) + 2) + 64);
+    P.dres = dalloc<double>(c, c->arn_len + 64);
+    P.dgram = dalloc<double>(c, (size_t)(c->m_alloc + 1) * (c->m_alloc + 1));
+    P.dcount = dalloc<unsigned>(c, 4);
+    hipchk(c, hipMemset(P.dcount, 0, 4 * sizeof(unsigned)), "memset");
+    void* h = nullptr;
+    hipchk(c, hipHostMalloc(&h, (2 * c->arn_len + 64) * sizeof(double)), "hipHostMalloc");
+    P.hres = (double*)h;
+}
+
+static void pair_free(hbpc_ctx* c) {
+    StageSys& P = c->pair;
+    void* bufs[] = {P.X, P.G, P.dX, P.rhs, P.b, P.trw, P.trs, P.X32, P.trw32, P.trs32, P.V, P.Z, P.kv,
+                    P.part, P.dres, P.dgram, P.dcount};
+    for (void* q : bufs) dfree(q);
+    if (P.hres) (void)hipHostFree(P.hres);
+    std::memset(&P, 0, sizeof(P));
+}
+
+static void sys_traces(hbpc_ctx* c, const StageSys& S, int mixed) {
+    op_trace(c, S.X, S.trw, 0);
+    op_trace(c, S.X + c->ndof, S.trs, 0);
+    if (mixed) {
+        hipchk(c, blas_axpby(1.0, S.X, 0, 0.0, S.X32, 1, c->n2, c->stream), "cast");
+        op_trace(c, S.X32, S.trw32, 1);
+        op_trace(c, S.X32 + c->ndof, S.trs32, 1);
+    }
+}
+
+// PCPRE products a = vw - bcoef K vs, c = vs + K (vw - a1dt vs) of one Krylov vector into kv
+static void pcpre_into(hbpc_ctx* c, const void* w, const void* trw, const void* X, void* kv, int f32) {
+    const size_t esz = f32 ? 4 : 8;
+    LaunchReq r = op_req(c, OPK_PCPRE);
+    r.fld[0] = w;
+    r.fld[1] = X;
+    r.fld[2] = (const char*)X + c->ndof * esz;
+    r.trc[0] = trw;
+    r.qtr[0] = op_lift(c, w, trw, 0, f32);
+    r.out[0] = kv;
+    r.out[1] = (char*)kv + c->ndof * esz;
+    r.c0 = c->pc_a1dt;
+    r.c1 = c->pc_bc;
+    op_launch(c, r, f32);
+}
+
+static void fgmres_pair(hbpc_ctx* c, StageSys* S, int* active, double a1dt, double bc, int f32, int* its) {
+    const size_t n2 = c->n2, n = c->ndof, esz = f32 ? 4 : 8;
+    const int m = c->prm.gmres_restart, maxit = c->prm.gmres_maxit;
+    const double rtol = c->prm.gmres_rtol;
+    const size_t R = (size_t)c->m_alloc + 1;
+    struct Cyc {
+        std::vector<double> H, cs, sn, g, y;
+        int j = 0, total = 0;
+        double beta0 = 0.0;
+        bool on = false;
+    } cy[2];
+    auto Vj = [&](int i, int j) { return (void*)(S[i].V + (size_t)j * n2 * esz); };
+    auto Zj = [&](int i, int j) { return (void*)(S[i].Z + (size_t)j * n2 * esz); };
+    auto wst = [&](int i) { return f32 ? (const void*)S[i].X32 : (const void*)S[i].X; };
+    auto sst = [&](int i) { return f32 ? (const void*)(S[i].X32 + n) : (const void*)(S[i].X + n); };
+    auto tw = [&](int i) { return f32 ? (const void*)S[i].trw32 : (const void*)S[i].trw; };
+    auto ts = [&](int i) { return f32 ? (const void*)S[i].trs32 : (const void*)S[i].trs; };
+    // a new cycle of system i from the residual in V_0: normalise, reset the Hessenberg data
+    auto start_cycle = [&](int i) {
+        const double beta = dnorm(c, Vj(i, 0), n2, f32);
+        if (!std::isfinite(beta)) set_err(c, HBPC_ERR_NONFINITE, "non-finite Krylov residual");
+        hipchk(c, blas_axpby(1.0 / beta, Vj(i, 0), f32, 0.0, Vj(i, 0), f32, n2, c->stream), "scale");
+        Cyc& C = cy[i];
+        C.H.assign((size_t)(m + 1) * m, 0.0);
+        C.cs.assign(m, 0.0);
+        C.sn.assign(m, 0.0);
+        C.g.assign(m + 1, 0.0);
+        C.y.assign(m, 0.0);
+        C.g[0] = beta;
+        C.j = 0;
+    };
+    for (int i = 0; i < 2; ++i) {
+        its[i] = 0;
+        if (!active[i]) continue;
+        hipchk(c, hipMemsetAsync(S[i].dX, 0, n2 * 8, c->stream), "memset");
+        cy[i].beta0 = dnorm(c, S[i].rhs, n2, 0);
+        if (!std::isfinite(cy[i].beta0)) set_err(c, HBPC_ERR_NONFINITE, "non-finite Newton residual");
+        if (cy[i].beta0 == 0.0) continue;
+        hipchk(c, blas_axpby(1.0, S[i].rhs, 0, 0.0, Vj(i, 0), f32, n2, c->stream), "copy");
+        start_cycle(i);
+        cy[i].on = true;
+    }
+    for (;;) {
+        int on[2], non = 0;
+        for (int i = 0; i < 2; ++i) {
+            on[i] = cy[i].on;
+            non += on[i];
+        }
+        if (non == 0) break;
+        // z_j = P^-1 v_j of every running system: one pass over the shared blocks
+        const void* xs[4];
+        void* ys[4];
+        int nr = 0;
+        for (int i = 0; i < 2; ++i) {
+            if (!on[i]) continue;
+            const int j = cy[i].j;
+            pcpre_into(c, wst(i), tw(i), Vj(i, j), S[i].kv, f32);
+            xs[nr] = S[i].kv;
+            ys[nr++] = Zj(i, j);
+            xs[nr] = (const char*)S[i].kv + n * esz;
+            ys[nr++] = (char*)Zj(i, j) + n * esz;
+        }
+        {
+            long pi = prof_begin(c, KC_BJAPPLY);
+            hipchk(c, bj_apply_n(c->Sinv, c->sinv_type, xs, ys, nr, f32, c->NE, c->nE, c->stream), "bj_apply");
+            prof_end(c, pi, KC_BJAPPLY,
+                     (double)c->nE * c->NE * c->NE * (c->sinv_type == 2 ? 2.0 : (c->sinv_type == 1 ? 4.0 : 8.0)) +
+                         2.0 * nr * n * esz);
+        }
+        // u = J z_j at each system's state, two classical Gram-Schmidt passes (Gram-matrix form)
+        for (int i = 0; i < 2; ++i) {
+            if (!on[i]) continue;
+            const int j = cy[i].j;
+            void* u = Vj(i, j + 1);
+            op_jvp(c, wst(i), sst(i), tw(i), ts(i), Zj(i, j), u, a1dt, bc, f32, c->prm.hessian);
+            double* h1 = S[i].dres;
+            double* hn = S[i].dres + 2 * R;
+            double* h = S[i].dres + 2 * R + 4;
+            const double vb = (double)n2 * esz;
+            long pi = prof_begin(c, KC_GSDOT);
+            hipchk(c, blas_gs_gram(S[i].V, n2, j + 1, u, Vj(i, j), n2, f32, S[i].part, h1, h1 + (j + 1), S[i].dgram,
+                                   m + 1, h, S[i].dcount, c->stream),
+                   "gs dot");
+            prof_end(c, pi, KC_GSDOT, (j + 3) * vb);
+            pi = prof_begin(c, KC_GSUPD);
+            hipchk(c, blas_gs_update_normalize(S[i].V, n2, j + 1, h, u, n2, f32, S[i].part, hn, c->stream),
+                   "gs update");
+            prof_end(c, pi, KC_GSUPD, (j + 5) * vb);
+            hipchk(c, hipMemcpyAsync(S[i].hres, S[i].dres, (3 * R + 4) * sizeof(double), hipMemcpyDeviceToHost,
+                                     c->stream),
+                   "copy");
+        }
+        hipchk(c, hipEventRecord(c->arn_ev[0], c->stream), "event");
+        hipchk(c, hipEventSynchronize(c->arn_ev[0]), "sync");
+        for (int i = 0; i < 2; ++i) {
+            if (!on[i]) continue;
+            Cyc& C = cy[i];
+            const int j = C.j;
+            auto Hc = [&](int a, int b) -> double& { return C.H[(size_t)a * m + b]; };
+            const double* hr = S[i].hres;
+            for (int a = 0; a <= j; ++a) Hc(a, j) = hr[2 * R + 4 + a];
+            const double hnrm = std::sqrt(hr[2 * R]);
+            if (!std::isfinite(hnrm)) set_err(c, HBPC_ERR_NONFINITE, "non-finite Arnoldi vector");
+            Hc(j + 1, j) = hnrm;
+            for (int a = 0; a < j; ++a) {
+                const double t = C.cs[a] * Hc(a, j) + C.sn[a] * Hc(a + 1, j);
+                Hc(a + 1, j) = -C.sn[a] * Hc(a, j) + C.cs[a] * Hc(a + 1, j);
+                Hc(a, j) = t;
+            }
+            const double den = std::hypot(Hc(j, j), Hc(j + 1, j));
+            C.cs[j] = Hc(j, j) / den;
+            C.sn[j] = Hc(j + 1, j) / den;
+            Hc(j, j) = den;
+            Hc(j + 1, j) = 0.0;
+            C.g[j + 1] = -C.sn[j] * C.g[j];
+            C.g[j] = C.cs[j] * C.g[j];
+            ++C.total;
+            C.j = j + 1;
+            const bool conv = std::fabs(C.g[j + 1]) <= rtol * C.beta0 || hnrm == 0.0;
+            if (!conv && C.j < m && C.total < maxit) continue;
+            // end of the cycle: y = H^-1 g, dX += Z y
+            const int k = C.j;
+            for (int a = k - 1; a >= 0; --a) {
+                double t = C.g[a];
+                for (int l = a + 1; l < k; ++l) t -= Hc(a, l) * C.y[l];
+                C.y[a] = t / Hc(a, a);
+            }
+            hipchk(c, blas_gemv_add(S[i].Z, f32, n2, k, C.y.data(), S[i].dX, 0, n2, c->stream), "update");
+            if (conv) {
+                C.on = false;
+                its[i] = C.total;
+                continue;
+            }
+            if (C.total >= maxit)
+                set_err(c, HBPC_ERR_GMRES, "GMRES did not reach eps_G within " + std::to_string(maxit) + " iterations");
+            // restart: r = rhs - J dX in V_0
+            void* xw = Vj(i, 1);
+            hipchk(c, blas_axpby(1.0, S[i].dX, 0, 0.0, xw, f32, n2, c->stream), "cast");
+            op_jvp(c, wst(i), sst(i), tw(i), ts(i), xw, Vj(i, 0), a1dt, bc, f32, c->prm.hessian);
+            hipchk(c, blas_axpby(1.0, S[i].rhs, 0, -1.0, Vj(i, 0), f32, n2, c->stream), "residual");
+            start_cycle(i);
+        }
+    }
+}
+
+// Newton on two corrector stage equations g(W_i) = b_i side by side (see fgmres_pair); keep_pc: the
+// active slot's blocks, built for the same coefficients and precision, are used as they are
+static void newton_solve_pair(hbpc_ctx* c, const double* const* b, double a1dt, double bc,
+                              const double* const* guess, double* const* out, bool keep_pc) {
+    pair_alloc(c);
+    const size_t n = c->ndof;
+    const int mixed = c->prm.precision == HBPC_MIXED;
+    StageSys S[2] = {sys_ctx(c), c->pair};
+    int active[2], its[2] = {0, 0}, gits[2] = {0, 0};
+    double n0[2], nw0[2], nr_prev[2];
+    for (int i = 0; i < 2; ++i) {
+        hipchk(c, hipMemcpyAsync(S[i].X, guess[i], n * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
+        op_r1(c, S[i].X, S[i].X + n, S[i].trw);   // sigma^0 = R1(guess)
+        sys_traces(c, S[i], 0);
+        op_res(c, S[i].X, b[i], a1dt, bc, S[i].G, S[i].trw, S[i].trs);
+        n0[i] = dnorm(c, S[i].G, c->n2, 0);
+        if (!std::isfinite(n0[i])) set_err(c, HBPC_ERR_NONFINITE, "non-finite residual at the Newton initial guess");
+        nw0[i] = dnorm(c, S[i].X, n, 0);
+        nr_prev[i] = n0[i];
+        active[i] = n0[i] > 1e-14 * std::sqrt((double)c->n2);
+        if (active[i] && mixed) sys_traces(c, S[i], 1);
+    }
+    if (active[0] || active[1]) {
+        const bool kept = keep_pc && c->pc_valid && c->pc_a1dt == a1dt && c->pc_bc == bc && c->sinv_f32 == mixed &&
+                          !c->pc_hess;
+        c->pc_kept = kept;
+        if (!kept) pc_build(c, S[active[0] ? 0 : 1].X, nullptr, a1dt, bc, mixed);
+    }
+    while (active[0] || active[1]) {
+        int run[2] = {active[0], active[1]};
+        for (int i = 0; i < 2; ++i)
+            if (run[i]) {
+                ++its[i];
+                hipchk(c, blas_axpby(-1.0, S[i].G, 0, 0.0, S[i].rhs, 0, c->n2, c->stream), "rhs");
+            }
+        int git[2];
+        const double tg = now_ms();
+        fgmres_pair(c, S, run, a1dt, bc, mixed, git);
+        c->st.t_gmres_ms += now_ms() - tg;
+        for (int i = 0; i < 2; ++i) {
+            if (!run[i]) continue;
+            gits[i] += git[i];
+            hipchk(c, blas_axpby(1.0, S[i].dX, 0, 1.0, S[i].X, 0, c->n2, c->stream), "update");
+            sys_traces(c, S[i], mixed);
+            op_res(c, S[i].X, b[i], a1dt, bc, S[i].G, S[i].trw, S[i].trs);
+            const double nr = dnorm(c, S[i].G, c->n2, 0);
+            const double ndw = dnorm(c, S[i].dX, n, 0);
+            if (c->verbose)
+                std::fprintf(stderr, "[hbpc] solve %d (paired) newton %d |G| %.6e (|G0| %.6e) |dw| %.3e gmres %d\n",
+                             c->cur_solve + i, its[i], nr, n0[i], ndw, gits[i]);
+            if (!std::isfinite(nr)) set_err(c, HBPC_ERR_NONFINITE, "non-finite Newton residual");
+            if (nr <= c->prm.newton_rtol * n0[i] || ndw <= c->prm.newton_atol_dw * std::sqrt((double)n)) {
+                active[i] = 0;
+            } else if (its[i] >= 2 && nr > 0.5 * nr_prev[i] && ndw <= 1e-12 * nw0[i]) {
+                c->st.newton_floor_stops++;
+                active[i] = 0;
+            } else if (its[i] >= c->prm.newton_maxit) {
+                set_err(c, HBPC_ERR_NEWTON,
+                        "Newton did not converge within " + std::to_string(c->prm.newton_maxit) + " iterations");
+            }
+            nr_prev[i] = nr;
+        }
+    }
+    for (int i = 0; i < 2; ++i) {
+        hipchk(c, hipMemcpyAsync(out[i], S[i].X, n * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
+        const int sidx = c->cur_solve + i;
+        if (sidx < HBPC_MAX_SOLVES) {
+            c->st.newton_per_solve[sidx] = its[i];
+            c->st.gmres_per_solve[sidx] = gits[i];
+        }
+        c->st.newton_its += its[i];
+        c->st.gmres_its += gits[i];
+    }
+    c->cur_solve += 2;
+    c->st.n_solves = c->cur_solve;
+}
+
 // ------------------------------------------------------------------ HBPC step (Algorithm 1)
 static void hbpc_step_impl(hbpc_ctx* c, double* w_inout, double dt) {
     Tab t;
@@ -1073,6 +1392,7 @@ static void hbpc_step_impl(hbpc_ctx* c, double* w_inout, double dt) {
         op_r1r2(c, W[l], R1(l), R2(l));
     }
     // corrector sweeps: every stage of sweep k uses iterate [k] of all stages
+    const bool paired = c->prm.pc_rebuild == HBPC_PC_PAIRED;
     for (int k = 0; k < c->prm.kmax; ++k) {
         for (int l = 1; l < s; ++l) {
             double coef1[4], coef2[4];
@@ -1080,10 +1400,32 @@ static void hbpc_step_impl(hbpc_ctx* c, double* w_inout, double dt) {
                 coef1[j] = dt * t.B1[l][j] - (j == l ? dt : 0.0);
                 coef2[j] = dt * dt * t.B2[l][j] + (j == l ? dt * dt / 2 : 0.0);
             }
+            if (paired && l + 1 < s) {
+                // stages l and l + 1 side by side, on the blocks of slot l - 1 (built at stage l's
+                // state in the first sweep, kept for the later ones)
+                pair_alloc(c);
+                double* bb[2] = {c->b, c->pair.b};
+                for (int i = 0; i < 2; ++i) {
+                    double cf1[4], cf2[4];
+                    for (int j = 0; j < s; ++j) {
+                        cf1[j] = dt * t.B1[l + i][j] - (j == l + i ? dt : 0.0);
+                        cf2[j] = dt * dt * t.B2[l + i][j] + (j == l + i ? dt * dt / 2 : 0.0);
+                    }
+                    hipchk(c, hipMemcpyAsync(bb[i], W[0], n * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
+                    hipchk(c, blas_gemv_add(c->R1all, 0, n, s, cf1, bb[i], 0, n, c->stream), "b");
+                    hipchk(c, blas_gemv_add(c->R2all, 0, n, s, cf2, bb[i], 0, n, c->stream), "b");
+                }
+                pc_use_slot(c, l - 1);
+                const double* gs[2] = {W[l], W[l + 1]};
+                double* os[2] = {c->Wn[l], c->Wn[l + 1]};
+                newton_solve_pair(c, bb, dt, dt * dt / 2, gs, os, k > 0);
+                ++l;
+                continue;
+            }
             hipchk(c, hipMemcpyAsync(c->b, W[0], n * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
             hipchk(c, blas_gemv_add(c->R1all, 0, n, s, coef1, c->b, 0, n, c->stream), "b");
             hipchk(c, blas_gemv_add(c->R2all, 0, n, s, coef2, c->b, 0, n, c->stream), "b");
-            const bool per_stage = c->prm.pc_rebuild == HBPC_PC_PER_STAGE;
+            const bool per_stage = c->prm.pc_rebuild == HBPC_PC_PER_STAGE || paired;
             pc_use_slot(c, per_stage || across ? l - 1 : 0);
             newton_solve(c, c->b, dt, dt * dt / 2, W[l], c->Wn[l], (per_stage && k > 0) || across);
         }
@@ -1113,6 +1455,7 @@ static void ctx_free(hbpc_ctx* c) {
                     c->mgrad, c->ap_X, c->ap_G1, c->ap_G2, c->ap_H1, c->ap_H2, c->ap_Y, c->ap_s, c->tr_buf, c->tr_idx_dev,
                     c->col_elems};
     for (void* p : bufs) dfree(p);
+    pair_free(c);
     for (int i = 0; i < 4; ++i) dfree(c->Sinv_slot[i]);
     c->Sinv = nullptr;
     for (int i = 0; i < 6; ++i) dfree(c->fd[i]);
@@ -1245,8 +1588,10 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
         set_err(c, HBPC_ERR_ARG, "gmres_restart must be 1.." + std::to_string(HBPC_MAX_RESTART));
     if (prm->precond < HBPC_PC_NONE || prm->precond > HBPC_PC_BJEXT_H)
         set_err(c, HBPC_ERR_ARG, "unknown precond");
-    if (prm->pc_rebuild < HBPC_PC_PER_SOLVE || prm->pc_rebuild > HBPC_PC_ACROSS_STEPS)
+    if (prm->pc_rebuild < HBPC_PC_PER_SOLVE || prm->pc_rebuild > HBPC_PC_PAIRED)
         set_err(c, HBPC_ERR_ARG, "unknown pc_rebuild");
+    if (prm->pc_rebuild == HBPC_PC_PAIRED && (prm->precond != HBPC_PC_BJEXT || prm->jvp_mode != HBPC_JVP_LINEARISED))
+        set_err(c, HBPC_ERR_ARG, "HBPC_PC_PAIRED needs BJ_ext and the linearised JVP");
     if (prm->pc_rebuild == HBPC_PC_ACROSS_STEPS && prm->q > 6)
         set_err(c, HBPC_ERR_ARG, "HBPC_PC_ACROSS_STEPS keeps 2 (s - 1) block sets: q <= 6");
     if (prm->pc_rebuild == HBPC_PC_ACROSS_STEPS && prm->pc_reuse_steps < 1)

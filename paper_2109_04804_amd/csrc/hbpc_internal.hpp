@@ -16,6 +16,8 @@ hipError_t bj_invert(double* KT, const double* HT, void* SinvT, int type, int NE
                      hipStream_t st);
 hipError_t bj_apply(const void* SinvT, int m_type, const void* xa, const void* xc, void* yw, void* ys, int v_f32,
                     int NE, int nE, hipStream_t st);
+hipError_t bj_apply_n(const void* SinvT, int m_type, const void* const* xs, void* const* ys, int nr, int v_f32,
+                      int NE, int nE, hipStream_t st);
 int blas_mdot_grid(size_t n);
 hipError_t blas_mdot(const void* V, size_t ld, int k, const void* w, size_t n, int f32, double* part, double* h,
                      hipStream_t st);
@@ -80,6 +82,17 @@ struct DevBuf {
 
 constexpr int KC_MAXCLS = 24;
 
+// Buffers of one stage system of the paired corrector solves (HBPC_PC_PAIRED): the first system
+// uses the context's own buffers, the second these (allocated on first use).
+struct StageSys {
+    double *X, *G, *dX, *rhs, *b, *trw, *trs;
+    float *X32, *trw32, *trs32;
+    char *V, *Z;
+    void* kv;                 // PCPRE products a | c (type of the Krylov vectors)
+    double *part, *dres, *dgram, *hres;
+    unsigned* dcount;
+};
+
 struct hbpc_ctx {
     hbpc_mesh mesh;
     hbpc_params prm;
@@ -141,6 +154,7 @@ struct hbpc_ctx {
     unsigned* dcount;         // grid-wide hand-over counters of the fused reductions (0 between launches)
     double* hres;             // pinned host copies: two Arnoldi slots of arn_len, then 64 words
     hipEvent_t arn_ev[2];     // Arnoldi results of iteration j copied to slot j % 2
+    StageSys pair;            // second system of HBPC_PC_PAIRED (null pointers until used)
     int* dstatus;
     // FD scratch (allocated on demand)
     double* fd[6];

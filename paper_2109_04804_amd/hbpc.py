@@ -23,7 +23,7 @@ PRECISION = {"fp64": 0, "mixed": 1}
 PRECOND = {"none": 0, "bjext": 1, "learned": 2, "learned_first": 3, "learned_guess": 4, "bjext_h": 5}
 MLP_PRECISION = {"bf16": 0, "fp32": 1}
 PAIRS = {"newton": 0, "krylov": 1, "random": 2}
-PC_REBUILD = {"per_solve": 0, "per_newton_it": 1, "per_stage": 2, "across_steps": 3}
+PC_REBUILD = {"per_solve": 0, "per_newton_it": 1, "per_stage": 2, "across_steps": 3, "paired": 4}
 JVP = {"linearised": 0, "fd": 1}
 MAX_SOLVES = 64
 

@@ -108,6 +108,29 @@ def test_vortex_step_bench_composition(form):
 
 
 @pytest.mark.parametrize("form", ["fp64", "mixed"])
+def test_vortex_step_paired_stages(form):
+    """The same step with the two corrector stages of every sweep solved side by side
+    (HBPC_PC_PAIRED: lock-step Newton and FGMRES iterations, one S^-1 set built at the first
+    stage's state and applied to both stages' four right-hand sides per iteration)."""
+    from paper_2109_04804_amd.hbpc import Context
+    w0, ref, meta = golden.load("vortex8")
+    n = meta["nelem"][0]
+    precision = "fp64" if form == "fp64" else "mixed"
+    rtol = 1e-12 if form == "fp64" else 1e-8
+    ctx = Context(2, [n, n], [10.0, 10.0], 5, "euler", flux="rusanov", gamma=1.4, eps_ref=1.0, q=6, kmax=4,
+                  newton_rtol=rtol, gmres_rtol=1e-3, gmres_restart=30, gmres_maxit=7000, precision=precision,
+                  precond="bjext", pc_rebuild="paired")
+    w = dev(w0)
+    st = ctx.step(w, meta["dt"])
+    ctx.close()
+    err = rel(host(w), ref)
+    print(form, "paired newton", st["newton_its"], "gmres", st["gmres_its"], "per solve", st["gmres_per_solve"],
+          "builds", st["pc_builds"], "rel err %.3e" % err, flush=True)
+    assert st["n_solves"] == 10 and st["pc_builds"] == 3   # two predictor solves, one set for the pair
+    assert err < (1e-10 if form == "fp64" else 1e-8)
+
+
+@pytest.mark.parametrize("form", ["fp64", "mixed"])
 def test_tgv_step_bench_composition(form):
     """FGMRES(200), as the 48^3 workload at this Courant number runs (FGMRES(30) stalls there)."""
     if not os.path.exists(golden.path_of("tgv3")):

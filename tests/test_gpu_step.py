@@ -348,3 +348,28 @@ def _ns_reference(name):
         _NS_REF[name] = dg_hbpc_step(dg, state(dg, seed=4), dt, 6, kmax,
                                      StageSolver(dg, newton_rtol=1e-12, gmres_rtol=1e-5))
     return _NS_REF[name]
+
+
+@pytest.mark.parametrize("name,q,kmax", [("euler2_n3_lobatto", 8, 3), ("burgers2", 6, 2), ("ns2", 6, 2),
+                                         ("euler3_n3", 6, 1)])
+def test_paired_stage_solves(name, q, kmax):
+    """HBPC_PC_PAIRED: corrector stages solved in pairs (q = 8: stages 1 and 2 paired, stage 3
+    alone) on the Euler vortex (4 x 4, N = 3), viscous Burgers with BR1 (8 x 8, N = 4),
+    Navier-Stokes with BR2 (4 x 4, N = 4) and the 3-D Taylor-Green field (2^3, N = 3), FP64
+    at eps_N = 1e-12 against the oracle (relative L2 <= 1e-10)."""
+    case = dict(CASES[name])
+    case.update(nelem={"euler2_n3_lobatto": [4, 4], "burgers2": [8, 8], "ns2": [4, 4], "euler3_n3": [2, 2, 2]}[name])
+    if name == "euler2_n3_lobatto":
+        case.update(nodes="gauss")
+    dg = oracle_for(case)
+    w0 = state(dg, seed=6)
+    dt = 0.1
+    ctx = ctx_for(case, q=q, kmax=kmax, newton_rtol=1e-12, gmres_rtol=1e-5, precision="fp64", pc_rebuild="paired")
+    wg = dev(w0)
+    stats = ctx.step(wg, dt)
+    print(name, "paired", stats["newton_its"], stats["gmres_its"], stats["gmres_per_solve"], flush=True)
+    assert stats["n_solves"] == (q // 2 - 1) * (1 + kmax)
+    ref = dg_hbpc_step(dg, w0, dt, q, kmax, StageSolver(dg, newton_rtol=1e-12, gmres_rtol=1e-5))
+    err = rel(host(wg), ref)
+    print("rel err", err, flush=True)
+    assert err < 1e-10
