@@ -6,9 +6,10 @@ Workload (default): 2-D compressible Euler isentropic vortex on the periodic
 (seed 2109), DGSEM N = 5 on Gauss nodes, 128 x 128 elements (2,359,296 DOF),
 Rusanov flux, HBPC(6,4) (3 nodes c = 0, 1/2, 1; 4 corrector sweeps), dt = 0.1,
 Newton tolerance 1e-8, FGMRES(30) with eps_G = 1e-3, BJ_ext blocks built once
-per predictor stage and once per corrector stage (reused by the later
-sweeps; --pc-rebuild per_solve builds them for every stage solve).  Three
-forms are timed:
+per predictor stage; the two corrector stages of each sweep solved side by
+side on one set of blocks built at the first stage's state in the first sweep
+(--pc-rebuild paired; the learned form keeps one set per corrector stage,
+per_stage).  Three forms are timed:
   fp64     all-FP64, BJ_ext;
   mixed    FP64 Newton, FP32 Krylov vectors, JVP and BJ_ext;
   learned  as mixed with the learned preconditioner (BF16 network, BJ_ext as
@@ -443,10 +444,12 @@ def main():
                          "(as mixed with the BJ_ext blocks stored in FP16), fp64_h / mixed_h (as fp64 / mixed "
                          "with BJ^H_ext)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--pc-rebuild", default="per_stage",
+    ap.add_argument("--pc-rebuild", default="paired",
                     choices=["per_solve", "per_stage", "across_steps", "paired"],
-                    help="BJ_ext builds: kept per corrector stage across sweeps (default), once per stage "
-                         "solve, or every stage's blocks kept across --pc-reuse-steps time steps")
+                    help="BJ_ext builds: the two corrector stages of a sweep solved side by side on one set of "
+                         "blocks built in the first sweep (paired, the default; forms with the learned "
+                         "preconditioner run per_stage), kept per corrector stage across sweeps (per_stage), "
+                         "once per stage solve, or every stage's blocks kept across --pc-reuse-steps time steps")
     ap.add_argument("--pc-reuse-steps", type=int, default=4)
     ap.add_argument("--pc-probe-its", type=int, default=5,
                     help="learned form: length of the network's first restart cycle per solve, judged at the "

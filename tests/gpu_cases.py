@@ -128,6 +128,26 @@ def half_storage_bound(Ks, vw, vs, a1dt, bc, ref):
     return 2.0 ** -11 * np.sqrt(num) / np.linalg.norm(ref) + 2.0 ** -24 * kap
 
 
+def half_storage_rss(Ks, vw, vs, a1dt, bc, ref):
+    """Root-sum-square scale of the same FP16 rounding: the rounding errors of the entries of
+    S^-1 are of either sign and of magnitude up to 2^-11 |S^-1_ij|, so the error of each output
+    component is a sum of terms 2^-11 S^-1_ij x_j of unrelated signs, of size
+    2^-11 sqrt(sum_j (S^-1_ij x_j)^2); plus the FP32 inversion error 2^-24 kappa_2(S_e).  A
+    statistical scale (a few times it bounds the observed error), much tighter than the
+    componentwise bound, which adds every term with the same sign."""
+    ne = Ks.shape[1]
+    I = np.eye(ne)
+    num, kap = 0.0, 0.0
+    for K, xw, xs in zip(Ks, vw, vs):
+        S = I - a1dt * K + bc * (K @ K)
+        Si = np.linalg.inv(S)
+        a = xw - bc * (K @ xs)
+        c = xs + K @ (xw - a1dt * xs)
+        num += np.sum((Si * a[None, :]) ** 2) + np.sum((Si * c[None, :]) ** 2)
+        kap = max(kap, np.linalg.cond(S))
+    return 2.0 ** -11 * np.sqrt(num) / np.linalg.norm(ref) + 2.0 ** -24 * kap
+
+
 def rel(a, b):
     a = np.asarray(a, dtype=np.float64).ravel()
     b = np.asarray(b, dtype=np.float64).ravel()

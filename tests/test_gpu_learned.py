@@ -135,8 +135,8 @@ def _vortex(ctx, nelem, L, seed):
     return inputs.isentropic_vortex(X[0], X[1], xc, yc, beta, mach=0.5, gamma=1.4, box=L)
 
 
-def test_training_and_gain():
-    """16 x 16 elements, N = 3, [0,10]^2, HBPC(6,2), dt = 0.4 (element acoustic CFL
+def _gain_run():
+    """The gain run: 16 x 16 elements, N = 3, [0,10]^2, HBPC(6,2), dt = 0.4 (element acoustic CFL
     about 1): Newton pairs (FP64 BJ_ext solves, eps_G 1e-6) for vortex seeds 1..4,
     BF16 training, then one mixed step at eps_G = 1e-3 on held-out seed 99 with no
     preconditioner, the network alone (no fallback, at most 20000 Krylov iterations
@@ -178,9 +178,34 @@ def test_training_and_gain():
         except Exception as ex:
             print(form, "did not converge:", ex, flush=True)
         ctx.close()
+    print("Krylov iterations per step:", {k: v[0] for k, v in ev.items()})
+    return ev
+
+
+_GAIN = {}
+
+
+def test_training_and_gain():
+    """See _gain_run: training lowers the loss and every form that converges reaches the same
+    Newton root as BJ_ext."""
+    if "ev" not in _GAIN:
+        _GAIN["ev"] = _gain_run()
+    ev = _GAIN["ev"]
     for form in ("none", "network", "network+fallback", "network+fallback, 5-iteration probe", "network-first",
                  "network-guess"):
         if form in ev:
             assert rel(ev[form][2], ev["bjext"][2]) < 1e-7, form
     assert "network+fallback" in ev and "network-first" in ev and "network-guess" in ev
-    print("Krylov iterations per step:", {k: v[0] for k, v in ev.items()})
+
+
+@pytest.mark.xfail(strict=False, reason="measured: the trained patch network does not beat BJ_ext (network + "
+                                        "fallback 708, with the 5-iteration probe 558, BJ_ext 528 Krylov "
+                                        "iterations on held-out seed 99); BJ_ext takes over in every solve")
+def test_learned_gain_over_bjext():
+    """The gain the learned preconditioner should show: fewer Krylov iterations than BJ_ext alone
+    on the held-out vortex (seed 99) with the network and its fallback."""
+    if "ev" not in _GAIN:
+        _GAIN["ev"] = _gain_run()
+    ev = _GAIN["ev"]
+    best = min(ev[f][0] for f in ("network+fallback", "network+fallback, 5-iteration probe") if f in ev)
+    assert best < ev["bjext"][0]
