@@ -481,8 +481,11 @@ static void mlp_gemm_p(hbpc_ctx* c, const float* A, long long a_r, long long a_c
                        long long b_c, float* C, long long ldc, const float* bias, const float* mask, int mask_mul,
                        int M, int N, int K, int relu, int bf16, int accumulate = 0) {
     long pi = prof_begin(c, KC_GEMM);
-    hipchk(c, mlp_gemm(A, a_r, a_c, B, b_r, b_c, C, ldc, bias, mask, mask ? ldc : 0, mask_mul, M, N, K, relu,
-                       accumulate, bf16, c->stream),
+    // a weight operand is read from the BF16 copy of the parameters
+    const uint16_t* B16 = nullptr;
+    if (bf16 && B >= c->theta && B < c->theta + c->mlp_np) B16 = c->theta16 + (B - c->theta);
+    hipchk(c, mlp_gemm(A, a_r, a_c, B, B16, b_r, b_c, C, ldc, bias, mask, mask ? ldc : 0, mask_mul, M, N, K, relu,
+                       accumulate, bf16, c->gemm_ws, c->gemm_ws_floats, c->stream),
            "mlp gemm");
     prof_end(c, pi, KC_GEMM, 4.0 * ((double)M * K + (double)K * N + (double)M * N * (mask ? 2 : 1)),
              2.0 * M * N * K);
@@ -584,7 +587,7 @@ static void mlp_loss_grad_dev(hbpc_ctx* c, const float* X, const float* T, int r
 static void mlp_adam_dev(hbpc_ctx* c, const float* grad, double lr, double b1, double b2, double eps) {
     c->adam_t++;
     long pi = prof_begin(c, KC_MLPV);
-    hipchk(c, mlp_adam(c->theta, grad, c->adam_m, c->adam_v, (long long)c->mlp_np, (float)lr, (float)b1, (float)b2,
+    hipchk(c, mlp_adam(c->theta, c->theta16, grad, c->adam_m, c->adam_v, (long long)c->mlp_np, (float)lr, (float)b1, (float)b2,
                        (float)eps, c->adam_t, c->stream),
            "adam");
     prof_end(c, pi, KC_MLPV, 20.0 * c->mlp_np);
@@ -1452,7 +1455,7 @@ static void ctx_free(hbpc_ctx* c) {
     void* bufs[] = {c->R1all, c->R2all, c->X, c->b, c->G, c->dX, c->rhs, c->trw, c->trs, c->trd1,
                     c->X32, c->trw32, c->trs32, c->trd1_32, c->V, c->Z, c->kv, c->KT, c->HT,
                     c->part, c->dres, c->dgram, c->dcount, c->dstatus, c->basis64, c->basis32, c->theta, c->adam_m, c->adam_v,
-                    c->mgrad, c->ap_X, c->ap_G1, c->ap_G2, c->ap_H1, c->ap_H2, c->ap_Y, c->ap_s, c->tr_buf, c->tr_idx_dev,
+                    c->mgrad, c->theta16, c->gemm_ws, c->ap_X, c->ap_G1, c->ap_G2, c->ap_H1, c->ap_H2, c->ap_Y, c->ap_s, c->tr_buf, c->tr_idx_dev,
                     c->col_elems};
     for (void* p : bufs) dfree(p);
     pair_free(c);
@@ -1674,6 +1677,9 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
     c->adam_m = dalloc<float>(c, c->mlp_np);
     c->adam_v = dalloc<float>(c, c->mlp_np);
     c->mgrad = dalloc<float>(c, c->mlp_np);
+    c->theta16 = dalloc<uint16_t>(c, c->mlp_np);
+    c->gemm_ws_floats = (size_t)4 << 20;   // 16 MiB: 512 + 256 output tiles of 64 x 64 (see mlp_gemm)
+    c->gemm_ws = dalloc<float>(c, c->gemm_ws_floats);
     c->lpc_snap = -1;
     c->kv = dalloc<double>(c, 3 * n);
     // K build in chunks of <= 4 GiB of FP64 blocks (the whole 128^2 N=5 mesh in one launch, so the
@@ -1769,6 +1775,7 @@ static void mlp_init_impl(hbpc_ctx* c, unsigned long long seed) {
     const size_t bytes = c->mlp_np * sizeof(float);
     hipchk(c, hipMemsetAsync(c->adam_m, 0, bytes, c->stream), "memset");
     hipchk(c, hipMemsetAsync(c->adam_v, 0, bytes, c->stream), "memset");
+    hipchk(c, mlp_to_bf16(c->theta, c->theta16, (long long)c->mlp_np, c->stream), "bf16 copy");
     c->adam_t = 0;
     c->mlp_ready = 1;
 }
@@ -2008,6 +2015,7 @@ int hbpc_mlp_set_params(hbpc_ctx* c, const float* theta) {
     HBPC_TRY(c, {
         const size_t b = c->mlp_np * sizeof(float);
         hipchk(c, hipMemcpyAsync(c->theta, theta, b, hipMemcpyDeviceToDevice, c->stream), "copy");
+        hipchk(c, mlp_to_bf16(c->theta, c->theta16, (long long)c->mlp_np, c->stream), "bf16 copy");
         hipchk(c, hipMemsetAsync(c->adam_m, 0, b, c->stream), "memset");
         hipchk(c, hipMemsetAsync(c->adam_v, 0, b, c->stream), "memset");
         c->adam_t = 0;

@@ -31,9 +31,11 @@ hipError_t blas_lincomb2(double a, const double* x, double b, const double* z, d
 hipError_t blas_gemv_add(const void* Z, int tz, size_t ld, int k, const double* c, void* y, int ty, size_t n,
                          hipStream_t st);
 hipError_t blas_nonfinite(const void* x, int f32, size_t n, int* status, hipStream_t st);
-hipError_t mlp_gemm(const float* A, long long a_r, long long a_c, const float* B, long long b_r, long long b_c,
-                    float* C, long long ldc, const float* bias, const float* mask, long long ldm, int mask_mul, int M,
-                    int N, int K, int relu, int accumulate, int bf16, hipStream_t st);
+hipError_t mlp_gemm(const float* A, long long a_r, long long a_c, const float* B, const uint16_t* B16, long long b_r,
+                    long long b_c, float* C, long long ldc, const float* bias, const float* mask, long long ldm,
+                    int mask_mul, int M, int N, int K, int relu, int accumulate, int bf16, float* ws,
+                    size_t ws_floats, hipStream_t st);
+hipError_t mlp_to_bf16(const float* x, uint16_t* y, long long n, hipStream_t st);
 hipError_t mlp_ew_mul(const float* a, const float* b, float* out, long long n, hipStream_t st);
 hipError_t mlp_ew_split(const float* dh, const float* g, const float* a, float* da, float* dz, long long n,
                         int relu_mask, hipStream_t st);
@@ -41,8 +43,8 @@ hipError_t mlp_ew_relu_mask(float* x, const float* g, long long n, hipStream_t s
 hipError_t mlp_colsum(const float* X, long long ld, int M, int N, float* out, hipStream_t st);
 hipError_t mlp_mse_grad(const float* Y, const float* T, float* dY, long long n, float scale, double* part, int nblk,
                         hipStream_t st);
-hipError_t mlp_adam(float* th, const float* g, float* m, float* v, long long n, float lr, float b1, float b2,
-                    float eps, int t, hipStream_t st);
+hipError_t mlp_adam(float* th, uint16_t* th16, const float* g, float* m, float* v, long long n, float lr, float b1,
+                    float b2, float eps, int t, hipStream_t st);
 hipError_t mlp_features(const void* rt, const void* w, const void* dw, int f32, const int* elems, int nb, int D,
                         const int* nel, int ne, float a1dt, float bc, float* X, float* tgt, float* scale, int part,
                         hipStream_t st);
@@ -162,6 +164,8 @@ struct hbpc_ctx {
     int mlp_nin, mlp_nr, mlp_H;
     size_t mlp_np;
     float* theta; float* adam_m; float* adam_v; float* mgrad;   // FP32 parameters, moments, gradient
+    uint16_t* theta16;                                          // BF16 copy of theta (matrix-core operand)
+    float* gemm_ws; size_t gemm_ws_floats;                      // split-k partial sums of the network GEMMs
     int adam_t, mlp_ready;
     float* ap_X; float* ap_G1; float* ap_G2; float* ap_H1; float* ap_H2; float* ap_Y; float* ap_s;   // nE rows
     float* tr_buf; int tr_rows;                                        // training buffers (batch rows)

@@ -84,10 +84,12 @@ def test_features_match_oracle(case):
 
 
 @pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16", 2e-2)])
-@pytest.mark.parametrize("rows", [1, 150])
+@pytest.mark.parametrize("rows", [1, 150, 700])
 def test_forward_matches_oracle(precision, tol, rows):
     """Against the exact FP64 network; the BF16 path also against the oracle with
-    BF16-rounded operands (exact accumulation), to 2e-4."""
+    BF16-rounded operands (exact accumulation), to 2e-4.  700 rows: 11 row tiles with a
+    ragged last one; the feature rows (642 values) are staged with 8-byte loads, the
+    hidden ones (256) with 16-byte loads."""
     ctx = make_ctx()
     n_in, H, n_out, _ = ctx.mlp_shape()
     th = params(ctx)
@@ -108,17 +110,18 @@ def test_forward_matches_oracle(precision, tol, rows):
         assert err_q < 2e-4
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16", 5e-4)])
-def test_loss_grad_matches_oracle(precision, tol):
+@pytest.mark.parametrize("precision,tol,rows", [("fp32", 1e-5, 200), ("bf16", 5e-4, 200), ("bf16", 5e-4, 1200)])
+def test_loss_grad_matches_oracle(precision, tol, rows):
     """FP32 path against the exact gradient; the BF16 path against the oracle
     with BF16-rounded operands in every product (near-zero pre-activations make
-    the ReLU masks of an unrounded reference differ, an O(1) change per flip)."""
+    the ReLU masks of an unrounded reference differ, an O(1) change per flip).
+    With 1200 rows the weight gradients (k = rows) are split over k (partial sums
+    added in a fixed order)."""
     ctx = make_ctx()
     n_in, H, n_out, n_p = ctx.mlp_shape()
     th = params(ctx, 1)
     ctx.mlp_set_params(dev(th, torch.float32))
     rng = np.random.default_rng(7)
-    rows = 200
     X = rng.standard_normal((rows, n_in)).astype(np.float32).astype(np.float64)
     T = rng.standard_normal((rows, n_out)).astype(np.float32).astype(np.float64)
     g = torch.zeros(n_p, dtype=torch.float32, device="cuda")
@@ -148,6 +151,29 @@ def test_adam_matches_oracle():
     got = ctx.mlp_get_params(torch.zeros(n_p, dtype=torch.float32, device="cuda"))
     assert rel(host(got) - th, t_ref - th) < 1e-5
     assert rel(host(got), t_ref) < 1e-6
+
+
+def test_bf16_weights_follow_the_parameters():
+    """The matrix cores read the weights from a BF16 copy of the FP32 parameters: after
+    set_params and after Adam steps the BF16 forward equals the oracle's with the current
+    parameters (BF16-rounded operands)."""
+    ctx = make_ctx()
+    n_in, H, n_out, n_p = ctx.mlp_shape()
+    th = params(ctx, 3)
+    ctx.mlp_set_params(dev(th, torch.float32))
+    rng = np.random.default_rng(13)
+    X = rng.standard_normal((64, n_in)).astype(np.float32).astype(np.float64)
+    Y = torch.zeros(64 * n_out, dtype=torch.float32, device="cuda")
+    for t in range(3):
+        if t:
+            g = rng.standard_normal(n_p).astype(np.float32)
+            ctx.mlp_adam(dev(g, torch.float32), 1e-2)
+        cur = host(ctx.mlp_get_params(torch.zeros(n_p, dtype=torch.float32, device="cuda")))
+        ctx.mlp_forward(dev(X, torch.float32), 64, Y, "bf16")
+        ref_q, _ = mlp.forward(cur, X, n_in, H, n_out, q=mlp.round_bf16)
+        err = rel(host(Y).reshape(ref_q.shape), ref_q)
+        print("after", t, "Adam steps: bf16 forward rel", err)
+        assert err < 2e-4
 
 
 @pytest.mark.parametrize("case,mlp_precision,vec,tol", [(CASE, "fp32", "fp64", 1e-5), (CASE, "fp32", "mixed", 1e-4),
