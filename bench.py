@@ -8,8 +8,8 @@ Rusanov flux, HBPC(6,4) (3 nodes c = 0, 1/2, 1; 4 corrector sweeps), dt = 0.1,
 Newton tolerance 1e-8, FGMRES(30) with eps_G = 1e-3, BJ_ext blocks built once
 per predictor stage; the two corrector stages of each sweep solved side by
 side on one set of blocks built at the first stage's state in the first sweep
-(--pc-rebuild paired; the learned form keeps one set per corrector stage,
-per_stage).  Three forms are timed:
+(--pc-rebuild paired; the BJ^H_ext forms and the learned_first / learned_guess
+variants keep one set per corrector stage, per_stage).  Three forms are timed:
   fp64     all-FP64, BJ_ext;
   mixed    FP64 Newton, FP32 Krylov vectors, JVP and BJ_ext;
   learned  as mixed with the learned preconditioner (BF16 network, BJ_ext as
@@ -198,8 +198,8 @@ def run_form(wl, form, steps, warmup, theta=None, pc_rebuild="per_solve", pc_reu
     import torch
     from paper_2109_04804_amd.hbpc import Context
     precision, pc, half = form_settings(form)
-    if pc_rebuild == "paired" and pc != "bjext":
-        pc_rebuild = "per_stage"   # the paired corrector solves run BJ_ext only
+    if pc_rebuild == "paired" and pc not in ("bjext", "learned"):
+        pc_rebuild = "per_stage"   # the paired corrector solves run BJ_ext or the learned preconditioner
     q, kmax = scheme_of(wl)
     ctx = Context(wl["dim"], wl["nelem"], wl["length"], wl["N"], wl.get("equation", "euler"), q=q, kmax=kmax,
                   newton_rtol=1e-8, gmres_rtol=1e-3, gmres_restart=restart_of(wl, precision), gmres_maxit=7000,
@@ -253,7 +253,8 @@ def run_form(wl, form, steps, warmup, theta=None, pc_rebuild="per_solve", pc_reu
             "finite": finite}
 
 
-SINGLE_KERNEL_CLASSES = ("bj_apply", "bj_invert", "jvp", "pcpre", "kcol", "trace", "res", "r1", "r2", "gs_update")
+SINGLE_KERNEL_CLASSES = ("bj_apply", "bj_apply4", "bj_invert", "jvp", "pcpre", "kcol", "trace", "res", "r1", "r2",
+                         "gs_update")
 
 
 def dominant_class(prof):
@@ -364,7 +365,7 @@ def form_parity(wl, forms, ref, theta, pc_rebuild, pc_reuse_steps, pc_probe_its)
     out = {}
     for f in forms:
         precision, pc, half = form_settings(f)
-        rebuild = "per_stage" if (pc_rebuild == "paired" and pc != "bjext") else pc_rebuild
+        rebuild = "per_stage" if (pc_rebuild == "paired" and pc not in ("bjext", "learned")) else pc_rebuild
         ctx = Context(2, [PARITY_N, PARITY_N], [10.0, 10.0], 5, "euler", q=6, kmax=4, newton_rtol=1e-8,
                       gmres_rtol=1e-3, gmres_restart=30, gmres_maxit=7000, precond=pc, precision=precision,
                       pc_fallback=0.5, pc_rebuild=rebuild, pc_half=half, pc_reuse_steps=pc_reuse_steps,
@@ -447,8 +448,9 @@ def main():
     ap.add_argument("--pc-rebuild", default="paired",
                     choices=["per_solve", "per_stage", "across_steps", "paired"],
                     help="BJ_ext builds: the two corrector stages of a sweep solved side by side on one set of "
-                         "blocks built in the first sweep (paired, the default; forms with the learned "
-                         "preconditioner run per_stage), kept per corrector stage across sweeps (per_stage), "
+                         "blocks built in the first sweep (paired, the default; the BJ^H_ext forms and the "
+                         "learned_first / learned_guess variants run per_stage), kept per corrector stage "
+                         "across sweeps (per_stage), "
                          "once per stage solve, or every stage's blocks kept across --pc-reuse-steps time steps")
     ap.add_argument("--pc-reuse-steps", type=int, default=4)
     ap.add_argument("--pc-probe-its", type=int, default=5,

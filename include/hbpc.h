@@ -108,7 +108,9 @@ typedef struct hbpc_ctx hbpc_ctx;
                                       stage's state in the first sweep serve both stages and every
                                       later sweep, and one pass over the blocks applies them to the
                                       four right-hand sides of an iteration; the predictor as
-                                      HBPC_PC_PER_SOLVE.  BJ_ext with the linearised JVP only. */
+                                      HBPC_PC_PER_SOLVE.  BJ_ext or HBPC_PC_LEARNED (each stage
+                                      solve starts on the network and falls back to the shared
+                                      blocks), with the linearised JVP only. */
 
 /* Jacobian-vector product */
 #define HBPC_JVP_LINEARISED 0      /* exact directional derivatives (hyper-dual flux) */
@@ -383,7 +385,9 @@ int hbpc_step(hbpc_ctx* ctx, double* w_inout, double dt, hbpc_stats* stats);
 /* Kernel timing (HIP events recorded around every launch on the context's
  * stream, resolved after synchronisation).  Classes: trace, r1, r2, res, jvp,
  * kcol, pcpre, bj_apply, bj_invert, mdot, gemv, vec, gs_dot, gs_update, lin
- * (x + c R1'(w) s), mlp_feat, mlp_gemm, mlp_vec.  `bytes` and `flops` are
+ * (x + c R1'(w) s), mlp_feat, mlp_gemm, mlp_vec, ns_grad (BR2 face gradients),
+ * bj_apply4 (the apply to the four right-hand sides of two paired stage
+ * systems, HBPC_PC_PAIRED).  `bytes` and `flops` are
  * the algorithmic figures of all recorded launches: inputs read once and
  * outputs written once (bytes), the method's floating-point operations
  * (flops, only for bj_invert and mlp_gemm).  Timing adds a few microseconds per launch. */

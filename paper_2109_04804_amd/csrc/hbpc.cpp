@@ -105,7 +105,7 @@ double now_ms() {
 // ------------------------------------------------------------------ kernel timing
 static const char* KC_NAMES[KC_COUNT] = {"trace",    "r1",        "r2",   "res",  "jvp", "kcol",   "pcpre",
                                          "bj_apply", "bj_invert", "mdot", "gemv", "vec", "gs_dot", "gs_update",
-                                         "lin",      "mlp_feat",  "mlp_gemm", "mlp_vec", "ns_grad"};
+                                         "lin",      "mlp_feat",  "mlp_gemm", "mlp_vec", "ns_grad", "bj_apply4"};
 
 // record a launch of class cls (all classes, or only c->prof_only when that is >= 0)
 static long prof_begin(hbpc_ctx* c, int cls) {
@@ -623,18 +623,20 @@ static void features_p(hbpc_ctx* c, const void* rt, const void* w, const void* d
 }
 
 // gates of the learned preconditioner at linearisation state w (precision f32) and the coefficients
-static void lpc_prepare(hbpc_ctx* c, const void* w, int f32, double a1dt, double bc) {
+static void lpc_prepare(hbpc_ctx* c, const void* w, int f32, double a1dt, double bc, float* G1 = nullptr,
+                        float* G2 = nullptr) {
     lpc_buffers(c);
     c->pc_a1dt = a1dt;
     c->pc_bc = bc;
     const int bf16 = c->prm.mlp_precision == HBPC_MLP_BF16;
     features_p(c, nullptr, w, nullptr, f32, nullptr, c->nE, a1dt, bc, c->ap_X, nullptr, nullptr, 2);
-    mlp_gates(c, c->ap_X, c->nE, c->ap_G1, c->ap_G2, bf16);
+    mlp_gates(c, c->ap_X, c->nE, G1 ? G1 : c->ap_G1, G2 ? G2 : c->ap_G2, bf16);
 }
 
 // Y = P^-1 X with the learned preconditioner, vectors in precision f32, linearisation state w
-// (traces trw) as given to the last lpc_prepare
-static void lpc_apply(hbpc_ctx* c, const void* w, const void* trw, const void* Xv, void* Y, int f32) {
+// (traces trw) and gates G1, G2 (default: the context's) as given to the last lpc_prepare for w
+static void lpc_apply(hbpc_ctx* c, const void* w, const void* trw, const void* Xv, void* Y, int f32,
+                      const float* G1 = nullptr, const float* G2 = nullptr) {
     const size_t esz = f32 ? 4 : 8, n = c->ndof;
     const char* vw = (const char*)Xv;
     const char* vs = vw + n * esz;
@@ -644,7 +646,7 @@ static void lpc_apply(hbpc_ctx* c, const void* w, const void* trw, const void* X
     const int bf16 = c->prm.mlp_precision == HBPC_MLP_BF16;
     op_lin_local(c, w, trw, vs, vw, -c->pc_bc, rt, f32);   // rt = vw - bcoef K vs
     features_p(c, rt, w, nullptr, f32, nullptr, c->nE, c->pc_a1dt, c->pc_bc, c->ap_X, nullptr, c->ap_s, 1);
-    mlp_residual_path(c, c->ap_X, c->nE, c->ap_G1, c->ap_G2, c->ap_H1, c->ap_H2, c->ap_Y, bf16);
+    mlp_residual_path(c, c->ap_X, c->nE, G1 ? G1 : c->ap_G1, G2 ? G2 : c->ap_G2, c->ap_H1, c->ap_H2, c->ap_Y, bf16);
     long pi = prof_begin(c, KC_MLPV);
     hipchk(c, mlp_rescale(c->ap_Y, c->ap_s, yw, f32, (long long)n, c->NE, c->stream), "mlp rescale");
     prof_end(c, pi, KC_MLPV, (double)n * (4.0 + esz) + 4.0 * c->nE);
@@ -711,19 +713,26 @@ static void lpc_collect_krylov(hbpc_ctx* c, const void* w, const void* trw, cons
 }
 
 // Training pairs from the Newton correction just computed: rhs = -G, dX (FP64), state X with traces trw
-static void lpc_collect(hbpc_ctx* c, double a1dt, double bc) {
+static void lpc_collect(hbpc_ctx* c, double a1dt, double bc, const double* X = nullptr, const double* trw = nullptr,
+                        const double* rhs = nullptr, const double* dX = nullptr) {
     if (!c->col_X || c->col_count >= c->col_cap || c->col_source != HBPC_MLP_PAIRS_NEWTON) return;
+    if (!X) {   // the single-stage system
+        X = c->X;
+        trw = c->trw;
+        rhs = c->rhs;
+        dX = c->dX;
+    }
     const size_t n = c->ndof;
     int k = (int)std::min<size_t>((size_t)c->col_per, c->col_cap - c->col_count);
     k = std::min(k, c->nE);
     if (k <= 0) return;
     double* rt = (double*)c->kv;
-    op_lin_local(c, c->X, c->trw, c->rhs + n, c->rhs, -bc, rt, 0);   // rt = rhs_w - bcoef K rhs_s
+    op_lin_local(c, X, trw, rhs + n, rhs, -bc, rt, 0);   // rt = rhs_w - bcoef K rhs_s
     std::vector<int> el;
     draw_distinct(c->col_seed, c->nE, k, el);
     hipchk(c, hipMemcpyAsync(c->col_elems, el.data(), (size_t)k * sizeof(int), hipMemcpyHostToDevice, c->stream),
            "copy");
-    features_p(c, rt, c->X, c->dX, 0, c->col_elems, k, a1dt, bc, c->col_X + c->col_count * c->mlp_nin,
+    features_p(c, rt, X, dX, 0, c->col_elems, k, a1dt, bc, c->col_X + c->col_count * c->mlp_nin,
                c->col_T + c->col_count * c->NE, nullptr, 3);
     hipchk(c, hipStreamSynchronize(c->stream), "sync");   // el is host memory of this frame
     c->col_count += k;
@@ -1053,8 +1062,11 @@ static void newton_solve(hbpc_ctx* c, const double* b, double a1dt, double bc, c
 // HBPC_PC_PAIRED: two corrector stage equations of a sweep (independent, Alg. 1) solved side by
 // side.  Newton and FGMRES iterations advance in lock step; per iteration the PCPRE products of
 // both systems, one pass of bj_apply over the shared S^-1 for the four right-hand sides, then per
-// system the JVP at its own state and the Gram-Schmidt passes.  A system that converges drops out
-// while the other goes on.  Stopping rules as in fgmres() and newton_solve().
+// system the JVP at its own state and the Gram-Schmidt passes, with the next iteration enqueued
+// before the host reads this one's results.  A system that converges drops out while the other
+// goes on.  With the learned preconditioner each system starts its stage solve on the network
+// (gates at its own state) and falls back to the shared BJ_ext blocks on its own.  Stopping
+// rules as in fgmres() and newton_solve().
 static StageSys sys_ctx(hbpc_ctx* c) {
     StageSys S;
     S.X = c->X;
@@ -1075,6 +1087,9 @@ static StageSys sys_ctx(hbpc_ctx* c) {
     S.dgram = c->dgram;
     S.hres = c->hres;
     S.dcount = c->dcount;
+    S.lpc = 0;
+    S.G1 = c->ap_G1;
+    S.G2 = c->ap_G2;
     return S;
 }
 
@@ -1108,7 +1123,7 @@ static void pair_alloc(hbpc_ctx* c) {
 static void pair_free(hbpc_ctx* c) {
     StageSys& P = c->pair;
     void* bufs[] = {P.X, P.G, P.dX, P.rhs, P.b, P.trw, P.trs, P.X32, P.trw32, P.trs32, P.V, P.Z, P.kv,
-                    P.part, P.dres, P.dgram, P.dcount};
+                    P.part, P.dres, P.dgram, P.dcount, P.G1, P.G2};
     for (void* q : bufs) dfree(q);
     if (P.hres) (void)hipHostFree(P.hres);
     std::memset(&P, 0, sizeof(P));
@@ -1145,11 +1160,14 @@ static void fgmres_pair(hbpc_ctx* c, StageSys* S, int* active, double a1dt, doub
     const int m = c->prm.gmres_restart, maxit = c->prm.gmres_maxit;
     const double rtol = c->prm.gmres_rtol;
     const size_t R = (size_t)c->m_alloc + 1;
+    // per system: the current restart cycle (H, Givens rotations, g), iteration j to be read next
+    // and e to be enqueued next (e - j <= 2), and a generation number that marks iterations of
+    // a cycle that has ended (they are discarded)
     struct Cyc {
         std::vector<double> H, cs, sn, g, y;
-        int j = 0, total = 0;
-        double beta0 = 0.0;
-        bool on = false;
+        int j = 0, e = 0, total = 0, cycle = 0, gen = 0, mc = 0;
+        double beta0 = 0.0, beta_cyc = 0.0, fall = 0.0;
+        bool on = false, learned = false;
     } cy[2];
     auto Vj = [&](int i, int j) { return (void*)(S[i].V + (size_t)j * n2 * esz); };
     auto Zj = [&](int i, int j) { return (void*)(S[i].Z + (size_t)j * n2 * esz); };
@@ -1157,7 +1175,8 @@ static void fgmres_pair(hbpc_ctx* c, StageSys* S, int* active, double a1dt, doub
     auto sst = [&](int i) { return f32 ? (const void*)(S[i].X32 + n) : (const void*)(S[i].X + n); };
     auto tw = [&](int i) { return f32 ? (const void*)S[i].trw32 : (const void*)S[i].trw; };
     auto ts = [&](int i) { return f32 ? (const void*)S[i].trs32 : (const void*)S[i].trs; };
-    // a new cycle of system i from the residual in V_0: normalise, reset the Hessenberg data
+    // a new cycle of system i from the residual in V_0: normalise, reset the Hessenberg data; the
+    // learned preconditioner's first cycle may be a shorter probe, judged at the same mean rate
     auto start_cycle = [&](int i) {
         const double beta = dnorm(c, Vj(i, 0), n2, f32);
         if (!std::isfinite(beta)) set_err(c, HBPC_ERR_NONFINITE, "non-finite Krylov residual");
@@ -1169,7 +1188,13 @@ static void fgmres_pair(hbpc_ctx* c, StageSys* S, int* active, double a1dt, doub
         C.g.assign(m + 1, 0.0);
         C.y.assign(m, 0.0);
         C.g[0] = beta;
-        C.j = 0;
+        C.beta_cyc = beta;
+        C.j = C.e = 0;
+        C.gen++;
+        C.learned = S[i].lpc != 0;
+        const int probe = c->prm.pc_probe_its;
+        C.mc = C.learned && C.cycle == 0 && probe > 0 && probe < m ? probe : m;
+        C.fall = C.mc < m ? std::pow(c->prm.pc_fallback, (double)C.mc / m) : c->prm.pc_fallback;
     };
     for (int i = 0; i < 2; ++i) {
         its[i] = 0;
@@ -1182,37 +1207,52 @@ static void fgmres_pair(hbpc_ctx* c, StageSys* S, int* active, double a1dt, doub
         start_cycle(i);
         cy[i].on = true;
     }
-    for (;;) {
-        int on[2], non = 0;
+    // Round r: the next Arnoldi iteration of every system that has one, enqueued without
+    // waiting for the host: z = P^-1 v (the learned systems first, since the network's work
+    // space is the first system's PCPRE buffer; then the PCPRE products of the BJ_ext systems
+    // and one pass of bj_apply over the shared blocks for all their right-hand sides), then per
+    // system u = J z at its own state, the two Gram-Schmidt passes, results to host slot r % 2.
+    struct Round {
+        int cnt = 0, sys[2], it[2], gen[2];
+    } rd[2];
+    auto enqueue = [&](int r) {
+        Round& Rr = rd[r & 1];
+        Rr.cnt = 0;
         for (int i = 0; i < 2; ++i) {
-            on[i] = cy[i].on;
-            non += on[i];
+            Cyc& C = cy[i];
+            if (!C.on || C.e >= C.mc || C.total + (C.e - C.j) >= maxit) continue;
+            Rr.sys[Rr.cnt] = i;
+            Rr.it[Rr.cnt] = C.e++;
+            Rr.gen[Rr.cnt++] = C.gen;
         }
-        if (non == 0) break;
-        // z_j = P^-1 v_j of every running system: one pass over the shared blocks
+        if (Rr.cnt == 0) return false;
+        for (int q = 0; q < Rr.cnt; ++q) {
+            const int i = Rr.sys[q], j = Rr.it[q];
+            if (cy[i].learned) lpc_apply(c, wst(i), tw(i), Vj(i, j), Zj(i, j), f32, S[i].G1, S[i].G2);
+        }
         const void* xs[4];
         void* ys[4];
         int nr = 0;
-        for (int i = 0; i < 2; ++i) {
-            if (!on[i]) continue;
-            const int j = cy[i].j;
+        for (int q = 0; q < Rr.cnt; ++q) {
+            const int i = Rr.sys[q], j = Rr.it[q];
+            if (cy[i].learned) continue;
             pcpre_into(c, wst(i), tw(i), Vj(i, j), S[i].kv, f32);
             xs[nr] = S[i].kv;
             ys[nr++] = Zj(i, j);
             xs[nr] = (const char*)S[i].kv + n * esz;
             ys[nr++] = (char*)Zj(i, j) + n * esz;
         }
-        {
-            long pi = prof_begin(c, KC_BJAPPLY);
+        if (nr > 0) {
+            // one system: the plain apply (w and sigma halves); both: the four-right-hand-side kernel
+            const int cls = nr > 2 ? KC_BJAPPLY4 : KC_BJAPPLY;
+            long pi = prof_begin(c, cls);
             hipchk(c, bj_apply_n(c->Sinv, c->sinv_type, xs, ys, nr, f32, c->NE, c->nE, c->stream), "bj_apply");
-            prof_end(c, pi, KC_BJAPPLY,
+            prof_end(c, pi, cls,
                      (double)c->nE * c->NE * c->NE * (c->sinv_type == 2 ? 2.0 : (c->sinv_type == 1 ? 4.0 : 8.0)) +
                          2.0 * nr * n * esz);
         }
-        // u = J z_j at each system's state, two classical Gram-Schmidt passes (Gram-matrix form)
-        for (int i = 0; i < 2; ++i) {
-            if (!on[i]) continue;
-            const int j = cy[i].j;
+        for (int q = 0; q < Rr.cnt; ++q) {
+            const int i = Rr.sys[q], j = Rr.it[q];
             void* u = Vj(i, j + 1);
             op_jvp(c, wst(i), sst(i), tw(i), ts(i), Zj(i, j), u, a1dt, bc, f32, c->prm.hessian);
             double* h1 = S[i].dres;
@@ -1228,21 +1268,29 @@ static void fgmres_pair(hbpc_ctx* c, StageSys* S, int* active, double a1dt, doub
             hipchk(c, blas_gs_update_normalize(S[i].V, n2, j + 1, h, u, n2, f32, S[i].part, hn, c->stream),
                    "gs update");
             prof_end(c, pi, KC_GSUPD, (j + 5) * vb);
-            hipchk(c, hipMemcpyAsync(S[i].hres, S[i].dres, (3 * R + 4) * sizeof(double), hipMemcpyDeviceToHost,
-                                     c->stream),
+            hipchk(c, hipMemcpyAsync(S[i].hres + c->arn_len * (r & 1), S[i].dres, (3 * R + 4) * sizeof(double),
+                                     hipMemcpyDeviceToHost, c->stream),
                    "copy");
         }
-        hipchk(c, hipEventRecord(c->arn_ev[0], c->stream), "event");
-        hipchk(c, hipEventSynchronize(c->arn_ev[0]), "sync");
-        for (int i = 0; i < 2; ++i) {
-            if (!on[i]) continue;
-            Cyc& C = cy[i];
-            const int j = C.j;
-            auto Hc = [&](int a, int b) -> double& { return C.H[(size_t)a * m + b]; };
-            const double* hr = S[i].hres;
-            for (int a = 0; a <= j; ++a) Hc(a, j) = hr[2 * R + 4 + a];
-            const double hnrm = std::sqrt(hr[2 * R]);
-            if (!std::isfinite(hnrm)) set_err(c, HBPC_ERR_NONFINITE, "non-finite Arnoldi vector");
+        hipchk(c, hipEventRecord(c->arn_ev[r & 1], c->stream), "event");
+        return true;
+    };
+    // the host's part of iteration C.j of system i (slot: its results): Givens rotations, stopping
+    // tests, and at the end of a cycle the update of dX, then a restart or the fallback to BJ_ext
+    auto process = [&](int i, const double* hr) {
+        Cyc& C = cy[i];
+        const int j = C.j;
+        auto Hc = [&](int a, int b) -> double& { return C.H[(size_t)a * m + b]; };
+        for (int a = 0; a <= j; ++a) Hc(a, j) = hr[2 * R + 4 + a];
+        const double hnrm = std::sqrt(hr[2 * R]);
+        bool bad = false, conv = false;
+        int k = j + 1;
+        if (!std::isfinite(hnrm)) {
+            // a non-finite learned-preconditioner output: drop column j and fall back
+            if (!(C.learned && c->prm.pc_fallback > 0)) set_err(c, HBPC_ERR_NONFINITE, "non-finite Arnoldi vector");
+            bad = true;
+            k = j;
+        } else {
             Hc(j + 1, j) = hnrm;
             for (int a = 0; a < j; ++a) {
                 const double t = C.cs[a] * Hc(a, j) + C.sn[a] * Hc(a + 1, j);
@@ -1258,30 +1306,59 @@ static void fgmres_pair(hbpc_ctx* c, StageSys* S, int* active, double a1dt, doub
             C.g[j] = C.cs[j] * C.g[j];
             ++C.total;
             C.j = j + 1;
-            const bool conv = std::fabs(C.g[j + 1]) <= rtol * C.beta0 || hnrm == 0.0;
-            if (!conv && C.j < m && C.total < maxit) continue;
-            // end of the cycle: y = H^-1 g, dX += Z y
-            const int k = C.j;
-            for (int a = k - 1; a >= 0; --a) {
-                double t = C.g[a];
-                for (int l = a + 1; l < k; ++l) t -= Hc(a, l) * C.y[l];
-                C.y[a] = t / Hc(a, a);
-            }
-            hipchk(c, blas_gemv_add(S[i].Z, f32, n2, k, C.y.data(), S[i].dX, 0, n2, c->stream), "update");
-            if (conv) {
-                C.on = false;
-                its[i] = C.total;
-                continue;
-            }
-            if (C.total >= maxit)
-                set_err(c, HBPC_ERR_GMRES, "GMRES did not reach eps_G within " + std::to_string(maxit) + " iterations");
-            // restart: r = rhs - J dX in V_0
-            void* xw = Vj(i, 1);
-            hipchk(c, blas_axpby(1.0, S[i].dX, 0, 0.0, xw, f32, n2, c->stream), "cast");
-            op_jvp(c, wst(i), sst(i), tw(i), ts(i), xw, Vj(i, 0), a1dt, bc, f32, c->prm.hessian);
-            hipchk(c, blas_axpby(1.0, S[i].rhs, 0, -1.0, Vj(i, 0), f32, n2, c->stream), "residual");
-            start_cycle(i);
+            conv = std::fabs(C.g[j + 1]) <= rtol * C.beta0 || hnrm == 0.0;
+            if (!conv && C.j < C.mc && C.total < maxit) return;
         }
+        // end of the cycle: y = H^-1 g, dX += Z y
+        for (int a = k - 1; a >= 0; --a) {
+            double t = C.g[a];
+            for (int l = a + 1; l < k; ++l) t -= Hc(a, l) * C.y[l];
+            C.y[a] = t / Hc(a, a);
+        }
+        if (k > 0) hipchk(c, blas_gemv_add(S[i].Z, f32, n2, k, C.y.data(), S[i].dX, 0, n2, c->stream), "update");
+        if (conv) {
+            C.on = false;
+            its[i] = C.total;
+            return;
+        }
+        if (C.total >= maxit)
+            set_err(c, HBPC_ERR_GMRES, "GMRES did not reach eps_G within " + std::to_string(maxit) + " iterations");
+        ++C.cycle;
+        if (C.learned && c->prm.pc_fallback > 0 && (bad || std::fabs(C.g[k]) > C.fall * C.beta_cyc)) {
+            // BJ_ext takes over for the rest of this stage solve, from the right-hand side
+            S[i].lpc = 0;
+            c->st.pc_fallbacks++;
+            if (c->verbose)
+                std::fprintf(stderr, "[hbpc] (paired) learned preconditioner -> BJ_ext (%s, reduced |r| by %.3e)\n",
+                             bad ? "non-finite" : "slow", std::fabs(C.g[k]) / C.beta_cyc);
+            hipchk(c, hipMemsetAsync(S[i].dX, 0, n2 * 8, c->stream), "memset");
+            hipchk(c, blas_axpby(1.0, S[i].rhs, 0, 0.0, Vj(i, 0), f32, n2, c->stream), "copy");
+            start_cycle(i);
+            return;
+        }
+        // restart: r = rhs - J dX in V_0
+        void* xw = Vj(i, 1);
+        hipchk(c, blas_axpby(1.0, S[i].dX, 0, 0.0, xw, f32, n2, c->stream), "cast");
+        op_jvp(c, wst(i), sst(i), tw(i), ts(i), xw, Vj(i, 0), a1dt, bc, f32, c->prm.hessian);
+        hipchk(c, blas_axpby(1.0, S[i].rhs, 0, -1.0, Vj(i, 0), f32, n2, c->stream), "residual");
+        start_cycle(i);
+    };
+    auto any_on = [&]() { return cy[0].on || cy[1].on; };
+    // one round in flight ahead of the host: round r + 1 is enqueued before round r's results
+    // are read (its iterations are discarded where round r ends a cycle)
+    int r = 0;
+    bool pend = any_on() && enqueue(0);
+    while (pend) {
+        const bool ahead = enqueue(r + 1);
+        hipchk(c, hipEventSynchronize(c->arn_ev[r & 1]), "sync");
+        const Round& Rr = rd[r & 1];
+        for (int q = 0; q < Rr.cnt; ++q) {
+            const int i = Rr.sys[q];
+            if (!cy[i].on || cy[i].gen != Rr.gen[q]) continue;
+            process(i, S[i].hres + c->arn_len * (r & 1));
+        }
+        ++r;
+        pend = ahead || (any_on() && enqueue(r));
     }
 }
 
@@ -1292,6 +1369,15 @@ static void newton_solve_pair(hbpc_ctx* c, const double* const* b, double a1dt, 
     pair_alloc(c);
     const size_t n = c->ndof;
     const int mixed = c->prm.precision == HBPC_MIXED;
+    const bool learned = c->prm.precond == HBPC_PC_LEARNED;
+    if (learned) {
+        if (!c->mlp_ready) set_err(c, HBPC_ERR_ARG, "learned preconditioner without parameters");
+        lpc_buffers(c);
+        if (!c->pair.G1) {   // the second system's gates
+            c->pair.G1 = dalloc<float>(c, (size_t)c->nE * c->mlp_H);
+            c->pair.G2 = dalloc<float>(c, (size_t)c->nE * c->mlp_H);
+        }
+    }
     StageSys S[2] = {sys_ctx(c), c->pair};
     int active[2], its[2] = {0, 0}, gits[2] = {0, 0};
     double n0[2], nw0[2], nr_prev[2];
@@ -1312,12 +1398,18 @@ static void newton_solve_pair(hbpc_ctx* c, const double* const* b, double a1dt, 
                           !c->pc_hess;
         c->pc_kept = kept;
         if (!kept) pc_build(c, S[active[0] ? 0 : 1].X, nullptr, a1dt, bc, mixed);
+        // learned: the network first in each stage solve, BJ_ext (the blocks above) after a fallback
+        for (int i = 0; i < 2; ++i) S[i].lpc = learned && active[i];
     }
     while (active[0] || active[1]) {
         int run[2] = {active[0], active[1]};
         for (int i = 0; i < 2; ++i)
             if (run[i]) {
                 ++its[i];
+                // learned: gates at the system's current linearisation state
+                if (S[i].lpc)
+                    lpc_prepare(c, mixed ? (const void*)S[i].X32 : (const void*)S[i].X, mixed, a1dt, bc, S[i].G1,
+                                S[i].G2);
                 hipchk(c, blas_axpby(-1.0, S[i].G, 0, 0.0, S[i].rhs, 0, c->n2, c->stream), "rhs");
             }
         int git[2];
@@ -1327,6 +1419,7 @@ static void newton_solve_pair(hbpc_ctx* c, const double* const* b, double a1dt, 
         for (int i = 0; i < 2; ++i) {
             if (!run[i]) continue;
             gits[i] += git[i];
+            lpc_collect(c, a1dt, bc, S[i].X, S[i].trw, S[i].rhs, S[i].dX);
             hipchk(c, blas_axpby(1.0, S[i].dX, 0, 1.0, S[i].X, 0, c->n2, c->stream), "update");
             sys_traces(c, S[i], mixed);
             op_res(c, S[i].X, b[i], a1dt, bc, S[i].G, S[i].trw, S[i].trs);
@@ -1593,8 +1686,9 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
         set_err(c, HBPC_ERR_ARG, "unknown precond");
     if (prm->pc_rebuild < HBPC_PC_PER_SOLVE || prm->pc_rebuild > HBPC_PC_PAIRED)
         set_err(c, HBPC_ERR_ARG, "unknown pc_rebuild");
-    if (prm->pc_rebuild == HBPC_PC_PAIRED && (prm->precond != HBPC_PC_BJEXT || prm->jvp_mode != HBPC_JVP_LINEARISED))
-        set_err(c, HBPC_ERR_ARG, "HBPC_PC_PAIRED needs BJ_ext and the linearised JVP");
+    if (prm->pc_rebuild == HBPC_PC_PAIRED && ((prm->precond != HBPC_PC_BJEXT && prm->precond != HBPC_PC_LEARNED) ||
+                                              prm->jvp_mode != HBPC_JVP_LINEARISED))
+        set_err(c, HBPC_ERR_ARG, "HBPC_PC_PAIRED needs BJ_ext or the learned preconditioner and the linearised JVP");
     if (prm->pc_rebuild == HBPC_PC_ACROSS_STEPS && prm->q > 6)
         set_err(c, HBPC_ERR_ARG, "HBPC_PC_ACROSS_STEPS keeps 2 (s - 1) block sets: q <= 6");
     if (prm->pc_rebuild == HBPC_PC_ACROSS_STEPS && prm->pc_reuse_steps < 1)

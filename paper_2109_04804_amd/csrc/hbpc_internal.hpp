@@ -93,6 +93,8 @@ struct StageSys {
     void* kv;                 // PCPRE products a | c (type of the Krylov vectors)
     double *part, *dres, *dgram, *hres;
     unsigned* dcount;
+    int lpc;                  // learned preconditioner active for this system's solve
+    float *G1, *G2;           // its network gates at the current linearisation state
 };
 
 struct hbpc_ctx {
@@ -191,7 +193,7 @@ struct hbpc_ctx {
 };
 
 enum { KC_TRACE = 0, KC_R1, KC_R2, KC_RES, KC_JVP, KC_KCOL, KC_PCPRE, KC_BJAPPLY, KC_BJINV, KC_MDOT, KC_GEMV,
-       KC_VEC, KC_GSDOT, KC_GSUPD, KC_LIN, KC_FEAT, KC_GEMM, KC_MLPV, KC_NSGRAD, KC_COUNT };
+       KC_VEC, KC_GSDOT, KC_GSUPD, KC_LIN, KC_FEAT, KC_GEMM, KC_MLPV, KC_NSGRAD, KC_BJAPPLY4, KC_COUNT };
 
 // helpers implemented in ops.cpp
 int op_launch(hbpc_ctx* c, const LaunchReq& r, int f32);

@@ -59,7 +59,8 @@ def test_host_only_calls():
         assert lib.hbpc_create(ctypes.byref(m), N, 1, ctypes.byref(pa), ctypes.byref(h)) == -7, (dim, N)
     m = hbpc.make_mesh(2, [2, 2], [1.0, 1.0])
     for bad in (dict(gmres_restart=1025), dict(pc_rebuild="paired", precond="none"),
-                dict(pc_rebuild="paired", jvp_mode="fd")):
+                dict(pc_rebuild="paired", jvp_mode="fd"), dict(pc_rebuild="paired", precond="bjext_h"),
+                dict(pc_rebuild="paired", precond="learned_first")):
         pa = hbpc.make_params(flux="upwind", adv=[1.0, 0.5], **bad)
         assert lib.hbpc_create(ctypes.byref(m), 3, 1, ctypes.byref(pa), ctypes.byref(h)) == -1, bad
     pa = hbpc.make_params(flux="upwind", adv=[1.0, 0.5], gmres_restart=1025)
