@@ -230,16 +230,24 @@ template <typename T, bool LOC> struct OpLin {
     }
 };
 
-// elements per block: as many as fit 256 threads and ~64 KB of LDS (EXTRA: bytes per element of
-// LDS beyond the jet fields, fluxes and face fluxes; with it the budget is gfx950's 160 KB)
-template <int D, int NP, int NV, int NJ, int NC, typename T, int EXTRA = 0> constexpr int op_epb() {
-    constexpr int NN = ipow(NP, D), NFP = ipow(NP, D - 1);
-    constexpr int bytes = (NJ * NV * NN + NC * D * NV * NN + NC * 2 * D * NV * NFP) * (int)sizeof(T) + EXTRA + 64;
-    constexpr int budget = EXTRA > 0 ? 159 * 1024 : 65536;
-    constexpr int by_lds = budget / bytes;
-    constexpr int by_thr = 256 / NN;
-    constexpr int e = by_lds < by_thr ? by_lds : by_thr;
-    return e < 1 ? 1 : e;
+// elements per block of the operator kernel: the count (up to 256 threads) that keeps the most
+// waves resident on a CU under gfx950's 160 KB of LDS (per CU and per workgroup), counted up to
+// 12 waves (3 per SIMD: the register budget of the jet kernels, 100-160 VGPRs, allows no more);
+// ties go to more elements per block (fewer idle threads in the face phase).  bytes: LDS per element.
+template <int NN> constexpr int best_epb(int bytes) {
+    int best = 1, best_w = 0;
+    for (int e = 1; e * NN <= 256; ++e) {
+        const int blk = e * bytes + 1024;   // + the 1-D operators
+        if (blk > 163840) break;
+        const int per_cu = 163840 / blk;
+        int w = per_cu * ((e * NN + 63) / 64);
+        if (w > 12) w = 12;
+        if (w >= best_w) {
+            best_w = w;
+            best = e;
+        }
+    }
+    return best;
 }
 
 // Navier-Stokes: number of lifted variables g = (v, T) (0 for the other equations)
@@ -253,8 +261,15 @@ template <int D, int NP, class EQ, class S> constexpr int ns_lds_bytes() {
     constexpr int NN = ipow(NP, D), NFP = ipow(NP, D - 1), NG = eq_ng<EQ>();
     return (NG * NN + NG * 2 * D * NFP + NG * D * NN) * (int)sizeof(S);
 }
+// LDS per element of dg_op_kernel: jet fields, one direction's flux combinations, face-flux
+// combinations, BR1 lifted gradients and u* (viscous Burgers), the BR2 lifting (Navier-Stokes)
 template <int D, int NP, class EQ, class OP, typename T> constexpr int kernel_epb() {
-    return op_epb<D, NP, EQ::NV, OP::NJ, OP::NC, T, ns_lds_bytes<D, NP, EQ, typename OP::S>()>();
+    constexpr int NN = ipow(NP, D), NFP = ipow(NP, D - 1), NV = EQ::NV;
+    constexpr int NQ = EQ::VISC ? OP::NJ : 0;
+    constexpr int bytes = (OP::NJ * NV * NN + OP::NC * NV * NN + OP::NC * 2 * D * NV * NFP + NQ * D * NN +
+                           NQ * 2 * D * NFP) * (int)sizeof(T) +
+                          ns_lds_bytes<D, NP, EQ, typename OP::S>();
+    return best_epb<NN>(bytes);
 }
 // elements per block of the BR2 face-gradient kernel (jet fields and the lifting in LDS)
 template <int D, int NP, class EQ, class OP, typename T> constexpr int aux_epb() {
@@ -665,7 +680,7 @@ __global__ void __launch_bounds__(256) dg_op_kernel(OpArgs<T> a, EqParams<T> ep)
     __shared__ S s_g[NG > 0 ? NG * EPB * NN : 1];
     __shared__ S s_jmp[NG > 0 ? NG * EPB * 2 * D * NFP : 1];
     __shared__ S s_dv[NG > 0 ? NG * D * EPB * NN : 1];
-    __shared__ T s_flx[NC][D][EPB][NV][NN];
+    __shared__ T s_flx[NC][EPB][NV][NN];                 // flux combinations of one direction
     __shared__ T s_fs[NC][EPB][2 * D][NV][NFP];
     __shared__ T s_b[basis_len<NP>()];
     constexpr int NQ = EQ::VISC ? NJ : 0;                 // BR1: lifted gradients of the jet fields
@@ -742,51 +757,7 @@ __global__ void __launch_bounds__(256) dg_op_kernel(OpArgs<T> a, EqParams<T> ep)
         __syncthreads();
     }
 
-    // 2) jet-valued volume fluxes at this node
-    if (valid) {
-        S wn[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            T x[NJ];
-#pragma unroll
-            for (int j = 0; j < NJ; ++j) x[j] = s_fld[j][el][v][node];
-            wn[v] = OP::make(x, a);
-        }
-        S F[D][NV];
-        EQ::flux_all(wn, F, ep);
-        if constexpr (EQ::NS) {
-            // minus the viscous flux of the volume gradient (global lifting)
-            S d[eq_ng<EQ>()][D];
-            ns_volume_grad<D, NP, EQ, OP, T, EPB, NN, NFP>(a, s_b, s_dv, s_jmp, el, node, d);
-#pragma unroll
-            for (int m = 0; m < D; ++m) {
-                S Fv[NV];
-                EQ::viscous_flux(wn, d, m, Fv, ep);
-#pragma unroll
-                for (int v = 0; v < NV; ++v) F[m][v] = F[m][v] - Fv[v];
-            }
-        }
-        if constexpr (EQ::VISC) {
-#pragma unroll
-            for (int m = 0; m < D; ++m) {
-                T x[NJ];
-#pragma unroll
-                for (int j = 0; j < NJ; ++j) x[j] = s_q[((j * D + m) * EPB + el) * NN + node];
-                F[m][0] = F[m][0] - OP::make(x, a) * ep.nu;
-            }
-        }
-#pragma unroll
-        for (int m = 0; m < D; ++m)
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                T c[NC];
-                OP::combo(F[m][v], c, a);
-#pragma unroll
-                for (int k = 0; k < NC; ++k) s_flx[k][m][el][v][node] = c[k];
-            }
-    }
-
-    // 3) numerical fluxes at the face points (own trace from LDS, neighbour trace from HBM); items
+    // 2) numerical fluxes at the face points (own trace from LDS, neighbour trace from HBM); items
     //    ordered (direction, element, side, face point), so that a wave holds one direction (two
     //    where it straddles a direction boundary) and evaluates one flux body per direction
     constexpr int PER_M = 2 * NFP;
@@ -809,34 +780,89 @@ __global__ void __launch_bounds__(256) dg_op_kernel(OpArgs<T> a, EqParams<T> ep)
                                                                side);
         }
     }
-    __syncthreads();
-    if (!valid) return;
 
-    // 4) volume sweep + surface lifting, DG[.] per combination and variable
+    // 3) jet-valued volume fluxes at this node, kept in registers
+    S F[D][NV];
+    if (valid) {
+        S wn[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            T x[NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) x[j] = s_fld[j][el][v][node];
+            wn[v] = OP::make(x, a);
+        }
+        EQ::flux_all(wn, F, ep);
+        if constexpr (EQ::NS) {
+            // minus the viscous flux of the volume gradient (global lifting)
+            S d[eq_ng<EQ>()][D];
+            ns_volume_grad<D, NP, EQ, OP, T, EPB, NN, NFP>(a, s_b, s_dv, s_jmp, el, node, d);
+#pragma unroll
+            for (int m = 0; m < D; ++m) {
+                S Fv[NV];
+                EQ::viscous_flux(wn, d, m, Fv, ep);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) F[m][v] = F[m][v] - Fv[v];
+            }
+        }
+        if constexpr (EQ::VISC) {
+#pragma unroll
+            for (int m = 0; m < D; ++m) {
+                T x[NJ];
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) x[j] = s_q[((j * D + m) * EPB + el) * NN + node];
+                F[m][0] = F[m][0] - OP::make(x, a) * ep.nu;
+            }
+        }
+    }
+
+    // 4) per direction m: the flux combinations of F_m to LDS, then the D-hat sweep along m and the
+    //    surface lifting of faces 2m, 2m+1, summed over m in increasing order
     const int idx[3] = {node % NP, (node / NP) % NP, node / (NP * NP)};
-    T gv[NC];
+    T acc[NV][NC];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int k = 0; k < NC; ++k) acc[v][k] = T(0);
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+        if (m > 0) __syncthreads();   // the previous direction's sweep has read s_flx
+        if (valid) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                T c[NC];
+                OP::combo(F[m][v], c, a);
+#pragma unroll
+                for (int k = 0; k < NC; ++k) s_flx[k][el][v][node] = c[k];
+            }
+        }
+        __syncthreads();   // s_flx of direction m and (first pass) the face fluxes are in LDS
+        if (valid) {
+            const int im = idx[m];
+            const int stride = m == 0 ? 1 : (m == 1 ? NP : NP * NP);
+            const int b0 = node - im * stride;
+            const T* Drow = s_b + BOff<NP>::D + im * NP;
+            const int fp = fp_of_node<D, NP>(node, m);
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    T sm = T(0);
+#pragma unroll
+                    for (int q = 0; q < NP; ++q) sm += Drow[q] * s_flx[k][el][v][b0 + q * stride];
+                    sm += s_b[BOff<NP>::LHP + im] * s_fs[k][el][2 * m + 1][v][fp] -
+                          s_b[BOff<NP>::LHM + im] * s_fs[k][el][2 * m][v][fp];
+                    acc[v][k] += a.two_h[m] * sm;
+                }
+        }
+    }
+    if (!valid) return;
     const int e = e0 + el;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
+        T gv[NC];
 #pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            T acc = T(0);
-#pragma unroll
-            for (int m = 0; m < D; ++m) {
-                const int im = idx[m];
-                const int stride = m == 0 ? 1 : (m == 1 ? NP : NP * NP);
-                const int b0 = node - im * stride;
-                const T* Drow = s_b + BOff<NP>::D + im * NP;
-                T s = T(0);
-#pragma unroll
-                for (int q = 0; q < NP; ++q) s += Drow[q] * s_flx[k][m][el][v][b0 + q * stride];
-                const int fp = fp_of_node<D, NP>(node, m);
-                s += s_b[BOff<NP>::LHP + im] * s_fs[k][el][2 * m + 1][v][fp] -
-                     s_b[BOff<NP>::LHM + im] * s_fs[k][el][2 * m][v][fp];
-                acc += a.two_h[m] * s;
-            }
-            gv[k] = -acc;
-        }
+        for (int k = 0; k < NC; ++k) gv[k] = -acc[v][k];
         const int loc = v * NN + node;
         OP::output(a, (size_t)e * NV * NN + loc, e, loc, gv);
     }

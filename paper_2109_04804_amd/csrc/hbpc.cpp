@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include "hbpc_internal.hpp"
 
 // ------------------------------------------------------------------ tableaux (appendix)
@@ -101,6 +102,17 @@ double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 }  // namespace
+
+// Named host ranges (roctx, seen by rocprofv3 --marker-trace) around the phases of a step: the
+// step, each predictor stage, each corrector sweep, each stage solve (or pair of them) and each
+// BJ_ext build.  Launches are asynchronous, but every Arnoldi iteration waits for its results, so
+// a range's host time follows the GPU work it enqueues.
+struct PhaseRange {
+    explicit PhaseRange(const char* name) { roctxRangePushA(name); }
+    ~PhaseRange() { roctxRangePop(); }
+    PhaseRange(const PhaseRange&) = delete;
+    PhaseRange& operator=(const PhaseRange&) = delete;
+};
 
 // ------------------------------------------------------------------ kernel timing
 static const char* KC_NAMES[KC_COUNT] = {"trace",    "r1",        "r2",   "res",  "jvp", "kcol",   "pcpre",
@@ -327,6 +339,7 @@ static double dnorm(hbpc_ctx* c, const void* x, size_t n, int f32) {
 // ------------------------------------------------------------------ BJ_ext
 // BJ_ext blocks at w, or with sigma given the BJ^H_ext blocks at (w, sigma) (Sec. 3.2.3)
 static void pc_build(hbpc_ctx* c, const double* w, const double* sigma, double a1dt, double bc, int f32) {
+    PhaseRange range("BJ_ext build");
     const bool hess = sigma != nullptr;
     double t0 = now_ms();
     if (c->NE > 1024) set_err(c, HBPC_ERR_UNSUPPORTED, "BJ_ext supports element blocks up to 1024 unknowns");
@@ -986,6 +999,7 @@ static void state_traces(hbpc_ctx* c, int mixed) {
 // as they are.
 static void newton_solve(hbpc_ctx* c, const double* b, double a1dt, double bc, const double* guess, double* out,
                          bool keep_pc = false) {
+    PhaseRange range("stage solve");
     const size_t n = c->ndof;
     const int mixed = c->prm.precision == HBPC_MIXED;
     double* X = c->X;
@@ -1366,6 +1380,7 @@ static void fgmres_pair(hbpc_ctx* c, StageSys* S, int* active, double a1dt, doub
 // active slot's blocks, built for the same coefficients and precision, are used as they are
 static void newton_solve_pair(hbpc_ctx* c, const double* const* b, double a1dt, double bc,
                               const double* const* guess, double* const* out, bool keep_pc) {
+    PhaseRange range("paired stage solves");
     pair_alloc(c);
     const size_t n = c->ndof;
     const int mixed = c->prm.precision == HBPC_MIXED;
@@ -1457,6 +1472,7 @@ static void newton_solve_pair(hbpc_ctx* c, const double* const* b, double a1dt, 
 
 // ------------------------------------------------------------------ HBPC step (Algorithm 1)
 static void hbpc_step_impl(hbpc_ctx* c, double* w_inout, double dt) {
+    PhaseRange range("hbpc_step");
     Tab t;
     if (!tableau(c->prm.q, t)) set_err(c, HBPC_ERR_ARG, "q must be 4, 6 or 8");
     const int s = t.s;
@@ -1474,6 +1490,7 @@ static void hbpc_step_impl(hbpc_ctx* c, double* w_inout, double dt) {
     }
     // predictor: successive two-point Hermite-Birkhoff substeps
     for (int l = 1; l < s; ++l) {
+        PhaseRange stage("predictor stage");
         double dc = t.c[l] - t.c[l - 1];
         double a1dt = dc / 2 * dt;
         double bc = dc * dc / 6 * dt * dt / 2;
@@ -1490,6 +1507,7 @@ static void hbpc_step_impl(hbpc_ctx* c, double* w_inout, double dt) {
     // corrector sweeps: every stage of sweep k uses iterate [k] of all stages
     const bool paired = c->prm.pc_rebuild == HBPC_PC_PAIRED;
     for (int k = 0; k < c->prm.kmax; ++k) {
+        PhaseRange sweep("corrector sweep");
         for (int l = 1; l < s; ++l) {
             double coef1[4], coef2[4];
             for (int j = 0; j < s; ++j) {
