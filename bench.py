@@ -62,16 +62,17 @@ WORKLOADS = {
                                   dt=0.027, equation="euler", field="tgv", eps_ref=0.1),
     # the same workload at its configured acoustic CFL of about 20 (dt = 0.06), with the longer restart
     # that the paper's Euler runs use (Sec. 4.1.2 restarts after 700): FGMRES(200) in FP32, FGMRES(100) in
-    # FP64 (101 + 100 basis vectors of 70.8M FP64 values = 114 GB beside 91 GB of FP64 S^-1 blocks)
+    # FP64 (101 + 100 basis vectors of 70.8M FP64 values = 114 GB beside 91 GB of FP64 S^-1 blocks); one
+    # stage solve at a time (`rebuild`), since a second system's basis would not fit beside them
     "euler_tgv_48x48x48_N3_cfl20": dict(dim=3, nelem=[48, 48, 48], length=[2 * 3.141592653589793] * 3, N=3,
                                         dt=0.06, equation="euler", field="tgv", eps_ref=0.1,
-                                        restart={"fp64": 100, "mixed": 200}),
+                                        restart={"fp64": 100, "mixed": 200}, rebuild="per_stage"),
     # the paper's viscous Taylor-Green vortex (Sec. 5.3.3): Navier-Stokes with BR2 lifting, mu = 1.25e-3
     # (Re = 800), eps = 0.1, N = 3 on 32^3 elements of [0, 2 pi]^3, HBPC(4,0) at dt = 0.25 (acoustic CFL
     # about 56), FGMRES(200) in FP32 / FGMRES(100) in FP64
     "ns_tgv_32x32x32_N3": dict(dim=3, nelem=[32, 32, 32], length=[2 * 3.141592653589793] * 3, N=3, dt=0.25,
                                equation="navier_stokes", field="tgv", eps_ref=0.1, mu=1.25e-3, q=4, kmax=0,
-                               restart={"fp64": 100, "mixed": 200}),
+                               restart={"fp64": 100, "mixed": 200}, rebuild="per_stage"),
     # the same at a tenth of the step (acoustic CFL about 5.6) with the bench's HBPC(6,4)
     "ns_tgv_32x32x32_N3_dt0025": dict(dim=3, nelem=[32, 32, 32], length=[2 * 3.141592653589793] * 3, N=3,
                                       dt=0.025, equation="navier_stokes", field="tgv", eps_ref=0.1, mu=1.25e-3),
@@ -445,10 +446,11 @@ def main():
                          "(as mixed with the BJ_ext blocks stored in FP16), fp64_h / mixed_h (as fp64 / mixed "
                          "with BJ^H_ext)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--pc-rebuild", default="paired",
+    ap.add_argument("--pc-rebuild", default=None,
                     choices=["per_solve", "per_stage", "across_steps", "paired"],
                     help="BJ_ext builds: the two corrector stages of a sweep solved side by side on one set of "
-                         "blocks built in the first sweep (paired, the default; the BJ^H_ext forms and the "
+                         "blocks built in the first sweep (paired, the default except on the workloads with "
+                         "FGMRES(100/200), whose basis leaves no room for a second system; the BJ^H_ext forms and the "
                          "learned_first / learned_guess variants run per_stage), kept per corrector stage "
                          "across sweeps (per_stage), "
                          "once per stage solve, or every stage's blocks kept across --pc-reuse-steps time steps")
@@ -493,6 +495,8 @@ def main():
         del src, dst
         print("[bench] reference copy of %d bytes done" % a.copy_bytes, file=sys.stderr, flush=True)
     wl = WORKLOADS[a.workload]
+    if a.pc_rebuild is None:   # paired unless the workload's Krylov basis leaves no room for a second system
+        a.pc_rebuild = wl.get("rebuild", "paired")
     forms = [f for f in a.forms.split(",") if f]
     for f in forms:
         form_settings(f)   # an unknown form fails before any form runs
