@@ -52,12 +52,12 @@ def host(t):
 
 
 def bench_context(dim, nelem, length, N, precision, precond, newton_rtol, eps_ref=1.0, probe=0, restart=30,
-                  rebuild="paired"):
+                  rebuild="paired", half=False):
     from paper_2109_04804_amd.hbpc import Context
     return Context(dim, nelem, length, N, "euler", flux="rusanov", gamma=1.4, eps_ref=eps_ref, q=6, kmax=4,
                    newton_rtol=newton_rtol, gmres_rtol=1e-3, gmres_restart=restart, gmres_maxit=7000,
                    precision=precision, precond=precond, pc_rebuild=rebuild, pc_fallback=0.5,
-                   pc_probe_its=probe)
+                   pc_probe_its=probe, pc_half=1 if half else 0)
 
 
 _THETA = {}
@@ -97,20 +97,21 @@ def trained_params(n):
 
 
 @pytest.mark.parametrize("rebuild", ["paired", "per_stage"])
-@pytest.mark.parametrize("form", ["fp64", "mixed", "learned"])
+@pytest.mark.parametrize("form", ["fp64", "mixed", "learned", "mixed16"])
 def test_vortex_step_bench_composition(form, rebuild):
     """paired (the benchmark's default, HBPC_PC_PAIRED): lock-step Newton and FGMRES iterations
     of the two corrector stages of a sweep, one S^-1 set built at the first stage's state and
     applied to both stages' four right-hand sides per iteration, the next Arnoldi iteration of
     both in flight ahead of the host; in the learned form each stage solve starts on the network
     and falls back to the shared blocks on its own.  per_stage: one stage solve at a time, blocks
-    kept per corrector stage over the sweeps."""
+    kept per corrector stage over the sweeps.  mixed16: the mixed form with the S^-1 blocks
+    stored in FP16 (the paired apply reads each FP16 block once for four right-hand sides)."""
     w0, ref, meta = golden.load("vortex8")
     n = meta["nelem"][0]
     precision = "fp64" if form == "fp64" else "mixed"
     rtol = 1e-12 if form == "fp64" else 1e-8
     ctx = bench_context(2, [n, n], [10.0, 10.0], 5, precision, "learned" if form == "learned" else "bjext", rtol,
-                        probe=5 if form == "learned" else 0, rebuild=rebuild)
+                        probe=5 if form == "learned" else 0, rebuild=rebuild, half=form == "mixed16")
     if form == "learned":
         ctx.mlp_set_params(trained_params(n))
     w = dev(w0)
