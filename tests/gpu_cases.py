@@ -32,6 +32,9 @@ CASES = {
     # 3-D eps-scaled Euler (eps = 0.1), N = 3 as in the Taylor-Green workload
     "euler3_n3": dict(dim=3, nelem=[3, 4, 5], length=[TWO_PI] * 3, N=3, equation="euler", nodes="gauss",
                       flux="rusanov", eps_ref=0.1),
+    # 27 elements: not a multiple of the operator kernel's 4 elements per block (ragged last block)
+    "euler3_n3_odd": dict(dim=3, nelem=[3, 3, 3], length=[TWO_PI] * 3, N=3, equation="euler", nodes="gauss",
+                          flux="rusanov", eps_ref=0.1),
     # element blocks above the register kernel's 144 unknowns: 216 (ragged panel and tile) and
     # 625 (odd: padded LDS pitch)
     "adv3_n5": dict(dim=3, nelem=[2, 3, 2], length=[1.0, 1.0, 1.0], N=5, equation="advection", nodes="gauss",
@@ -56,6 +59,9 @@ CASES = {
                 flux="rusanov", mu=0.05),
     "ns3": dict(dim=3, nelem=[3, 2, 2], length=[TWO_PI] * 3, N=3, equation="navier_stokes", nodes="gauss",
                 flux="rusanov", mu=0.02, eps_ref=0.5),
+    # 18 elements: a ragged last block of the operator and face-gradient kernels
+    "ns3_odd": dict(dim=3, nelem=[3, 3, 2], length=[TWO_PI] * 3, N=3, equation="navier_stokes", nodes="gauss",
+                    flux="rusanov", mu=0.02, eps_ref=0.5),
     "ns2_lobatto_lfl": dict(dim=2, nelem=[3, 4], length=[TWO_PI, TWO_PI], N=3, equation="navier_stokes",
                             nodes="lobatto", flux="lf_literal", mu=0.1, eta_br2=3.0),
     # degenerate: one element per direction (every neighbour is the element itself)

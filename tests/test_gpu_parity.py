@@ -121,7 +121,8 @@ def test_jvp_fp64(name, hessian):
     assert rel(host(out), np.concatenate([Jw.ravel(), Js.ravel()])) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["euler2_n5", "euler3_n3", "adv2_ragged", "euler2_single", "burgers2", "ns2", "ns3"])
+@pytest.mark.parametrize("name", ["euler2_n5", "euler3_n3", "euler3_n3_odd", "adv2_ragged", "euler2_single", "burgers2",
+                                  "ns2", "ns3", "ns3_odd"])
 def test_jvp_fp32(name):
     case, dg, ctx = setup(name)
     f32 = lambda x: np.asarray(x, dtype=np.float32).astype(np.float64)
