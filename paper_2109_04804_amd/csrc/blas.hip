@@ -5,6 +5,8 @@
 // a fixed set of indices in a fixed order, partial results are combined by
 // one block in a fixed tree, so two runs give bitwise equal results.
 #include <hip/hip_runtime.h>
+#include <type_traits>
+#include <algorithm>
 #include <cstddef>
 #include <cstdint>
 
@@ -32,12 +34,12 @@ template <typename T> __device__ __forceinline__ double block_sum(double v, doub
 // Grid-wide "last block" hand-over: every block publishes its result, then takes a ticket; the
 // block with the last ticket sees every published result (device-scope fences around the ticket)
 // and finishes the reduction, then rewinds the counter for the next launch.
-__device__ __forceinline__ bool last_block(unsigned* counter) {
+__device__ __forceinline__ bool last_block(unsigned* counter, unsigned nblocks) {
     __shared__ bool last;
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
-        last = atomicAdd(counter, 1u) == gridDim.x - 1;
+        last = atomicAdd(counter, 1u) == nblocks - 1;
     }
     __syncthreads();
     if (last) __threadfence();
@@ -116,12 +118,24 @@ __global__ void __launch_bounds__(BLAS_THREADS) mdot_kernel(const T* __restrict_
 
 // column c0 + j of the block partials (layout as for mdot_kernel): sum V_j[i] w1[i]; column
 // off2 + c0 + j: sum V_j[i] w2[i], for j < kc (<= MDOT2_CHUNK): the projections of a new vector and
-// the Gram column of the newest basis vector in one pass over V
+// the Gram column of the newest basis vector in one pass over V.  blockIdx.y selects the system
+// (g0, or g1 for the second system of a pair of stage solves); kc = 0: no work for it.
+template <typename T> struct GramSys {
+    const T* V;
+    const T* w1;
+    const T* w2;
+    double* part;
+    int kc, c0, off2;
+};
+
 template <typename T, int VEC>
-__global__ void __launch_bounds__(BLAS_THREADS) mdot2_kernel(const T* __restrict__ V, size_t ld, int kc,
-                                                             const T* __restrict__ w1, const T* __restrict__ w2,
-                                                             size_t n, double* __restrict__ part, int c0,
-                                                             int off2) {
+__global__ void __launch_bounds__(BLAS_THREADS) mdot2_kernel(GramSys<T> g0, GramSys<T> g1, size_t ld, size_t n) {
+    const GramSys<T>& g = blockIdx.y ? g1 : g0;
+    const int kc = g.kc;
+    if (kc <= 0) return;
+    const T* __restrict__ V = g.V;
+    const T* __restrict__ w1 = g.w1;
+    const T* __restrict__ w2 = g.w2;
     __shared__ double shw[BLAS_THREADS / 64][2 * MDOT2_CHUNK];
     double a1[MDOT2_CHUNK], a2[MDOT2_CHUNK];
 #pragma unroll
@@ -166,27 +180,39 @@ __global__ void __launch_bounds__(BLAS_THREADS) mdot2_kernel(const T* __restrict
         const int j = threadIdx.x < kc ? threadIdx.x : threadIdx.x - kc + MDOT2_CHUNK;
         double r = 0.0;
         for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += shw[i][j];
-        const int col = c0 + (threadIdx.x < kc ? threadIdx.x : off2 + threadIdx.x - kc);
-        part[(size_t)col * gridDim.x + blockIdx.x] = r;
+        const int col = g.c0 + (threadIdx.x < kc ? threadIdx.x : g.off2 + threadIdx.x - kc);
+        g.part[(size_t)col * gridDim.x + blockIdx.x] = r;
     }
 }
 
 // out[j] = sum_b part[j * nb + b] for the 2k columns j = blockIdx.x (out = h1 | g); then the last
 // block forms the Gram-Schmidt coefficients of both passes: with G = V^T V (column k-1 = g, stored
 // symmetric, leading dimension ldg) and h1 = V^T u, the second classical pass V^T (u - V h1) =
-// h1 - G h1, so the two passes together subtract V h with h = 2 h1 - G h1.
-__global__ void __launch_bounds__(BLAS_THREADS) reduce_gram_kernel(const double* part, int nb, double* out, int k,
-                                                                   double* G, int ldg, double* h,
-                                                                   unsigned* counter) {
+// h1 - G h1, so the two passes together subtract V h with h = 2 h1 - G h1.  blockIdx.y selects the
+// system; blocks beyond its 2k columns take no part (nor a ticket).
+struct RedSys {
+    const double* part;
+    double* out;
+    int k;
+    double* G;
+    double* h;
+    unsigned* counter;
+};
+
+__global__ void __launch_bounds__(BLAS_THREADS) reduce_gram_kernel(RedSys r0, RedSys r1, int nb, int ldg) {
+    const RedSys& r = blockIdx.y ? r1 : r0;
+    const int k = r.k;
+    if ((int)blockIdx.x >= 2 * k) return;
     __shared__ double sh[BLAS_THREADS / 64];
     const int j = blockIdx.x;
     double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(size_t)j * nb + b];
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += r.part[(size_t)j * nb + b];
     s = block_sum<double>(s, sh);
-    if (threadIdx.x == 0) out[j] = s;
-    if (!last_block(counter)) return;
-    const double* h1 = out;
-    const double* g = out + k;
+    if (threadIdx.x == 0) r.out[j] = s;
+    if (!last_block(r.counter, 2u * k)) return;
+    const double* h1 = r.out;
+    const double* g = r.out + k;
+    double* G = r.G;
     const int jj = k - 1;
     for (int i = threadIdx.x; i <= jj; i += blockDim.x) {
         G[(size_t)i * ldg + jj] = g[i];
@@ -196,9 +222,9 @@ __global__ void __launch_bounds__(BLAS_THREADS) reduce_gram_kernel(const double*
     for (int i = threadIdx.x; i <= jj; i += blockDim.x) {
         double t = 0.0;
         for (int l = 0; l <= jj; ++l) t += G[(size_t)i * ldg + l] * h1[l];
-        h[i] = 2.0 * h1[i] - t;
+        r.h[i] = 2.0 * h1[i] - t;
     }
-    if (threadIdx.x == 0) *counter = 0u;
+    if (threadIdx.x == 0) *r.counter = 0u;
 }
 
 // out[j] = scale * sum_b part[j * nb + b]; one block per j
@@ -263,15 +289,27 @@ __global__ void __launch_bounds__(BLAS_THREADS) nonfinite_kernel(const T* __rest
 // ------------------------------------------------------------------ Gram-Schmidt passes
 // w[i] -= sum_j h[j] V_j[i] and a per-block partial of ||w||^2 (part[blockIdx.x]); VEC values per
 // load (n and ld multiples of VEC).  (A last-block final sum here costs more than a second launch:
-// the device-scope release of each block writes back the freshly updated w from L2.)
+// the device-scope release of each block writes back the freshly updated w from L2.)  blockIdx.y
+// selects the system (k = 0: none).
+template <typename T> struct UpdSys {
+    const T* V;
+    int k;
+    const double* h;
+    T* w;
+    double* part;
+};
+
 template <typename T, int VEC>
-__global__ void __launch_bounds__(BLAS_THREADS) gemv_sub_norm_kernel(const T* __restrict__ V, size_t ld, int k,
-                                                                     const double* __restrict__ h,
-                                                                     T* __restrict__ w, size_t n,
-                                                                     double* __restrict__ part) {
+__global__ void __launch_bounds__(BLAS_THREADS) gemv_sub_norm_kernel(UpdSys<T> u0, UpdSys<T> u1, size_t ld,
+                                                                     size_t n) {
+    const UpdSys<T>& u = blockIdx.y ? u1 : u0;
+    const int k = u.k;
+    if (k <= 0) return;
+    const T* __restrict__ V = u.V;
+    T* __restrict__ w = u.w;
     __shared__ double sh[GS_MAXK];
     __shared__ double red[BLAS_THREADS / 64];
-    for (int j = threadIdx.x; j < k; j += blockDim.x) sh[j] = h[j];
+    for (int j = threadIdx.x; j < k; j += blockDim.x) sh[j] = u.h[j];
     __syncthreads();
     double nrm = 0.0;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -295,23 +333,31 @@ __global__ void __launch_bounds__(BLAS_THREADS) gemv_sub_norm_kernel(const T* __
         vstore<T, VEC>(w + i * VEC, wv);
     }
     double t = block_sum<double>(nrm, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
+    if (threadIdx.x == 0) u.part[blockIdx.x] = t;
 }
 
 // hn = sum of the nb block partials of ||u||^2 (every block forms the same sum in the same fixed
-// order; block 0 stores it in nrm2[0]), then u /= sqrt(hn) (u unchanged when hn is 0)
+// order; block 0 stores it in nrm2[0]), then u /= sqrt(hn) (u unchanged when hn is 0);
+// blockIdx.y selects the system (null u: none)
+template <typename T> struct ScaleSys {
+    T* u;
+    const double* part;
+    double* nrm2;
+};
+
 template <typename T>
-__global__ void __launch_bounds__(BLAS_THREADS) sum_scale_kernel(T* __restrict__ u, size_t n,
-                                                                 const double* __restrict__ part, int nb,
-                                                                 double* __restrict__ nrm2) {
+__global__ void __launch_bounds__(BLAS_THREADS) sum_scale_kernel(ScaleSys<T> s0, ScaleSys<T> s1, size_t n, int nb) {
+    const ScaleSys<T>& sc_ = blockIdx.y ? s1 : s0;
+    if (!sc_.u) return;
+    T* __restrict__ u = sc_.u;
     __shared__ double red[BLAS_THREADS / 64];
     __shared__ double hn_s;
     double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[b];
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += sc_.part[b];
     s = block_sum<double>(s, red);
     if (threadIdx.x == 0) {
         hn_s = s;
-        if (blockIdx.x == 0) nrm2[0] = s;
+        if (blockIdx.x == 0) sc_.nrm2[0] = s;
     }
     __syncthreads();
     const double hn = hn_s;
@@ -367,64 +413,114 @@ hipError_t blas_mdot(const void* V, size_t ld, int k, const void* w, size_t n, i
 
 // u -= V h (k columns, h on the device), nrm2[0] = ||u||^2, u /= ||u||: the Arnoldi update of
 // a new basis vector.  part: blas_grid(n) doubles.
-hipError_t blas_gs_update_normalize(const void* V, size_t ld, int k, const double* h, void* u, size_t n, int f32,
-                                    double* part, double* nrm2, hipStream_t st) {
-    if (k > GS_MAXK) return hipErrorInvalidValue;
-    const int vec = vec_of(n, ld, f32, V, u);
-    int g = blas_grid(n / vec);
-    if (f32 && vec == 4)
-        hipLaunchKernelGGL((gemv_sub_norm_kernel<float, 4>), dim3(g), dim3(BLAS_THREADS), 0, st, (const float*)V, ld,
-                           k, h, (float*)u, n, part);
-    else if (f32)
-        hipLaunchKernelGGL((gemv_sub_norm_kernel<float, 1>), dim3(g), dim3(BLAS_THREADS), 0, st, (const float*)V, ld,
-                           k, h, (float*)u, n, part);
-    else if (vec == 2)
-        hipLaunchKernelGGL((gemv_sub_norm_kernel<double, 2>), dim3(g), dim3(BLAS_THREADS), 0, st, (const double*)V,
-                           ld, k, h, (double*)u, n, part);
-    else
-        hipLaunchKernelGGL((gemv_sub_norm_kernel<double, 1>), dim3(g), dim3(BLAS_THREADS), 0, st, (const double*)V,
-                           ld, k, h, (double*)u, n, part);
-    const int g2 = blas_grid(n);
-    if (f32)
-        hipLaunchKernelGGL(sum_scale_kernel<float>, dim3(g2), dim3(BLAS_THREADS), 0, st, (float*)u, n, part, g, nrm2);
-    else
-        hipLaunchKernelGGL(sum_scale_kernel<double>, dim3(g2), dim3(BLAS_THREADS), 0, st, (double*)u, n, part, g,
-                           nrm2);
+// For s < ns (1 or 2) systems: u_s -= V_s h_s (k_s columns), then u_s /= ||u_s|| (||u_s||^2 in
+// nrm2_s[0]); one launch of each kernel for all systems.  part_s: grid doubles each.
+hipError_t blas_gs_update_normalize_n(int ns, const void* const* V, size_t ld, const int* k, const double* const* h,
+                                      void* const* u, size_t n, int f32, double* const* part,
+                                      double* const* nrm2, hipStream_t st) {
+    int vec = f32 ? 4 : 2;
+    for (int i = 0; i < ns; ++i) {
+        if (k[i] > GS_MAXK) return hipErrorInvalidValue;
+        vec = std::min(vec, vec_of(n, ld, f32, V[i], u[i]));
+    }
+    const int g = blas_grid(n / vec);
+    const dim3 gd(g, ns);
+    if (f32) {
+        UpdSys<float> a[2] = {};
+        ScaleSys<float> b[2] = {};
+        for (int i = 0; i < ns; ++i) {
+            a[i] = UpdSys<float>{(const float*)V[i], k[i], h[i], (float*)u[i], part[i]};
+            b[i] = ScaleSys<float>{(float*)u[i], part[i], nrm2[i]};
+        }
+        if (vec == 4)
+            hipLaunchKernelGGL((gemv_sub_norm_kernel<float, 4>), gd, dim3(BLAS_THREADS), 0, st, a[0], a[1], ld, n);
+        else
+            hipLaunchKernelGGL((gemv_sub_norm_kernel<float, 1>), gd, dim3(BLAS_THREADS), 0, st, a[0], a[1], ld, n);
+        hipLaunchKernelGGL(sum_scale_kernel<float>, dim3(blas_grid(n), ns), dim3(BLAS_THREADS), 0, st, b[0], b[1], n,
+                           g);
+    } else {
+        UpdSys<double> a[2] = {};
+        ScaleSys<double> b[2] = {};
+        for (int i = 0; i < ns; ++i) {
+            a[i] = UpdSys<double>{(const double*)V[i], k[i], h[i], (double*)u[i], part[i]};
+            b[i] = ScaleSys<double>{(double*)u[i], part[i], nrm2[i]};
+        }
+        if (vec == 2)
+            hipLaunchKernelGGL((gemv_sub_norm_kernel<double, 2>), gd, dim3(BLAS_THREADS), 0, st, a[0], a[1], ld, n);
+        else
+            hipLaunchKernelGGL((gemv_sub_norm_kernel<double, 1>), gd, dim3(BLAS_THREADS), 0, st, a[0], a[1], ld, n);
+        hipLaunchKernelGGL(sum_scale_kernel<double>, dim3(blas_grid(n), ns), dim3(BLAS_THREADS), 0, st, b[0], b[1], n,
+                           g);
+    }
     return hipGetLastError();
 }
 
-// h1[i] = V_i . w1 and g[i] = V_i . w2 for i < k, then the combined two-pass coefficients
-// h = 2 h1 - G h1 with G's column k-1 set from g (G: device, ldg x ldg).  part: grid * 2k doubles;
-// counter: a device word that is 0 between launches.
+hipError_t blas_gs_update_normalize(const void* V, size_t ld, int k, const double* h, void* u, size_t n, int f32,
+                                    double* part, double* nrm2, hipStream_t st) {
+    return blas_gs_update_normalize_n(1, &V, ld, &k, &h, &u, n, f32, &part, &nrm2, st);
+}
+
+// For s < ns (1 or 2) systems: h1_s[i] = V_s,i . w1_s and g_s[i] = V_s,i . w2_s for i < k_s, then the
+// combined two-pass coefficients h_s = 2 h1_s - G_s h1_s with G_s's column k_s-1 set from g_s
+// (G_s: device, ldg x ldg); one launch per chunk of MDOT2_CHUNK columns for all systems and one
+// reduction launch.  part_s: grid * 2k_s doubles; counter_s: a device word that is 0 between launches.
+hipError_t blas_gs_gram_n(int ns, const void* const* V, size_t ld, const int* k, const void* const* w1,
+                          const void* const* w2, size_t n, int f32, double* const* part, double* const* h1,
+                          double* const* G, int ldg, double* const* h, unsigned* const* counter, hipStream_t st) {
+    int vec = f32 ? 4 : 2, kmax = 0;
+    for (int i = 0; i < ns; ++i) {
+        if (k[i] > GS_MAXK || k[i] > ldg) return hipErrorInvalidValue;
+        vec = std::min(vec, std::min(vec_of(n, ld, f32, V[i], w1[i]), vec_of(n, ld, f32, V[i], w2[i])));
+        kmax = std::max(kmax, k[i]);
+    }
+    const int gr = blas_grid(n / vec, MDOT_GRID);
+    for (int j0 = 0; j0 < kmax; j0 += MDOT2_CHUNK) {
+        const size_t es = f32 ? 4 : 8;
+        auto sys = [&](int i, auto* tp) {
+            using T = std::remove_pointer_t<decltype(tp)>;
+            GramSys<T> q{};
+            if (i < ns && j0 < k[i]) {
+                q.V = (const T*)((const char*)V[i] + (size_t)j0 * ld * es);
+                q.w1 = (const T*)w1[i];
+                q.w2 = (const T*)w2[i];
+                q.part = part[i];
+                q.kc = std::min(MDOT2_CHUNK, k[i] - j0);
+                q.c0 = j0;
+                q.off2 = k[i];
+            }
+            return q;
+        };
+        const dim3 gd(gr, ns);
+        if (f32) {
+            float* tag = nullptr;
+            if (vec == 4)
+                hipLaunchKernelGGL((mdot2_kernel<float, 4>), gd, dim3(BLAS_THREADS), 0, st, sys(0, tag), sys(1, tag),
+                                   ld, n);
+            else
+                hipLaunchKernelGGL((mdot2_kernel<float, 1>), gd, dim3(BLAS_THREADS), 0, st, sys(0, tag), sys(1, tag),
+                                   ld, n);
+        } else {
+            double* tag = nullptr;
+            if (vec == 2)
+                hipLaunchKernelGGL((mdot2_kernel<double, 2>), gd, dim3(BLAS_THREADS), 0, st, sys(0, tag),
+                                   sys(1, tag), ld, n);
+            else
+                hipLaunchKernelGGL((mdot2_kernel<double, 1>), gd, dim3(BLAS_THREADS), 0, st, sys(0, tag),
+                                   sys(1, tag), ld, n);
+        }
+    }
+    // h1 = part columns 0..k-1, g = columns k..2k-1 (h1 and g adjacent: g = h1 + k)
+    RedSys r[2] = {};
+    for (int i = 0; i < ns; ++i) r[i] = RedSys{part[i], h1[i], k[i], G[i], h[i], counter[i]};
+    hipLaunchKernelGGL(reduce_gram_kernel, dim3(2 * kmax, ns), dim3(BLAS_THREADS), 0, st, r[0], r[1], gr, ldg);
+    return hipGetLastError();
+}
+
 hipError_t blas_gs_gram(const void* V, size_t ld, int k, const void* w1, const void* w2, size_t n, int f32,
                         double* part, double* h1, double* g, double* G, int ldg, double* h, unsigned* counter,
                         hipStream_t st) {
-    if (k > GS_MAXK || k > ldg || g != h1 + k) return hipErrorInvalidValue;
-    const int vec = (vec_of(n, ld, f32, V, w1) == vec_of(n, ld, f32, V, w2)) ? vec_of(n, ld, f32, V, w1) : 1;
-    int gr = blas_grid(n / vec, MDOT_GRID);
-    for (int j0 = 0; j0 < k; j0 += MDOT2_CHUNK) {
-        int kc = k - j0 < MDOT2_CHUNK ? k - j0 : MDOT2_CHUNK;
-        if (f32 && vec == 4)
-            hipLaunchKernelGGL((mdot2_kernel<float, 4>), dim3(gr), dim3(BLAS_THREADS), 0, st,
-                               (const float*)V + j0 * ld, ld, kc, (const float*)w1, (const float*)w2, n, part, j0,
-                               k);
-        else if (f32)
-            hipLaunchKernelGGL((mdot2_kernel<float, 1>), dim3(gr), dim3(BLAS_THREADS), 0, st,
-                               (const float*)V + j0 * ld, ld, kc, (const float*)w1, (const float*)w2, n, part, j0,
-                               k);
-        else if (vec == 2)
-            hipLaunchKernelGGL((mdot2_kernel<double, 2>), dim3(gr), dim3(BLAS_THREADS), 0, st,
-                               (const double*)V + j0 * ld, ld, kc, (const double*)w1, (const double*)w2, n,
-                               part, j0, k);
-        else
-            hipLaunchKernelGGL((mdot2_kernel<double, 1>), dim3(gr), dim3(BLAS_THREADS), 0, st,
-                               (const double*)V + j0 * ld, ld, kc, (const double*)w1, (const double*)w2, n,
-                               part, j0, k);
-    }
-    // h1 = part columns 0..k-1, g = columns k..2k-1 (h1 and g adjacent: g = h1 + k)
-    hipLaunchKernelGGL(reduce_gram_kernel, dim3(2 * k), dim3(BLAS_THREADS), 0, st, part, gr, h1, k, G, ldg, h,
-                       counter);
-    return hipGetLastError();
+    if (g != h1 + k) return hipErrorInvalidValue;
+    return blas_gs_gram_n(1, &V, ld, &k, &w1, &w2, n, f32, &part, &h1, &G, ldg, &h, &counter, st);
 }
 
 // type codes: 0 = double, 1 = float

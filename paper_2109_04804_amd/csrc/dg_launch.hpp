@@ -34,6 +34,7 @@ struct LaunchReq {
     int col;
     int e_begin, e_end;   // element range (e_end <= 0: whole mesh)
     hipStream_t stream;
+    const LaunchReq* pair;   // the same op on a second system's arrays in the same launch (or null)
 };
 
 template <typename T> const T* basis_ptr(const GeomHost& g);
@@ -108,8 +109,11 @@ hipError_t launch_op(const GeomHost& g, const LaunchReq& r) {
     OpArgs<T> a = make_args<T>(g, r);
     int grid = (a.e_end - a.e_begin + EPB - 1) / EPB;
     if (grid <= 0) return hipSuccess;
-    dim3 gd(grid, (r.op == OPK_KCOL || r.op == OPK_KHCOL) ? EQ::NV * NN : 1);   // one grid row per column
-    hipLaunchKernelGGL((dg_op_kernel<D, NP, EQ, OP, T>), gd, dim3(EPB * NN), 0, r.stream, a, make_eq<T>(g));
+    OpArgs<T> a1 = r.pair ? make_args<T>(g, *r.pair) : a;
+    const int grid1 = r.pair ? (a1.e_end - a1.e_begin + EPB - 1) / EPB : 0;
+    dim3 gd(grid + grid1, (r.op == OPK_KCOL || r.op == OPK_KHCOL) ? EQ::NV * NN : 1);   // one grid row per column
+    hipLaunchKernelGGL((dg_op_kernel<D, NP, EQ, OP, T>), gd, dim3(EPB * NN), 0, r.stream, a, make_eq<T>(g), a1,
+                       grid);
     return hipGetLastError();
 }
 
@@ -122,8 +126,10 @@ template <int D, int NP, class EQ, typename T> hipError_t launch_family_np(const
         int grid = (g.nE + EPB - 1) / EPB;
         if (grid == 0) return hipSuccess;
         const int nf = r.col > 1 ? r.col : 1;   // consecutive fields (col = their number)
-        hipLaunchKernelGGL((trace_kernel<D, NP, NV, T>), dim3(grid, nf), dim3(EPB * NN), 0, r.stream,
-                           (const T*)r.fld[0], (T*)r.out[0], g.nE, basis_ptr<T>(g));
+        const T* x2 = r.pair ? (const T*)r.pair->fld[0] : (const T*)r.fld[0];
+        T* tr2 = r.pair ? (T*)r.pair->out[0] : (T*)r.out[0];
+        hipLaunchKernelGGL((trace_kernel<D, NP, NV, T>), dim3(grid, nf, r.pair ? 2 : 1), dim3(EPB * NN), 0, r.stream,
+                           (const T*)r.fld[0], (T*)r.out[0], g.nE, basis_ptr<T>(g), x2, tr2);
         return hipGetLastError();
     }
     case OPK_R1: return launch_op<D, NP, EQ, OpR1<T>, T>(g, r);

@@ -284,7 +284,7 @@ template <int D, int NP, class EQ, class OP, typename T> constexpr int aux_epb()
 // ----------------------------------------------------------------- trace kernel
 template <int D, int NP, int NV, typename T>
 __global__ void __launch_bounds__(256) trace_kernel(const T* x, T* tr, int nE,
-                                                     const T* __restrict__ basis) {
+                                                     const T* __restrict__ basis, const T* x2, T* tr2) {
     constexpr int NN = ipow(NP, D), NFP = ipow(NP, D - 1);
     constexpr int EPB = 256 / NN > 0 ? 256 / NN : 1;
     constexpr int NT = EPB * NN;
@@ -295,7 +295,12 @@ __global__ void __launch_bounds__(256) trace_kernel(const T* x, T* tr, int nE,
     const int e0 = blockIdx.x * EPB;
     const int nloc = min(EPB, nE - e0);
     const size_t base = (size_t)e0 * NV * NN;
-    // field blockIdx.y of consecutive fields (stride: one state vector in, one trace array out)
+    // blockIdx.z = 1: the second system's fields (paired stage solves); field blockIdx.y of
+    // consecutive fields (stride: one state vector in, one trace array out)
+    if (blockIdx.z) {
+        x = x2;
+        tr = tr2;
+    }
     x += (size_t)blockIdx.y * nE * NV * NN;
     tr += (size_t)blockIdx.y * nE * PER_E;
     if (tid < 2 * NP) s_l[tid / NP][tid % NP] = basis[(tid < NP ? BOff<NP>::LM : BOff<NP>::LP) + tid % NP];
@@ -667,8 +672,13 @@ __device__ __forceinline__ void face_point(const OpArgs<T>& a, const EqParams<T>
     }
 }
 
+// a0: the arguments of the first nb0 blocks; a1: those of the rest (the second system of a pair
+// of stage solves, one launch for both; a single launch passes nb0 = its grid)
 template <int D, int NP, class EQ, class OP, typename T>
-__global__ void __launch_bounds__(256) dg_op_kernel(OpArgs<T> a, EqParams<T> ep) {
+__global__ void __launch_bounds__(256) dg_op_kernel(OpArgs<T> a0, EqParams<T> ep, OpArgs<T> a1, int nb0) {
+    const bool second = (int)blockIdx.x >= nb0;
+    const OpArgs<T>& a = second ? a1 : a0;
+    const int bx = second ? (int)blockIdx.x - nb0 : (int)blockIdx.x;
     constexpr int NN = ipow(NP, D), NFP = ipow(NP, D - 1);
     constexpr int NV = EQ::NV, NJ = OP::NJ, NC = OP::NC;
     constexpr int EPB = kernel_epb<D, NP, EQ, OP, T>();
@@ -688,7 +698,7 @@ __global__ void __launch_bounds__(256) dg_op_kernel(OpArgs<T> a, EqParams<T> ep)
     __shared__ T s_us[NQ > 0 ? NQ * EPB * 2 * D * NFP : 1];   // u* = (u_own + u_nbr)/2 at face points
 
     const int tid = threadIdx.x;
-    const int e0 = a.e_begin + blockIdx.x * EPB;
+    const int e0 = a.e_begin + bx * EPB;
     const int nloc = min(EPB, a.e_end - e0);
 
     // 1) stage the 1-D operators and the jet fields of EPB consecutive elements

@@ -185,6 +185,10 @@ int op_launch(hbpc_ctx* c, const LaunchReq& r, int f32) {
     case OPK_PCPRE: cls = KC_PCPRE; bytes = 5 * n * esz; break;
     case OPK_LINLOC: cls = KC_LIN; bytes = 4 * n * esz; break;
     }
+    if (r.pair) {
+        if (c->ns) set_err(c, HBPC_ERR_UNSUPPORTED, "paired operator launch with BR2 lifting");
+        bytes *= 2;
+    }
     if (c->ns && r.op != OPK_TRACE) {
         // BR2: the face gradients of this op's jet over the whole mesh first (neighbour data of
         // the operator kernel), then the operator with them
@@ -314,6 +318,40 @@ static void op_jvp(hbpc_ctx* c, const void* w, const void* s, const void* trw, c
     r.c0 = a1dt;
     r.c1 = bc;
     op_launch(c, r, f32);
+}
+
+// J X_i for two systems in one trace launch and one operator launch (equations without BR1/BR2
+// lifting): system i at state (w_i, s_i) with traces (trw_i, trs_i), its dX_i traced into tx_i
+// (2 tsz values of the Krylov precision)
+static void op_jvp_pair(hbpc_ctx* c, const void* const* w, const void* const* s, const void* const* trw,
+                        const void* const* trs, const void* const* dX, void* const* Y, void* const* tx, double a1dt,
+                        double bc, int f32, int hess) {
+    if (c->visc || c->ns) set_err(c, HBPC_ERR_UNSUPPORTED, "paired JVP launch with lifting");
+    const size_t esz = f32 ? 4 : 8, tb = c->tsz * esz;
+    LaunchReq t[2], r[2];
+    for (int i = 0; i < 2; ++i) {
+        t[i] = op_req(c, OPK_TRACE);
+        t[i].fld[0] = dX[i];
+        t[i].out[0] = tx[i];
+        t[i].col = 2;
+        r[i] = op_req(c, hess ? OPK_JVP : OPK_JVP_NOHESS);
+        r[i].fld[0] = w[i];
+        r[i].fld[1] = s[i];
+        r[i].fld[2] = dX[i];
+        r[i].fld[3] = (const char*)dX[i] + c->ndof * esz;
+        r[i].trc[0] = trw[i];
+        r[i].trc[1] = trs[i];
+        r[i].trc[2] = tx[i];
+        r[i].trc[3] = (const char*)tx[i] + tb;
+        r[i].out[0] = Y[i];
+        r[i].out[1] = (char*)Y[i] + c->ndof * esz;
+        r[i].c0 = a1dt;
+        r[i].c1 = bc;
+    }
+    t[0].pair = &t[1];
+    r[0].pair = &r[1];
+    op_launch(c, t[0], f32);
+    op_launch(c, r[0], f32);
 }
 
 static void status_reset(hbpc_ctx* c) { hipchk(c, hipMemsetAsync(c->dstatus, 0, sizeof(int), c->stream), "memset"); }
@@ -1104,6 +1142,8 @@ static StageSys sys_ctx(hbpc_ctx* c) {
     S.lpc = 0;
     S.G1 = c->ap_G1;
     S.G2 = c->ap_G2;
+    S.trd1 = c->trd1;
+    S.trd1_32 = c->trd1_32;
     return S;
 }
 
@@ -1132,12 +1172,14 @@ static void pair_alloc(hbpc_ctx* c) {
     void* h = nullptr;
     hipchk(c, hipHostMalloc(&h, (2 * c->arn_len + 64) * sizeof(double)), "hipHostMalloc");
     P.hres = (double*)h;
+    P.trd1 = dalloc<double>(c, 2 * c->tsz);
+    P.trd1_32 = dalloc<float>(c, 2 * c->tsz);
 }
 
 static void pair_free(hbpc_ctx* c) {
     StageSys& P = c->pair;
     void* bufs[] = {P.X, P.G, P.dX, P.rhs, P.b, P.trw, P.trs, P.X32, P.trw32, P.trs32, P.V, P.Z, P.kv,
-                    P.part, P.dres, P.dgram, P.dcount, P.G1, P.G2};
+                    P.part, P.dres, P.dgram, P.dcount, P.G1, P.G2, P.trd1, P.trd1_32};
     for (void* q : bufs) dfree(q);
     if (P.hres) (void)hipHostFree(P.hres);
     std::memset(&P, 0, sizeof(P));
@@ -1264,6 +1306,54 @@ static void fgmres_pair(hbpc_ctx* c, StageSys* S, int* active, double a1dt, doub
             prof_end(c, pi, cls,
                      (double)c->nE * c->NE * c->NE * (c->sinv_type == 2 ? 2.0 : (c->sinv_type == 1 ? 4.0 : 8.0)) +
                          2.0 * nr * n * esz);
+        }
+        if (Rr.cnt == 2 && !c->visc && !c->ns) {
+            // both systems: one trace and one JVP launch, one multi-dot (per chunk), one reduction,
+            // one update and one normalisation launch for the two
+            const void *w2[2], *s2[2], *tw2[2], *ts2[2], *dx2[2], *V2[2], *vj2[2], *u2c[2];
+            void *y2[2], *tx2[2], *u2[2];
+            int k2[2];
+            double *part2[2], *h12[2], *G2[2], *h2[2], *hn2[2];
+            unsigned* cnt2[2];
+            double vb = 0.0, ub = 0.0;
+            for (int q = 0; q < 2; ++q) {
+                const int i = Rr.sys[q], j = Rr.it[q];
+                w2[q] = wst(i);
+                s2[q] = sst(i);
+                tw2[q] = tw(i);
+                ts2[q] = ts(i);
+                dx2[q] = Zj(i, j);
+                y2[q] = u2[q] = Vj(i, j + 1);
+                u2c[q] = u2[q];
+                tx2[q] = f32 ? (void*)S[i].trd1_32 : (void*)S[i].trd1;
+                V2[q] = S[i].V;
+                vj2[q] = Vj(i, j);
+                k2[q] = j + 1;
+                part2[q] = S[i].part;
+                h12[q] = S[i].dres;
+                hn2[q] = S[i].dres + 2 * R;
+                h2[q] = S[i].dres + 2 * R + 4;
+                G2[q] = S[i].dgram;
+                cnt2[q] = S[i].dcount;
+                vb += (j + 3) * (double)n2 * esz;
+                ub += (j + 5) * (double)n2 * esz;
+            }
+            op_jvp_pair(c, w2, s2, tw2, ts2, dx2, y2, tx2, a1dt, bc, f32, c->prm.hessian);
+            long pi = prof_begin(c, KC_GSDOT);
+            hipchk(c, blas_gs_gram_n(2, V2, n2, k2, u2c, vj2, n2, f32, part2, h12, G2, m + 1, h2, cnt2, c->stream),
+                   "gs dot");
+            prof_end(c, pi, KC_GSDOT, vb);
+            pi = prof_begin(c, KC_GSUPD);
+            hipchk(c, blas_gs_update_normalize_n(2, V2, n2, k2, h2, u2, n2, f32, part2, hn2, c->stream), "gs update");
+            prof_end(c, pi, KC_GSUPD, ub);
+            for (int q = 0; q < 2; ++q) {
+                const int i = Rr.sys[q];
+                hipchk(c, hipMemcpyAsync(S[i].hres + c->arn_len * (r & 1), S[i].dres, (3 * R + 4) * sizeof(double),
+                                         hipMemcpyDeviceToHost, c->stream),
+                       "copy");
+            }
+            hipchk(c, hipEventRecord(c->arn_ev[r & 1], c->stream), "event");
+            return true;
         }
         for (int q = 0; q < Rr.cnt; ++q) {
             const int i = Rr.sys[q], j = Rr.it[q];

@@ -21,6 +21,12 @@ hipError_t bj_apply_n(const void* SinvT, int m_type, const void* const* xs, void
 int blas_mdot_grid(size_t n);
 hipError_t blas_mdot(const void* V, size_t ld, int k, const void* w, size_t n, int f32, double* part, double* h,
                      hipStream_t st);
+hipError_t blas_gs_update_normalize_n(int ns, const void* const* V, size_t ld, const int* k, const double* const* h,
+                                      void* const* u, size_t n, int f32, double* const* part,
+                                      double* const* nrm2, hipStream_t st);
+hipError_t blas_gs_gram_n(int ns, const void* const* V, size_t ld, const int* k, const void* const* w1,
+                          const void* const* w2, size_t n, int f32, double* const* part, double* const* h1,
+                          double* const* G, int ldg, double* const* h, unsigned* const* counter, hipStream_t st);
 hipError_t blas_gs_update_normalize(const void* V, size_t ld, int k, const double* h, void* u, size_t n, int f32,
                                     double* part, double* nrm2, hipStream_t st);
 hipError_t blas_gs_gram(const void* V, size_t ld, int k, const void* w1, const void* w2, size_t n, int f32,
@@ -95,6 +101,8 @@ struct StageSys {
     unsigned* dcount;
     int lpc;                  // learned preconditioner active for this system's solve
     float *G1, *G2;           // its network gates at the current linearisation state
+    double* trd1;             // traces of a JVP input (2 tsz values: dw then dsigma), FP64 / FP32
+    float* trd1_32;
 };
 
 struct hbpc_ctx {
