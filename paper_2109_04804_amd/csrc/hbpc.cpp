@@ -1211,6 +1211,26 @@ static void pcpre_into(hbpc_ctx* c, const void* w, const void* trw, const void* 
     op_launch(c, r, f32);
 }
 
+// the PCPRE products of two systems' Krylov vectors in one launch (no lifting)
+static void pcpre_pair(hbpc_ctx* c, const void* const* w, const void* const* trw, const void* const* X,
+                       void* const* kv, int f32) {
+    const size_t esz = f32 ? 4 : 8;
+    LaunchReq r[2];
+    for (int i = 0; i < 2; ++i) {
+        r[i] = op_req(c, OPK_PCPRE);
+        r[i].fld[0] = w[i];
+        r[i].fld[1] = X[i];
+        r[i].fld[2] = (const char*)X[i] + c->ndof * esz;
+        r[i].trc[0] = trw[i];
+        r[i].out[0] = kv[i];
+        r[i].out[1] = (char*)kv[i] + c->ndof * esz;
+        r[i].c0 = c->pc_a1dt;
+        r[i].c1 = c->pc_bc;
+    }
+    r[0].pair = &r[1];
+    op_launch(c, r[0], f32);
+}
+
 static void fgmres_pair(hbpc_ctx* c, StageSys* S, int* active, double a1dt, double bc, int f32, int* its) {
     const size_t n2 = c->n2, n = c->ndof, esz = f32 ? 4 : 8;
     const int m = c->prm.gmres_restart, maxit = c->prm.gmres_maxit;
@@ -1289,10 +1309,23 @@ static void fgmres_pair(hbpc_ctx* c, StageSys* S, int* active, double a1dt, doub
         const void* xs[4];
         void* ys[4];
         int nr = 0;
+        const bool pre2 = Rr.cnt == 2 && !cy[Rr.sys[0]].learned && !cy[Rr.sys[1]].learned && !c->visc && !c->ns;
+        if (pre2) {   // both systems' pre-products in one launch
+            const void *w2[2], *t2[2], *x2[2];
+            void* k2[2];
+            for (int q = 0; q < 2; ++q) {
+                const int i = Rr.sys[q];
+                w2[q] = wst(i);
+                t2[q] = tw(i);
+                x2[q] = Vj(i, Rr.it[q]);
+                k2[q] = S[i].kv;
+            }
+            pcpre_pair(c, w2, t2, x2, k2, f32);
+        }
         for (int q = 0; q < Rr.cnt; ++q) {
             const int i = Rr.sys[q], j = Rr.it[q];
             if (cy[i].learned) continue;
-            pcpre_into(c, wst(i), tw(i), Vj(i, j), S[i].kv, f32);
+            if (!pre2) pcpre_into(c, wst(i), tw(i), Vj(i, j), S[i].kv, f32);
             xs[nr] = S[i].kv;
             ys[nr++] = Zj(i, j);
             xs[nr] = (const char*)S[i].kv + n * esz;
