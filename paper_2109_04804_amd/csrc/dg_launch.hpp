@@ -28,7 +28,7 @@ struct LaunchReq {
     const void* q[4][3];
     const void* qtr[4];
     void* out[4];
-    void* nsg[4];         // BR2 face gradients per jet component (Navier-Stokes)
+    void* nsg[4];         // BR2: viscous fluxes at the face points per jet component (Navier-Stokes)
     int aux;              // 1: run the BR2 face-gradient kernel of this op instead of the op
     double c0, c1;
     int col;

@@ -234,7 +234,7 @@ template <typename T, bool LOC> struct OpLin {
 // waves resident on a CU under gfx950's 160 KB of LDS (per CU and per workgroup), counted up to
 // 12 waves (3 per SIMD: the register budget of the jet kernels, 100-160 VGPRs, allows no more);
 // ties go to more elements per block (fewer idle threads in the face phase).  bytes: LDS per element.
-template <int NN> constexpr int best_epb(int bytes) {
+template <int NN> constexpr int best_epb(int bytes, bool small_ties = false) {
     int best = 1, best_w = 0;
     for (int e = 1; e * NN <= 256; ++e) {
         const int blk = e * bytes + 1024;   // + the 1-D operators
@@ -242,7 +242,7 @@ template <int NN> constexpr int best_epb(int bytes) {
         const int per_cu = 163840 / blk;
         int w = per_cu * ((e * NN + 63) / 64);
         if (w > 12) w = 12;
-        if (w >= best_w) {
+        if (small_ties ? w > best_w : w >= best_w) {
             best_w = w;
             best = e;
         }
@@ -272,13 +272,13 @@ template <int D, int NP, class EQ, class OP, typename T> constexpr int kernel_ep
     return best_epb<NN>(bytes);
 }
 // elements per block of the BR2 face-gradient kernel (jet fields and the lifting in LDS)
+// (the lifting data leave a CU only a few waves whatever the block size; there independent small
+// blocks hide latency better than one block of several waves, and this kernel has no face phase
+// whose threads a one-element block would leave idle)
 template <int D, int NP, class EQ, class OP, typename T> constexpr int aux_epb() {
     constexpr int NN = ipow(NP, D);
-    constexpr int bytes = OP::NJ * EQ::NV * NN * (int)sizeof(T) + ns_lds_bytes<D, NP, EQ, typename OP::S>() + 64;
-    constexpr int by_lds = 159 * 1024 / bytes;
-    constexpr int by_thr = 256 / NN;
-    constexpr int e = by_lds < by_thr ? by_lds : by_thr;
-    return e < 1 ? 1 : e;
+    constexpr int bytes = OP::NJ * EQ::NV * NN * (int)sizeof(T) + ns_lds_bytes<D, NP, EQ, typename OP::S>();
+    return best_epb<NN>(bytes, true);
 }
 
 // ----------------------------------------------------------------- trace kernel
@@ -518,9 +518,40 @@ __device__ __forceinline__ void ns_face_grad(const OpArgs<T>& a, const EqParams<
     }
 }
 
-// BR2 face-gradient kernel: for every element and face point the element's own face gradient
-// d (jet components j < NGLOB) into a.nsg[j][((e * 2D + face) * NG * D + k * D + jdir) * NFP + fp];
-// the operator kernel reads the neighbours' values from there
+// the element's own viscous flux F^v(w, d) . e_M at a face point of its face 2M + side: w the
+// trace of its fields there (jet components >= NGLOB zero), d its BR2 face gradient
+template <int D, int NP, int M, class EQ, class OP, typename T, int EPB, int NN, int NFP>
+__device__ __forceinline__ void ns_face_vflux(const OpArgs<T>& a, const EqParams<T>& ep, const T* s_b,
+                                              const T (*s_fld)[EPB][EQ::NV][NN], const typename OP::S* s_dv,
+                                              const typename OP::S* s_jmp, int fel, int side, int fp,
+                                              typename OP::S* fv) {
+    using S = typename OP::S;
+    constexpr int NV = EQ::NV, NG = EQ::NG, NJ = OP::NJ;
+    S d[NG][D];
+    ns_face_grad<D, NP, M, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_dv, s_jmp, fel, side, fp, d);
+    const T* l = s_b + (side ? BOff<NP>::LP : BOff<NP>::LM);
+    S own[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        T x[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            T acc = T(0);
+            if (j < OP::NGLOB) {
+#pragma unroll
+                for (int q = 0; q < NP; ++q) acc += l[q] * s_fld[j][fel][v][node_on_line<D, NP>(fp, M, q)];
+            }
+            x[j] = acc;
+        }
+        own[v] = OP::make(x, a);
+    }
+    EQ::viscous_flux(own, d, M, fv, ep);
+}
+
+// BR2 face-gradient kernel: for every element and face point the element's own viscous flux
+// F^v(w, d) . e_m with its BR2 face gradient d (jet components j < NGLOB) into
+// a.nsg[j][((e * 2D + face) * NV + v) * NFP + fp]; the operator kernel reads the neighbours'
+// values from there (NV values per face point instead of the (d + 1) d of the gradient)
 template <int D, int NP, class EQ, class OP, typename T>
 __global__ void __launch_bounds__(256) ns_facegrad_kernel(OpArgs<T> a, EqParams<T> ep) {
     if constexpr (EQ::NS) {
@@ -558,27 +589,27 @@ __global__ void __launch_bounds__(256) ns_facegrad_kernel(OpArgs<T> a, EqParams<
         for (int i = tid; i < nloc * 2 * D * NFP; i += NT) {
             const int fel = i / (2 * D * NFP), r = i % (2 * D * NFP);
             const int face = r / NFP, fp = r % NFP;
-            S d[NG][D];
+            S fv[NV];
             const int m = face >> 1, side = face & 1;
             if (m == 0) {
-                ns_face_grad<D, NP, 0, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_dv, s_jmp, fel, side, fp, d);
+                ns_face_vflux<D, NP, 0, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_dv, s_jmp, fel, side, fp, fv);
             } else if (m == 1) {
                 if constexpr (D > 1)
-                    ns_face_grad<D, NP, 1, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_dv, s_jmp, fel, side, fp, d);
+                    ns_face_vflux<D, NP, 1, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_dv, s_jmp, fel, side, fp,
+                                                                      fv);
             } else {
                 if constexpr (D > 2)
-                    ns_face_grad<D, NP, 2, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_dv, s_jmp, fel, side, fp, d);
+                    ns_face_vflux<D, NP, 2, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_fld, s_dv, s_jmp, fel, side, fp,
+                                                                      fv);
             }
-            const size_t base = ((size_t)(e0 + fel) * 2 * D + face) * NG * D;
+            const size_t base = ((size_t)(e0 + fel) * 2 * D + face) * NV;
 #pragma unroll
-            for (int k = 0; k < NG; ++k)
+            for (int v = 0; v < NV; ++v) {
+                T x[NJ];
+                OP::split(fv[v], x);
 #pragma unroll
-                for (int j = 0; j < D; ++j) {
-                    T x[NJ];
-                    OP::split(d[k][j], x);
-#pragma unroll
-                    for (int c = 0; c < OP::NGLOB; ++c) a.nsg[c][(base + k * D + j) * NFP + fp] = x[c];
-                }
+                for (int c = 0; c < OP::NGLOB; ++c) a.nsg[c][(base + v) * NFP + fp] = x[c];
+            }
         }
     }
 }
@@ -642,26 +673,20 @@ __device__ __forceinline__ void face_point(const OpArgs<T>& a, const EqParams<T>
     }
     if constexpr (EQ::NS) {
         // BR2 viscous surface flux (F^v(w_own, d_own) + F^v(w_nbr, d_nbr))/2 (Eq. Riemann_visc), the
-        // neighbour's face gradient from the face-gradient kernel
+        // neighbour's flux from the face-gradient kernel
         constexpr int NG = EQ::NG;
-        S dn[NG][D], dnb[NG][D];
+        S dn[NG][D];
         ns_face_grad<D, NP, M, EQ, OP, T, EPB, NN, NFP>(a, ep, s_b, s_dv, s_jmp, fel, side, fp, dn);
-        const size_t gb = ((size_t)enb * 2 * D + (2 * M + 1 - side)) * NG * D;
-#pragma unroll
-        for (int k = 0; k < NG; ++k)
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-                T y[NJ];
-#pragma unroll
-                for (int c = 0; c < NJ; ++c)
-                    y[c] = c < OP::NGLOB ? a.nsg[c][(gb + k * D + j) * NFP + fp] : T(0);
-                dnb[k][j] = OP::make(y, a);
-            }
-        S fo[NV], fn[NV];
+        S fo[NV];
         EQ::viscous_flux(own, dn, M, fo, ep);
-        EQ::viscous_flux(nb, dnb, M, fn, ep);
+        const size_t gb = ((size_t)enb * 2 * D + (2 * M + 1 - side)) * NV;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) f[v] = f[v] - (fo[v] + fn[v]) * T(0.5);
+        for (int v = 0; v < NV; ++v) {
+            T y[NJ];
+#pragma unroll
+            for (int c = 0; c < NJ; ++c) y[c] = c < OP::NGLOB ? a.nsg[c][(gb + v) * NFP + fp] : T(0);
+            f[v] = f[v] - (fo[v] + OP::make(y, a)) * T(0.5);
+        }
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {

@@ -1888,8 +1888,8 @@ static void ctx_init(hbpc_ctx* c, const hbpc_mesh* mesh, int N, int equation, co
             c->qtr[0][j] = dalloc<double>(c, c->tsz);
             c->qtr[1][j] = dalloc<float>(c, c->tsz);
         }
-    if (c->ns) {   // per element and face: NG = d + 1 lifted variables x d gradient directions
-        const size_t gsz = (size_t)c->nE * 2 * c->D * (c->D + 1) * c->D * c->NFP;
+    if (c->ns) {   // per element, face and face point: the nvar components of the viscous flux
+        const size_t gsz = (size_t)c->nE * 2 * c->D * c->NV * c->NFP;
         for (int j = 0; j < 4; ++j) {
             c->nsg[0][j] = dalloc<double>(c, gsz);
             c->nsg[1][j] = dalloc<float>(c, gsz);

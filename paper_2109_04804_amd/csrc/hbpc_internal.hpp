@@ -131,7 +131,7 @@ struct hbpc_ctx {
     double* basis64; float* basis32;                         // 1-D operators on the device
     int visc;                                                // BR1 viscous terms (Burgers)
     int ns;                                                  // BR2 viscous terms (Navier-Stokes)
-    void* nsg[2][4];          // BR2 face gradients per jet component, [FP64|FP32][component]
+    void* nsg[2][4];          // BR2: each element's viscous flux at its face points per jet component, [FP64|FP32][component]
     void* qtr[2][4];                                         // BR1 lifted-gradient traces [f32][field]
     // FP32 snapshots
     float* X32;               // 2 ndof
