@@ -56,6 +56,25 @@ def test_measured_traffic_follows_the_source_hash(tmp_path, monkeypatch):
     assert bench.measured_traffic("bj_apply", "wl") is None
 
 
+def test_committed_traffic_records_are_current():
+    """Every committed counter record that bench.py reads names a kernel source whose SHA-256 it
+    recorded; a kernel changed since its counters were taken would make the bench report no
+    measured traffic."""
+    import glob
+    import hashlib
+    import re
+    recs = []
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
+        m = re.search(r"<!-- traffic (\{.*\}) -->", open(path).read())
+        if m:
+            recs.append((path, json.loads(m.group(1))))
+    assert recs
+    for path, rec in recs:
+        src = os.path.join(ROOT, rec["source"])
+        assert hashlib.sha256(open(src, "rb").read()).hexdigest() == rec["sha256"], os.path.basename(path)
+        assert bench.measured_traffic(rec["kernel"], rec["workload"]) == float(rec["bytes_per_launch"])
+
+
 def test_form_settings():
     """Each benchmark form maps to the precision, preconditioner and block storage it names."""
     assert bench.form_settings("fp64") == ("fp64", "bjext", 0)
