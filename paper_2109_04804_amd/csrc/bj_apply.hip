@@ -11,7 +11,7 @@
 // y_k = S^-1 x_k for NR right-hand sides: the w and sigma blocks of one Krylov vector (NR = 2), or
 // of two systems that share the blocks (NR = 4: the corrector stages of a sweep solved together).
 // S^-1 stored transposed (column-major blocks, SinvT[e][c][r]), each thread owns groups of VR
-// consecutive rows (one 16-byte load per column when VR * sizeof(TM) == 16): min(NE / VR, 256)
+// consecutive rows (loads of at most 16 bytes, VR * sizeof(TM) bytes per column): min(NE / VR, 256)
 // threads per element, a thread taking every tpe-th group when there are more groups than threads;
 // several elements per block; the right-hand sides staged in LDS.  One pass over S^-1 serves all NR.
 template <typename T, int NR> struct ApplyVecs {
@@ -19,7 +19,7 @@ template <typename T, int NR> struct ApplyVecs {
     T* y[NR];
 };
 
-template <typename TM, typename T, int VR, int NR>
+template <typename TM, typename T, int VR, int NR, int UNR>
 __global__ void __launch_bounds__(256) bj_apply_kernel(const TM* __restrict__ SinvT, ApplyVecs<T, NR> v, int NE,
                                                       int nE) {
     extern __shared__ unsigned char smem_raw[];
@@ -39,7 +39,8 @@ __global__ void __launch_bounds__(256) bj_apply_kernel(const TM* __restrict__ Si
     __syncthreads();
     const int e = e0 + el;
     if (el >= epb || e >= nE) return;
-    typedef TM VT __attribute__((ext_vector_type(VR)));
+    constexpr int LV = 16 / sizeof(TM) < VR ? 16 / (int)sizeof(TM) : VR;   // values per load (<= 16 bytes)
+    typedef TM VT __attribute__((ext_vector_type(LV)));
     const T* x = sx + NR * el * NE;
     for (int gr = threadIdx.x % tpe; gr < ng; gr += tpe) {
         const int r0 = gr * VR;
@@ -49,9 +50,15 @@ __global__ void __launch_bounds__(256) bj_apply_kernel(const TM* __restrict__ Si
         for (int k = 0; k < NR; ++k)
 #pragma unroll
             for (int q = 0; q < VR; ++q) s[k][q] = T(0);
-#pragma unroll 4
+#pragma unroll UNR
         for (int c = 0; c < NE; ++c) {
-            const VT m = *reinterpret_cast<const VT*>(M + (size_t)c * NE);
+            TM m[VR];
+#pragma unroll
+            for (int h = 0; h < VR / LV; ++h) {
+                const VT t = *reinterpret_cast<const VT*>(M + (size_t)c * NE + h * LV);
+#pragma unroll
+                for (int q = 0; q < LV; ++q) m[h * LV + q] = t[q];
+            }
 #pragma unroll
             for (int k = 0; k < NR; ++k) {
                 const T xc = x[NR * c + k];
@@ -66,7 +73,7 @@ __global__ void __launch_bounds__(256) bj_apply_kernel(const TM* __restrict__ Si
     }
 }
 
-template <typename TM, typename T, int VR, int NR>
+template <typename TM, typename T, int VR, int NR, int UNR = 4>
 static void launch_apply(const TM* SinvT, const ApplyVecs<T, NR>& v, int NE, int nE, hipStream_t st) {
     const int ng = NE / VR;
     const int tpe = ng < 256 ? ng : 256;
@@ -74,7 +81,7 @@ static void launch_apply(const TM* SinvT, const ApplyVecs<T, NR>& v, int NE, int
     const int threads = epb * tpe;
     const int grid = (nE + epb - 1) / epb;
     const size_t sh = (size_t)NR * epb * NE * sizeof(T);
-    hipLaunchKernelGGL((bj_apply_kernel<TM, T, VR, NR>), dim3(grid), dim3(threads), sh, st, SinvT, v, NE, nE);
+    hipLaunchKernelGGL((bj_apply_kernel<TM, T, VR, NR, UNR>), dim3(grid), dim3(threads), sh, st, SinvT, v, NE, nE);
 }
 
 // rows per thread: a 16-byte load of S^-1 when NE allows it
@@ -86,6 +93,18 @@ static void apply_vr(const void* SinvT, const void* const* xs, void* const* ys, 
     for (int k = 0; k < NR; ++k) {
         v.x[k] = (const T*)xs[k];
         v.y[k] = (T*)ys[k];
+    }
+    if constexpr (sizeof(TM) == 4 && sizeof(T) == 4) {
+        // FP32 blocks and vectors: rows per thread and unroll depth as measured fastest for the
+        // element blocks of the 2-D (NE = 144) and 3-D (NE = 320) Euler workloads, each with two
+        // and four right-hand sides (the others keep 4 rows and an unroll of 4)
+        if (NE <= 160) {
+            if (NR == 2 && NE % 8 == 0) return launch_apply<TM, T, 8, NR, 4>(M, v, NE, nE, st);
+            if (NR == 4 && NE % 4 == 0) return launch_apply<TM, T, 4, NR, 2>(M, v, NE, nE, st);
+        } else {
+            if (NR == 2 && NE % 4 == 0) return launch_apply<TM, T, 4, NR, 8>(M, v, NE, nE, st);
+            if (NR == 4 && NE % 8 == 0) return launch_apply<TM, T, 8, NR, 2>(M, v, NE, nE, st);
+        }
     }
     if (NE % V == 0)
         launch_apply<TM, T, V, NR>(M, v, NE, nE, st);
