@@ -335,6 +335,32 @@ def test_navier_stokes_step(name, precision, rtol, tol):
     assert np.abs(dg.integral(host(wg).reshape(w0.shape)) - dg.integral(w0)).max() < 1e-10 * np.abs(dg.integral(w0)).max()
 
 
+
+@pytest.mark.parametrize("name,N", [("euler2_lf", 4), ("euler2_lf", 6), ("euler2_n7_lfl", 7), ("burgers2", 4)])
+def test_paired_mixed_block_sizes(name, N):
+    """Paired corrector solves in mixed precision for element blocks of 100, 196, 256 and 25
+    unknowns, so that the FP32 apply to four right-hand sides runs with every row grouping the
+    launcher picks by block size (4 rows and unroll 2; 4 rows and unroll 4 when 8 does not
+    divide the block; 8 rows and unroll 2; one row) and the one-system FP32 apply of the
+    predictor solves with its own choices: HBPC(6,2), dt = 0.1, eps_N = 1e-8, against the oracle
+    at the same eps_N (relative L2 <= 1e-8)."""
+    case = dict(CASES[name])
+    case.update(N=N)
+    if name == "burgers2":
+        case.update(nelem=[6, 6])
+    dg = oracle_for(case)
+    w0 = state(dg, seed=8)
+    ctx = ctx_for(case, q=6, kmax=2, newton_rtol=1e-8, gmres_rtol=1e-5, precision="mixed", pc_rebuild="paired")
+    wg = dev(w0)
+    stats = ctx.step(wg, 0.1)
+    print(name, N, "block", ctx.block, stats["newton_its"], stats["gmres_its"], stats["gmres_per_solve"], flush=True)
+    assert stats["n_solves"] == 2 * (1 + 2)
+    ref = dg_hbpc_step(dg, w0, 0.1, 6, 2, StageSolver(dg, newton_rtol=1e-8, gmres_rtol=1e-5))
+    err = rel(host(wg), ref)
+    print("rel err", err, flush=True)
+    assert err < 1e-8
+
+
 _NS_REF = {}
 
 
