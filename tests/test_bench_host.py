@@ -87,3 +87,21 @@ def test_form_settings():
     with pytest.raises(ValueError):
         bench.form_settings("fp16")
     assert bench.STUDY_PC == ("none", "bjext", "bjext_h")
+
+
+def test_profile_commands_run_committed_files():
+    """Every profile summary gives the command that made it, and the scripts that command runs
+    are files of this repository (no working files)."""
+    import glob
+    import re
+    paths = sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md")))
+    assert paths
+    for path in paths:
+        text = open(path).read()
+        blocks = re.findall(r"```\n(.*?)```", text, re.S)
+        assert blocks, os.path.basename(path)
+        cmd = " ".join(blocks)
+        assert "rocprofv3" in cmd, os.path.basename(path)
+        assert "_work" not in cmd, os.path.basename(path)
+        for script in re.findall(r"(?:python3?|--)\s+(\S+\.py)", cmd):
+            assert os.path.exists(os.path.join(ROOT, script)), (os.path.basename(path), script)
