@@ -122,13 +122,14 @@ template <int D, int NP, class EQ, typename T> hipError_t launch_family_np(const
     constexpr int NN = ipow(NP, D);
     switch (r.op) {
     case OPK_TRACE: {
-        constexpr int EPB = 256 / NN > 0 ? 256 / NN : 1;
+        constexpr int EPB = trace_epb<NN>();
         int grid = (g.nE + EPB - 1) / EPB;
         if (grid == 0) return hipSuccess;
         const int nf = r.col > 1 ? r.col : 1;   // consecutive fields (col = their number)
         const T* x2 = r.pair ? (const T*)r.pair->fld[0] : (const T*)r.fld[0];
         T* tr2 = r.pair ? (T*)r.pair->out[0] : (T*)r.out[0];
-        hipLaunchKernelGGL((trace_kernel<D, NP, NV, T>), dim3(grid, nf, r.pair ? 2 : 1), dim3(EPB * NN), 0, r.stream,
+        hipLaunchKernelGGL((trace_kernel<D, NP, NV, T>), dim3(grid, nf, r.pair ? 2 : 1), dim3(trace_threads<NN>()), 0,
+                           r.stream,
                            (const T*)r.fld[0], (T*)r.out[0], g.nE, basis_ptr<T>(g), x2, tr2);
         return hipGetLastError();
     }

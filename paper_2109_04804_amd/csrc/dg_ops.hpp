@@ -282,14 +282,19 @@ template <int D, int NP, class EQ, class OP, typename T> constexpr int aux_epb()
 }
 
 // ----------------------------------------------------------------- trace kernel
+// threads per block (whole elements' nodes, at most 256) and elements per block (twice as many:
+// each thread loads and interpolates for two elements, more loads in flight per block)
+template <int NN> constexpr int trace_threads() { return (256 / NN > 0 ? 256 / NN : 1) * NN; }
+template <int NN> constexpr int trace_epb() { return 2 * (256 / NN > 0 ? 256 / NN : 1); }
+
 template <int D, int NP, int NV, typename T>
 __global__ void __launch_bounds__(256) trace_kernel(const T* x, T* tr, int nE,
                                                      const T* __restrict__ basis, const T* x2, T* tr2) {
     constexpr int NN = ipow(NP, D), NFP = ipow(NP, D - 1);
-    constexpr int EPB = 256 / NN > 0 ? 256 / NN : 1;
-    constexpr int NT = EPB * NN;
+    constexpr int EPB = trace_epb<NN>();
+    constexpr int NT = trace_threads<NN>();
     constexpr int PER_E = 2 * D * NV * NFP;
-    __shared__ T s[EPB * NV * NN];
+    __shared__ __align__(16) T s[EPB * NV * NN];
     __shared__ T s_l[2][NP];      // l(-1), l(+1)
     const int tid = threadIdx.x;
     const int e0 = blockIdx.x * EPB;
@@ -304,7 +309,19 @@ __global__ void __launch_bounds__(256) trace_kernel(const T* x, T* tr, int nE,
     x += (size_t)blockIdx.y * nE * NV * NN;
     tr += (size_t)blockIdx.y * nE * PER_E;
     if (tid < 2 * NP) s_l[tid / NP][tid % NP] = basis[(tid < NP ? BOff<NP>::LM : BOff<NP>::LP) + tid % NP];
-    for (int i = tid; i < nloc * NV * NN; i += NT) s[i] = x[base + i];
+    constexpr int VW = 16 / (int)sizeof(T);   // values per 16-byte load
+    if constexpr ((NV * NN) % VW == 0) {
+        if ((reinterpret_cast<uintptr_t>(x) & 15) == 0) {   // whole elements are whole 16-byte pieces
+            typedef T VT __attribute__((ext_vector_type(VW)));
+            const VT* xv = reinterpret_cast<const VT*>(x + base);
+            VT* sv = reinterpret_cast<VT*>(s);
+            for (int i = tid; i < nloc * NV * NN / VW; i += NT) sv[i] = xv[i];
+        } else {
+            for (int i = tid; i < nloc * NV * NN; i += NT) s[i] = x[base + i];
+        }
+    } else {
+        for (int i = tid; i < nloc * NV * NN; i += NT) s[i] = x[base + i];
+    }
     __syncthreads();
     for (int i = tid; i < nloc * PER_E; i += NT) {
         int el = i / PER_E, r = i % PER_E;
