@@ -137,6 +137,34 @@ def test_jvp_fp32(name):
     assert rel(host(out), np.concatenate([Jw.ravel(), Js.ravel()])) < 5e-5
 
 
+@pytest.mark.parametrize("name", ["euler2_n5", "euler3_n3"])
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_jvp_inputs_off_16_byte_boundaries(name, dtype):
+    """The trace kernel loads whole elements as 16-byte pieces when its input starts on a
+    16-byte boundary and value by value otherwise: inputs that start one value past such a
+    boundary (views into a larger array) give bitwise the same JVP as aligned copies."""
+    case, dg, ctx = setup(name)
+    tdt = torch.float64 if dtype == "fp64" else torch.float32
+    w = state(dg)
+    s = dg.r1(w)
+    X = np.concatenate([perturbation(dg, 4).ravel(), perturbation(dg, 5).ravel()])
+    a1dt, bc = 0.1, 0.1 ** 2 / 2
+    call = ctx.jvp if dtype == "fp64" else ctx.jvp_f32
+
+    def shifted(x):
+        buf = torch.zeros(x.size + 1, dtype=tdt, device="cuda")
+        buf[1:] = torch.tensor(np.ascontiguousarray(x).reshape(-1), dtype=tdt, device="cuda")
+        v = buf[1:]
+        assert v.data_ptr() % 16 != 0
+        return v
+
+    out_a = torch.empty(2 * ctx.ndof, dtype=tdt, device="cuda")
+    out_s = torch.empty(2 * ctx.ndof, dtype=tdt, device="cuda")
+    call(dev(w, tdt), dev(s, tdt), a1dt, bc, dev(X, tdt), out_a)
+    call(shifted(w), shifted(s), a1dt, bc, shifted(X), out_s)
+    assert torch.equal(out_a, out_s)
+
+
 @pytest.mark.parametrize("name", ["euler2_n5", "euler3_n3", "adv1_upwind", "burgers2", "ns2"])
 def test_jvp_finite_difference(name):
     """Eq. MatrixFree_nonlinear on the GPU against the exact (oracle) JVP."""
